@@ -1,0 +1,322 @@
+"""Pins of the CPU oracle against results that do not come from the oracle.
+
+Every test here checks the oracle against mathematics or the paper: closed
+forms, textbook special cases, library routines on special cases, invariants
+and brute force.  They run on the CPU (no GPU marker).
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.special as sps
+import mpmath
+
+from oracle import ge, mesh, pipeline, rmatrix, system
+from tests.helpers import CustomSystem, diagonal_potential, relerr
+from workload import make_system
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
+
+
+# ---------------------------------------------------------------- mesh ----
+
+@pytest.mark.parametrize("nr", [1, 2, 7, 40, 100])
+def test_gauss_points_are_legendre_zeros(nr):
+    x, lam = mesh.gauss_points(nr)
+    assert np.all(np.diff(x) > 0) and x[0] > 0 and x[-1] < 1
+    assert abs(lam.sum() - 1.0) < 1e-14
+    # zeros of P_N(2x - 1), checked with scipy's Legendre evaluation
+    assert np.max(np.abs(sps.eval_legendre(nr, 2 * x - 1))) < 1e-12
+    # exact for monomials of degree <= 2N - 1 on (0, 1)
+    for d in range(0, 2 * nr):
+        assert abs(np.dot(lam, x ** d) - 1.0 / (d + 1)) < 1e-13 * max(1, d)
+
+
+@pytest.mark.parametrize("nr,a", [(10, 5.0), (40, 15.0), (100, 30.0)])
+def test_lagrange_property(nr, a):
+    r, w = mesh.mesh(nr, a)
+    F = mesh.basis(nr, a, r)
+    assert np.max(np.abs(F * np.sqrt(w)[:, None] - np.eye(nr))) < 1e-11
+    # basis vanishes at r = 0
+    assert np.max(np.abs(mesh.basis(nr, a, np.array([0.0])))) == 0.0
+
+
+@pytest.mark.parametrize("nr,a", [(10, 5.0), (40, 15.0), (60, 20.0), (100, 30.0)])
+def test_kinetic_bloch_acts_exactly_on_polynomials(nr, a):
+    """For u = (r/a)^k, 1 <= k <= N (inside the span of the f_i):
+    sum_j TL_ij c_j = f_i(a) u'(a) - integral f_i u'' dr, and the last integral is
+    sqrt(a lambda_i) u''(r_i) by the Gauss rule (exact for degree <= 2N-1)."""
+    r, w = mesh.mesh(nr, a)
+    TL = mesh.kinetic_bloch(nr, a)
+    q = mesh.surface_values(nr, a)
+    for k in sorted({1, 2, 3, 5, nr // 2, nr}):
+        c = np.sqrt(w) * (r / a) ** k
+        upp = k * (k - 1) / a ** 2 * (r / a) ** (k - 2) if k >= 2 else 0.0 * r
+        rhs = (k / a) * q - np.sqrt(w) * upp
+        scale = np.abs(TL) @ np.abs(c) + np.abs(rhs)
+        assert np.max(np.abs(TL @ c - rhs) / scale) < 5e-12, k
+
+
+@pytest.mark.parametrize("nr,a", [(12, 6.0), (60, 20.0)])
+def test_kinetic_bloch_is_a_gram_matrix(nr, a):
+    TL = mesh.kinetic_bloch(nr, a)
+    assert np.max(np.abs(TL - TL.T)) <= 1e-14 * np.max(np.abs(TL))
+    assert np.linalg.eigvalsh(TL).min() > 0
+
+
+def test_surface_values_closed_form():
+    # f_i(a) = (-1)^(N+i) / sqrt(a x_i (1 - x_i)) follows from P_N(1) = 1
+    for nr, a in [(5, 3.0), (40, 15.0), (100, 30.0)]:
+        x, _ = mesh.gauss_points(nr)
+        i = np.arange(1, nr + 1)
+        ref = (-1.0) ** (nr + i) / np.sqrt(a * x * (1 - x))
+        assert relerr(mesh.surface_values(nr, a), ref) < 1e-12
+
+
+# ------------------------------------------------------------ assembly ----
+
+def test_paper_sparsity_fraction():
+    """Sec. 2: about 3% non-zero elements for n_ch ~ 50, n_lag ~ 100."""
+    g = json.load(open(GOLDEN))["sparsity"]
+    sp = make_system("small", nc=g["nc"], nr=g["nr"])
+    M, B = system.assemble(sp, 12.0)
+    frac = np.count_nonzero(M) / M.size
+    assert abs(frac - g["fraction_approx"]) < 0.005
+    # exactly: dense diagonal blocks + one diagonal per off-diagonal block
+    nc, nr = g["nc"], g["nr"]
+    assert np.count_nonzero(M) == nc * nr * nr + nc * (nc - 1) * nr
+
+
+def test_assembly_symmetric_and_structured_apply():
+    sp = make_system("small")
+    M, B = system.assemble(sp, sp.energies[3])
+    assert np.array_equal(M, M.T)  # complex symmetric, exactly
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((sp.n, 3)) + 1j * rng.standard_normal((sp.n, 3))
+    assert relerr(system.apply(sp, sp.energies[3], X), M @ X) < 1e-13
+    # B: column c holds q in block c only
+    md = system.MeshData(sp.nr, sp.a)
+    for c in range(sp.nc):
+        col = np.zeros(sp.n, complex)
+        col[c * sp.nr:(c + 1) * sp.nr] = md.q
+        assert np.array_equal(B[:, c], col)
+
+
+def test_assembly_entries_by_hand():
+    """Spot entries of M against Eq. block_structure written out directly."""
+    sp = make_system("small")
+    E = 7.0
+    md = system.MeshData(sp.nr, sp.a)
+    M, _ = system.assemble(sp, E, md)
+    v = sp.potential(md.r)
+    nr = sp.nr
+    c, cp, i, j = 2, 0, 5, 9
+    assert M[c * nr + i, cp * nr + j] == 0  # off-diagonal block, i != j
+    assert M[c * nr + i, cp * nr + i] == v[i, c, cp]
+    h = sp.hbar2_2mu
+    lc = sp.l[c]
+    diag = h * md.tl[i, i] + h * lc * (lc + 1) / md.r[i] ** 2 + sp.eps[c] - E + v[i, c, c]
+    assert abs(M[c * nr + i, c * nr + i] - diag) < 1e-12 * abs(diag)
+    assert M[c * nr + i, c * nr + j] == h * md.tl[i, j]
+
+
+# ------------------------------------------------------ linear solve ----
+
+@pytest.mark.parametrize("n", [1, 2, 5, 17, 64])
+def test_ge_matches_inverse_and_lapack_pivots(n):
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    B = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+    X, LU, ipiv = ge.solve(A, B)
+    assert relerr(X, np.linalg.inv(A) @ B) < 1e-11
+    # same pivot rule as LAPACK getrf (largest |Re|+|Im|, first on ties)
+    _, piv = scipy.linalg.lu_factor(A)
+    assert np.array_equal(ipiv, piv)
+    # P A = L U
+    L = np.tril(LU, -1) + np.eye(n)
+    U = np.triu(LU)
+    PA = A.copy()
+    for k in range(n):
+        PA[[k, ipiv[k]]] = PA[[ipiv[k], k]]
+    assert relerr(L @ U, PA) < 1e-14 * n
+
+
+def test_ge_manufactured_solution():
+    """Sec. 6 (Table mgpu): x = 1, b = A 1, 64 right-hand sides."""
+    g = json.load(open(GOLDEN))["manufactured_solution"]
+    rng = np.random.default_rng(7)
+    n = 300
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 30 * np.eye(n)
+    X1 = np.ones((n, g["nrhs"]), complex)
+    X, _, _ = ge.solve(A, A @ X1)
+    assert np.max(np.abs(X - 1)) < g["max_forward_error"]
+
+
+def test_ge_zero_pivot_reported():
+    A = np.zeros((4, 4), complex)
+    A[0, 0] = 1
+    with pytest.raises(ZeroDivisionError):
+        ge.solve(A, np.ones((4, 1), complex))
+
+
+def test_ge_partial_steps_match_full_elimination():
+    rng = np.random.default_rng(3)
+    n = 40
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    B = np.ones((n, 2), complex)
+    A1, B1 = A.copy(), B.copy()
+    ge.eliminate_steps(A1, B1, 10)
+    ge.eliminate_steps(A1, B1, 0)
+    _, LU, _ = ge.solve(A, B)
+    # the first 10 rows of U are final after 10 steps
+    assert relerr(np.triu(A1[:10, :]), np.triu(LU[:10, :])) < 1e-14
+
+
+# ----------------------------------------------------- Coulomb functions ----
+
+@pytest.mark.parametrize("l,eta,rho", [(0, 0.0, 3.0), (4, 0.0, 12.5), (2, 1.5, 9.0),
+                                       (0, 18.2, 11.9), (20, 25.8, 11.2), (20, 0.4, 116.0)])
+def test_coulomb_wronskian(l, eta, rho):
+    F, Fp, G, Gp = rmatrix.coulomb(l, eta, rho)
+    assert abs(Fp * G - F * Gp - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("l", [0, 1, 3, 8])
+def test_coulomb_eta0_is_riccati_bessel(l):
+    rho = 7.3
+    F, Fp, G, Gp = rmatrix.coulomb(l, 0.0, rho)
+    jl, yl = sps.spherical_jn(l, rho), sps.spherical_yn(l, rho)
+    jp, yp = sps.spherical_jn(l, rho, derivative=True), sps.spherical_yn(l, rho, derivative=True)
+    assert abs(F - rho * jl) < 1e-13
+    assert abs(G + rho * yl) < 1e-13
+    assert abs(Fp - (jl + rho * jp)) < 1e-13
+    assert abs(Gp + (yl + rho * yp)) < 1e-13
+
+
+def test_coulomb_derivative_numerical():
+    l, eta, rho = 3, 4.2, 14.0
+    F, Fp, G, Gp = rmatrix.coulomb(l, eta, rho)
+    with mpmath.workdps(40):
+        dF = mpmath.diff(lambda x: mpmath.coulombf(l, eta, x), rho)
+        dG = mpmath.diff(lambda x: mpmath.coulombg(l, eta, x), rho)
+    assert abs(Fp - float(dF)) < 1e-13 * max(1, abs(Fp))
+    assert abs(Gp - float(dG)) < 1e-13 * max(1, abs(Gp))
+
+
+# --------------------------------------------------- physics special cases ----
+
+@pytest.mark.parametrize("z1z2", [0, 20])
+def test_zero_nuclear_potential_gives_unit_S(z1z2):
+    """V = 0 (or pure point Coulomb, matched with the same Coulomb functions): U = 1."""
+    nc = 5
+    l = np.array([0, 1, 3, 6, 10])
+    sp = CustomSystem(nc=nc, nr=60, a=15.0, l=l, eps=np.array([0.0, 0.5, 1.0, 2.0, 3.0]),
+                      z1z2=z1z2,
+                      pot=diagonal_potential(nc, lambda r: z1z2 * 1.44 / r + 0j))
+    out = pipeline.solve_energy(sp, 12.0)
+    assert np.max(np.abs(out["S"] - np.eye(nc))) < 1e-11
+
+
+@pytest.mark.parametrize("E", [0.7, 5.0, 23.0])
+def test_square_well_s_wave_textbook_phase(E):
+    """Square well of radius a (the channel radius), l = 0:
+    tan(ka + delta) = (k/K) tan(Ka), K = sqrt((E + V0)/h)."""
+    V0, a, h = 30.0, 8.0, 2.0
+    sp = CustomSystem(nc=1, nr=40, a=a, l=np.array([0]), eps=np.zeros(1), hbar2_2mu=h,
+                      pot=diagonal_potential(1, lambda r: np.full(len(r), -V0 + 0j)))
+    out = pipeline.solve_energy(sp, E)
+    k, K = np.sqrt(E / h), np.sqrt((E + V0) / h)
+    delta = np.arctan(k / K * np.tan(K * a)) - k * a
+    assert abs(out["S"][0, 0] - np.exp(2j * delta)) < 1e-11
+
+
+@pytest.mark.parametrize("l", [0, 2, 5, 9])
+def test_square_well_R_analytic(l):
+    """Internal solution K r j_l(K r): R = u(a) / (a u'(a)) exactly."""
+    V0, a, h, E = 30.0, 8.0, 2.0, 5.0
+    sp = CustomSystem(nc=1, nr=40, a=a, l=np.array([l]), eps=np.zeros(1), hbar2_2mu=h,
+                      pot=diagonal_potential(1, lambda r: np.full(len(r), -V0 + 0j)))
+    out = pipeline.solve_energy(sp, E, with_smatrix=False)
+    K = np.sqrt((E + V0) / h)
+    x = K * a
+    u = x * sps.spherical_jn(l, x)
+    up = K * (sps.spherical_jn(l, x) + x * sps.spherical_jn(l, x, derivative=True))
+    assert abs(out["R"][0, 0] - u / (a * up)) < 1e-11 * abs(u / (a * up))
+
+
+def test_coupled_square_well_rotates_to_uncoupled():
+    """Constant real symmetric coupling W for r < a, equal thresholds, l = 0:
+    with W = Q D Q^T the channels decouple, U = Q diag(exp(2 i delta_d)) Q^T."""
+    a, h, E = 7.0, 2.0, 4.0
+    W = np.array([[-25.0, 4.0, -2.5], [4.0, -18.0, 3.0], [-2.5, 3.0, -31.0]])
+    nc = 3
+    sp = CustomSystem(nc=nc, nr=45, a=a, l=np.zeros(nc, int), eps=np.zeros(nc), hbar2_2mu=h,
+                      pot=lambda r: np.broadcast_to(W.astype(complex), (len(r), nc, nc)).copy())
+    out = pipeline.solve_energy(sp, E)
+    d, Q = np.linalg.eigh(W)
+    k = np.sqrt(E / h)
+    K = np.sqrt((E - d) / h)
+    delta = np.arctan(k / K * np.tan(K * a)) - k * a
+    ref = Q @ np.diag(np.exp(2j * delta)) @ Q.T
+    assert relerr(out["S"], ref) < 1e-11
+
+
+def _real_family(nc=6, nr=70, a=15.0):
+    sp = make_system("small", nc=nc, nr=nr, a=a)
+    sp.w0 = 0.0
+    return sp
+
+
+def test_real_potential_S_unitary_and_symmetric():
+    sp = _real_family()
+    out = pipeline.solve_energy(sp, 14.0)
+    S = out["S"]
+    assert np.max(np.abs(S.conj().T @ S - np.eye(sp.nc))) < 1e-10
+    assert np.max(np.abs(S - S.T)) < 1e-10
+
+
+def test_absorptive_potential_S_symmetric_and_contracting():
+    sp = make_system("small", nr=70)
+    out = pipeline.solve_energy(sp, 14.0)
+    S = out["S"]
+    assert np.max(np.abs(S - S.T)) < 1e-10
+    assert np.linalg.eigvalsh(S.conj().T @ S).max() < 1.0
+
+
+def test_rmatrix_pole_expansion():
+    """Real potential: R = (h/a) sum_n g_n g_n^T / (E_n - E) from the eigenpairs
+    of the real symmetric internal Hamiltonian (with Bloch term)."""
+    sp = _real_family(nc=4, nr=30)
+    E = 9.3
+    md = system.MeshData(sp.nr, sp.a)
+    M0, B = system.assemble(sp, 0.0, md)
+    H = M0.real
+    assert np.max(np.abs(M0.imag)) == 0
+    En, V = np.linalg.eigh(H)
+    g = B.real.T @ V  # (nc, n)
+    Rpole = (sp.hbar2_2mu / sp.a) * (g / (En - E)) @ g.T
+    out = pipeline.solve_energy(sp, E, md, with_smatrix=False)
+    assert relerr(out["R"], Rpole) < 1e-10
+
+
+def test_real_potential_optical_relation():
+    """Unitarity => sum_c sigma_{c<-c'} = (2 pi / k_c'^2) (1 - Re U_c'c')."""
+    sp = _real_family(nc=4, nr=60)
+    out = pipeline.solve_energy(sp, 11.0)
+    tot = out["sigma"].sum(axis=0)
+    ref = 2 * np.pi / out["k"] ** 2 * (1 - np.real(np.diag(out["S"])))
+    assert relerr(tot, ref) < 1e-9
+
+
+def test_solution_satisfies_system_structured_residual():
+    sp = make_system("small")
+    E = sp.energies[0]
+    md = system.MeshData(sp.nr, sp.a)
+    out = pipeline.solve_energy(sp, E, md, with_smatrix=False)
+    M, B = system.assemble(sp, E, md)
+    res = B - system.apply(sp, E, out["X"], md)
+    assert np.max(np.abs(res)) / (np.abs(M).sum(axis=1).max() * np.max(np.abs(out["X"]))) < 1e-14
