@@ -1,0 +1,154 @@
+"""Benchmark: one energy of the N = 25600 coupled-channel R-matrix solve per step.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu]
+
+Workload "large": nc = 256 channels x nr = 100 Lagrange-Legendre points
+(N = 25600), a = 30 fm, seeded Woods-Saxon optical-potential family, 10
+energies in [5, 30] MeV; step s solves energy s mod 10.  A step is the whole
+hot path on device-resident inputs: assemble C(E) -> LU -> solve for the 256
+surface right-hand sides (+ FP64 refinement) -> R-matrix -> collision matrix.
+
+Headline: FP32-LU + FP64 iterative refinement.  The plain FP64 LU is timed
+the same way and reported beside it.  TF/s counts the LU's (8/3) N^3 real
+flops per solve (the paper's count, Sec. 3.3).  The roofline entry is the
+dominant kernel, the trailing-update complex GEMM, measured with HIP events
+around its launches inside the timed region.  cpu_baseline times the CPU
+oracle (plain Gaussian elimination) on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "N=25600 complex solve s & TF/s, FP32-LU+IR vs FP64 LU; served solves/s, p99"
+PEAK_FP32_MFMA = 157.3  # TF/s, MI355X dense FP32 matrix
+PEAK_FP64_MFMA = 78.6   # TF/s, MI355X dense FP64 matrix
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="large")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--max-refine", type=int, default=30)
+    ap.add_argument("--tol", type=float, default=1e-13)
+    return ap.parse_args()
+
+
+def timed_steps(solver, energies, steps, warmup, H, torch):
+    """Warmup, then exactly `steps` steps bracketed by synchronizations."""
+    for s in range(warmup):
+        solver.run(float(energies[s % len(energies)]))
+    torch.cuda.synchronize()
+    H.hp_trace_enable(True)
+    infos = []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        r = solver.run(float(energies[s % len(energies)]))
+        infos.append((r.iterations, r.correction, r.fallback))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = H.hp_trace_read()
+    H.hp_trace_enable(False)
+    return (t1 - t0) / steps, infos, stages
+
+
+def cpu_baseline(n_full: int):
+    """Oracle (plain GE + R + S) on a reduced system of the same family, N^3-scaled."""
+    import numpy as np  # noqa: F401
+    from oracle import ge, pipeline as opipe, system as osys
+    from workload import make_system
+    ge.build(force=False)
+    nc_s = 48
+    sp = make_system("large", nc=nc_s)
+    md = osys.MeshData(sp.nr, sp.a)
+    E = float(sp.energies[0])
+    t0 = time.perf_counter()
+    opipe.solve_energy(sp, E, md)
+    t = time.perf_counter() - t0
+    n_s = sp.n
+    tflops = (8.0 / 3.0) * n_s ** 3 / t / 1e12
+    t_full = (8.0 / 3.0) * n_full ** 3 / (tflops * 1e12)
+    return {"value": tflops, "unit": "TF/s", "cores": ge.threads(), "kind": "oracle",
+            "sample": (f"one full oracle solve (GE with partial pivoting + R + S) of the same potential family "
+                       f"at nc={nc_s}, nr={sp.nr} (N={n_s}), E={E} MeV: {t:.2f} s; "
+                       f"N={n_full} time extrapolated as (8/3)N^3 / rate = {t_full:.0f} s")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2512_11590_amd import hprmat as H
+    from paper_2512_11590_amd import pipeline as P
+    from workload import make_system
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no HIP device"}))
+        sys.exit(1)
+    sp = make_system(args.config)
+    n = sp.n
+    flops = (8.0 / 3.0) * n ** 3
+    d = P.DeviceSystem(sp)
+    torch.cuda.synchronize()
+
+    out = {"metric": METRIC, "unit": "TF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "c64 LU + f64 refinement", "data": "synthetic",
+           "config": {"workload": f"{args.config}: nc={sp.nc}, nr={sp.nr} (N={n}), a={sp.a} fm, "
+                                  f"Woods-Saxon optical family seed {sp.label}, energies 5..30 MeV",
+                      "global_batch": 1, "nrhs": sp.nc}}
+
+    s32 = P.Solver(d, H.HP_C64)
+    print(f"[bench] fp32-LU+IR N={n}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    t32, info32, st32 = timed_steps(s32, sp.energies, args.steps, args.warmup, H, torch)
+    out["value"] = flops / t32 / 1e12
+    out["ms_per_step"] = t32 * 1e3
+    out["refinement"] = [{"steps": it, "correction": c, "fp64_fallback": fb} for it, c, fb in info32]
+    out["stages_ms_per_step"] = {k: v["ms"] / args.steps for k, v in st32.items() if v["launches"]}
+    g = st32["gemm_c64"]
+    ach = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+    out["roofline"] = {"bound": "mfma", "kernel": "gemm_sub_kernel<float> (complex 4M GEMM, FP32 MFMA)",
+                       "achieved": ach, "peak": PEAK_FP32_MFMA, "unit": "TF/s", "frac": ach / PEAK_FP32_MFMA,
+                       "traffic": None, "launches_per_step": g["launches"] / args.steps,
+                       "avg_launch_us": g["ms"] * 1e3 / max(1, g["launches"])}
+    S32 = s32.S.cpu().numpy().copy()
+    last_e = float(sp.energies[(args.steps - 1) % len(sp.energies)])
+    del s32
+    torch.cuda.empty_cache()
+
+    if not args.no_fp64:
+        s64 = P.Solver(d, H.HP_C128)
+        print(f"[bench] fp64-LU N={n}", file=sys.stderr, flush=True)
+        t64, _, st64 = timed_steps(s64, sp.energies, args.steps, args.warmup, H, torch)
+        g64 = st64["gemm_c128"]
+        ach64 = g64["flops"] / (g64["ms"] * 1e-3) / 1e12 if g64["ms"] > 0 else 0.0
+        S64 = s64.S.cpu().numpy()
+        import numpy as np
+        err = float(np.max(np.abs(S32 - S64)) / np.max(np.abs(S64)))
+        out["fp64_lu"] = {"ms_per_step": t64 * 1e3, "tflops": flops / t64 / 1e12,
+                          "gemm_achieved_tflops": ach64, "gemm_frac_of_fp64_peak": ach64 / PEAK_FP64_MFMA,
+                          "stages_ms_per_step": {k: v["ms"] / args.steps for k, v in st64.items()
+                                                 if v["launches"]},
+                          "S_relerr_fp32ir_vs_fp64_at_E": [last_e, err]}
+        del s64
+        torch.cuda.empty_cache()
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * hprmat.h -- C ABI of the MI355X coupled-channel R-matrix internal-region solver.
+ *
+ * The library solves, on one AMD Instinct MI355X (gfx950), the dense complex
+ * symmetric system of the Lagrange-mesh R-matrix method (arXiv 2512.11590,
+ * Sec. 2, Eqs. linear_system and block_structure):
+ *
+ *     C(E) X = B,   C = T + L(Bloch) + centrifugal + V + thresholds - E,
+ *
+ * on nc channels x nr Lagrange-Legendre points (N = nc * nr), with B the nc
+ * surface vectors q_i = f_i(a) (Sec. 3.1, step 2), then extracts the
+ * R-matrix (Sec. 3.1, step 4) and the collision matrix.
+ *
+ * Conventions for every entry point
+ *  - Matrices are row-major.  Because C is complex symmetric (C = C^T), the
+ *    row-major array is also the column-major array of the same matrix.
+ *  - Complex values are interleaved (re, im) pairs of double (complex128) or
+ *    float (complex64); "ld" arguments count complex elements.
+ *  - Pointers named d_* or documented "device" must be device memory from the
+ *    caller (hipMalloc or equivalent); the library allocates nothing on the
+ *    device.  Host pointers are documented as such.
+ *  - `stream` is a hipStream_t (passed as void*; NULL = the null stream).
+ *    All work is enqueued on it; entry points that must read a device-side
+ *    result (the refinement loop, the singular-pivot check) synchronize it.
+ *  - Return value: HP_OK or a negative HP_ERR_* code.  Argument errors are
+ *    detected before any work is enqueued.
+ *  - Channel-major unknown index: (c, i) -> c * nr + i  (Sec. 3.1, step 4).
+ */
+#ifndef HPRMAT_H
+#define HPRMAT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HP_OK 0
+#define HP_ERR_ARG (-1)         /* invalid argument (sizes, null pointers, precision) */
+#define HP_ERR_HIP (-2)         /* a HIP runtime call or kernel launch failed */
+#define HP_ERR_SINGULAR (-3)    /* the factorization met an exactly zero pivot */
+#define HP_ERR_NOCONV (-4)      /* iterative refinement did not reach the tolerance */
+#define HP_ERR_WORKSPACE (-5)   /* workspace smaller than hp_workspace_bytes() */
+#define HP_ERR_UNSUPPORTED (-6) /* outside what this build implements (e.g. closed channels) */
+#define HP_ERR_SYNC (-7)        /* a bounded inter-workgroup wait expired (no hang: reported) */
+
+/* Working precision of the matrix and its LU factors. */
+#define HP_C128 0 /* complex FP64 */
+#define HP_C64 1  /* complex FP32 (factor); refinement residual stays FP64 */
+
+/* Description of one coupled-channel system.  Scalars by value; arrays in
+ * device memory, owned by the caller, read-only for the library. */
+typedef struct hp_system {
+  int nc;            /* number of channels, >= 1 */
+  int nr;            /* Lagrange-Legendre points per channel, >= 1 */
+  double a;          /* channel radius a (fm) */
+  double hbar2_2mu;  /* hbar^2 / 2 mu (MeV fm^2), common to all channels */
+  double z1z2e2;     /* Z1 Z2 e^2 (MeV fm) of the external Coulomb field */
+  const double *r;   /* device [nr]: mesh points r_i */
+  const double *q;   /* device [nr]: surface values q_i = f_i(a) */
+  const double *tl;  /* device [nr*nr]: (T + L)_ij / (hbar^2/2mu), row-major */
+  const int *l;      /* device [nc]: orbital angular momentum per channel */
+  const double *eps; /* device [nc]: threshold energy per channel (MeV) */
+  const double *v;   /* device [nr*nc*nc] complex128: V[i][c][c'] = V_cc'(r_i) (MeV) */
+} hp_system;
+
+/* Outcome of hp_solve (host struct, written by the library). */
+typedef struct hp_solve_info {
+  int iterations;        /* refinement corrections applied */
+  int converged;         /* 1 if the last correction met tol (or no refinement asked) */
+  double correction;     /* max over columns of |d|_inf / |x|_inf of the last correction */
+  double residual;       /* max over columns of |b - C x|_inf / (|C|_inf |x|_inf + |b|_inf) */
+} hp_solve_info;
+
+/* ---- host-side precompute ---------------------------------------------- */
+
+/* Lagrange-Legendre mesh on (0, a) (Sec. 2): points r[i], weights w[i]
+ * (summing to a), surface values q[i] = f_i(a) and the kinetic + Bloch
+ * matrix tl[i*nr + j] = (T + L)_ij / (hbar^2/2mu) in closed form.  All
+ * four arrays are HOST memory of nr (tl: nr*nr) doubles; any may be NULL.
+ * Errors: HP_ERR_ARG if nr < 1 or a <= 0. */
+int hp_mesh(int nr, double a, double *r, double *w, double *q, double *tl);
+
+/* Device workspace (bytes) that hp_factor, hp_solve and hp_smatrix need for
+ * an n x n factorization with nrhs right-hand sides in precision prec.  One
+ * workspace may serve all three calls on one stream in sequence. */
+size_t hp_workspace_bytes(int n, int nrhs, int prec);
+
+/* ---- the hot path ----------------------------------------------------- */
+
+/* Assemble C(E) (Eq. block_structure) into device matrix C (n x n, n =
+ * nc*nr, leading dimension ldc >= n, complex128 if prec == HP_C128, complex64
+ * if HP_C64, converted from FP64 values), overwriting every element:
+ *   C[(c,i),(c',j)] = delta_cc' [ h tl_ij + delta_ij (h l_c(l_c+1)/r_i^2 + eps_c - E) ]
+ *                     + delta_ij V_cc'(r_i),   h = hbar2_2mu.
+ * Errors: HP_ERR_ARG (null pointer, ldc < n, bad prec), HP_ERR_HIP. */
+int hp_build_matrix(const hp_system *sys, double E, int prec, void *C, long ldc, void *stream);
+
+/* LU factorization with partial pivoting in place, P A = L U (Sec. 3.1,
+ * Type 1; Type 2/4 in FP32).  A: device n x n, leading dimension lda >= n,
+ * precision prec; on return the strict lower triangle holds L (unit diagonal
+ * implied) and the upper triangle U.  ipiv: device [n], ipiv[k] = row
+ * exchanged with row k at step k (0-based, LAPACK order).  perm: device [n],
+ * perm[i] = original row now in row i (used by hp_solve).  info: device int,
+ * set to 0, or k+1 for the first exactly zero pivot column k, or -1 if a
+ * bounded inter-workgroup wait expired.  work: device workspace of at least
+ * hp_workspace_bytes(n, 0, prec) bytes.  Asynchronous: does not synchronize;
+ * read *info after the stream completes.
+ * Errors: HP_ERR_ARG, HP_ERR_WORKSPACE, HP_ERR_UNSUPPORTED (n too large for
+ * the co-resident panel grid), HP_ERR_HIP. */
+int hp_factor(int n, int prec, void *A, long lda, int *ipiv, int *perm, int *info,
+              void *work, size_t work_bytes, void *stream);
+
+/* Solve C(E) X = B for the nc surface right-hand sides (Sec. 3.1, steps 2-3)
+ * with the factors of hp_factor (LU, lda, perm, precision prec).  X: device
+ * n x nc complex128 (leading dimension nc), overwritten with the solution.
+ * prec == HP_C64: the FP32 factors give X0; then up to max_refine steps of
+ * iterative refinement (Sec. 3.2 and Sec. 3.4 step 7, here entirely on the
+ * device): r = B - C X in FP64 from the block structure of sys (no N x N FP64
+ * matrix), correction from the FP32 factors, X += d in FP64.  Stops when the
+ * relative correction <= tol.  prec == HP_C128: direct FP64 solve, then the
+ * same refinement if max_refine > 0.  info (host, may be NULL) receives the
+ * outcome.  Synchronizes the stream once per refinement step.
+ * Errors: HP_ERR_ARG, HP_ERR_WORKSPACE, HP_ERR_NOCONV (refinement stopped
+ * contracting or max_refine exhausted above tol; X holds the last iterate),
+ * HP_ERR_SINGULAR (zero pivot reported by hp_factor), HP_ERR_SYNC, HP_ERR_HIP. */
+int hp_solve(const hp_system *sys, double E, int prec, const void *LU, long lda,
+             const int *perm, const int *info_factor, double *X, int max_refine, double tol,
+             void *work, size_t work_bytes, hp_solve_info *info, void *stream);
+
+/* General solve with the factors: X (device n x nrhs, leading dimension ldx,
+ * precision prec) holds B on entry and X = A^-1 B on return. */
+int hp_lu_solve(int n, int nrhs, int prec, const void *LU, long lda, const int *perm,
+                void *X, long ldx, void *work, size_t work_bytes, void *stream);
+
+/* R-matrix (Sec. 3.1, step 4, with the factor hbar^2/(2 mu a)):
+ *   R[c][c'] = (hbar2_2mu / a) sum_i q_i X[(c,i)][c'],
+ * X device n x nc complex128, R device nc x nc complex128 (row-major). */
+int hp_rmatrix(const hp_system *sys, const double *X, double *R, void *stream);
+
+/* Collision matrix U from R by matching to Coulomb functions at r = a in
+ * every channel (the Coulomb-asymptotics step the paper performs with its
+ * Coulomb routine, Sec. 4.1): with rho_c = k_c a, k_c = sqrt((E - eps_c)/h),
+ * eta_c = z1z2e2 / (2 h k_c), O = G + iF, I = G - iF,
+ *   U = (O - Rt O')^-1 (I - Rt I'),   Rt = rho^1/2 R rho^1/2.
+ * R, S: device nc x nc complex128.  nopen (host, may be NULL) receives the
+ * number of open channels.  All channels must be open (E > eps_c), else
+ * HP_ERR_UNSUPPORTED.  Uses work (hp_workspace_bytes(nc, nc, HP_C128)).
+ * Synchronizes the stream. */
+int hp_smatrix(const hp_system *sys, double E, const double *R, double *S, int *nopen,
+               void *work, size_t work_bytes, void *stream);
+
+/* ---- helpers ------------------------------------------------------------ */
+
+/* Coulomb functions F_l, F_l', G_l, G_l' (d/drho) at (eta, rho), computed on
+ * the HOST with the same routine the device uses (for tests).  out: host [4].
+ * Errors: HP_ERR_ARG if l < 0, rho <= 0 or eta < 0. */
+int hp_coulomb(int l, double eta, double rho, double *out);
+
+/* Same routine on the device for nch channels: device arrays l[nch],
+ * eta[nch], rho[nch] -> out[nch*4]. */
+int hp_coulomb_device(int nch, const int *l, const double *eta, const double *rho,
+                      double *out, void *stream);
+
+/* ---- instrumentation ---------------------------------------------------- */
+
+/* Per-stage device timers.  hp_trace_enable(1) clears the record and starts
+ * bracketing every kernel launch with HIP events on its stream;
+ * hp_trace_enable(0) stops.  hp_trace_read() waits for the recorded events,
+ * fills out[0 .. HP_TRACE_STAGES-1] (host array) with, per stage, the launch
+ * count, summed kernel time (ms) and summed algorithmic flops and bytes of
+ * those launches, clears the record and returns HP_TRACE_STAGES.
+ * Errors: HP_ERR_ARG if max_stats < HP_TRACE_STAGES, HP_ERR_HIP. */
+#define HP_TRACE_STAGES 10
+typedef struct hp_trace_stat {
+  const char *name; /* stage name, owned by the library */
+  long launches;
+  double ms;
+  double flops;
+  double bytes;
+} hp_trace_stat;
+int hp_trace_enable(int on);
+int hp_trace_read(hp_trace_stat *out, int max_stats);
+
+/* Static description of the build: string owned by the library. */
+const char *hp_build_info(void);
+
+/* The last failing HIP call on this host thread ("file:line: HIP error
+ * text"), or "" if none; string owned by the library. */
+const char *hp_last_error(void);
+
+/* Human-readable text for an HP_* code. */
+const char *hp_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPRMAT_H */

@@ -32,9 +32,10 @@ from numpy.polynomial import legendre as npleg
 
 
 def gauss_points(nr: int) -> tuple[np.ndarray, np.ndarray]:
-    """x_i (ascending) and lambda_i on (0, 1)."""
-    t, w = npleg.leggauss(nr)
-    return 0.5 * (t + 1.0), 0.5 * w
+    """x_i (ascending) and lambda_i on (0, 1), rounded once to FP64 from an
+    extended-precision Gauss rule."""
+    t, w = _gauss_rule_extended(nr)
+    return ((t + 1) / 2).astype(np.float64), (w / 2).astype(np.float64)
 
 
 def mesh(nr: int, a: float) -> tuple[np.ndarray, np.ndarray]:
@@ -44,8 +45,8 @@ def mesh(nr: int, a: float) -> tuple[np.ndarray, np.ndarray]:
 
 
 def _legendre(n: int, s: np.ndarray) -> list[np.ndarray]:
-    """[P_0(s), ..., P_n(s)] by the three-term recurrence."""
-    s = np.asarray(s, dtype=np.float64)
+    """[P_0(s), ..., P_n(s)] by the three-term recurrence (in the dtype of s)."""
+    s = np.asarray(s)
     out = [np.ones_like(s), s.copy()]
     for m in range(1, n):
         out.append(((2 * m + 1) * s * out[m] - m * out[m - 1]) / (m + 1))
@@ -60,8 +61,8 @@ def _divided_difference(n: int, t: np.ndarray, s: np.ndarray) -> tuple[np.ndarra
     which contains no division by t - s, so it stays accurate when t is close
     to s.  Since P_n(t_i) = 0 at a mesh point, D(t, t_i) = P_n(t) / (t - t_i).
     """
-    t = np.asarray(t, dtype=np.float64)
-    s = np.asarray(s, dtype=np.float64)
+    t = np.asarray(t)
+    s = np.asarray(s)
     t, s = np.broadcast_arrays(t, s)
     ps = _legendre(n, s)
     d_prev, d = np.zeros_like(t), np.ones_like(t)
@@ -76,30 +77,54 @@ def _divided_difference(n: int, t: np.ndarray, s: np.ndarray) -> tuple[np.ndarra
     return d, dd
 
 
-def _prefactor(nr: int, a: float) -> tuple[np.ndarray, np.ndarray]:
-    """Mesh points t_i = 2 x_i - 1 and c_i with f_i(r) = c_i r D(2r/a - 1, t_i)."""
-    x, _ = gauss_points(nr)
+def _prefactor(nr: int, a: float, dtype=np.float64) -> tuple[np.ndarray, np.ndarray]:
+    """Mesh points t_i = 2 x_i - 1 and c_i with f_i(r) = c_i r D(2r/a - 1, t_i).
+
+    In long double the nodes are the extended-precision zeros (not their FP64
+    rounding), so that D(t, t_i) is P_N(t)/(t - t_i) to extended accuracy."""
+    if dtype == np.longdouble:
+        t_ext, _ = _gauss_rule_extended(nr)
+        x = (t_ext + 1) / 2
+    else:
+        x, _ = gauss_points(nr)
+    x = x.astype(dtype)
+    a = dtype(a)
     i = np.arange(1, nr + 1)
-    sign = np.where((nr + i) % 2 == 0, 1.0, -1.0)
+    sign = np.where((nr + i) % 2 == 0, 1.0, -1.0).astype(dtype)
     # f_i = sign sqrt(a x_i (1-x_i)) / (a x_i) * r * P_N(t) / (r - r_i),  r - r_i = (a/2)(t - t_i)
-    c = sign * np.sqrt(a * x * (1.0 - x)) / (a * x) * (2.0 / a)
-    return 2.0 * x - 1.0, c
+    c = sign * np.sqrt(a * x * (1 - x)) / (a * x) * (2 / a)
+    return 2 * x - 1, c
 
 
 def basis(nr: int, a: float, r: np.ndarray) -> np.ndarray:
-    """f_i(r) for every i: shape (len(r), nr)."""
-    r = np.asarray(r, dtype=np.float64)
-    ti, c = _prefactor(nr, a)
-    d, _ = _divided_difference(nr, (2.0 * r / a - 1.0)[:, None], ti[None, :])
-    return c[None, :] * r[:, None] * d
+    """f_i(r) for every i: shape (len(r), nr) (evaluated in long double)."""
+    r = np.asarray(r).astype(np.longdouble)
+    ti, c = _prefactor(nr, a, np.longdouble)
+    d, _ = _divided_difference(nr, (2 * r / np.longdouble(a) - 1)[:, None], ti[None, :])
+    return (c[None, :] * r[:, None] * d).astype(np.float64)
 
 
-def basis_derivative(nr: int, a: float, r: np.ndarray) -> np.ndarray:
+def basis_derivative(nr: int, a: float, r: np.ndarray, dtype=np.float64) -> np.ndarray:
     """f_i'(r): shape (len(r), nr).  d/dr [r D(t)] = D + r (2/a) dD/dt."""
-    r = np.asarray(r, dtype=np.float64)
-    ti, c = _prefactor(nr, a)
-    d, dd = _divided_difference(nr, (2.0 * r / a - 1.0)[:, None], ti[None, :])
-    return c[None, :] * (d + r[:, None] * (2.0 / a) * dd)
+    r = np.asarray(r).astype(dtype)
+    ti, c = _prefactor(nr, a, dtype)
+    a = dtype(a)
+    d, dd = _divided_difference(nr, (2 * r / a - 1)[:, None], ti[None, :])
+    return c[None, :] * (d + r[:, None] * (2 / a) * dd)
+
+
+def _gauss_rule_extended(n: int) -> tuple[np.ndarray, np.ndarray]:
+    """Gauss-Legendre rule on (-1, 1) in extended precision: numpy's nodes
+    polished by Newton steps on P_n in long double, weights 2/((1-t^2) P_n'^2)."""
+    t0, _ = npleg.leggauss(n)
+    t = t0.astype(np.longdouble)
+    for _ in range(3):
+        p = _legendre(n, t)
+        dp = n * (p[n - 1] - t * p[n]) / (1 - t * t)
+        t = t - p[n] / dp
+    p = _legendre(n, t)
+    dp = n * (p[n - 1] - t * p[n]) / (1 - t * t)
+    return t, 2 / ((1 - t * t) * dp * dp)
 
 
 def surface_values(nr: int, a: float) -> np.ndarray:
@@ -111,12 +136,15 @@ def kinetic_bloch(nr: int, a: float) -> np.ndarray:
     """(T + L)_ij / (hbar^2/2mu) = integral_0^a f_i' f_j' dr, shape (nr, nr).
 
     Quadrature with an (N+1)-point Gauss rule on (0, a); exact for the
-    degree-(2N-2) integrand.
+    degree-(2N-2) integrand.  Evaluated in long double (x86 extended
+    precision) and rounded once to FP64, so the matrix is accurate to the last
+    bit and does not add its own error to the parity comparisons.
     """
-    t, w = npleg.leggauss(nr + 1)
-    rq = 0.5 * a * (t + 1.0)
-    wq = 0.5 * a * w
-    d = basis_derivative(nr, a, rq)  # (nr+1, nr)
-    g = (d * wq[:, None]).T @ d
+    t, w = _gauss_rule_extended(nr + 1)
+    al = np.longdouble(a)
+    rq = al * (t + 1) / 2
+    wq = al * w / 2
+    d = basis_derivative(nr, a, rq, dtype=np.longdouble)  # (nr+1, nr)
+    g = np.einsum("q,qi,qj->ij", wq, d, d)
     # the sum is symmetric in exact arithmetic; average the two summation orders
-    return 0.5 * (g + g.T)
+    return (0.5 * (g + g.T)).astype(np.float64)

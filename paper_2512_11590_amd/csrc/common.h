@@ -1,0 +1,133 @@
+// Shared device/host definitions of the HIP R-matrix library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "hprmat.h"
+
+namespace hp {
+
+// ---------------------------------------------------------------- complex --
+template <typename T>
+struct cplx {
+  T re, im;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cmk(T re, T im) { return cplx<T>{re, im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a - b*c (the elimination update)
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cfms(cplx<T> a, cplx<T> b, cplx<T> c) {
+  return {a.re - (b.re * c.re - b.im * c.im), a.im - (b.re * c.im + b.im * c.re)};
+}
+template <typename T>
+__host__ __device__ __forceinline__ T cabs1(cplx<T> a) {
+  return (a.re < 0 ? -a.re : a.re) + (a.im < 0 ? -a.im : a.im);
+}
+// 1 / z with scaling against overflow (Smith's method)
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> crcp(cplx<T> z) {
+  T ar = z.re < 0 ? -z.re : z.re, ai = z.im < 0 ? -z.im : z.im;
+  if (ar >= ai) {
+    T t = z.im / z.re, d = z.re + z.im * t;
+    return {T(1) / d, -t / d};
+  } else {
+    T t = z.re / z.im, d = z.re * t + z.im;
+    return {t / d, T(-1) / d};
+  }
+}
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cdiv(cplx<T> a, cplx<T> b) { return cmul(a, crcp(b)); }
+
+// --------------------------------------------------------------- tracing --
+enum TraceCat {
+  TR_ASSEMBLE = 0, TR_PANEL, TR_LASWP, TR_TRSM, TR_GEMM64, TR_GEMM32, TR_RESIDUAL, TR_REFINE, TR_RMATRIX,
+  TR_SMATRIX, TR_COUNT
+};
+static_assert(TR_COUNT == HP_TRACE_STAGES, "trace stage count");
+bool trace_on();
+// Brackets the launches issued during its lifetime with events on `st`.
+class TraceScope {
+ public:
+  TraceScope(int cat, hipStream_t st, double flops, double bytes);
+  ~TraceScope();
+  TraceScope(const TraceScope &) = delete;
+  TraceScope &operator=(const TraceScope &) = delete;
+
+ private:
+  int cat_;
+  hipStream_t st_;
+  double flops_, bytes_;
+  void *a_;
+};
+
+// ------------------------------------------------------------ constants --
+constexpr int kPanelWidth = 32;     // columns factored by one cooperative panel launch
+constexpr int kOuterBlock = 256;    // columns per trailing-update step (GEMM K)
+constexpr int kMaxPanelGroups = 1024;
+constexpr unsigned kSpinLimit = 1u << 22;  // bounded grid-barrier wait (a few seconds)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Workspace carve-up shared by all entry points (offsets in bytes).
+struct Workspace {
+  size_t sync_off, sync_bytes;      // grid-barrier counters
+  size_t slot_off, slot_bytes;      // panel pivot-candidate slots
+  size_t flag_off;                  // device status flags
+  size_t rhs_off, rhs_bytes;        // working-precision right-hand sides (n x nrhs)
+  size_t res_off, res_bytes;        // FP64 residual (n x nrhs)
+  size_t aux_off, aux_bytes;        // nrhs x nrhs complex128 (collision-matrix solve)
+  size_t red_off, red_bytes;        // reductions, Coulomb values, small index arrays
+  size_t total;
+};
+Workspace plan_workspace(int n, int nrhs, int prec);
+
+// Internal launchers (defined in lu.hip).
+template <typename T>
+int lu_factor(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *info, char *work,
+              const Workspace &ws, hipStream_t st);
+template <typename T>
+int lu_solve(int n, int nrhs, const cplx<T> *LU, long lda, const int *perm, cplx<T> *X, long ldx,
+             cplx<T> *tmp, hipStream_t st);
+template <typename T>
+int lu_solve_permuted(int n, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, long ldy, hipStream_t st);
+template <typename T>
+int gemm_sub(int M, int N, int K, const cplx<T> *A, long lda, const cplx<T> *B, long ldb, cplx<T> *C,
+             long ldc, hipStream_t st);
+// batched: matrix b of A, B, C starts at A + b*sa, B + b*sb, C + b*sc
+template <typename T>
+int gemm_sub_batched(int M, int N, int K, const cplx<T> *A, long lda, long sa, const cplx<T> *B, long ldb,
+                     long sb, cplx<T> *C, long ldc, long sc, int batch, hipStream_t st);
+size_t factor_sync_bytes(int n);
+size_t factor_slot_bytes();
+
+}  // namespace hp
+
+namespace hp {
+// Records the failing HIP call (file, line, HIP error text) for hp_last_error().
+void note_hip_error(hipError_t e, const char *file, int line);
+// Raises the dynamic-LDS limit of a kernel when a launch needs more than the
+// default 64 KB (once per kernel and size).
+int ensure_dynamic_lds(const void *func, size_t bytes);
+}  // namespace hp
+
+#define HP_CHECK_HIP(x)                                 \
+  do {                                                  \
+    hipError_t e_ = (x);                                \
+    if (e_ != hipSuccess) {                             \
+      hp::note_hip_error(e_, __FILE__, __LINE__);       \
+      return HP_ERR_HIP;                                \
+    }                                                   \
+  } while (0)
+
+#define HP_CHECK_LAUNCH() HP_CHECK_HIP(hipGetLastError())

@@ -1,0 +1,277 @@
+// Coulomb functions and the collision matrix.
+//
+// F_l(eta, rho), G_l(eta, rho) and their rho-derivatives for the matching at
+// the channel radius (the role of the paper's Coulomb routine, Sec. 4.1).
+// Method (Steed's algorithm as used by Barnett's COULFG, with an inward
+// integration below the barrier):
+//  * CF1: f = F'/F by backward recurrence of the ratio of the minimal
+//    solution in l (from the Abramowitz & Stegun 14.2 recurrences),
+//      f_n = S_{n+1} - R_{n+1}^2 / (S_{n+1} + f_{n+1}),
+//      S_n = n/rho + eta/n,  R_n^2 = 1 + eta^2/n^2,
+//    started far above l; the signs of S_{n+1} + f_{n+1} = R_{n+1} F_n/F_{n+1}
+//    give the sign of F_l.
+//  * CF2: p + iq = (G' + iF')/(G + iF) as the continued fraction
+//      i(1 - eta/rho) + (i/rho) K_n (a_n / b_n),
+//      a_n = (i eta - l + n - 1)(i eta + l + n),  b_n = 2(rho - eta + n i),
+//    by the modified Lentz method.
+//  * With the Wronskian F'G - FG' = 1: F = w / sqrt(q (1 + g^2)),
+//    g = (f - p)/q, G = g F, F' = f F, G' = (p g - q) F.
+//  * Inside the Coulomb + centrifugal barrier (rho below the turning point
+//    rho_t = eta + sqrt(eta^2 + l(l+1))), q is too small to carry F, so G and
+//    G' are taken from Steed at rho_t + 2 and carried inward by Taylor
+//    series of the Coulomb equation (G grows inward: stable), and
+//    F = 1 / (f G - G') from the Wronskian with CF1 at rho.
+//
+// Collision matrix (matching u(a) = R a u'(a) with u_c = k_c^-1/2 (I_c delta -
+// U O_c)):  U = (O - Rt O')^-1 (I - Rt I'),  Rt = rho^1/2 R rho^1/2.
+#include "common.h"
+
+#include <cmath>
+#include <vector>
+
+namespace hp {
+
+struct CoulombOut {
+  double F, Fp, G, Gp;
+  int status;  // 0 ok, 1 continued fraction did not converge
+};
+
+__host__ __device__ static double cf1_ratio(int L, double eta, double rho, double *sign) {
+  const int ltop = L + (int)rho + 60;
+  auto S = [&](int n) { return n / rho + eta / n; };
+  auto R2 = [&](int n) { return 1.0 + (eta / n) * (eta / n); };
+  double f = S(ltop + 1);
+  double sg = 1.0;
+  for (int n = ltop - 1; n >= L; --n) {
+    double d = S(n + 1) + f;
+    if (d == 0.0) d = 1e-300;
+    if (d < 0.0) sg = -sg;
+    f = S(n + 1) - R2(n + 1) / d;
+  }
+  *sign = sg;
+  return f;
+}
+
+__host__ __device__ static int cf2_pq(int L, double eta, double rho, double *p, double *q) {
+  // Lentz on K(a_n / b_n), complex arithmetic written out
+  const double tiny = 1e-300;
+  const cplx<double> a{-(double)L, eta}, b{(double)L + 1.0, eta};
+  cplx<double> f{tiny, 0.0}, C = f, D{0.0, 0.0};
+  int ok = 1;
+  for (int n = 1; n < 200000; ++n) {
+    const cplx<double> an = cmul(cplx<double>{a.re + n - 1, a.im}, cplx<double>{b.re + n - 1, b.im});
+    const cplx<double> bn{2.0 * (rho - eta), 2.0 * n};
+    D = cadd(bn, cmul(an, D));
+    if (D.re == 0.0 && D.im == 0.0) D.re = tiny;
+    C = cadd(bn, cdiv(an, C));
+    if (C.re == 0.0 && C.im == 0.0) C.re = tiny;
+    D = crcp(D);
+    const cplx<double> delta = cmul(C, D);
+    f = cmul(f, delta);
+    const double dr = delta.re - 1.0, di = delta.im;
+    if (dr * dr + di * di < 1e-32) {
+      ok = 0;
+      break;
+    }
+  }
+  // i(1 - eta/rho) + (i/rho) f
+  *p = -f.im / rho;
+  *q = (1.0 - eta / rho) + f.re / rho;
+  return ok;
+}
+
+__host__ __device__ static void steed(int L, double eta, double rho, CoulombOut &o) {
+  double w;
+  const double f = cf1_ratio(L, eta, rho, &w);
+  double p, q;
+  o.status = cf2_pq(L, eta, rho, &p, &q);
+  const double g = (f - p) / q;
+  const double F = w / sqrt(q * (1.0 + g * g));
+  o.F = F;
+  o.Fp = f * F;
+  o.G = g * F;
+  o.Gp = (p * g - q) * F;
+}
+
+// one Taylor step of u'' = (L(L+1)/x^2 + 2 eta/x - 1) u from x0 to x0 + h
+__host__ __device__ static void taylor_step(double LL, double eta, double x0, double h, double &u, double &up) {
+  double cm2 = 0.0, cm1 = 0.0, c0 = u, c1 = up;
+  double s = u + up * h, sp = up;
+  double hp = h;  // h^(n+1)
+  const double A = LL + 2.0 * eta * x0 - x0 * x0;
+  const double B = 2.0 * eta - 2.0 * x0;
+  for (int n = 0; n < 300; ++n) {
+    const double c2 = (A * c0 + B * cm1 - cm2 - 2.0 * x0 * (n + 1) * n * c1 - (double)n * (n - 1) * c0) /
+                      (x0 * x0 * (n + 2.0) * (n + 1.0));
+    const double dterm = (n + 2.0) * c2 * hp;  // (n+2) c_{n+2} h^(n+1)
+    hp *= h;
+    const double term = c2 * hp;               // c_{n+2} h^(n+2)
+    s += term;
+    sp += dterm;
+    cm2 = cm1;
+    cm1 = c0;
+    c0 = c1;
+    c1 = c2;
+    if (n > 8 && fabs(term) <= 1e-18 * fabs(s) && fabs(dterm) <= 1e-18 * fabs(sp)) break;
+  }
+  u = s;
+  up = sp;
+}
+
+__host__ __device__ static CoulombOut coulomb_fg(int L, double eta, double rho) {
+  CoulombOut o;
+  const double LL = (double)L * (L + 1);
+  const double rtp = eta + sqrt(eta * eta + LL);
+  if (rho >= rtp) {
+    steed(L, eta, rho, o);
+    return o;
+  }
+  double x = rtp + 2.0;
+  steed(L, eta, x, o);
+  double G = o.G, Gp = o.Gp;
+  while (x > rho) {
+    double h = -fmin(1.0, fmin(0.25 * x, x - rho));
+    taylor_step(LL, eta, x, h, G, Gp);
+    x += h;
+  }
+  double sg;
+  const double f = cf1_ratio(L, eta, rho, &sg);
+  const double F = 1.0 / (f * G - Gp);
+  o.F = F;
+  o.Fp = f * F;
+  o.G = G;
+  o.Gp = Gp;
+  return o;
+}
+
+__global__ void coulomb_kernel(int nch, const int *__restrict__ l, const double *__restrict__ eta,
+                               const double *__restrict__ rho, double *__restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nch) return;
+  CoulombOut o = coulomb_fg(l[c], eta[c], rho[c]);
+  out[4 * c + 0] = o.F;
+  out[4 * c + 1] = o.Fp;
+  out[4 * c + 2] = o.G;
+  out[4 * c + 3] = o.Gp;
+}
+
+// Per channel: k, eta, rho, then (F, F', G, G'); status per channel in st[c]
+// (0 ok, 1 closed channel, 2 continued fraction did not converge).
+__global__ void channel_kernel(int nc, double E, double h, double z1z2e2, double a, const int *__restrict__ l,
+                               const double *__restrict__ eps, double *__restrict__ fg, double *__restrict__ sqrho,
+                               int *__restrict__ stat) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const double ec = E - eps[c];
+  if (!(ec > 0.0)) {
+    stat[c] = 1;
+    fg[4 * c] = fg[4 * c + 1] = fg[4 * c + 2] = fg[4 * c + 3] = 0.0;
+    sqrho[c] = 0.0;
+    return;
+  }
+  const double k = sqrt(ec / h);
+  const double eta = z1z2e2 / (2.0 * h * k);
+  const double rho = k * a;
+  CoulombOut o = coulomb_fg(l[c], eta, rho);
+  fg[4 * c + 0] = o.F;
+  fg[4 * c + 1] = o.Fp;
+  fg[4 * c + 2] = o.G;
+  fg[4 * c + 3] = o.Gp;
+  sqrho[c] = sqrt(rho);
+  stat[c] = o.status ? 2 : 0;
+}
+
+// ZO = diag(O) - Rt diag(O'), ZI = diag(I) - Rt diag(I'), both nc x nc row-major.
+__global__ void zmat_kernel(int nc, const cplx<double> *__restrict__ R, const double *__restrict__ fg,
+                            const double *__restrict__ sqrho, cplx<double> *__restrict__ ZO,
+                            cplx<double> *__restrict__ ZI) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)nc * nc) return;
+  const int c = (int)(e / nc), cp = (int)(e - (long)c * nc);
+  const double s = sqrho[c] * sqrho[cp];
+  const cplx<double> rt{s * R[e].re, s * R[e].im};
+  const double F = fg[4 * cp], Fp = fg[4 * cp + 1], G = fg[4 * cp + 2], Gp = fg[4 * cp + 3];
+  // Rt * O'_c' with O' = G' + i F', I' = G' - i F'
+  cplx<double> zo = cmul(rt, cplx<double>{Gp, Fp});
+  cplx<double> zi = cmul(rt, cplx<double>{Gp, -Fp});
+  zo = cplx<double>{-zo.re, -zo.im};
+  zi = cplx<double>{-zi.re, -zi.im};
+  if (c == cp) {
+    zo.re += G;
+    zo.im += F;
+    zi.re += G;
+    zi.im -= F;
+  }
+  ZO[e] = zo;
+  ZI[e] = zi;
+}
+
+}  // namespace hp
+
+using namespace hp;
+
+extern "C" int hp_coulomb(int l, double eta, double rho, double *out) {
+  if (l < 0 || !(rho > 0.0) || !(eta >= 0.0) || !out) return HP_ERR_ARG;
+  CoulombOut o = coulomb_fg(l, eta, rho);
+  out[0] = o.F;
+  out[1] = o.Fp;
+  out[2] = o.G;
+  out[3] = o.Gp;
+  return o.status ? HP_ERR_NOCONV : HP_OK;
+}
+
+extern "C" int hp_coulomb_device(int nch, const int *l, const double *eta, const double *rho, double *out,
+                                 void *stream) {
+  if (nch < 0 || (nch > 0 && (!l || !eta || !rho || !out))) return HP_ERR_ARG;
+  if (nch == 0) return HP_OK;
+  hipLaunchKernelGGL(coulomb_kernel, dim3((nch + 63) / 64), dim3(64), 0, (hipStream_t)stream, nch, l, eta, rho,
+                     out);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+extern "C" int hp_smatrix(const hp_system *sys, double E, const double *R, double *S, int *nopen, void *work,
+                          size_t work_bytes, void *stream) {
+  if (!sys || sys->nc < 1 || !(sys->a > 0) || !(sys->hbar2_2mu > 0) || !sys->l || !sys->eps || !R || !S || !work)
+    return HP_ERR_ARG;
+  const int nc = sys->nc;
+  Workspace ws = plan_workspace(nc, nc, HP_C128);
+  if (work_bytes < ws.total) return HP_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)work;
+  cplx<double> *ZO = (cplx<double> *)(w + ws.aux_off);
+  cplx<double> *tmp = (cplx<double> *)(w + ws.rhs_off);
+  double *fg = (double *)(w + ws.red_off);
+  double *sqrho = fg + 4 * (size_t)nc;
+  int *stat = (int *)(sqrho + nc);
+  int *ipiv = stat + nc;
+  int *perm = ipiv + nc;
+  int *finfo = (int *)(w + ws.flag_off);
+  TraceScope ts(TR_SMATRIX, st, 8.0 / 3.0 * (double)nc * nc * nc, 0.0);
+  hipLaunchKernelGGL(channel_kernel, dim3((nc + 63) / 64), dim3(64), 0, st, nc, E, sys->hbar2_2mu, sys->z1z2e2,
+                     sys->a, sys->l, sys->eps, fg, sqrho, stat);
+  HP_CHECK_LAUNCH();
+  const long cnt = (long)nc * nc;
+  hipLaunchKernelGGL(zmat_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, nc,
+                     (const cplx<double> *)R, fg, sqrho, ZO, (cplx<double> *)S);
+  HP_CHECK_LAUNCH();
+  int rc;
+  if ((rc = lu_factor<double>(nc, ZO, nc, ipiv, perm, finfo, w, ws, st))) return rc;
+  if ((rc = lu_solve<double>(nc, nc, ZO, nc, perm, (cplx<double> *)S, nc, tmp, st))) return rc;
+  int hinfo = 0;
+  std::vector<int> hstat(nc);
+  HP_CHECK_HIP(hipMemcpyAsync(&hinfo, finfo, sizeof(int), hipMemcpyDeviceToHost, st));
+  HP_CHECK_HIP(hipMemcpyAsync(hstat.data(), stat, sizeof(int) * nc, hipMemcpyDeviceToHost, st));
+  HP_CHECK_HIP(hipStreamSynchronize(st));
+  int open = 0, bad = 0;
+  for (int c = 0; c < nc; ++c) {
+    if (hstat[c] == 0) ++open;
+    if (hstat[c] == 2) bad = 1;
+  }
+  if (nopen) *nopen = open;
+  if (open < nc) return HP_ERR_UNSUPPORTED;
+  if (bad) return HP_ERR_NOCONV;
+  if (hinfo == -1) return HP_ERR_SYNC;
+  if (hinfo > 0) return HP_ERR_SINGULAR;
+  return HP_OK;
+}

@@ -1,0 +1,303 @@
+// Right-hand sides, iterative refinement and R-matrix extraction.
+//
+// The surface right-hand sides B (Sec. 3.1, step 2) are never stored: column
+// c' of B is q_i in block c' and zero elsewhere, so P B is generated straight
+// from the row permutation of the factorization.
+//
+// Refinement (Sec. 3.2; Sec. 3.4, step 7) runs entirely on the device: the
+// FP64 residual r = B - C X is formed from the block structure of C
+// (Eq. block_structure) instead of an N x N FP64 matrix:
+//   (C X)[(c,i)] = h sum_j TL_ij X[(c,j)] + (h l_c(l_c+1)/r_i^2 + eps_c - E) X[(c,i)]
+//                  + sum_c' V_cc'(r_i) X[(c',i)],
+// which costs nc nr^2 + nr nc^2 complex operations per column instead of
+// (nc nr)^2.  The kinetic part is a real x complex product per channel
+// (residual_local_kernel); the coupling part is one complex GEMM per radial
+// point (batched MFMA gemm_sub).
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace hp {
+
+// P B in working precision: Y[i][c'] = B[perm[i]][c'], scaled by 1/s[c'] if s given.
+template <typename T>
+__global__ void rhs_from_perm_kernel(int nc, int nr, const int *__restrict__ perm, const double *__restrict__ q,
+                                     cplx<T> *__restrict__ Y) {
+  const long n = (long)nc * nr;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nc) return;
+  const long i = e / nc;
+  const int col = (int)(e - i * nc);
+  const int src = perm[i];
+  const int c = src / nr, ii = src - (src / nr) * nr;
+  Y[e] = cplx<T>{(T)((c == col) ? q[ii] : 0.0), T(0)};
+}
+
+// r = B - (h TL (x) I_c) X - diag X, for a column tile of 32 and one channel.
+constexpr int kResCols = 32;
+__global__ __launch_bounds__(256) void residual_local_kernel(int nc, int nr, double h, double E,
+                                                             const double *__restrict__ tl,
+                                                             const double *__restrict__ r,
+                                                             const int *__restrict__ l,
+                                                             const double *__restrict__ eps,
+                                                             const double *__restrict__ q,
+                                                             const cplx<double> *__restrict__ X,
+                                                             cplx<double> *__restrict__ R) {
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<double> *Xs = reinterpret_cast<cplx<double> *>(smem_raw);  // [nr][kResCols]
+  const int c = blockIdx.y;
+  const int col0 = blockIdx.x * kResCols;
+  const int ncw = min(kResCols, nc - col0);
+  const int tid = threadIdx.x;
+  const cplx<double> *Xc = X + (long)c * nr * nc;
+  for (int e = tid; e < nr * kResCols; e += 256) {
+    const int j = e / kResCols, cc = e - j * kResCols;
+    Xs[e] = (cc < ncw) ? Xc[(long)j * nc + col0 + cc] : cplx<double>{0.0, 0.0};
+  }
+  __syncthreads();
+  const int lc = l[c];
+  const double shift = eps[c] - E;
+  for (int e = tid; e < nr * kResCols; e += 256) {
+    const int i = e / kResCols, cc = e - i * kResCols;
+    if (cc >= ncw) continue;
+    const double *trow = tl + (long)i * nr;
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < nr; ++j) {
+      const double t = trow[j];
+      sr += t * Xs[j * kResCols + cc].re;
+      si += t * Xs[j * kResCols + cc].im;
+    }
+    const double ri = r[i];
+    const double dg = h * (double)lc * (double)(lc + 1) / (ri * ri) + shift;
+    const cplx<double> x = Xs[i * kResCols + cc];
+    const int col = col0 + cc;
+    const double b = (col == c) ? q[i] : 0.0;
+    R[((long)c * nr + i) * nc + col] = cplx<double>{b - h * sr - dg * x.re, -h * si - dg * x.im};
+  }
+}
+
+// Per-column max |v| into out[col] (ordered as unsigned bit patterns: v >= 0).
+__global__ void colmax_kernel(long nrows, int ncols, const cplx<double> *__restrict__ V,
+                              unsigned long long *__restrict__ out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  // each thread scans a strided set of rows for one column
+  const int col = (int)(e % ncols);
+  const long r0 = e / ncols;
+  const long step = ((long)gridDim.x * blockDim.x) / ncols;
+  if (step == 0 || r0 >= step) return;
+  double m = 0.0;
+  for (long rr = r0; rr < nrows; rr += step) {
+    const cplx<double> v = V[rr * ncols + col];
+    m = fmax(m, fabs(v.re) + fabs(v.im));
+  }
+  atomicMax(&out[col], (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// Y = P r / s (working precision), s[col] = max|r_col| (1 if zero).
+template <typename T>
+__global__ void scale_perm_kernel(long n, int nc, const int *__restrict__ perm, const cplx<double> *__restrict__ Rr,
+                                  const unsigned long long *__restrict__ smax, cplx<T> *__restrict__ Y) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nc) return;
+  const long i = e / nc;
+  const int col = (int)(e - i * nc);
+  double s = __longlong_as_double((long long)smax[col]);
+  const double inv = (s > 0.0) ? 1.0 / s : 1.0;
+  const cplx<double> v = Rr[(long)perm[i] * nc + col];
+  Y[e] = cplx<T>{(T)(v.re * inv), (T)(v.im * inv)};
+}
+
+// X += s * D (FP64); per-column max |s D| into dmax.
+template <typename T>
+__global__ void update_kernel(long n, int nc, const cplx<T> *__restrict__ D, const unsigned long long *__restrict__ smax,
+                              cplx<double> *__restrict__ X, unsigned long long *__restrict__ dmax) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nc) return;
+  const int col = (int)(e % nc);
+  const double s = __longlong_as_double((long long)smax[col]);
+  const double f = (s > 0.0) ? s : 1.0;
+  const cplx<T> d = D[e];
+  const double dr = f * (double)d.re, di = f * (double)d.im;
+  cplx<double> x = X[e];
+  x.re += dr;
+  x.im += di;
+  X[e] = x;
+  atomicMax(&dmax[col], (unsigned long long)__double_as_longlong(fabs(dr) + fabs(di)));
+}
+
+// FP64 copy of a working-precision solution.
+template <typename T>
+__global__ void widen_kernel(long count, const cplx<T> *__restrict__ S, cplx<double> *__restrict__ X) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const cplx<T> s = S[e];
+  X[e] = cplx<double>{(double)s.re, (double)s.im};
+}
+
+static unsigned nblk(long count) { return (unsigned)((count + 255) / 256); }
+
+static int residual(const hp_system *sys, double E, const cplx<double> *X, cplx<double> *R, hipStream_t st) {
+  const int nc = sys->nc, nr = sys->nr;
+  const size_t shm = (size_t)nr * kResCols * sizeof(cplx<double>);
+  if (shm > 150 * 1024) return HP_ERR_UNSUPPORTED;
+  int rc0 = ensure_dynamic_lds((const void *)residual_local_kernel, shm);
+  if (rc0) return rc0;
+  dim3 grid((nc + kResCols - 1) / kResCols, nc);
+  TraceScope ts(TR_RESIDUAL, st, 4.0 * (double)nc * nr * nr * nc, 0.0);
+  hipLaunchKernelGGL(residual_local_kernel, grid, dim3(256), shm, st, nc, nr, sys->hbar2_2mu, E, sys->tl, sys->r,
+                     sys->l, sys->eps, sys->q, X, R);
+  HP_CHECK_LAUNCH();
+  // coupling part: for every radial point i, R_i -= V_i X_i with
+  // V_i = V[i] (nc x nc), X_i = rows (c', i) of X (stride nr rows).
+  const long ld = (long)nr * nc;
+  return gemm_sub_batched<double>(nc, nc, nc, (const cplx<double> *)sys->v, nc, (long)nc * nc, X + 0, ld,
+                                  (long)nc, R, ld, (long)nc, nr, st);
+}
+
+template <typename T>
+static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long lda, const int *perm,
+                      const int *finfo, cplx<double> *X, int max_refine, double tol, char *work,
+                      const Workspace &ws, hp_solve_info *info, hipStream_t st) {
+  const int nc = sys->nc, nr = sys->nr;
+  const long n = (long)nc * nr;
+  const long cnt = n * nc;
+  int rc;
+  if (info) {
+    info->iterations = 0;
+    info->converged = 0;
+    info->correction = -1.0;
+    info->residual = -1.0;
+  }
+  cplx<T> *Y = (cplx<T> *)(work + ws.rhs_off);
+  cplx<double> *Rr = (cplx<double> *)(work + ws.res_off);
+  unsigned long long *smax = (unsigned long long *)(work + ws.red_off);
+  unsigned long long *dmax = smax + nc;
+  unsigned long long *xmax = dmax + nc;
+  // initial solve
+  hipLaunchKernelGGL(rhs_from_perm_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, nc, nr, perm, sys->q, Y);
+  HP_CHECK_LAUNCH();
+  if ((rc = lu_solve_permuted<T>((int)n, nc, LU, lda, Y, nc, st))) return rc;
+  hipLaunchKernelGGL(widen_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, cnt, Y, X);
+  HP_CHECK_LAUNCH();
+  int hinfo = 0;
+  if (finfo) {
+    HP_CHECK_HIP(hipMemcpyAsync(&hinfo, finfo, sizeof(int), hipMemcpyDeviceToHost, st));
+    HP_CHECK_HIP(hipStreamSynchronize(st));
+    if (hinfo == -1) return HP_ERR_SYNC;
+    if (hinfo > 0) return HP_ERR_SINGULAR;
+  }
+  if (max_refine <= 0) {
+    if (info) info->converged = 1;
+    return HP_OK;
+  }
+  std::vector<unsigned long long> h(3 * (size_t)nc);
+  double prev = INFINITY;
+  const unsigned cm_blocks = (unsigned)std::min<long>(4096, std::max<long>(1, (n * nc + 255) / 256));
+  for (int it = 1; it <= max_refine; ++it) {
+    if ((rc = residual(sys, E, X, Rr, st))) return rc;
+    {
+      TraceScope ts(TR_REFINE, st, 0.0, 16.0 * 2 * cnt + sizeof(cplx<T>) * (double)cnt);
+      hipLaunchKernelGGL(zero_u64_kernel, dim3(nblk(3 * nc)), dim3(256), 0, st, smax, 3 * nc);
+      HP_CHECK_LAUNCH();
+      hipLaunchKernelGGL(colmax_kernel, dim3(cm_blocks), dim3(256), 0, st, n, nc, Rr, smax);
+      HP_CHECK_LAUNCH();
+      hipLaunchKernelGGL(scale_perm_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, n, nc, perm, Rr, smax, Y);
+      HP_CHECK_LAUNCH();
+    }
+    if ((rc = lu_solve_permuted<T>((int)n, nc, LU, lda, Y, nc, st))) return rc;
+    {
+      TraceScope ts(TR_REFINE, st, 0.0, (sizeof(cplx<T>) + 16.0 * 3) * (double)cnt);
+      hipLaunchKernelGGL(update_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, n, nc, Y, smax, X, dmax);
+      HP_CHECK_LAUNCH();
+      hipLaunchKernelGGL(colmax_kernel, dim3(cm_blocks), dim3(256), 0, st, n, nc, X, xmax);
+      HP_CHECK_LAUNCH();
+    }
+    HP_CHECK_HIP(hipMemcpyAsync(h.data(), smax, 3 * nc * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HP_CHECK_HIP(hipStreamSynchronize(st));
+    double corr = 0.0, res = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      double s, d, x;
+      long long bits;
+      bits = (long long)h[c];
+      std::memcpy(&s, &bits, 8);
+      bits = (long long)h[nc + c];
+      std::memcpy(&d, &bits, 8);
+      bits = (long long)h[2 * nc + c];
+      std::memcpy(&x, &bits, 8);
+      if (x > 0) corr = std::max(corr, d / x);
+      res = std::max(res, s);
+    }
+    if (info) {
+      info->iterations = it;
+      info->correction = corr;
+      info->residual = res;
+    }
+    if (!(corr == corr)) return HP_ERR_NOCONV;  // NaN
+    if (corr <= tol) {
+      if (info) info->converged = 1;
+      return HP_OK;
+    }
+    if (it > 1 && corr > 0.5 * prev) return HP_ERR_NOCONV;  // stopped contracting
+    prev = corr;
+  }
+  return HP_ERR_NOCONV;
+}
+
+// R[c][c'] = (h/a) sum_i q_i X[(c,i)][c']
+__global__ void rmatrix_kernel(int nc, int nr, double scale, const double *__restrict__ q,
+                               const cplx<double> *__restrict__ X, cplx<double> *__restrict__ R) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)nc * nc) return;
+  const int c = (int)(e / nc), cp = (int)(e - (long)c * nc);
+  double sr = 0.0, si = 0.0;
+  for (int i = 0; i < nr; ++i) {
+    const cplx<double> x = X[((long)c * nr + i) * nc + cp];
+    sr += q[i] * x.re;
+    si += q[i] * x.im;
+  }
+  R[e] = cplx<double>{scale * sr, scale * si};
+}
+
+}  // namespace hp
+
+using namespace hp;
+
+static bool sys_ok(const hp_system *sys) {
+  return sys && sys->nc >= 1 && sys->nr >= 1 && sys->a > 0 && sys->r && sys->q && sys->tl && sys->l && sys->eps &&
+         sys->v;
+}
+
+extern "C" int hp_solve(const hp_system *sys, double E, int prec, const void *LU, long lda, const int *perm,
+                        const int *info_factor, double *X, int max_refine, double tol, void *work,
+                        size_t work_bytes, hp_solve_info *info, void *stream) {
+  if (!sys_ok(sys) || !LU || !perm || !X || !work) return HP_ERR_ARG;
+  const long n = (long)sys->nc * sys->nr;
+  if (lda < n || (prec != HP_C128 && prec != HP_C64) || max_refine < 0) return HP_ERR_ARG;
+  Workspace ws = plan_workspace((int)n, sys->nc, prec);
+  if (work_bytes < ws.total) return HP_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == HP_C128)
+    return solve_impl<double>(sys, E, (const cplx<double> *)LU, lda, perm, info_factor, (cplx<double> *)X,
+                              max_refine, tol, (char *)work, ws, info, st);
+  return solve_impl<float>(sys, E, (const cplx<float> *)LU, lda, perm, info_factor, (cplx<double> *)X,
+                           max_refine, tol, (char *)work, ws, info, st);
+}
+
+extern "C" int hp_rmatrix(const hp_system *sys, const double *X, double *R, void *stream) {
+  if (!sys || sys->nc < 1 || sys->nr < 1 || !(sys->a > 0) || !sys->q || !X || !R) return HP_ERR_ARG;
+  const long cnt = (long)sys->nc * sys->nc;
+  TraceScope ts(TR_RMATRIX, (hipStream_t)stream, 4.0 * (double)cnt * sys->nr, 16.0 * (double)cnt * sys->nr);
+  hipLaunchKernelGGL(rmatrix_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     sys->nc, sys->nr, sys->hbar2_2mu / sys->a, sys->q, (const cplx<double> *)X,
+                     (cplx<double> *)R);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}

@@ -1,0 +1,228 @@
+"""ctypes binding of libhprmat.so (the C ABI in include/hprmat.h).
+
+Argument marshalling only: every function forwards to the entry point of the
+same name.  Device buffers are torch tensors on the HIP device (PyTorch is
+used for device memory and streams); their data pointers and the current
+stream are passed through.  If the library has not been built, or the HIP
+device is missing, calls raise instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhprmat.so")
+
+HP_OK = 0
+HP_ERR_ARG = -1
+HP_ERR_HIP = -2
+HP_ERR_SINGULAR = -3
+HP_ERR_NOCONV = -4
+HP_ERR_WORKSPACE = -5
+HP_ERR_UNSUPPORTED = -6
+HP_ERR_SYNC = -7
+
+HP_C128 = 0
+HP_C64 = 1
+
+c_int, c_long, c_double, c_void_p, c_size_t = (ctypes.c_int, ctypes.c_long, ctypes.c_double,
+                                               ctypes.c_void_p, ctypes.c_size_t)
+
+
+class HpSystem(ctypes.Structure):
+    _fields_ = [("nc", c_int), ("nr", c_int), ("a", c_double), ("hbar2_2mu", c_double),
+                ("z1z2e2", c_double), ("r", c_void_p), ("q", c_void_p), ("tl", c_void_p),
+                ("l", c_void_p), ("eps", c_void_p), ("v", c_void_p)]
+
+
+class HpTraceStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", c_long), ("ms", c_double), ("flops", c_double),
+                ("bytes", c_double)]
+
+
+HP_TRACE_STAGES = 10
+
+
+class HpSolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", c_int), ("converged", c_int), ("correction", c_double),
+                ("residual", c_double)]
+
+
+EXPORTS = ["hp_mesh", "hp_workspace_bytes", "hp_build_matrix", "hp_factor", "hp_solve",
+           "hp_lu_solve", "hp_rmatrix", "hp_smatrix", "hp_coulomb", "hp_coulomb_device",
+           "hp_build_info", "hp_strerror", "hp_trace_enable", "hp_trace_read", "hp_last_error"]
+
+_lib = None
+
+
+class HprmatError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        detail = ""
+        if code == HP_ERR_HIP:
+            try:
+                detail = " [" + lib().hp_last_error().decode() + "]"
+            except ImportError:
+                pass
+        super().__init__(f"{where}: {strerror(code)} ({code}){detail}")
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhprmat.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    L.hp_mesh.argtypes = [c_int, c_double, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.hp_mesh.restype = c_int
+    L.hp_workspace_bytes.argtypes = [c_int, c_int, c_int]
+    L.hp_workspace_bytes.restype = c_size_t
+    L.hp_build_matrix.argtypes = [P(HpSystem), c_double, c_int, c_void_p, c_long, c_void_p]
+    L.hp_build_matrix.restype = c_int
+    L.hp_factor.argtypes = [c_int, c_int, c_void_p, c_long, c_void_p, c_void_p, c_void_p, c_void_p,
+                            c_size_t, c_void_p]
+    L.hp_factor.restype = c_int
+    L.hp_solve.argtypes = [P(HpSystem), c_double, c_int, c_void_p, c_long, c_void_p, c_void_p,
+                           c_void_p, c_int, c_double, c_void_p, c_size_t, P(HpSolveInfo), c_void_p]
+    L.hp_solve.restype = c_int
+    L.hp_lu_solve.argtypes = [c_int, c_int, c_int, c_void_p, c_long, c_void_p, c_void_p, c_long,
+                              c_void_p, c_size_t, c_void_p]
+    L.hp_lu_solve.restype = c_int
+    L.hp_rmatrix.argtypes = [P(HpSystem), c_void_p, c_void_p, c_void_p]
+    L.hp_rmatrix.restype = c_int
+    L.hp_smatrix.argtypes = [P(HpSystem), c_double, c_void_p, c_void_p, P(c_int), c_void_p,
+                             c_size_t, c_void_p]
+    L.hp_smatrix.restype = c_int
+    L.hp_coulomb.argtypes = [c_int, c_double, c_double, c_void_p]
+    L.hp_coulomb.restype = c_int
+    L.hp_coulomb_device.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.hp_coulomb_device.restype = c_int
+    L.hp_trace_enable.argtypes = [c_int]
+    L.hp_trace_enable.restype = c_int
+    L.hp_trace_read.argtypes = [ctypes.POINTER(HpTraceStat), c_int]
+    L.hp_trace_read.restype = c_int
+    L.hp_last_error.argtypes = []
+    L.hp_last_error.restype = ctypes.c_char_p
+    L.hp_build_info.argtypes = []
+    L.hp_build_info.restype = ctypes.c_char_p
+    L.hp_strerror.argtypes = [c_int]
+    L.hp_strerror.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().hp_strerror(code).decode()
+    except ImportError:
+        return f"code {code}"
+
+
+def _check(code: int, where: str) -> int:
+    if code != HP_OK:
+        raise HprmatError(code, where)
+    return code
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+# ------------------------------------------------------------------ host --
+
+def hp_mesh(nr: int, a: float):
+    """(r, w, q, tl) as numpy arrays (closed-form Lagrange-Legendre mesh)."""
+    r = np.zeros(nr)
+    w = np.zeros(nr)
+    q = np.zeros(nr)
+    tl = np.zeros((nr, nr))
+    _check(lib().hp_mesh(nr, a, r.ctypes.data, w.ctypes.data, q.ctypes.data, tl.ctypes.data), "hp_mesh")
+    return r, w, q, tl
+
+
+def hp_workspace_bytes(n: int, nrhs: int, prec: int) -> int:
+    return int(lib().hp_workspace_bytes(n, nrhs, prec))
+
+
+def hp_coulomb(l: int, eta: float, rho: float) -> np.ndarray:
+    out = np.zeros(4)
+    _check(lib().hp_coulomb(int(l), float(eta), float(rho), out.ctypes.data), "hp_coulomb")
+    return out
+
+
+def hp_build_info() -> str:
+    return lib().hp_build_info().decode()
+
+
+# ---------------------------------------------------------------- device --
+
+def hp_build_matrix(sys: HpSystem, E: float, prec: int, C, ldc: int, stream=None) -> None:
+    _check(lib().hp_build_matrix(ctypes.byref(sys), float(E), prec, _ptr(C), ldc, _stream(stream)),
+           "hp_build_matrix")
+
+
+def hp_factor(n: int, prec: int, A, lda: int, ipiv, perm, info, work, stream=None) -> None:
+    _check(lib().hp_factor(n, prec, _ptr(A), lda, _ptr(ipiv), _ptr(perm), _ptr(info), _ptr(work),
+                           work.numel() * work.element_size(), _stream(stream)), "hp_factor")
+
+
+def hp_solve(sys: HpSystem, E: float, prec: int, LU, lda: int, perm, info_factor, X,
+             max_refine: int, tol: float, work, stream=None, check: bool = True):
+    """Returns (code, HpSolveInfo); raises on errors other than HP_ERR_NOCONV unless check=False."""
+    info = HpSolveInfo()
+    code = lib().hp_solve(ctypes.byref(sys), float(E), prec, _ptr(LU), lda, _ptr(perm),
+                          _ptr(info_factor), _ptr(X), int(max_refine), float(tol), _ptr(work),
+                          work.numel() * work.element_size(), ctypes.byref(info), _stream(stream))
+    if check and code not in (HP_OK, HP_ERR_NOCONV, HP_ERR_SINGULAR):
+        raise HprmatError(code, "hp_solve")
+    return code, info
+
+
+def hp_lu_solve(n: int, nrhs: int, prec: int, LU, lda: int, perm, X, ldx: int, work, stream=None) -> None:
+    _check(lib().hp_lu_solve(n, nrhs, prec, _ptr(LU), lda, _ptr(perm), _ptr(X), ldx, _ptr(work),
+                             work.numel() * work.element_size(), _stream(stream)), "hp_lu_solve")
+
+
+def hp_rmatrix(sys: HpSystem, X, R, stream=None) -> None:
+    _check(lib().hp_rmatrix(ctypes.byref(sys), _ptr(X), _ptr(R), _stream(stream)), "hp_rmatrix")
+
+
+def hp_smatrix(sys: HpSystem, E: float, R, S, work, stream=None) -> int:
+    nopen = c_int(0)
+    _check(lib().hp_smatrix(ctypes.byref(sys), float(E), _ptr(R), _ptr(S), ctypes.byref(nopen),
+                            _ptr(work), work.numel() * work.element_size(), _stream(stream)),
+           "hp_smatrix")
+    return int(nopen.value)
+
+
+def hp_coulomb_device(l, eta, rho, out, stream=None) -> None:
+    _check(lib().hp_coulomb_device(int(l.numel()), _ptr(l), _ptr(eta), _ptr(rho), _ptr(out),
+                                   _stream(stream)), "hp_coulomb_device")
+
+
+def hp_trace_enable(on: bool) -> None:
+    _check(lib().hp_trace_enable(1 if on else 0), "hp_trace_enable")
+
+
+def hp_trace_read() -> dict:
+    """{stage: dict(launches, ms, flops, bytes)} for the launches since hp_trace_enable(1)."""
+    arr = (HpTraceStat * HP_TRACE_STAGES)()
+    n = lib().hp_trace_read(arr, HP_TRACE_STAGES)
+    if n < 0:
+        raise HprmatError(n, "hp_trace_read")
+    return {arr[i].name.decode(): dict(launches=int(arr[i].launches), ms=float(arr[i].ms),
+                                       flops=float(arr[i].flops), bytes=float(arr[i].bytes))
+            for i in range(n)}

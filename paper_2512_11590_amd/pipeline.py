@@ -1,0 +1,115 @@
+"""Persistent device buffers and the per-energy call sequence of the C ABI.
+
+A :class:`DeviceSystem` uploads one coupled-channel system (mesh, kinetic +
+Bloch matrix, surface values, channel data and the potential values at the
+mesh points) to the device once.  A :class:`Solver` owns the matrix, pivot,
+solution and workspace buffers for that system, allocated once and reused for
+every energy of a scan (persistent buffers as in the paper's GPU solver), and
+runs the entry points in order:
+
+    hp_build_matrix -> hp_factor -> hp_solve -> hp_rmatrix -> hp_smatrix
+
+In FP32 mode a refinement that does not converge (or a zero FP32 pivot) is
+followed by the FP64 path on the same system (the paper's fallback, Sec. 5.3),
+and the result says so.  All arithmetic runs in the HIP library.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import hprmat as H
+
+E2 = 1.44  # e^2 in MeV fm
+
+
+class DeviceSystem:
+    def __init__(self, params, device: str = "cuda"):
+        self.params = params
+        self.nc, self.nr = int(params.nc), int(params.nr)
+        self.n = self.nc * self.nr
+        self.device = torch.device(device)
+        r, w, q, tl = H.hp_mesh(self.nr, float(params.a))
+        self.r_host, self.q_host, self.tl_host = r, q, tl
+        v = np.ascontiguousarray(params.potential(r), dtype=np.complex128)  # user-supplied V(r_i)
+        dev = self.device
+        self.r = torch.from_numpy(r).to(dev)
+        self.q = torch.from_numpy(q).to(dev)
+        self.tl = torch.from_numpy(np.ascontiguousarray(tl)).to(dev)
+        self.l = torch.from_numpy(np.asarray(params.l, dtype=np.int32)).to(dev)
+        self.eps = torch.from_numpy(np.asarray(params.eps, dtype=np.float64)).to(dev)
+        self.v = torch.from_numpy(v).to(dev)
+        self.sys = H.HpSystem(self.nc, self.nr, float(params.a), float(params.hbar2_2mu),
+                              float(params.z1z2) * E2, self.r.data_ptr(), self.q.data_ptr(),
+                              self.tl.data_ptr(), self.l.data_ptr(), self.eps.data_ptr(),
+                              self.v.data_ptr())
+
+
+@dataclass
+class EnergyResult:
+    E: float
+    prec: int
+    R: torch.Tensor
+    S: torch.Tensor | None
+    iterations: int
+    correction: float
+    fallback: bool
+    nopen: int
+
+
+class Solver:
+    """Buffers for one system in one working precision (HP_C64 or HP_C128)."""
+
+    def __init__(self, dsys: DeviceSystem, prec: int = H.HP_C64, ld: int | None = None,
+                 fallback: bool = True):
+        self.d = dsys
+        self.prec = prec
+        self.fallback = fallback
+        n, nc = dsys.n, dsys.nc
+        self.ld = ld or n
+        dev = dsys.device
+        ctype = torch.complex64 if prec == H.HP_C64 else torch.complex128
+        self.A = torch.empty((n, self.ld), dtype=ctype, device=dev)
+        self.ipiv = torch.empty(n, dtype=torch.int32, device=dev)
+        self.perm = torch.empty(n, dtype=torch.int32, device=dev)
+        self.info = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.X = torch.empty((n, nc), dtype=torch.complex128, device=dev)
+        self.R = torch.empty((nc, nc), dtype=torch.complex128, device=dev)
+        self.S = torch.empty((nc, nc), dtype=torch.complex128, device=dev)
+        self.work = torch.empty(H.hp_workspace_bytes(n, nc, prec), dtype=torch.uint8, device=dev)
+        self.swork = torch.empty(H.hp_workspace_bytes(nc, nc, H.HP_C128), dtype=torch.uint8, device=dev)
+        self._fp64 = None
+
+    def factor(self, E: float) -> None:
+        H.hp_build_matrix(self.d.sys, E, self.prec, self.A, self.ld)
+        H.hp_factor(self.d.n, self.prec, self.A, self.ld, self.ipiv, self.perm, self.info, self.work)
+
+    def solve(self, E: float, max_refine: int, tol: float):
+        return H.hp_solve(self.d.sys, E, self.prec, self.A, self.ld, self.perm, self.info, self.X,
+                          max_refine, tol, self.work)
+
+    def run(self, E: float, max_refine: int = 30, tol: float = 1e-13, smatrix: bool = True) -> EnergyResult:
+        self.factor(E)
+        code, info = self.solve(E, max_refine if self.prec == H.HP_C64 else 0, tol)
+        used_fallback = False
+        if code != H.HP_OK:
+            if not (self.fallback and self.prec == H.HP_C64 and code in (H.HP_ERR_NOCONV, H.HP_ERR_SINGULAR)):
+                raise H.HprmatError(code, "hp_solve")
+            if self._fp64 is None:
+                self._fp64 = Solver(self.d, H.HP_C128, fallback=False)
+            self._fp64.factor(E)
+            code, info = self._fp64.solve(E, 0, tol)
+            if code != H.HP_OK:
+                raise H.HprmatError(code, "hp_solve (FP64 fallback)")
+            self.X.copy_(self._fp64.X)
+            used_fallback = True
+        H.hp_rmatrix(self.d.sys, self.X, self.R)
+        nopen = 0
+        S = None
+        if smatrix:
+            nopen = H.hp_smatrix(self.d.sys, E, self.R, self.S, self.swork)
+            S = self.S
+        return EnergyResult(E=E, prec=self.prec, R=self.R, S=S, iterations=info.iterations,
+                            correction=info.correction, fallback=used_fallback, nopen=nopen)

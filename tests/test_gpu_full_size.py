@@ -1,0 +1,95 @@
+"""GPU parity at the full workload sizes against stored oracle results.
+
+The oracle results in tests/golden/{mid,large}_oracle.npz are written by
+tests/golden/make_golden.py, which calls only oracle/ and workload/.
+
+Tolerances (normwise relative): S 1e-10 after refinement (FP32 LU + FP64
+refinement, and FP64 LU); R 1e-10; cross sections without refinement 1e-3.
+Properties that hold at any size are checked too: S symmetric (C = C^T),
+|S| contracting for the absorptive potential.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from tests.helpers import relerr  # noqa: E402
+from workload import make_system  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2512_11590_amd import hprmat, pipeline
+    hprmat.lib()
+    return hprmat, pipeline
+
+
+def golden(config):
+    path = os.path.join(GOLD, f"{config}_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return np.load(path)
+
+
+def energy_indices(g):
+    return sorted(int(k[2:]) for k in g.files if k.startswith("S_"))
+
+
+def sigma(S, k):
+    d = np.eye(S.shape[0]) - S
+    return np.pi / (k[None, :] ** 2) * np.abs(d) ** 2
+
+
+@pytest.mark.parametrize("config", ["mid", "large"])
+@pytest.mark.parametrize("prec", [1, 0])
+def test_full_size_against_oracle(mods, config, prec):
+    H, P = mods
+    g = golden(config)
+    sp = make_system(config)
+    d = P.DeviceSystem(sp)
+    s = P.Solver(d, prec)
+    for e in energy_indices(g):
+        E = float(g[f"E_{e}"])
+        say(config, "N", sp.n, "prec", prec, "E", E)
+        res = s.run(E)
+        R = res.R.cpu().numpy()
+        S = res.S.cpu().numpy()
+        er, es = relerr(R, g[f"R_{e}"]), relerr(S, g[f"S_{e}"])
+        print(f"   R err {er:.2e}  S err {es:.2e}  refinement {res.iterations} fallback {res.fallback}",
+              flush=True)
+        assert es < 1e-10
+        assert er < 1e-10
+        assert np.max(np.abs(S - S.T)) < 1e-9
+        assert np.linalg.norm(S, 2) <= 1.0 + 1e-9
+
+
+def test_cross_sections_without_refinement(mods):
+    """FP32 LU, no refinement: cross sections within 1e-3 (the paper's Type 4 level)."""
+    H, P = mods
+    g = golden("mid")
+    sp = make_system("mid")
+    d = P.DeviceSystem(sp)
+    s = P.Solver(d, H.HP_C64, fallback=False)
+    for e in energy_indices(g):
+        E = float(g[f"E_{e}"])
+        say("mid FP32 no refinement E", E)
+        res = s.run(E, max_refine=0)
+        k = np.sqrt((E - sp.eps) / sp.hbar2_2mu)
+        sg = sigma(res.S.cpu().numpy(), k)
+        err = relerr(sg, g[f"sigma_{e}"])
+        print(f"   sigma err {err:.2e}", flush=True)
+        assert err < 1e-3

@@ -1,0 +1,95 @@
+"""CPU tests of the HIP library: it loads, exports every declared symbol, and its
+host-side logic (mesh, kinetic+Bloch matrix, Coulomb functions, argument
+checks) agrees with the oracle.  No device call is made here."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import mesh, rmatrix
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hprmat.h")
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_2512_11590_amd import hprmat
+    if not os.path.exists(hprmat.LIB_PATH):
+        from paper_2512_11590_amd import build
+        build.build()
+    hprmat.lib()
+    return hprmat
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(hp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(H):
+    names = declared_symbols()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(H.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) <= set(H.EXPORTS)
+
+
+@pytest.mark.parametrize("nr,a", [(1, 3.0), (2, 5.0), (7, 4.0), (40, 15.0), (60, 20.0), (100, 30.0)])
+def test_mesh_matches_oracle(H, nr, a):
+    r, w, q, tl = H.hp_mesh(nr, a)
+    ro, wo = mesh.mesh(nr, a)
+    assert np.max(np.abs(r - ro)) <= 1e-14 * a
+    assert np.max(np.abs(w - wo)) <= 1e-12 * a
+    qo = mesh.surface_values(nr, a)
+    assert np.max(np.abs(q - qo)) <= 1e-12 * np.max(np.abs(qo))
+    tlo = mesh.kinetic_bloch(nr, a)
+    # the oracle integrates f_i' f_j' numerically; the library uses the closed form
+    assert np.max(np.abs(tl - tlo)) <= 5e-12 * np.max(np.abs(tlo))
+    assert np.array_equal(tl, tl.T)
+
+
+COULOMB_CASES = [(l, eta, rho) for l in (0, 1, 6, 20) for eta in (0.0, 2.0, 18.2, 25.8)
+                 for rho in (11.2, 23.7, 58.0, 116.0)]
+
+
+@pytest.mark.parametrize("l,eta,rho", COULOMB_CASES)
+def test_coulomb_host_routine_matches_oracle(H, l, eta, rho):
+    out = H.hp_coulomb(l, eta, rho)
+    ref = np.array(rmatrix.coulomb(l, eta, rho))
+    assert np.max(np.abs(out - ref) / np.abs(ref)) < 1e-12
+    F, Fp, G, Gp = out
+    assert abs(Fp * G - F * Gp - 1.0) < 1e-12
+
+
+def test_argument_errors_without_device(H):
+    L = H.lib()
+    assert L.hp_mesh(0, 1.0, None, None, None, None) == H.HP_ERR_ARG
+    assert L.hp_mesh(5, -1.0, None, None, None, None) == H.HP_ERR_ARG
+    assert H.hp_workspace_bytes(0, 1, H.HP_C128) == 0
+    assert H.hp_workspace_bytes(10, 2, 7) == 0
+    assert L.hp_build_matrix(None, 1.0, H.HP_C128, None, 10, None) == H.HP_ERR_ARG
+    assert L.hp_factor(0, H.HP_C128, None, 0, None, None, None, None, 0, None) == H.HP_ERR_ARG
+    assert L.hp_factor(4, 9, 1, 4, 1, 1, 1, 1, 1 << 20, None) == H.HP_ERR_ARG
+    assert L.hp_rmatrix(None, None, None, None) == H.HP_ERR_ARG
+    assert L.hp_coulomb(-1, 0.0, 1.0, None) == H.HP_ERR_ARG
+    assert L.hp_lu_solve(4, 1, H.HP_C64, None, 4, None, None, 1, None, 0, None) == H.HP_ERR_ARG
+    sys_ = H.HpSystem()
+    sys_.nc, sys_.nr = 0, 4
+    assert L.hp_solve(ctypes.byref(sys_), 1.0, H.HP_C64, 1, 4, 1, None, 1, 0, 0.0, 1, 1, None, None) == H.HP_ERR_ARG
+    assert L.hp_smatrix(ctypes.byref(sys_), 1.0, 1, 1, None, 1, 1, None) == H.HP_ERR_ARG
+    # workspace too small is detected before any device work
+    assert L.hp_factor(64, H.HP_C128, 1, 64, 1, 1, 1, 1, 16, None) == H.HP_ERR_WORKSPACE
+
+
+def test_workspace_grows_with_size(H):
+    a = H.hp_workspace_bytes(1000, 10, H.HP_C64)
+    b = H.hp_workspace_bytes(2000, 10, H.HP_C64)
+    c = H.hp_workspace_bytes(2000, 10, H.HP_C128)
+    assert 0 < a < b <= c
+    assert H.hp_workspace_bytes(25600, 256, H.HP_C64) < 1 << 30
