@@ -67,9 +67,10 @@ typedef struct hp_system {
 /* Outcome of hp_solve (host struct, written by the library). */
 typedef struct hp_solve_info {
   int iterations;        /* refinement corrections applied */
-  int converged;         /* 1 if the last correction met tol (or no refinement asked) */
+  int converged;         /* 1 if refinement converged (or no refinement was asked) */
   double correction;     /* max over columns of |d|_inf / |x|_inf of the last correction */
-  double residual;       /* max over columns of |b - C x|_inf / (|C|_inf |x|_inf + |b|_inf) */
+  double residual;       /* backward error of the returned X: max over columns of
+                            |b - C x|_inf / (|C|_inf |x|_inf + |b|_inf), norms of |Re|+|Im| */
 } hp_solve_info;
 
 /* ---- host-side precompute ---------------------------------------------- */
@@ -114,16 +115,21 @@ int hp_factor(int n, int prec, void *A, long lda, int *ipiv, int *perm, int *inf
 /* Solve C(E) X = B for the nc surface right-hand sides (Sec. 3.1, steps 2-3)
  * with the factors of hp_factor (LU, lda, perm, precision prec).  X: device
  * n x nc complex128 (leading dimension nc), overwritten with the solution.
- * prec == HP_C64: the FP32 factors give X0; then up to max_refine steps of
- * iterative refinement (Sec. 3.2 and Sec. 3.4 step 7, here entirely on the
- * device): r = B - C X in FP64 from the block structure of sys (no N x N FP64
- * matrix), correction from the FP32 factors, X += d in FP64.  Stops when the
- * relative correction <= tol.  prec == HP_C128: direct FP64 solve, then the
- * same refinement if max_refine > 0.  info (host, may be NULL) receives the
- * outcome.  Synchronizes the stream once per refinement step.
- * Errors: HP_ERR_ARG, HP_ERR_WORKSPACE, HP_ERR_NOCONV (refinement stopped
- * contracting or max_refine exhausted above tol; X holds the last iterate),
- * HP_ERR_SINGULAR (zero pivot reported by hp_factor), HP_ERR_SYNC, HP_ERR_HIP. */
+ * The factors give X0 (prec == HP_C64: FP32 factors, X0 widened to FP64).
+ * With max_refine > 0, iterative refinement follows (Sec. 3.2 and Sec. 3.4
+ * step 7, here entirely on the device): r = B - C X in FP64 from the block
+ * structure of sys (no N x N FP64 matrix), correction from the factors,
+ * X += d in FP64.  The relative correction max_c |d_c| / |x_c| tracks the
+ * forward error: refinement stops converged when it is <= tol (tol <= 0:
+ * 2^-52) or when it stops shrinking (a correction larger than half the
+ * previous one) while already <= 1e-6, and reports non-convergence when it
+ * stops shrinking above that (Sec. 6: the single-precision factor is then too
+ * inaccurate to contract) or after max_refine corrections.  info (host, may
+ * be NULL) receives the outcome, including the normwise backward error.
+ * Synchronizes the stream once per refinement pass.
+ * Errors: HP_ERR_ARG, HP_ERR_WORKSPACE, HP_ERR_NOCONV (X holds the last
+ * iterate), HP_ERR_SINGULAR (zero pivot reported by hp_factor), HP_ERR_SYNC,
+ * HP_ERR_HIP. */
 int hp_solve(const hp_system *sys, double E, int prec, const void *LU, long lda,
              const int *perm, const int *info_factor, double *X, int max_refine, double tol,
              void *work, size_t work_bytes, hp_solve_info *info, void *stream);
@@ -132,6 +138,13 @@ int hp_solve(const hp_system *sys, double E, int prec, const void *LU, long lda,
  * precision prec) holds B on entry and X = A^-1 B on return. */
 int hp_lu_solve(int n, int nrhs, int prec, const void *LU, long lda, const int *perm,
                 void *X, long ldx, void *work, size_t work_bytes, void *stream);
+
+/* The trailing-update kernel on its own: C -= A B for complex matrices
+ * (device, row-major, interleaved, precision prec), A M x K (lda >= K),
+ * B K x N (ldb >= N), C M x N (ldc >= N); the block operation of Sec. 3.1's
+ * LU and substitutions.  Exposed for tests and tuning.  Asynchronous. */
+int hp_gemm_sub(int M, int N, int K, int prec, const void *A, long lda, const void *B, long ldb, void *C,
+                long ldc, void *stream);
 
 /* R-matrix (Sec. 3.1, step 4, with the factor hbar^2/(2 mu a)):
  *   R[c][c'] = (hbar2_2mu / a) sum_i q_i X[(c,i)][c'],

@@ -74,7 +74,7 @@ class TraceScope {
 // ------------------------------------------------------------ constants --
 constexpr int kPanelWidth = 32;     // columns factored by one cooperative panel launch
 constexpr int kOuterBlock = 256;    // columns per trailing-update step (GEMM K)
-constexpr int kMaxPanelGroups = 1024;
+constexpr int kMaxPanelGroups = 128;  // candidate slots held in registers: 16 per thread
 constexpr unsigned kSpinLimit = 1u << 22;  // bounded grid-barrier wait (a few seconds)
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }

@@ -114,21 +114,25 @@ __device__ __forceinline__ void block_argmax(T &v, int &r, T *sv, int *sr) {
 constexpr int kBarGroup = 16;     // workgroups per group counter
 constexpr int kBarStride = 32;    // unsigned words between counters (128 B)
 
-__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned ngroups, unsigned epoch,
-                                             int *flag) {
-  // every lane's agent-scope stores must have completed before the arrival
+// Arrival: every lane's agent-scope stores must have completed first.
+__device__ __forceinline__ void grid_arrive(unsigned *bar, unsigned epoch) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned g = blockIdx.x / kBarGroup;
     const unsigned gsize = min((unsigned)kBarGroup, gridDim.x - g * kBarGroup);
-    unsigned *top = bar;
     unsigned *grp = bar + (g + 1) * kBarStride;
-    unsigned old = atomicAdd(grp, 1u);
-    if (old + 1 == gsize * epoch) atomicAdd(top, 1u);
+    const unsigned old = atomicAdd(grp, 1u);
+    if (old + 1 == gsize * epoch) atomicAdd(bar, 1u);
+  }
+}
+
+// Wait until every workgroup has arrived at `epoch` (bounded, see above).
+__device__ __forceinline__ void grid_wait(unsigned *bar, unsigned ngroups, unsigned epoch, int *flag) {
+  if (threadIdx.x == 0) {
     unsigned spins = 0;
-    while (__hip_atomic_load(top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < ngroups * epoch) {
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < ngroups * epoch) {
       __builtin_amdgcn_s_sleep(1);
       if (((++spins) & 1023u) == 0) {
         if (spins > kSpinLimit ||
@@ -148,13 +152,20 @@ static size_t barrier_words(int G) { return (size_t)(((G + kBarGroup - 1) / kBar
 //
 // Factor columns [j0, j0+w) of rows [j0, n) with partial pivoting.  The rows
 // are split into contiguous chunks of rpw rows, one per workgroup, held in
-// LDS for the whole panel.  Per column: each workgroup finds its candidate
-// pivot (largest |Re|+|Im|, smallest row on ties) and publishes it, with the
-// candidate's full panel row, in a slot; the owner of the diagonal row
-// publishes that row too; one grid barrier; every workgroup then picks the
-// same winner from the slots, the owners of the two rows exchange them, and
-// each workgroup scales and updates its own rows.  Slots alternate between
-// two buffers so a slow reader never sees the next column's writes.
+// LDS for the whole panel.  Per column j: every workgroup publishes its
+// candidate pivot for column j (largest |Re|+|Im|, smallest row on ties)
+// together with that row's panel values in a slot, and the owner of row j
+// publishes row j; a grid barrier; every workgroup reads all slots in one
+// round trip (the candidate rows go to registers), picks the same winner,
+// the owners of the two rows exchange them, and each workgroup eliminates in
+// its own rows.  The elimination is split so the barrier wait hides most of
+// it: column j+1 is updated first (it decides the next pivot), the next
+// candidate row and the next diagonal row are finished and published, and
+// the remaining columns are updated while the other workgroups arrive.
+// Slots alternate between two buffers, so a slow reader never sees the next
+// column's writes.
+constexpr int kMaxCandPerThread = kMaxPanelGroups * kPanelWidth / 256;
+
 template <typename T>
 __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T> *__restrict__ A,
                                                     long lda, int *__restrict__ ipiv,
@@ -172,6 +183,7 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
   const int rbeg = j0 + g * rpw;
   const int rend = min(n, rbeg + rpw);
   const int nrow = max(0, rend - rbeg);
+  const int ncand = G * W;  // slot values held in registers per column
 
   for (int e = tid; e < nrow * w; e += 256) {
     const int rr = e / w, cc = e - rr * w;
@@ -179,17 +191,9 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
   }
   __syncthreads();
 
-  for (int j = 0; j < w; ++j) {
-    const int jc = j0 + j;
-    const int par = j & 1;
-    // -- local pivot candidate in column j among rows >= jc
-    T best = T(-1);
-    int brow = INT_MAX;
-    for (int rr = tid; rr < nrow; rr += 256) {
-      const int gr = rbeg + rr;
-      if (gr >= jc) argmax_combine(best, brow, cabs1(Ls[rr * W + j]), gr);
-    }
-    block_argmax(best, brow, red_v, red_r);
+  // publish the candidate of column jj (slot buffer jj & 1) and row j0+jj
+  auto publish = [&](int jj, T best, int brow) {
+    const int par = jj & 1;
     if (tid == 0) {
       st_agent(&slot_val[par * G + g], best);
       st_agent(&slot_row[par * G + g], brow);
@@ -197,13 +201,36 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
     if (brow != INT_MAX)
       for (int cc = tid; cc < w; cc += 256)
         st_agent(&slot_rows[((size_t)par * G + g) * W + cc], Ls[(brow - rbeg) * W + cc]);
-    if (jc >= rbeg && jc < rend)
-      for (int cc = tid; cc < w; cc += 256) st_agent(&diag_rows[par * W + cc], Ls[(jc - rbeg) * W + cc]);
-    grid_barrier(bar, ngroups, (unsigned)(j + 1), info);
-    // -- global winner (identical in every workgroup)
+    const int jd = j0 + jj;
+    if (jd >= rbeg && jd < rend)
+      for (int cc = tid; cc < w; cc += 256) st_agent(&diag_rows[par * W + cc], Ls[(jd - rbeg) * W + cc]);
+  };
+
+  // prologue: candidate for the first column
+  {
+    T best = T(-1);
+    int brow = INT_MAX;
+    for (int rr = tid; rr < nrow; rr += 256) argmax_combine(best, brow, cabs1(Ls[rr * W]), rbeg + rr);
+    block_argmax(best, brow, red_v, red_r);
+    publish(0, best, brow);
+    grid_arrive(bar, 1u);
+  }
+
+  for (int j = 0; j < w; ++j) {
+    const int jc = j0 + j;
+    const int par = j & 1;
+    grid_wait(bar, ngroups, (unsigned)(j + 1), info);
+    // -- one round trip: all candidate values, rows and panel rows, and row jc
+    cplx<T> cand[kMaxCandPerThread];
+#pragma unroll
+    for (int q = 0; q < kMaxCandPerThread; ++q) {
+      const int e = tid + 256 * q;
+      if (e < ncand) cand[q] = ld_agent(&slot_rows[(size_t)par * G * W + e]);
+    }
     T wv = T(-1);
     int wr = INT_MAX;
     for (int e = tid; e < G; e += 256) argmax_combine(wv, wr, ld_agent(&slot_val[par * G + e]), ld_agent(&slot_row[par * G + e]));
+    if (tid < w) drow[tid] = ld_agent(&diag_rows[par * W + tid]);
     block_argmax(wv, wr, red_v, red_r);
     int p = wr;
     if (p < jc || p >= n) {  // cannot happen unless the exchange failed; never index out of range
@@ -212,9 +239,10 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
     }
     // the winning row's values sit in the slot of the workgroup that owns row p
     const int wg = min(G - 1, (p - j0) / rpw);
-    for (int cc = tid; cc < w; cc += 256) {
-      urow[cc] = ld_agent(&slot_rows[((size_t)par * G + wg) * W + cc]);
-      drow[cc] = ld_agent(&diag_rows[par * W + cc]);
+#pragma unroll
+    for (int q = 0; q < kMaxCandPerThread; ++q) {
+      const int e = tid + 256 * q;
+      if (e < ncand && e / W == wg && (e % W) < w) urow[e % W] = cand[q];
     }
     __syncthreads();
     if (g == 0 && tid == 0) {
@@ -226,20 +254,53 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
     if (p != jc && p >= rbeg && p < rend)
       for (int cc = tid; cc < w; cc += 256) Ls[(p - rbeg) * W + cc] = drow[cc];
     __syncthreads();
-    // -- scale the column below the pivot and update the rest of the panel
-    const cplx<T> piv = urow[j];
-    if (wv > T(0)) {
-      const cplx<T> inv = crcp(piv);
-      for (int rr = tid; rr < nrow; rr += 256) {
-        const int gr = rbeg + rr;
-        if (gr > jc) {
+    // -- eliminate: scale column j below the pivot (an exactly zero pivot
+    //    column is left as it is, and nothing is subtracted)
+    const bool nz = wv > T(0);
+    const cplx<T> inv = nz ? crcp(urow[j]) : cplx<T>{T(0), T(0)};
+    if (j == w - 1) {
+      if (nz)
+        for (int rr = tid; rr < nrow; rr += 256)
+          if (rbeg + rr > jc) Ls[rr * W + j] = cmul(Ls[rr * W + j], inv);
+      __syncthreads();
+      break;
+    }
+    // column j+1 first, with the next pivot search
+    T best = T(-1);
+    int brow = INT_MAX;
+    for (int rr = tid; rr < nrow; rr += 256) {
+      const int gr = rbeg + rr;
+      if (gr > jc) {
+        if (nz) {
           const cplx<T> lv = cmul(Ls[rr * W + j], inv);
           Ls[rr * W + j] = lv;
-          for (int cc = j + 1; cc < w; ++cc) Ls[rr * W + cc] = cfms(Ls[rr * W + cc], lv, urow[cc]);
+          Ls[rr * W + j + 1] = cfms(Ls[rr * W + j + 1], lv, urow[j + 1]);
         }
+        argmax_combine(best, brow, cabs1(Ls[rr * W + j + 1]), gr);
+      }
+    }
+    block_argmax(best, brow, red_v, red_r);
+    // finish the two rows that are published next: the candidate and row jc+1
+    const int r1 = (brow != INT_MAX) ? brow - rbeg : -1;
+    const int r2 = (jc + 1 >= rbeg && jc + 1 < rend) ? jc + 1 - rbeg : -1;
+    if (nz) {
+      for (int cc = j + 2 + tid; cc < w; cc += 256) {
+        if (r1 >= 0) Ls[r1 * W + cc] = cfms(Ls[r1 * W + cc], Ls[r1 * W + j], urow[cc]);
+        if (r2 >= 0 && r2 != r1) Ls[r2 * W + cc] = cfms(Ls[r2 * W + cc], Ls[r2 * W + j], urow[cc]);
       }
     }
     __syncthreads();
+    publish(j + 1, best, brow);
+    grid_arrive(bar, (unsigned)(j + 2));
+    // the remaining columns of the other rows, while the grid arrives
+    if (nz && j + 2 < w) {
+      for (int rr = tid; rr < nrow; rr += 256) {
+        if (rbeg + rr > jc && rr != r1 && rr != r2) {
+          const cplx<T> lv = Ls[rr * W + j];
+          for (int cc = j + 2; cc < w; ++cc) Ls[rr * W + cc] = cfms(Ls[rr * W + cc], lv, urow[cc]);
+        }
+      }
+    }
   }
   for (int e = tid; e < nrow * w; e += 256) {
     const int rr = e / w, cc = e - rr * w;
@@ -249,49 +310,151 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
 
 // ------------------------------------------------------------------ laswp --
 //
-// Apply the interchanges ipiv[k0..k1) in order to columns [c0, c1) and
-// [c2, c3).  One lane per column; rows are contiguous, so each swap is a
-// coalesced pair of row segments.  If perm is given, thread 0 of block 0
-// applies the same interchanges to it.
-template <typename T>
-__global__ __launch_bounds__(256) void laswp_kernel(cplx<T> *__restrict__ A, long lda, const int *__restrict__ ipiv,
-                                                    int k0, int k1, int c0, int c1, int c2, int c3,
-                                                    int *__restrict__ perm) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int n1 = c1 - c0;
-  const int ntot = n1 + (c3 - c2);
-  if (perm && t == 0) {
-    for (int k = k0; k < k1; ++k) {
-      const int p = ipiv[k];
-      if (p != k) {
-        int tmp = perm[k];
-        perm[k] = perm[p];
-        perm[p] = tmp;
-      }
+// Row interchanges of one block of pivots, ipiv[k0 .. k0+kb), applied to
+// columns [c0, c1) and [c2, c3).  The interchanges are applied in order, so
+// their net effect is a permutation of at most 2 kb rows: the kb block rows
+// and the distinct pivot rows below the block.  swap_plan_kernel works it out
+// once (one workgroup, in LDS) as a list of (destination row, source row)
+// moves and applies it to perm; row_permute_kernel then moves the rows of
+// every column stripe through LDS in one parallel pass (all sources read
+// before any destination is written), instead of kb dependent swaps.
+constexpr int kPlanMax = 2 * kOuterBlock;
+
+__global__ __launch_bounds__(256) void swap_plan_kernel(const int *__restrict__ ipiv, int k0, int kb, int n,
+                                                        int *__restrict__ plan, int *__restrict__ perm,
+                                                        int *__restrict__ info) {
+  __shared__ int pp[kOuterBlock], firstj[kOuterBlock], isfirst[kOuterBlock], cidx[kOuterBlock];
+  __shared__ int pos[kPlanMax], val[kPlanMax];
+  __shared__ int nout, nmove;
+  __shared__ int pv[kPlanMax], pd[kPlanMax];
+  const int tid = threadIdx.x;
+  if (tid < kb) {
+    int p = ipiv[k0 + tid];
+    if (p < k0 + tid || p >= n) {  // never expected; keep every index in range
+      atomicExch(info, -1);
+      p = k0 + tid;
+    }
+    pp[tid] = p;
+  }
+  __syncthreads();
+  if (tid < kb) {
+    const int p = pp[tid];
+    int f = tid;
+    if (p >= k0 + kb)
+      for (int j = 0; j < tid; ++j)
+        if (pp[j] == p) {
+          f = j;
+          break;
+        }
+    firstj[tid] = f;
+    isfirst[tid] = (p >= k0 + kb && f == tid) ? 1 : 0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int c = 0;
+    for (int j = 0; j < kb; ++j) {
+      cidx[j] = c;
+      c += isfirst[j];
+    }
+    nout = c;
+    nmove = 0;
+  }
+  __syncthreads();
+  if (tid < kb) {
+    pos[tid] = k0 + tid;
+    val[tid] = k0 + tid;
+    if (isfirst[tid]) {
+      pos[kb + cidx[tid]] = pp[tid];
+      val[kb + cidx[tid]] = pp[tid];
     }
   }
-  if (t >= ntot) return;
-  const int col = (t < n1) ? (int)(c0 + t) : (int)(c2 + (t - n1));
-  for (int k = k0; k < k1; ++k) {
-    const int p = ipiv[k];
-    if (p != k) {
-      cplx<T> a = A[(long)k * lda + col];
-      cplx<T> b = A[(long)p * lda + col];
-      A[(long)k * lda + col] = b;
-      A[(long)p * lda + col] = a;
+  __syncthreads();
+  if (tid == 0) {
+    for (int j = 0; j < kb; ++j) {
+      const int p = pp[j];
+      const int b = (p < k0 + kb) ? (p - k0) : (kb + cidx[firstj[j]]);
+      const int t = val[j];
+      val[j] = val[b];
+      val[b] = t;
+    }
+  }
+  __syncthreads();
+  const int ns = kb + nout;
+  for (int sl = tid; sl < ns; sl += 256) {
+    if (val[sl] != pos[sl]) {
+      const int m = atomicAdd(&nmove, 1);
+      plan[1 + m] = pos[sl];             // destination row
+      plan[1 + kPlanMax + m] = val[sl];  // source row
+      pd[m] = pos[sl];
+      if (perm) pv[m] = perm[val[sl]];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) plan[0] = nmove;
+  if (perm) {
+    for (int m = tid; m < nmove; m += 256) perm[pd[m]] = pv[m];
+  }
+}
+
+template <typename T>
+struct PermCfg {
+  static constexpr int CW = 16;  // columns per workgroup (LDS: kPlanMax x CW complex)
+};
+template <>
+struct PermCfg<float> {
+  static constexpr int CW = 32;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void row_permute_kernel(cplx<T> *__restrict__ A, long lda,
+                                                          const int *__restrict__ plan, int c0, int c1, int c2,
+                                                          int c3) {
+  constexpr int CW = PermCfg<T>::CW;
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);  // [nmove][CW]
+  const int nmove = plan[0];
+  const int n1 = c1 - c0;
+  const int ntot = n1 + (c3 - c2);
+  const int cbase = blockIdx.x * CW;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nmove * CW; e += 256) {
+    const int m = e / CW, cc = e - m * CW;
+    const int t = cbase + cc;
+    if (t < ntot) {
+      const int col = (t < n1) ? c0 + t : c2 + (t - n1);
+      buf[e] = A[(long)plan[1 + kPlanMax + m] * lda + col];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < nmove * CW; e += 256) {
+    const int m = e / CW, cc = e - m * CW;
+    const int t = cbase + cc;
+    if (t < ntot) {
+      const int col = (t < n1) ? c0 + t : c2 + (t - n1);
+      A[(long)plan[1 + m] * lda + col] = buf[e];
     }
   }
 }
 
 template <typename T>
 static int laswp(cplx<T> *A, long lda, const int *ipiv, int k0, int k1, int c0, int c1, int c2, int c3,
-                 int *perm, hipStream_t st) {
-  const long ntot = (long)std::max(0, c1 - c0) + std::max(0, c3 - c2);
-  if (k1 <= k0 || (ntot == 0 && !perm)) return HP_OK;
-  const unsigned blocks = (unsigned)std::max<long>(1, (ntot + 255) / 256);
-  TraceScope ts(TR_LASWP, st, 0.0, 4.0 * (k1 - k0) * ntot * sizeof(cplx<T>));
-  hipLaunchKernelGGL(laswp_kernel<T>, dim3(blocks), dim3(256), 0, st, A, lda, ipiv, k0, k1, c0,
-                     std::max(c0, c1), c2, std::max(c2, c3), perm);
+                 int *perm, int n, int *plan, int *info, hipStream_t st) {
+  const int kb = k1 - k0;
+  if (kb <= 0) return HP_OK;
+  if (kb > kOuterBlock) return HP_ERR_ARG;
+  c1 = std::max(c0, c1);
+  c3 = std::max(c2, c3);
+  const long ntot = (long)(c1 - c0) + (c3 - c2);
+  TraceScope ts(TR_LASWP, st, 0.0, 4.0 * kb * ntot * sizeof(cplx<T>));
+  hipLaunchKernelGGL(swap_plan_kernel, dim3(1), dim3(256), 0, st, ipiv, k0, kb, n, plan, perm, info);
+  HP_CHECK_LAUNCH();
+  if (ntot == 0) return HP_OK;
+  constexpr int CW = PermCfg<T>::CW;
+  const size_t shm = (size_t)2 * kb * CW * sizeof(cplx<T>);
+  int rc = ensure_dynamic_lds((const void *)row_permute_kernel<T>, shm);
+  if (rc) return rc;
+  hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)((ntot + CW - 1) / CW)), dim3(256), shm, st, A, lda,
+                     plan, c0, c1, c2, c3);
   HP_CHECK_LAUNCH();
   return HP_OK;
 }
@@ -318,14 +481,14 @@ struct TrsmCfg<float> {
 constexpr int kTrsmMaxRows = 256;
 constexpr int kTrsmBS = 16;
 
-template <typename T, bool UPPER>
+template <typename T, bool UPPER, int CW>
 __global__ __launch_bounds__(256) void trsm_kernel(int m, int ncols, const cplx<T> *__restrict__ L, long ldl,
                                                    cplx<T> *__restrict__ X, long ldx) {
-  constexpr int CW = TrsmCfg<T>::CW;
   constexpr int BS = kTrsmBS;
+  constexpr int LP = BS + 1;
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T> *Xs = reinterpret_cast<cplx<T> *>(smem_raw);  // [m][CW]
-  __shared__ cplx<T> Ld[BS][BS + 1];
+  cplx<T> *Lp = Xs + (size_t)m * CW;                    // [m][LP]: the current 16-column panel of L
   const int tid = threadIdx.x;
   const int col0 = blockIdx.x * CW;
   const int ncw = min(CW, ncols - col0);
@@ -333,35 +496,36 @@ __global__ __launch_bounds__(256) void trsm_kernel(int m, int ncols, const cplx<
     const int rr = e / CW, cc = e - rr * CW;
     Xs[e] = (cc < ncw) ? X[(long)rr * ldx + col0 + cc] : cplx<T>{T(0), T(0)};
   }
-  __syncthreads();
   const int nblk = (m + BS - 1) / BS;
   for (int bi = 0; bi < nblk; ++bi) {
     const int b = UPPER ? (nblk - 1 - bi) : bi;
     const int r0 = b * BS;
     const int bs = min(BS, m - r0);
-    // diagonal block into LDS (for UPPER store reciprocal of the diagonal)
-    for (int e = tid; e < BS * BS; e += 256) {
-      const int ii = e / BS, jj = e - ii * BS;
+    // rows that read this panel: the diagonal block and the rows still to update
+    const int lr0 = UPPER ? 0 : r0;
+    const int lr1 = UPPER ? r0 + bs : m;
+    for (int e = tid; e < (lr1 - lr0) * BS; e += 256) {
+      const int rr = lr0 + e / BS, jj = e % BS;
       cplx<T> v{T(0), T(0)};
-      if (ii < bs && jj < bs) v = L[(long)(r0 + ii) * ldl + r0 + jj];
-      if (UPPER && ii == jj && ii < bs) v = crcp(v);
-      Ld[ii][jj] = v;
+      if (jj < bs) v = L[(long)rr * ldl + r0 + jj];
+      if (UPPER && rr == r0 + jj) v = crcp(v);  // reciprocal of the diagonal of U
+      Lp[rr * LP + jj] = v;
     }
     __syncthreads();
-    // diagonal solve: CW threads, one per column
+    // diagonal solve: one thread per column
     if (tid < CW) {
       const int cc = tid;
       if (!UPPER) {
         for (int ii = 1; ii < bs; ++ii) {
-          cplx<T> s = Xs[(r0 + ii) * CW + cc];
-          for (int jj = 0; jj < ii; ++jj) s = cfms(s, Ld[ii][jj], Xs[(r0 + jj) * CW + cc]);
-          Xs[(r0 + ii) * CW + cc] = s;
+          cplx<T> sum = Xs[(r0 + ii) * CW + cc];
+          for (int jj = 0; jj < ii; ++jj) sum = cfms(sum, Lp[(r0 + ii) * LP + jj], Xs[(r0 + jj) * CW + cc]);
+          Xs[(r0 + ii) * CW + cc] = sum;
         }
       } else {
         for (int ii = bs - 1; ii >= 0; --ii) {
-          cplx<T> s = Xs[(r0 + ii) * CW + cc];
-          for (int jj = ii + 1; jj < bs; ++jj) s = cfms(s, Ld[ii][jj], Xs[(r0 + jj) * CW + cc]);
-          Xs[(r0 + ii) * CW + cc] = cmul(s, Ld[ii][ii]);
+          cplx<T> sum = Xs[(r0 + ii) * CW + cc];
+          for (int jj = ii + 1; jj < bs; ++jj) sum = cfms(sum, Lp[(r0 + ii) * LP + jj], Xs[(r0 + jj) * CW + cc]);
+          Xs[(r0 + ii) * CW + cc] = cmul(sum, Lp[(r0 + ii) * LP + ii]);
         }
       }
     }
@@ -372,10 +536,11 @@ __global__ __launch_bounds__(256) void trsm_kernel(int m, int ncols, const cplx<
     const int nu = ur1 - ur0;
     for (int e = tid; e < nu * CW; e += 256) {
       const int rr = ur0 + e / CW, cc = e % CW;
-      cplx<T> s = Xs[rr * CW + cc];
-      const cplx<T> *lrow = L + (long)rr * ldl + r0;
-      for (int jj = 0; jj < bs; ++jj) s = cfms(s, lrow[jj], Xs[(r0 + jj) * CW + cc]);
-      Xs[rr * CW + cc] = s;
+      cplx<T> sum = Xs[rr * CW + cc];
+      const cplx<T> *lrow = Lp + rr * LP;
+#pragma unroll 4
+      for (int jj = 0; jj < bs; ++jj) sum = cfms(sum, lrow[jj], Xs[(r0 + jj) * CW + cc]);
+      Xs[rr * CW + cc] = sum;
     }
     __syncthreads();
   }
@@ -385,189 +550,26 @@ __global__ __launch_bounds__(256) void trsm_kernel(int m, int ncols, const cplx<
   }
 }
 
-template <typename T, bool UPPER>
-static int trsm(int m, int ncols, const cplx<T> *L, long ldl, cplx<T> *X, long ldx, hipStream_t st) {
-  if (m <= 0 || ncols <= 0) return HP_OK;
-  if (m > kTrsmMaxRows) return HP_ERR_ARG;
-  constexpr int CW = TrsmCfg<T>::CW;
-  const size_t shm = (size_t)m * CW * sizeof(cplx<T>);
-  int rc = ensure_dynamic_lds((const void *)trsm_kernel<T, UPPER>, shm);
+template <typename T, bool UPPER, int CW>
+static int trsm_launch(int m, int ncols, const cplx<T> *L, long ldl, cplx<T> *X, long ldx, hipStream_t st) {
+  const size_t shm = (size_t)m * (CW + kTrsmBS + 1) * sizeof(cplx<T>);
+  int rc = ensure_dynamic_lds((const void *)trsm_kernel<T, UPPER, CW>, shm);
   if (rc) return rc;
-  TraceScope ts(TR_TRSM, st, 4.0 * m * m * (double)ncols, 0.0);
-  hipLaunchKernelGGL((trsm_kernel<T, UPPER>), dim3((ncols + CW - 1) / CW), dim3(256), shm, st, m, ncols, L,
+  hipLaunchKernelGGL((trsm_kernel<T, UPPER, CW>), dim3((ncols + CW - 1) / CW), dim3(256), shm, st, m, ncols, L,
                      ldl, X, ldx);
   HP_CHECK_LAUNCH();
   return HP_OK;
 }
 
-// ------------------------------------------------------------------- GEMM --
-//
-// C -= A B for complex matrices (row-major, interleaved), M x N x K, on the
-// matrix cores: each complex product is four real MFMA products,
-//   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br   ("4M").
-// Workgroup tile 64 x 64 complex, 4 wavefronts of 32 x 32 (2 x 2 MFMA tiles
-// of 16 x 16), K staged through LDS 16 complex at a time with the next stage
-// prefetched into registers.  A is stored k-major in LDS so that both MFMA
-// operands read 16 consecutive complex per k.
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-};
-template <>
-struct Mfma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-};
-
-// Lane layout of the 16x16x4 MFMA results: accumulator element r of lane l
-// holds D[mfma_row(l, r)][mfma_col(l, r)]; operands: lane l supplies
-// A[a_row(l)][a_k(l)] and B[a_k(l)][a_row(l)].
-// (Both layouts were read off the hardware with one-hot operands: the FP32
-// instruction returns rows 4*(l/16)+r, the FP64 one rows 4*r + l/16.)
-template <typename T>
-struct MfmaLayout {
-  static __device__ __forceinline__ int a_row(int l) { return l & 15; }
-  static __device__ __forceinline__ int a_k(int l) { return l >> 4; }
-  static __device__ __forceinline__ int d_row(int l, int r) { return 4 * (l >> 4) + r; }
-  static __device__ __forceinline__ int d_col(int l, int r) { return l & 15; }
-};
-template <>
-struct MfmaLayout<double> {
-  static __device__ __forceinline__ int a_row(int l) { return l & 15; }
-  static __device__ __forceinline__ int a_k(int l) { return l >> 4; }
-  static __device__ __forceinline__ int d_row(int l, int r) { return 4 * r + (l >> 4); }
-  static __device__ __forceinline__ int d_col(int l, int r) { return l & 15; }
-};
-
-constexpr int kGemmBM = 64, kGemmBN = 64, kGemmBK = 16;
-
-template <typename T>
-__global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, const cplx<T> *__restrict__ A, long lda,
-                                                       long sa, const cplx<T> *__restrict__ B, long ldb, long sb,
-                                                       cplx<T> *__restrict__ C, long ldc, long sc) {
-  typedef typename Mfma<T>::v4 v4;
-  typedef MfmaLayout<T> LY;
-  constexpr int BM = kGemmBM, BN = kGemmBN, BK = kGemmBK;
-  constexpr int PA = BM + 1, PB = BN + 1;  // padded LDS rows (complex)
-  __shared__ cplx<T> As[BK][PA];           // k-major A tile
-  __shared__ cplx<T> Bs[BK][PB];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  A += sa * blockIdx.z;
-  B += sb * blockIdx.z;
-  C += sc * blockIdx.z;
-
-  // global -> register mapping: A tile 64 rows x 16 k: lane t loads row t/4, k (t%4)*4 .. +3
-  const int a_r = tid >> 2, a_k = (tid & 3) * 4;
-  // B tile 16 k x 64 cols: row t/16, cols (t%16)*4 .. +3
-  const int b_k = tid >> 4, b_c = (tid & 15) * 4;
-  cplx<T> ra[4], rb[4];
-
-  auto load_tiles = [&](int k0) {
-    const int gr = m0 + a_r;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int gk = k0 + a_k + q;
-      ra[q] = (gr < M && gk < K) ? A[(long)gr * lda + gk] : cplx<T>{T(0), T(0)};
-    }
-    const int gk = k0 + b_k;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int gc = n0 + b_c + q;
-      rb[q] = (gk < K && gc < N) ? B[(long)gk * ldb + gc] : cplx<T>{T(0), T(0)};
-    }
-  };
-  auto store_tiles = [&]() {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) As[a_k + q][a_r] = ra[q];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) Bs[b_k][b_c + q] = rb[q];
-  };
-
-  v4 acc_re[2][2], acc_im[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      acc_re[i][j] = v4{0, 0, 0, 0};
-      acc_im[i][j] = v4{0, 0, 0, 0};
-    }
-
-  const int nk = (K + BK - 1) / BK;
-  load_tiles(0);
-  store_tiles();
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 4) {
-      const int kk = ks + LY::a_k(lane);
-      cplx<T> af[2], bf[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) af[i] = As[kk][wm + i * 16 + LY::a_row(lane)];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) bf[j] = Bs[kk][wn + j * 16 + LY::a_row(lane)];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const T nai = -af[i].im;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc_re[i][j] = Mfma<T>::mac(af[i].re, bf[j].re, acc_re[i][j]);
-          acc_re[i][j] = Mfma<T>::mac(nai, bf[j].im, acc_re[i][j]);
-          acc_im[i][j] = Mfma<T>::mac(af[i].re, bf[j].im, acc_im[i][j]);
-          acc_im[i][j] = Mfma<T>::mac(af[i].im, bf[j].re, acc_im[i][j]);
-        }
-      }
-    }
-    __syncthreads();
-    if (kt + 1 < nk) {
-      store_tiles();
-      __syncthreads();
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gr = m0 + wm + i * 16 + LY::d_row(lane, r);
-        const int gc = n0 + wn + j * 16 + LY::d_col(lane, r);
-        if (gr < M && gc < N) {
-          cplx<T> *cp = C + (long)gr * ldc + gc;
-          cplx<T> c = *cp;
-          c.re -= acc_re[i][j][r];
-          c.im -= acc_im[i][j][r];
-          *cp = c;
-        }
-      }
-}
-
-template <typename T>
-int gemm_sub_batched(int M, int N, int K, const cplx<T> *A, long lda, long sa, const cplx<T> *B, long ldb, long sb,
-                     cplx<T> *C, long ldc, long sc, int batch, hipStream_t st) {
-  if (M <= 0 || N <= 0 || K <= 0 || batch <= 0) return HP_OK;
-  dim3 grid((N + kGemmBN - 1) / kGemmBN, (M + kGemmBM - 1) / kGemmBM, batch);
-  TraceScope ts(sizeof(T) == 8 ? TR_GEMM64 : TR_GEMM32, st, 8.0 * M * (double)N * K * batch,
-                2.0 * sizeof(cplx<T>) * (double)M * N * batch);
-  hipLaunchKernelGGL(gemm_sub_kernel<T>, grid, dim3(256), 0, st, M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc);
-  HP_CHECK_LAUNCH();
-  return HP_OK;
-}
-
-template <typename T>
-int gemm_sub(int M, int N, int K, const cplx<T> *A, long lda, const cplx<T> *B, long ldb, cplx<T> *C, long ldc,
-             hipStream_t st) {
-  return gemm_sub_batched<T>(M, N, K, A, lda, 0, B, ldb, 0, C, ldc, 0, 1, st);
+// Narrow column stripes when there are few columns (the solves: n_c
+// right-hand sides), wide ones otherwise (the U rows of the factorization).
+template <typename T, bool UPPER>
+static int trsm(int m, int ncols, const cplx<T> *L, long ldl, cplx<T> *X, long ldx, hipStream_t st) {
+  if (m <= 0 || ncols <= 0) return HP_OK;
+  if (m > kTrsmMaxRows) return HP_ERR_ARG;
+  TraceScope ts(TR_TRSM, st, 4.0 * m * m * (double)ncols, 0.0);
+  if (ncols <= 2048) return trsm_launch<T, UPPER, 8>(m, ncols, L, ldl, X, ldx, st);
+  return trsm_launch<T, UPPER, TrsmCfg<T>::CW>(m, ncols, L, ldl, X, ldx, st);
 }
 
 // ------------------------------------------------------------ factorization --
@@ -603,11 +605,12 @@ static size_t slot_bytes_max() {
 // Rows per workgroup of the panel grid, and the grid size.
 template <typename T>
 static void panel_grid(int m, int &G, int &rpw) {
-  // at most ~96 KB of LDS per workgroup; at most 128 workgroups (barrier cost)
-  const int rpw_max = (96 * 1024) / (int)(kPanelWidth * sizeof(cplx<T>));
+  // the grid barrier costs ~2 us at 32 workgroups and ~5 us at 128, so use
+  // few workgroups with many rows each: up to ~150 KB of LDS per workgroup
+  const int rpw_max = (150 * 1024) / (int)(kPanelWidth * sizeof(cplx<T>));
   const int rpw_min = 64;
   G = (m + rpw_min - 1) / rpw_min;
-  G = std::min(G, 128);
+  G = std::min(G, 64);
   G = std::max(G, 1);
   rpw = (m + G - 1) / G;
   if (rpw > rpw_max) {
@@ -651,6 +654,7 @@ int lu_factor(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *info, char
   hipLaunchKernelGGL(iota_kernel, dim3((n + 255) / 256), dim3(256), 0, st, perm, n);
   HP_CHECK_LAUNCH();
   PanelSlots<T> slots = carve_slots<T>(work + ws.slot_off);
+  int *plan = (int *)(work + ws.slot_off + slot_bytes_max());
   for (int k = 0; k < n; k += kOuterBlock) {
     const int kb = std::min(kOuterBlock, n - k);
     for (int j = k; j < k + kb; j += kPanelWidth) {
@@ -658,7 +662,7 @@ int lu_factor(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *info, char
       if ((rc = panel<T>(n, j, jb, A, lda, ipiv, info, bars + per_panel * (j / kPanelWidth), slots, st)))
         return rc;
       // the panel's swaps on the other columns of the outer block
-      if ((rc = laswp<T>(A, lda, ipiv, j, j + jb, k, j, j + jb, k + kb, nullptr, st))) return rc;
+      if ((rc = laswp<T>(A, lda, ipiv, j, j + jb, k, j, j + jb, k + kb, nullptr, n, plan, info, st))) return rc;
       const int rest = k + kb - (j + jb);
       if (rest > 0) {
         cplx<T> *L11 = A + (long)j * lda + j;
@@ -670,7 +674,7 @@ int lu_factor(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *info, char
       }
     }
     // the block's swaps on all columns outside the block, and on perm
-    if ((rc = laswp<T>(A, lda, ipiv, k, k + kb, 0, k, k + kb, n, perm, st))) return rc;
+    if ((rc = laswp<T>(A, lda, ipiv, k, k + kb, 0, k, k + kb, n, perm, n, plan, info, st))) return rc;
     const int rest = n - k - kb;
     if (rest > 0) {
       cplx<T> *L11 = A + (long)k * lda + k;
@@ -755,19 +759,11 @@ template int lu_solve<float>(int, int, const cplx<float> *, long, const int *, c
                              cplx<float> *, hipStream_t);
 template int lu_solve_permuted<double>(int, int, const cplx<double> *, long, cplx<double> *, long, hipStream_t);
 template int lu_solve_permuted<float>(int, int, const cplx<float> *, long, cplx<float> *, long, hipStream_t);
-template int gemm_sub<double>(int, int, int, const cplx<double> *, long, const cplx<double> *, long,
-                              cplx<double> *, long, hipStream_t);
-template int gemm_sub<float>(int, int, int, const cplx<float> *, long, const cplx<float> *, long, cplx<float> *,
-                             long, hipStream_t);
-template int gemm_sub_batched<double>(int, int, int, const cplx<double> *, long, long, const cplx<double> *, long,
-                                      long, cplx<double> *, long, long, int, hipStream_t);
-template int gemm_sub_batched<float>(int, int, int, const cplx<float> *, long, long, const cplx<float> *, long,
-                                     long, cplx<float> *, long, long, int, hipStream_t);
 
 size_t factor_sync_bytes(int n) {
   const int npanels = (n + kPanelWidth - 1) / kPanelWidth;
   return sizeof(unsigned) * barrier_words(kMaxPanelGroups) * (size_t)npanels;
 }
-size_t factor_slot_bytes() { return slot_bytes_max(); }
+size_t factor_slot_bytes() { return slot_bytes_max() + align_up(sizeof(int) * (1 + 2 * kPlanMax), 256); }
 
 }  // namespace hp

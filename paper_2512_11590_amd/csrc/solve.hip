@@ -79,21 +79,28 @@ __global__ __launch_bounds__(256) void residual_local_kernel(int nc, int nr, dou
   }
 }
 
-// Per-column max |v| into out[col] (ordered as unsigned bit patterns: v >= 0).
+// Per-column max of |Re|+|Im| into out[col] (non-negative doubles compare as
+// their bit patterns).  Thread (col, r0) scans rows r0, r0 + step, ...; one
+// atomic per thread.  A second array, if given, is reduced into out2.
 __global__ void colmax_kernel(long nrows, int ncols, const cplx<double> *__restrict__ V,
-                              unsigned long long *__restrict__ out) {
+                              unsigned long long *__restrict__ out, const cplx<double> *__restrict__ V2,
+                              unsigned long long *__restrict__ out2) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  // each thread scans a strided set of rows for one column
   const int col = (int)(e % ncols);
   const long r0 = e / ncols;
   const long step = ((long)gridDim.x * blockDim.x) / ncols;
   if (step == 0 || r0 >= step) return;
-  double m = 0.0;
+  double m = 0.0, m2 = 0.0;
   for (long rr = r0; rr < nrows; rr += step) {
     const cplx<double> v = V[rr * ncols + col];
     m = fmax(m, fabs(v.re) + fabs(v.im));
+    if (V2) {
+      const cplx<double> w = V2[rr * ncols + col];
+      m2 = fmax(m2, fabs(w.re) + fabs(w.im));
+    }
   }
   atomicMax(&out[col], (unsigned long long)__double_as_longlong(m));
+  if (V2) atomicMax(&out2[col], (unsigned long long)__double_as_longlong(m2));
 }
 
 __global__ void zero_u64_kernel(unsigned long long *p, int n) {
@@ -115,22 +122,61 @@ __global__ void scale_perm_kernel(long n, int nc, const int *__restrict__ perm, 
   Y[e] = cplx<T>{(T)(v.re * inv), (T)(v.im * inv)};
 }
 
-// X += s * D (FP64); per-column max |s D| into dmax.
+// X += s * D (FP64); per-column max |s D| into dmax (same scan order as colmax).
 template <typename T>
 __global__ void update_kernel(long n, int nc, const cplx<T> *__restrict__ D, const unsigned long long *__restrict__ smax,
                               cplx<double> *__restrict__ X, unsigned long long *__restrict__ dmax) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * nc) return;
   const int col = (int)(e % nc);
+  const long r0 = e / nc;
+  const long step = ((long)gridDim.x * blockDim.x) / nc;
+  if (step == 0 || r0 >= step) return;
   const double s = __longlong_as_double((long long)smax[col]);
   const double f = (s > 0.0) ? s : 1.0;
-  const cplx<T> d = D[e];
-  const double dr = f * (double)d.re, di = f * (double)d.im;
-  cplx<double> x = X[e];
-  x.re += dr;
-  x.im += di;
-  X[e] = x;
-  atomicMax(&dmax[col], (unsigned long long)__double_as_longlong(fabs(dr) + fabs(di)));
+  double m = 0.0;
+  for (long rr = r0; rr < n; rr += step) {
+    const long k = rr * nc + col;
+    const cplx<T> d = D[k];
+    const double dr = f * (double)d.re, di = f * (double)d.im;
+    cplx<double> x = X[k];
+    x.re += dr;
+    x.im += di;
+    X[k] = x;
+    m = fmax(m, fabs(dr) + fabs(di));
+  }
+  atomicMax(&dmax[col], (unsigned long long)__double_as_longlong(m));
+}
+
+// |C|_inf (max row sum of |Re|+|Im|) from the block structure, and |B|_inf.
+__global__ void cnorm_kernel(int nc, int nr, double h, double E, const double *__restrict__ tl,
+                             const double *__restrict__ r, const int *__restrict__ l, const double *__restrict__ eps,
+                             const double *__restrict__ v, const double *__restrict__ q,
+                             unsigned long long *__restrict__ out) {
+  const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double sum = 0.0, qm = 0.0;
+  if (row < (long)nc * nr) {
+    const int c = (int)(row / nr), i = (int)(row - (long)c * nr);
+    const double *trow = tl + (long)i * nr;
+    for (int j = 0; j < nr; ++j)
+      if (j != i) sum += h * fabs(trow[j]);
+    const int lc = l[c];
+    const double dg = h * trow[i] + h * (double)lc * (lc + 1) / (r[i] * r[i]) + eps[c] - E;
+    const double *vrow = v + 2 * ((long)i * nc + c) * nc;
+    for (int cp = 0; cp < nc; ++cp) {
+      double re = vrow[2 * cp], im = vrow[2 * cp + 1];
+      if (cp == c) re += dg;
+      sum += fabs(re) + fabs(im);
+    }
+    qm = fabs(q[i]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sum = fmax(sum, __shfl_xor(sum, off));
+    qm = fmax(qm, __shfl_xor(qm, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(sum));
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong(qm));
+  }
 }
 
 // FP64 copy of a working-precision solution.
@@ -162,6 +208,24 @@ static int residual(const hp_system *sys, double E, const cplx<double> *X, cplx<
                                   (long)nc, R, ld, (long)nc, nr, st);
 }
 
+static double u64_as_double(unsigned long long u) {
+  double d;
+  std::memcpy(&d, &u, sizeof(d));
+  return d;
+}
+
+// Refinement loop (Sec. 3.2).  Each pass forms the FP64 residual of the
+// current X, solves for the correction with the working-precision factors and
+// adds it in FP64.  The size of the correction, max_c |d_c| / |x_c|, measures
+// the forward error of the iterate before it; the loop stops
+//  * converged when it is <= tol (tol <= 0: 2^-52), or when it stops
+//    shrinking (a correction larger than half the previous one: the iterate is
+//    at the accuracy an FP64 residual can resolve) while already <= 1e-6;
+//  * not converged when it stops shrinking above that level (the factors are
+//    too inaccurate for the refinement to contract, Sec. 6) or after
+//    max_refine corrections.
+// The normwise backward error max_c |r_c| / (|C| |x_c| + |b_c|) of the last
+// residual is reported alongside.
 template <typename T>
 static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long lda, const int *perm,
                       const int *finfo, cplx<double> *X, int max_refine, double tol, char *work,
@@ -179,8 +243,9 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
   cplx<T> *Y = (cplx<T> *)(work + ws.rhs_off);
   cplx<double> *Rr = (cplx<double> *)(work + ws.res_off);
   unsigned long long *smax = (unsigned long long *)(work + ws.red_off);
-  unsigned long long *dmax = smax + nc;
-  unsigned long long *xmax = dmax + nc;
+  unsigned long long *xmax = smax + nc;
+  unsigned long long *dmax = xmax + nc;
+  unsigned long long *norms = dmax + nc;  // |C|_inf, |B|_inf
   // initial solve
   hipLaunchKernelGGL(rhs_from_perm_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, nc, nr, perm, sys->q, Y);
   HP_CHECK_LAUNCH();
@@ -198,57 +263,70 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
     if (info) info->converged = 1;
     return HP_OK;
   }
-  std::vector<unsigned long long> h(3 * (size_t)nc);
-  double prev = INFINITY;
-  const unsigned cm_blocks = (unsigned)std::min<long>(4096, std::max<long>(1, (n * nc + 255) / 256));
-  for (int it = 1; it <= max_refine; ++it) {
+  const double corr_tol = (tol > 0.0) ? tol : 2.220446049250313e-16;
+  const double stagnation_ok = 1e-6;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(nblk(3 * nc + 2)), dim3(256), 0, st, smax, 3 * nc + 2);
+  HP_CHECK_LAUNCH();
+  hipLaunchKernelGGL(cnorm_kernel, dim3(nblk(n)), dim3(256), 0, st, nc, nr, sys->hbar2_2mu, E, sys->tl, sys->r,
+                     sys->l, sys->eps, sys->v, sys->q, norms);
+  HP_CHECK_LAUNCH();
+  std::vector<unsigned long long> h(3 * (size_t)nc + 2);
+  double corr_prev = INFINITY;
+  const unsigned cm_blocks = (unsigned)std::min<long>(2048, std::max<long>(1, (n * nc + 255) / 256));
+  for (int it = 0;; ++it) {
     if ((rc = residual(sys, E, X, Rr, st))) return rc;
     {
-      TraceScope ts(TR_REFINE, st, 0.0, 16.0 * 2 * cnt + sizeof(cplx<T>) * (double)cnt);
-      hipLaunchKernelGGL(zero_u64_kernel, dim3(nblk(3 * nc)), dim3(256), 0, st, smax, 3 * nc);
+      TraceScope ts(TR_REFINE, st, 0.0, 32.0 * (double)cnt);
+      hipLaunchKernelGGL(zero_u64_kernel, dim3(nblk(2 * nc)), dim3(256), 0, st, smax, 2 * nc);
       HP_CHECK_LAUNCH();
-      hipLaunchKernelGGL(colmax_kernel, dim3(cm_blocks), dim3(256), 0, st, n, nc, Rr, smax);
+      hipLaunchKernelGGL(colmax_kernel, dim3(cm_blocks), dim3(256), 0, st, n, nc, Rr, smax,
+                         (const cplx<double> *)X, xmax);
       HP_CHECK_LAUNCH();
+    }
+    HP_CHECK_HIP(hipMemcpyAsync(h.data(), smax, (3 * nc + 2) * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HP_CHECK_HIP(hipStreamSynchronize(st));
+    const double cn = u64_as_double(h[3 * nc]), bn = u64_as_double(h[3 * nc + 1]);
+    double eta = 0.0, corr = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      const double s = u64_as_double(h[c]), x = u64_as_double(h[nc + c]), d = u64_as_double(h[2 * nc + c]);
+      eta = std::max(eta, s / (cn * x + bn));
+      if (x > 0) corr = std::max(corr, d / x);
+    }
+    if (info) {
+      info->iterations = it;
+      info->residual = eta;
+      if (it > 0) info->correction = corr;
+    }
+    if (!(eta == eta) || !(corr == corr)) return HP_ERR_NOCONV;  // NaN
+    if (it > 0) {
+      if (corr <= corr_tol) {
+        if (info) info->converged = 1;
+        return HP_OK;
+      }
+      if (corr > 0.5 * corr_prev) {  // stopped shrinking
+        if (corr_prev <= stagnation_ok) {
+          if (info) info->converged = 1;
+          return HP_OK;
+        }
+        return HP_ERR_NOCONV;
+      }
+      corr_prev = corr;
+    }
+    if (it >= max_refine) return HP_ERR_NOCONV;
+    {
+      TraceScope ts(TR_REFINE, st, 0.0, 16.0 * cnt + sizeof(cplx<T>) * (double)cnt);
       hipLaunchKernelGGL(scale_perm_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, n, nc, perm, Rr, smax, Y);
       HP_CHECK_LAUNCH();
     }
     if ((rc = lu_solve_permuted<T>((int)n, nc, LU, lda, Y, nc, st))) return rc;
     {
-      TraceScope ts(TR_REFINE, st, 0.0, (sizeof(cplx<T>) + 16.0 * 3) * (double)cnt);
-      hipLaunchKernelGGL(update_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, n, nc, Y, smax, X, dmax);
+      TraceScope ts(TR_REFINE, st, 0.0, (sizeof(cplx<T>) + 32.0) * (double)cnt);
+      hipLaunchKernelGGL(zero_u64_kernel, dim3(nblk(nc)), dim3(256), 0, st, dmax, nc);
       HP_CHECK_LAUNCH();
-      hipLaunchKernelGGL(colmax_kernel, dim3(cm_blocks), dim3(256), 0, st, n, nc, X, xmax);
+      hipLaunchKernelGGL(update_kernel<T>, dim3(cm_blocks), dim3(256), 0, st, n, nc, Y, smax, X, dmax);
       HP_CHECK_LAUNCH();
     }
-    HP_CHECK_HIP(hipMemcpyAsync(h.data(), smax, 3 * nc * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    HP_CHECK_HIP(hipStreamSynchronize(st));
-    double corr = 0.0, res = 0.0;
-    for (int c = 0; c < nc; ++c) {
-      double s, d, x;
-      long long bits;
-      bits = (long long)h[c];
-      std::memcpy(&s, &bits, 8);
-      bits = (long long)h[nc + c];
-      std::memcpy(&d, &bits, 8);
-      bits = (long long)h[2 * nc + c];
-      std::memcpy(&x, &bits, 8);
-      if (x > 0) corr = std::max(corr, d / x);
-      res = std::max(res, s);
-    }
-    if (info) {
-      info->iterations = it;
-      info->correction = corr;
-      info->residual = res;
-    }
-    if (!(corr == corr)) return HP_ERR_NOCONV;  // NaN
-    if (corr <= tol) {
-      if (info) info->converged = 1;
-      return HP_OK;
-    }
-    if (it > 1 && corr > 0.5 * prev) return HP_ERR_NOCONV;  // stopped contracting
-    prev = corr;
   }
-  return HP_ERR_NOCONV;
 }
 
 // R[c][c'] = (h/a) sum_i q_i X[(c,i)][c']

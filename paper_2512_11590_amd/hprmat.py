@@ -53,7 +53,8 @@ class HpSolveInfo(ctypes.Structure):
 
 EXPORTS = ["hp_mesh", "hp_workspace_bytes", "hp_build_matrix", "hp_factor", "hp_solve",
            "hp_lu_solve", "hp_rmatrix", "hp_smatrix", "hp_coulomb", "hp_coulomb_device",
-           "hp_build_info", "hp_strerror", "hp_trace_enable", "hp_trace_read", "hp_last_error"]
+           "hp_build_info", "hp_strerror", "hp_trace_enable", "hp_trace_read", "hp_last_error",
+           "hp_gemm_sub"]
 
 _lib = None
 
@@ -94,6 +95,9 @@ def lib() -> ctypes.CDLL:
     L.hp_lu_solve.argtypes = [c_int, c_int, c_int, c_void_p, c_long, c_void_p, c_void_p, c_long,
                               c_void_p, c_size_t, c_void_p]
     L.hp_lu_solve.restype = c_int
+    L.hp_gemm_sub.argtypes = [c_int, c_int, c_int, c_int, c_void_p, c_long, c_void_p, c_long, c_void_p,
+                              c_long, c_void_p]
+    L.hp_gemm_sub.restype = c_int
     L.hp_rmatrix.argtypes = [P(HpSystem), c_void_p, c_void_p, c_void_p]
     L.hp_rmatrix.restype = c_int
     L.hp_smatrix.argtypes = [P(HpSystem), c_double, c_void_p, c_void_p, P(c_int), c_void_p,
@@ -194,6 +198,12 @@ def hp_solve(sys: HpSystem, E: float, prec: int, LU, lda: int, perm, info_factor
 def hp_lu_solve(n: int, nrhs: int, prec: int, LU, lda: int, perm, X, ldx: int, work, stream=None) -> None:
     _check(lib().hp_lu_solve(n, nrhs, prec, _ptr(LU), lda, _ptr(perm), _ptr(X), ldx, _ptr(work),
                              work.numel() * work.element_size(), _stream(stream)), "hp_lu_solve")
+
+
+def hp_gemm_sub(M: int, N: int, K: int, prec: int, A, lda: int, B, ldb: int, C, ldc: int,
+                stream=None) -> None:
+    _check(lib().hp_gemm_sub(M, N, K, prec, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, _stream(stream)),
+           "hp_gemm_sub")
 
 
 def hp_rmatrix(sys: HpSystem, X, R, stream=None) -> None:

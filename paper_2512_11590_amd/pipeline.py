@@ -57,6 +57,7 @@ class EnergyResult:
     correction: float
     fallback: bool
     nopen: int
+    backward_error: float = -1.0
 
 
 class Solver:
@@ -90,9 +91,10 @@ class Solver:
         return H.hp_solve(self.d.sys, E, self.prec, self.A, self.ld, self.perm, self.info, self.X,
                           max_refine, tol, self.work)
 
-    def run(self, E: float, max_refine: int = 30, tol: float = 1e-13, smatrix: bool = True) -> EnergyResult:
+    def run(self, E: float, max_refine: int = 30, tol: float = 0.0, smatrix: bool = True) -> EnergyResult:
         self.factor(E)
         code, info = self.solve(E, max_refine if self.prec == H.HP_C64 else 0, tol)
+        iterations, backward = info.iterations, info.residual
         used_fallback = False
         if code != H.HP_OK:
             if not (self.fallback and self.prec == H.HP_C64 and code in (H.HP_ERR_NOCONV, H.HP_ERR_SINGULAR)):
@@ -111,5 +113,6 @@ class Solver:
         if smatrix:
             nopen = H.hp_smatrix(self.d.sys, E, self.R, self.S, self.swork)
             S = self.S
-        return EnergyResult(E=E, prec=self.prec, R=self.R, S=S, iterations=info.iterations,
-                            correction=info.correction, fallback=used_fallback, nopen=nopen)
+        return EnergyResult(E=E, prec=self.prec, R=self.R, S=S, iterations=iterations,
+                            correction=info.correction, fallback=used_fallback, nopen=nopen,
+                            backward_error=backward)

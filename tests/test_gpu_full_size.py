@@ -3,8 +3,14 @@
 The oracle results in tests/golden/{mid,large}_oracle.npz are written by
 tests/golden/make_golden.py, which calls only oracle/ and workload/.
 
-Tolerances (normwise relative): S 1e-10 after refinement (FP32 LU + FP64
-refinement, and FP64 LU); R 1e-10; cross sections without refinement 1e-3.
+Tolerances (normwise relative):
+  * S: 1e-10 after refinement (FP32 LU + FP64 refinement, and FP64 LU);
+  * R: max(1e-10, 10 x the FP64 floor).  These systems are ill-conditioned
+    (R-matrix poles crowd the real axis), so FP64 arithmetic itself fixes R
+    only to a measured floor: the oracle's own result for the same system with
+    its channels numbered in reverse order differs from the first by
+    Rfloor_e (stored with the golden values);
+  * cross sections without refinement: 1e-3.
 Properties that hold at any size are checked too: S symmetric (C = C^T),
 |S| contracting for the absorptive potential.
 """
@@ -69,10 +75,14 @@ def test_full_size_against_oracle(mods, config, prec):
         R = res.R.cpu().numpy()
         S = res.S.cpu().numpy()
         er, es = relerr(R, g[f"R_{e}"]), relerr(S, g[f"S_{e}"])
-        print(f"   R err {er:.2e}  S err {es:.2e}  refinement {res.iterations} fallback {res.fallback}",
-              flush=True)
+        rfloor = float(g[f"Rfloor_{e}"]) if f"Rfloor_{e}" in g.files else float("nan")
+        sfloor = float(g[f"Sfloor_{e}"]) if f"Sfloor_{e}" in g.files else float("nan")
+        tol_r = max(1e-10, 10 * rfloor) if rfloor == rfloor else 1e-10
+        print(f"   R err {er:.2e} (FP64 floor {rfloor:.1e}, tol {tol_r:.1e})  S err {es:.2e} "
+              f"(floor {sfloor:.1e})  refinement {res.iterations} backward error {res.backward_error:.1e} "
+              f"fallback {res.fallback}", flush=True)
         assert es < 1e-10
-        assert er < 1e-10
+        assert er < tol_r
         assert np.max(np.abs(S - S.T)) < 1e-9
         assert np.linalg.norm(S, 2) <= 1.0 + 1e-9
 
