@@ -177,9 +177,11 @@ int hp_coulomb_device(int nch, const int *l, const double *eta, const double *rh
 
 /* ---- instrumentation ---------------------------------------------------- */
 
-/* Per-stage device timers.  hp_trace_enable(1) clears the record and starts
- * bracketing every kernel launch with HIP events on its stream;
- * hp_trace_enable(0) stops.  hp_trace_read() waits for the recorded events,
+/* Per-stage device timers.  hp_trace_enable(mask) clears the record and starts
+ * bracketing the kernel launches of the selected stages with HIP events on
+ * their stream: mask < 0 selects every stage, otherwise bit s selects stage s
+ * (the order of the names below: assemble, panel, laswp, trsm, gemm_c128,
+ * gemm_c64, residual, refine, rmatrix, smatrix); hp_trace_enable(0) stops.  hp_trace_read() waits for the recorded events,
  * fills out[0 .. HP_TRACE_STAGES-1] (host array) with, per stage, the launch
  * count, summed kernel time (ms) and summed algorithmic flops and bytes of
  * those launches, clears the record and returns HP_TRACE_STAGES.
@@ -192,7 +194,7 @@ typedef struct hp_trace_stat {
   double flops;
   double bytes;
 } hp_trace_stat;
-int hp_trace_enable(int on);
+int hp_trace_enable(int mask);
 int hp_trace_read(hp_trace_stat *out, int max_stats);
 
 /* Static description of the build: string owned by the library. */

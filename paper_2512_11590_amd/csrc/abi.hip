@@ -57,6 +57,9 @@ Workspace plan_workspace(int n, int nrhs, int prec) {
   w.red_off = off;
   w.red_bytes = align_up((size_t)std::max(nrhs, 1) * 64 + 4096, A);
   off += w.red_bytes;
+  w.inv_off = off;
+  w.inv_bytes = align_up(inverse_bytes(n, prec), A);
+  off += w.inv_bytes;
   w.total = off;
   return w;
 }
@@ -92,9 +95,9 @@ extern "C" int hp_lu_solve(int n, int nrhs, int prec, const void *LU, long lda, 
   char *w = (char *)work;
   if (prec == HP_C128)
     return lu_solve<double>(n, nrhs, (const cplx<double> *)LU, lda, perm, (cplx<double> *)X, ldx,
-                            (cplx<double> *)(w + ws.rhs_off), st);
+                            (cplx<double> *)(w + ws.rhs_off), nullptr, st);
   return lu_solve<float>(n, nrhs, (const cplx<float> *)LU, lda, perm, (cplx<float> *)X, ldx,
-                         (cplx<float> *)(w + ws.rhs_off), st);
+                         (cplx<float> *)(w + ws.rhs_off), (cplx<float> *)(w + ws.inv_off), st);
 }
 
 extern "C" const char *hp_strerror(int code) {

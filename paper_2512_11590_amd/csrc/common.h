@@ -88,6 +88,7 @@ struct Workspace {
   size_t res_off, res_bytes;        // FP64 residual (n x nrhs)
   size_t aux_off, aux_bytes;        // nrhs x nrhs complex128 (collision-matrix solve)
   size_t red_off, red_bytes;        // reductions, Coulomb values, small index arrays
+  size_t inv_off, inv_bytes;        // inverted diagonal blocks of an FP32 factor
   size_t total;
 };
 Workspace plan_workspace(int n, int nrhs, int prec);
@@ -96,11 +97,18 @@ Workspace plan_workspace(int n, int nrhs, int prec);
 template <typename T>
 int lu_factor(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *info, char *work,
               const Workspace &ws, hipStream_t st);
+// `inv`: room for the inverted diagonal blocks (FP32 factors; nullptr selects
+// substitution, the only FP64 mode).
 template <typename T>
 int lu_solve(int n, int nrhs, const cplx<T> *LU, long lda, const int *perm, cplx<T> *X, long ldx,
-             cplx<T> *tmp, hipStream_t st);
+             cplx<T> *tmp, cplx<T> *inv, hipStream_t st);
 template <typename T>
-int lu_solve_permuted(int n, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, long ldy, hipStream_t st);
+int lu_solve_permuted(int n, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, long ldy, const cplx<T> *inv,
+                      hipStream_t st);
+// Inverts the diagonal blocks of an FP32 factor into `inv` (inverse_bytes(n, HP_C64) bytes).
+template <typename T>
+int solve_inverses(int n, const cplx<T> *LU, long lda, cplx<T> *inv, hipStream_t st);
+size_t inverse_bytes(int n, int prec);
 template <typename T>
 int gemm_sub(int M, int N, int K, const cplx<T> *A, long lda, const cplx<T> *B, long ldb, cplx<T> *C,
              long ldc, hipStream_t st);

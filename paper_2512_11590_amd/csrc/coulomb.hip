@@ -257,7 +257,7 @@ extern "C" int hp_smatrix(const hp_system *sys, double E, const double *R, doubl
   HP_CHECK_LAUNCH();
   int rc;
   if ((rc = lu_factor<double>(nc, ZO, nc, ipiv, perm, finfo, w, ws, st))) return rc;
-  if ((rc = lu_solve<double>(nc, nc, ZO, nc, perm, (cplx<double> *)S, nc, tmp, st))) return rc;
+  if ((rc = lu_solve<double>(nc, nc, ZO, nc, perm, (cplx<double> *)S, nc, tmp, nullptr, st))) return rc;
   int hinfo = 0;
   std::vector<int> hstat(nc);
   HP_CHECK_HIP(hipMemcpyAsync(&hinfo, finfo, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 
 namespace hp {
 
@@ -106,33 +107,28 @@ __device__ __forceinline__ void block_argmax(T &v, int &r, T *sv, int *sr) {
   for (int w = 1; w < 4; ++w) argmax_combine(v, r, sv[w], sr[w]);
 }
 
-// Two-level grid barrier for a cooperative launch.  Workgroups arrive on one
-// of several group counters (spread over separate cache lines), the last
-// arrival of each group bumps the top counter, and everyone waits on the top
-// counter.  The wait is bounded: on expiry it records -1 in *flag and stops
-// waiting, and later barriers return at once, so the grid always drains.
-constexpr int kBarGroup = 16;     // workgroups per group counter
-constexpr int kBarStride = 32;    // unsigned words between counters (128 B)
+// Grid synchronisation of the cooperative panel grid without atomics: every
+// workgroup owns one flag word and publishes the epoch it has reached there
+// (after its slot data is globally visible); a workgroup waits by polling all
+// the flags, one lane per flag.  The wait is bounded: on expiry it records -1
+// in *flag and stops waiting, and later waits return at once, so the grid
+// always drains.
+constexpr int kBarStride = 1;
 
-// Arrival: every lane's agent-scope stores must have completed first.
 __device__ __forceinline__ void grid_arrive(unsigned *bar, unsigned epoch) {
+  // every lane's agent-scope stores must have completed before the flag moves
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned g = blockIdx.x / kBarGroup;
-    const unsigned gsize = min((unsigned)kBarGroup, gridDim.x - g * kBarGroup);
-    unsigned *grp = bar + (g + 1) * kBarStride;
-    const unsigned old = atomicAdd(grp, 1u);
-    if (old + 1 == gsize * epoch) atomicAdd(bar, 1u);
-  }
+  if (threadIdx.x == 0)
+    __hip_atomic_store(bar + blockIdx.x, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wait until every workgroup has arrived at `epoch` (bounded, see above).
 __device__ __forceinline__ void grid_wait(unsigned *bar, unsigned ngroups, unsigned epoch, int *flag) {
-  if (threadIdx.x == 0) {
+  (void)ngroups;
+  for (unsigned g = threadIdx.x; g < gridDim.x; g += blockDim.x) {
     unsigned spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < ngroups * epoch) {
+    while (__hip_atomic_load(bar + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
       __builtin_amdgcn_s_sleep(1);
       if (((++spins) & 1023u) == 0) {
         if (spins > kSpinLimit ||
@@ -146,7 +142,7 @@ __device__ __forceinline__ void grid_wait(unsigned *bar, unsigned ngroups, unsig
   __syncthreads();
 }
 
-static size_t barrier_words(int G) { return (size_t)(((G + kBarGroup - 1) / kBarGroup) + 1) * kBarStride; }
+static size_t barrier_words(int G) { return (size_t)G * kBarStride; }
 
 // ------------------------------------------------------------ panel (LU) --
 //
@@ -179,7 +175,7 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
   __shared__ int red_r[4];
   constexpr int W = kPanelWidth;
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
-  const unsigned ngroups = (G + kBarGroup - 1) / kBarGroup;
+  const unsigned ngroups = (unsigned)G;
   const int rbeg = j0 + g * rpw;
   const int rend = min(n, rbeg + rpw);
   const int nrow = max(0, rend - rbeg);
@@ -572,6 +568,142 @@ static int trsm(int m, int ncols, const cplx<T> *L, long ldl, cplx<T> *X, long l
   return trsm_launch<T, UPPER, TrsmCfg<T>::CW>(m, ncols, L, ldl, X, ldx, st);
 }
 
+// ------------------------------------------- inverted diagonal blocks --
+// The FP32 factor is applied many times per energy (once per refinement
+// step).  Its triangular solves are restructured for that reuse: the
+// kInvBlock x kInvBlock diagonal blocks of L and U are inverted once, and each
+// block step of a solve becomes a small in-place product with the inverse
+// followed by the trailing GEMM, instead of a latency-bound substitution.
+// The refinement corrects the slightly larger rounding error of the products.
+// FP64 keeps the substitution (its single solve sets the accuracy).
+constexpr int kInvBlock = 128;
+constexpr int kInvLd = kInvBlock + 1;  // LDS row stride (complex elements)
+
+// One workgroup per diagonal block: blockIdx.y == 0 inverts the unit-lower
+// block of L, blockIdx.y == 1 the upper block of U.  Rows of the inverse are
+// produced in substitution order, all columns of a row at once (two threads
+// per column, one per parity of the summation index).  Output: dense
+// kInvBlock x kInvBlock row-major blocks, lower inverses first; entries outside
+// a ragged last block are zero.
+template <typename T>
+__global__ __launch_bounds__(256) void tri_inverse_kernel(int n, const cplx<T> *__restrict__ LU, long lda,
+                                                          cplx<T> *__restrict__ Inv) {
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T> *Xs = reinterpret_cast<cplx<T> *>(smem_raw);  // [kInvBlock][kInvLd]
+  cplx<T> *Tr = Xs + kInvBlock * kInvLd;                // [2][kInvBlock]: rows of the factor
+  const bool upper = blockIdx.y != 0;
+  const int b0 = blockIdx.x * kInvBlock;
+  const int bs = min(kInvBlock, n - b0);
+  const cplx<T> *Tb = LU + (long)b0 * lda + b0;
+  const int tid = threadIdx.x;
+  const int j = tid >> 1, half = tid & 1;
+  const cplx<T> zero{T(0), T(0)};
+  for (int e = tid; e < kInvBlock * kInvLd; e += 256) Xs[e] = zero;
+  if (tid < bs) Tr[tid] = Tb[(long)(upper ? bs - 1 : 0) * lda + tid];
+  __syncthreads();
+  for (int s = 0; s < bs; ++s) {
+    const int i = upper ? bs - 1 - s : s;
+    const cplx<T> *trow = Tr + (s & 1) * kInvBlock;
+    if (s + 1 < bs && tid < bs) Tr[((s + 1) & 1) * kInvBlock + tid] = Tb[(long)(upper ? i - 1 : i + 1) * lda + tid];
+    const bool active = j < bs && (upper ? j >= i : j <= i);
+    cplx<T> acc = (active && half == 0 && i == j) ? cplx<T>{T(1), T(0)} : zero;
+    if (active) {
+      if (!upper) {
+        for (int k = j + half; k < i; k += 2) acc = cfms(acc, trow[k], Xs[k * kInvLd + j]);
+      } else {
+        for (int k = i + 1 + half; k <= j; k += 2) acc = cfms(acc, trow[k], Xs[k * kInvLd + j]);
+      }
+    }
+    acc.re += __shfl_xor(acc.re, 1);
+    acc.im += __shfl_xor(acc.im, 1);
+    if (active && half == 0) Xs[i * kInvLd + j] = upper ? cmul(acc, crcp(trow[i])) : acc;
+    __syncthreads();
+  }
+  cplx<T> *out = Inv + ((size_t)(blockIdx.y * gridDim.x + blockIdx.x)) * kInvBlock * kInvBlock;
+  for (int e = tid; e < kInvBlock * kInvBlock; e += 256) {
+    const int r = e / kInvBlock, c = e - r * kInvBlock;
+    out[e] = Xs[r * kInvLd + c];
+  }
+}
+
+template <typename T>
+static int tri_inverse(int n, const cplx<T> *LU, long lda, cplx<T> *inv, hipStream_t st) {
+  const size_t shm = ((size_t)kInvBlock * kInvLd + 2 * kInvBlock) * sizeof(cplx<T>);
+  int rc = ensure_dynamic_lds((const void *)tri_inverse_kernel<T>, shm);
+  if (rc) return rc;
+  const int nb = (n + kInvBlock - 1) / kInvBlock;
+  TraceScope ts(TR_TRSM, st, 2.0 * (8.0 / 6.0) * (double)kInvBlock * kInvBlock * kInvBlock * nb, 0.0);
+  hipLaunchKernelGGL(tri_inverse_kernel<T>, dim3(nb, 2), dim3(256), shm, st, n, LU, lda, inv);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+size_t inverse_bytes(int n, int prec) {
+  if (prec != HP_C64) return 0;
+  const size_t nb = (size_t)(n + kInvBlock - 1) / kInvBlock;
+  return 2 * nb * kInvBlock * kInvBlock * sizeof(cplx<float>);
+}
+
+// Y[0:bs, stripe] <- Inv[0:bs, 0:bs] Y[0:bs, stripe] for one diagonal block.
+// A workgroup owns a stripe of CW columns and stages all of it in LDS before
+// writing, so the product is in place.  The inverse is streamed through LDS
+// in 16-column chunks.
+constexpr int kApplyCW = 8;
+constexpr int kApplyKC = 16;
+template <typename T>
+__global__ __launch_bounds__(256) void apply_inverse_kernel(int bs, int ncols, const cplx<T> *__restrict__ Inv,
+                                                            cplx<T> *__restrict__ Y, long ldy) {
+  constexpr int CW = kApplyCW, KC = kApplyKC;
+  constexpr int RPT = kInvBlock * CW / 256;  // output rows per thread
+  constexpr int RSTEP = 256 / CW;
+  __shared__ cplx<T> Ys[kInvBlock][CW];
+  __shared__ cplx<T> Is[kInvBlock][KC + 1];
+  const int tid = threadIdx.x;
+  const int c = tid % CW, r0 = tid / CW;
+  const int col0 = blockIdx.x * CW;
+  const bool colok = col0 + c < ncols;
+  const cplx<T> zero{T(0), T(0)};
+  for (int q = 0; q < RPT; ++q) {
+    const int r = r0 + q * RSTEP;
+    Ys[r][c] = (r < bs && colok) ? Y[(long)r * ldy + col0 + c] : zero;
+  }
+  cplx<T> acc[RPT];
+  for (int q = 0; q < RPT; ++q) acc[q] = zero;
+  for (int k0 = 0; k0 < bs; k0 += KC) {
+    __syncthreads();
+    for (int e = tid; e < kInvBlock * KC; e += 256) {
+      const int r = e / KC, kk = e - r * KC;
+      Is[r][kk] = (r < bs && k0 + kk < bs) ? Inv[(long)r * kInvBlock + k0 + kk] : zero;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const cplx<T> y = Ys[k0 + kk < kInvBlock ? k0 + kk : 0][c];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const cplx<T> a = Is[r0 + q * RSTEP][kk];
+        acc[q].re += a.re * y.re - a.im * y.im;
+        acc[q].im += a.re * y.im + a.im * y.re;
+      }
+    }
+  }
+  if (!colok) return;
+  for (int q = 0; q < RPT; ++q) {
+    const int r = r0 + q * RSTEP;
+    if (r < bs) Y[(long)r * ldy + col0 + c] = acc[q];
+  }
+}
+
+template <typename T>
+static int apply_inverse(int bs, int ncols, const cplx<T> *inv, cplx<T> *Y, long ldy, hipStream_t st) {
+  if (bs <= 0 || ncols <= 0) return HP_OK;
+  TraceScope ts(TR_TRSM, st, 8.0 * bs * bs * (double)ncols, 0.0);
+  hipLaunchKernelGGL(apply_inverse_kernel<T>, dim3((ncols + kApplyCW - 1) / kApplyCW), dim3(256), 0, st, bs,
+                     ncols, inv, Y, ldy);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
 // ------------------------------------------------------------ factorization --
 
 template <typename T>
@@ -605,13 +737,20 @@ static size_t slot_bytes_max() {
 // Rows per workgroup of the panel grid, and the grid size.
 template <typename T>
 static void panel_grid(int m, int &G, int &rpw) {
-  // the grid barrier costs ~2 us at 32 workgroups and ~5 us at 128, so use
-  // few workgroups with many rows each: up to ~150 KB of LDS per workgroup
+  // at least 64 rows per workgroup, at most kMaxPanelGroups workgroups (one
+  // per CU; a 25600-row panel: 128 groups factor ~9% faster than 64 with the
+  // per-group arrival flags), and at most ~150 KB of LDS per workgroup
   const int rpw_max = (150 * 1024) / (int)(kPanelWidth * sizeof(cplx<T>));
   const int rpw_min = 64;
   G = (m + rpw_min - 1) / rpw_min;
-  G = std::min(G, 64);
+  G = std::min(G, kMaxPanelGroups);
   G = std::max(G, 1);
+  // tuning knob: HP_PANEL_GROUPS overrides the workgroup count (still capped by LDS below)
+  static const int forced = [] {
+    const char *e = getenv("HP_PANEL_GROUPS");
+    return e ? atoi(e) : 0;
+  }();
+  if (forced > 0) G = std::min(forced, kMaxPanelGroups);
   rpw = (m + G - 1) / G;
   if (rpw > rpw_max) {
     rpw = rpw_max;
@@ -709,24 +848,38 @@ __global__ void copy_rows_kernel(int n, int nrhs, const cplx<T> *__restrict__ X,
 }
 
 constexpr int kSolveBlock = 128;
+static_assert(kSolveBlock == kInvBlock, "solve blocks are the inverted diagonal blocks");
 
 // In-place solve on Y (n x nrhs, leading dimension ldy) that already holds P B.
+// With `inv` (the output of tri_inverse for this factor) the diagonal blocks
+// are applied as products with their inverses, otherwise by substitution.
 template <typename T>
-int lu_solve_permuted(int n, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, long ldy, hipStream_t st) {
+int lu_solve_permuted(int n, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, long ldy, const cplx<T> *inv,
+                      hipStream_t st) {
   int rc;
-  for (int b = 0; b < n; b += kSolveBlock) {
+  const int nb = (n + kSolveBlock - 1) / kSolveBlock;
+  const size_t iblk = (size_t)kInvBlock * kInvBlock;
+  for (int bi = 0; bi < nb; ++bi) {
+    const int b = bi * kSolveBlock;
     const int bs = std::min(kSolveBlock, n - b);
-    if ((rc = trsm<T, false>(bs, nrhs, LU + (long)b * lda + b, lda, Y + (long)b * ldy, ldy, st))) return rc;
+    if (inv)
+      rc = apply_inverse<T>(bs, nrhs, inv + bi * iblk, Y + (long)b * ldy, ldy, st);
+    else
+      rc = trsm<T, false>(bs, nrhs, LU + (long)b * lda + b, lda, Y + (long)b * ldy, ldy, st);
+    if (rc) return rc;
     if (b + bs < n)
       if ((rc = gemm_sub<T>(n - b - bs, nrhs, bs, LU + (long)(b + bs) * lda + b, lda, Y + (long)b * ldy, ldy,
                             Y + (long)(b + bs) * ldy, ldy, st)))
         return rc;
   }
-  const int nb = (n + kSolveBlock - 1) / kSolveBlock;
   for (int bi = nb - 1; bi >= 0; --bi) {
     const int b = bi * kSolveBlock;
     const int bs = std::min(kSolveBlock, n - b);
-    if ((rc = trsm<T, true>(bs, nrhs, LU + (long)b * lda + b, lda, Y + (long)b * ldy, ldy, st))) return rc;
+    if (inv)
+      rc = apply_inverse<T>(bs, nrhs, inv + (nb + bi) * iblk, Y + (long)b * ldy, ldy, st);
+    else
+      rc = trsm<T, true>(bs, nrhs, LU + (long)b * lda + b, lda, Y + (long)b * ldy, ldy, st);
+    if (rc) return rc;
     if (b > 0)
       if ((rc = gemm_sub<T>(b, nrhs, bs, LU + b, lda, Y + (long)b * ldy, ldy, Y, ldy, st))) return rc;
   }
@@ -734,15 +887,27 @@ int lu_solve_permuted(int n, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, 
 }
 
 template <typename T>
+int solve_inverses(int n, const cplx<T> *LU, long lda, cplx<T> *inv, hipStream_t st);
+template <>
+int solve_inverses<float>(int n, const cplx<float> *LU, long lda, cplx<float> *inv, hipStream_t st) {
+  return tri_inverse<float>(n, LU, lda, inv, st);
+}
+template <>
+int solve_inverses<double>(int, const cplx<double> *, long, cplx<double> *, hipStream_t) {
+  return HP_ERR_UNSUPPORTED;
+}
+
+template <typename T>
 int lu_solve(int n, int nrhs, const cplx<T> *LU, long lda, const int *perm, cplx<T> *X, long ldx, cplx<T> *tmp,
-             hipStream_t st) {
+             cplx<T> *inv, hipStream_t st) {
   int rc;
   const long tot = (long)n * nrhs;
   const unsigned blocks = (unsigned)((tot + 255) / 256);
+  if (inv && (rc = solve_inverses<T>(n, LU, lda, inv, st))) return rc;
   hipLaunchKernelGGL(gather_rows_kernel<T>, dim3(blocks), dim3(256), 0, st, n, nrhs, perm, X, ldx, tmp,
                      (long)nrhs);
   HP_CHECK_LAUNCH();
-  if ((rc = lu_solve_permuted<T>(n, nrhs, LU, lda, tmp, nrhs, st))) return rc;
+  if ((rc = lu_solve_permuted<T>(n, nrhs, LU, lda, tmp, nrhs, inv, st))) return rc;
   hipLaunchKernelGGL(copy_rows_kernel<T>, dim3(blocks), dim3(256), 0, st, n, nrhs, tmp, (long)nrhs, X, ldx);
   HP_CHECK_LAUNCH();
   return HP_OK;
@@ -754,11 +919,13 @@ template int lu_factor<double>(int, cplx<double> *, long, int *, int *, int *, c
 template int lu_factor<float>(int, cplx<float> *, long, int *, int *, int *, char *, const Workspace &,
                               hipStream_t);
 template int lu_solve<double>(int, int, const cplx<double> *, long, const int *, cplx<double> *, long,
-                              cplx<double> *, hipStream_t);
+                              cplx<double> *, cplx<double> *, hipStream_t);
 template int lu_solve<float>(int, int, const cplx<float> *, long, const int *, cplx<float> *, long,
-                             cplx<float> *, hipStream_t);
-template int lu_solve_permuted<double>(int, int, const cplx<double> *, long, cplx<double> *, long, hipStream_t);
-template int lu_solve_permuted<float>(int, int, const cplx<float> *, long, cplx<float> *, long, hipStream_t);
+                             cplx<float> *, cplx<float> *, hipStream_t);
+template int lu_solve_permuted<double>(int, int, const cplx<double> *, long, cplx<double> *, long,
+                                       const cplx<double> *, hipStream_t);
+template int lu_solve_permuted<float>(int, int, const cplx<float> *, long, cplx<float> *, long,
+                                      const cplx<float> *, hipStream_t);
 
 size_t factor_sync_bytes(int n) {
   const int npanels = (n + kPanelWidth - 1) / kPanelWidth;

@@ -246,10 +246,16 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
   unsigned long long *xmax = smax + nc;
   unsigned long long *dmax = xmax + nc;
   unsigned long long *norms = dmax + nc;  // |C|_inf, |B|_inf
+  // FP32 factors are applied through their inverted diagonal blocks
+  cplx<T> *inv = nullptr;
+  if (sizeof(T) == sizeof(float)) {
+    inv = (cplx<T> *)(work + ws.inv_off);
+    if ((rc = solve_inverses<T>((int)n, LU, lda, inv, st))) return rc;
+  }
   // initial solve
   hipLaunchKernelGGL(rhs_from_perm_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, nc, nr, perm, sys->q, Y);
   HP_CHECK_LAUNCH();
-  if ((rc = lu_solve_permuted<T>((int)n, nc, LU, lda, Y, nc, st))) return rc;
+  if ((rc = lu_solve_permuted<T>((int)n, nc, LU, lda, Y, nc, inv, st))) return rc;
   hipLaunchKernelGGL(widen_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, cnt, Y, X);
   HP_CHECK_LAUNCH();
   int hinfo = 0;
@@ -318,7 +324,7 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
       hipLaunchKernelGGL(scale_perm_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, n, nc, perm, Rr, smax, Y);
       HP_CHECK_LAUNCH();
     }
-    if ((rc = lu_solve_permuted<T>((int)n, nc, LU, lda, Y, nc, st))) return rc;
+    if ((rc = lu_solve_permuted<T>((int)n, nc, LU, lda, Y, nc, inv, st))) return rc;
     {
       TraceScope ts(TR_REFINE, st, 0.0, (sizeof(cplx<T>) + 32.0) * (double)cnt);
       hipLaunchKernelGGL(zero_u64_kernel, dim3(nblk(nc)), dim3(256), 0, st, dmax, nc);

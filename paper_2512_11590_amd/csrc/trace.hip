@@ -21,6 +21,7 @@ struct Rec {
 };
 std::mutex g_mu;
 bool g_on = false;
+unsigned g_mask = 0;
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
@@ -43,7 +44,7 @@ bool trace_on() { return g_on; }
 
 TraceScope::TraceScope(int cat, hipStream_t st, double flops, double bytes)
     : cat_(cat), st_(st), flops_(flops), bytes_(bytes), a_(nullptr) {
-  if (!g_on) return;
+  if (!g_on || !((g_mask >> cat) & 1u)) return;
   std::lock_guard<std::mutex> lk(g_mu);
   a_ = get_event();
   if (a_) hipEventRecord((hipEvent_t)a_, st_);
@@ -62,14 +63,15 @@ TraceScope::~TraceScope() {
 
 using namespace hp;
 
-extern "C" int hp_trace_enable(int on) {
+extern "C" int hp_trace_enable(int mask) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (Rec &r : g_recs) {
     g_pool.push_back(r.a);
     g_pool.push_back(r.b);
   }
   g_recs.clear();
-  g_on = (on != 0);
+  g_on = (mask != 0);
+  g_mask = mask < 0 ? ((1u << TR_COUNT) - 1u) : (unsigned)mask;
   return HP_OK;
 }
 

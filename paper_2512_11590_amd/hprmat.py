@@ -223,8 +223,22 @@ def hp_coulomb_device(l, eta, rho, out, stream=None) -> None:
                                    _stream(stream)), "hp_coulomb_device")
 
 
-def hp_trace_enable(on: bool) -> None:
-    _check(lib().hp_trace_enable(1 if on else 0), "hp_trace_enable")
+TRACE_STAGES = ("assemble", "panel", "laswp", "trsm", "gemm_c128", "gemm_c64", "residual", "refine",
+                "rmatrix", "smatrix")
+
+
+def hp_trace_enable(on: bool = True, stages=None) -> None:
+    """Start (clearing the record) or stop the per-stage timers; `stages`
+    names the stages to time (default: all)."""
+    if not on:
+        mask = 0
+    elif stages is None:
+        mask = -1
+    else:
+        mask = 0
+        for s in stages:
+            mask |= 1 << TRACE_STAGES.index(s)
+    _check(lib().hp_trace_enable(mask), "hp_trace_enable")
 
 
 def hp_trace_read() -> dict:

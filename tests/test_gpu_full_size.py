@@ -11,8 +11,10 @@ Tolerances (normwise relative):
     its channels numbered in reverse order differs from the first by
     Rfloor_e (stored with the golden values);
   * cross sections without refinement: 1e-3.
-Properties that hold at any size are checked too: S symmetric (C = C^T),
-|S| contracting for the absorptive potential.
+Properties that hold at any size are checked too: S symmetric (C = C^T), and
+|S| <= 1 where the potential is absorptive at every mesh point (Im V(r_i)
+negative semidefinite as a channel matrix; with many real-positive coupling
+strengths this need not hold, and then flux can be fed into some channels).
 """
 from __future__ import annotations
 
@@ -55,6 +57,11 @@ def energy_indices(g):
     return sorted(int(k[2:]) for k in g.files if k.startswith("S_"))
 
 
+def absorptive(sp, r):
+    vi = sp.potential(r).imag
+    return all(np.linalg.eigvalsh(vi[i]).max() <= 0.0 for i in range(vi.shape[0]))
+
+
 def sigma(S, k):
     d = np.eye(S.shape[0]) - S
     return np.pi / (k[None, :] ** 2) * np.abs(d) ** 2
@@ -68,6 +75,7 @@ def test_full_size_against_oracle(mods, config, prec):
     sp = make_system(config)
     d = P.DeviceSystem(sp)
     s = P.Solver(d, prec)
+    contracting = absorptive(sp, d.r_host)
     for e in energy_indices(g):
         E = float(g[f"E_{e}"])
         say(config, "N", sp.n, "prec", prec, "E", E)
@@ -84,7 +92,8 @@ def test_full_size_against_oracle(mods, config, prec):
         assert es < 1e-10
         assert er < tol_r
         assert np.max(np.abs(S - S.T)) < 1e-9
-        assert np.linalg.norm(S, 2) <= 1.0 + 1e-9
+        if contracting:
+            assert np.linalg.norm(S, 2) <= 1.0 + 1e-9
 
 
 def test_cross_sections_without_refinement(mods):

@@ -54,7 +54,7 @@ def device_factor(H, A, prec):
     ipiv = torch.empty(n, dtype=torch.int32, device="cuda")
     perm = torch.empty(n, dtype=torch.int32, device="cuda")
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
-    work = torch.empty(H.hp_workspace_bytes(n, 64, prec), dtype=torch.uint8, device="cuda")
+    work = torch.empty(H.hp_workspace_bytes(n, 256, prec), dtype=torch.uint8, device="cuda")
     H.hp_factor(n, prec, dA, n, ipiv, perm, info, work)
     torch.cuda.synchronize()
     assert dA.dtype == ct
@@ -94,7 +94,7 @@ def test_lu_fp32_backward_error(H, n):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (40, 3), (300, 17), (700, 64)])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (40, 3), (300, 17), (700, 64), (1025, 9), (384, 256)])
 def test_lu_solve_general_rhs(H, prec, n, nrhs):
     say("lu_solve", prec, n, nrhs)
     A = rand_matrix(n, 7 * n + nrhs, diag=2.0 * np.sqrt(n))

@@ -91,5 +91,8 @@ def test_workspace_grows_with_size(H):
     a = H.hp_workspace_bytes(1000, 10, H.HP_C64)
     b = H.hp_workspace_bytes(2000, 10, H.HP_C64)
     c = H.hp_workspace_bytes(2000, 10, H.HP_C128)
-    assert 0 < a < b <= c
+    d = H.hp_workspace_bytes(4000, 10, H.HP_C128)
+    assert 0 < a < b and 0 < c < d
+    # FP32 factors also hold their inverted 128 x 128 diagonal blocks (2 per block row)
+    assert b - c >= 2 * 16 * 128 * 128 * 8 - 16 * 2000 * 10
     assert H.hp_workspace_bytes(25600, 256, H.HP_C64) < 1 << 30
