@@ -78,7 +78,7 @@ extern "C" int hp_factor(int n, int prec, void *A, long lda, int *ipiv, int *per
   if (n < 1 || !A || !ipiv || !perm || !info || !work || lda < n) return HP_ERR_ARG;
   if (prec != HP_C128 && prec != HP_C64) return HP_ERR_ARG;
   Workspace ws = plan_workspace(n, 0, prec);
-  if (work_bytes < ws.sync_off + ws.sync_bytes + ws.slot_bytes + 256) return HP_ERR_WORKSPACE;
+  if (work_bytes < ws.total) return HP_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   if (prec == HP_C128)
     return lu_factor<double>(n, (cplx<double> *)A, lda, ipiv, perm, info, (char *)work, ws, st);

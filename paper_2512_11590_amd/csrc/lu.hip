@@ -18,6 +18,8 @@
 //   gemm_sub             A22 -= L21 U12 (MFMA complex GEMM, 4 real products)
 #include "common.h"
 
+#include <type_traits>
+
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
@@ -579,20 +581,22 @@ static int trsm(int m, int ncols, const cplx<T> *L, long ldl, cplx<T> *X, long l
 constexpr int kInvBlock = 128;
 constexpr int kInvLd = kInvBlock + 1;  // LDS row stride (complex elements)
 
-// One workgroup per diagonal block: blockIdx.y == 0 inverts the unit-lower
-// block of L, blockIdx.y == 1 the upper block of U.  Rows of the inverse are
-// produced in substitution order, all columns of a row at once (two threads
-// per column, one per parity of the summation index).  Output: dense
-// kInvBlock x kInvBlock row-major blocks, lower inverses first; entries outside
-// a ragged last block are zero.
+// One workgroup per diagonal block: block index blk0 + blockIdx.x; blockIdx.y
+// == 0 inverts the unit-lower block of L, blockIdx.y == 1 the upper block of
+// U.  Rows of the inverse are produced in substitution order, all columns of
+// a row at once (two threads per column, one per parity of the summation
+// index).  Output: dense kInvBlock x kInvBlock row-major blocks, the nbt lower
+// inverses first, then the nbt upper ones; entries outside a ragged last block
+// are zero.
 template <typename T>
-__global__ __launch_bounds__(256) void tri_inverse_kernel(int n, const cplx<T> *__restrict__ LU, long lda,
-                                                          cplx<T> *__restrict__ Inv) {
+__global__ __launch_bounds__(256) void tri_inverse_kernel(int n, int blk0, int nbt, const cplx<T> *__restrict__ LU,
+                                                          long lda, cplx<T> *__restrict__ Inv) {
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T> *Xs = reinterpret_cast<cplx<T> *>(smem_raw);  // [kInvBlock][kInvLd]
   cplx<T> *Tr = Xs + kInvBlock * kInvLd;                // [2][kInvBlock]: rows of the factor
   const bool upper = blockIdx.y != 0;
-  const int b0 = blockIdx.x * kInvBlock;
+  const int blk = blk0 + blockIdx.x;
+  const int b0 = blk * kInvBlock;
   const int bs = min(kInvBlock, n - b0);
   const cplx<T> *Tb = LU + (long)b0 * lda + b0;
   const int tid = threadIdx.x;
@@ -619,21 +623,26 @@ __global__ __launch_bounds__(256) void tri_inverse_kernel(int n, const cplx<T> *
     if (active && half == 0) Xs[i * kInvLd + j] = upper ? cmul(acc, crcp(trow[i])) : acc;
     __syncthreads();
   }
-  cplx<T> *out = Inv + ((size_t)(blockIdx.y * gridDim.x + blockIdx.x)) * kInvBlock * kInvBlock;
+  cplx<T> *out = Inv + ((size_t)blockIdx.y * nbt + blk) * kInvBlock * kInvBlock;
   for (int e = tid; e < kInvBlock * kInvBlock; e += 256) {
     const int r = e / kInvBlock, c = e - r * kInvBlock;
     out[e] = Xs[r * kInvLd + c];
   }
 }
 
+// Inverts diagonal blocks [blk0, blk0 + nblk) of L (and of U when `both`).
 template <typename T>
-static int tri_inverse(int n, const cplx<T> *LU, long lda, cplx<T> *inv, hipStream_t st) {
+static int tri_inverse(int n, const cplx<T> *LU, long lda, cplx<T> *inv, int blk0, int nblk, bool both,
+                       hipStream_t st) {
+  if (nblk <= 0) return HP_OK;
   const size_t shm = ((size_t)kInvBlock * kInvLd + 2 * kInvBlock) * sizeof(cplx<T>);
   int rc = ensure_dynamic_lds((const void *)tri_inverse_kernel<T>, shm);
   if (rc) return rc;
-  const int nb = (n + kInvBlock - 1) / kInvBlock;
-  TraceScope ts(TR_TRSM, st, 2.0 * (8.0 / 6.0) * (double)kInvBlock * kInvBlock * kInvBlock * nb, 0.0);
-  hipLaunchKernelGGL(tri_inverse_kernel<T>, dim3(nb, 2), dim3(256), shm, st, n, LU, lda, inv);
+  const int nbt = (n + kInvBlock - 1) / kInvBlock;
+  TraceScope ts(TR_TRSM, st, (both ? 2.0 : 1.0) * (8.0 / 6.0) * (double)kInvBlock * kInvBlock * kInvBlock * nblk,
+                0.0);
+  hipLaunchKernelGGL(tri_inverse_kernel<T>, dim3(nblk, both ? 2 : 1), dim3(256), shm, st, n, blk0, nbt, LU, lda,
+                     inv);
   HP_CHECK_LAUNCH();
   return HP_OK;
 }
@@ -645,46 +654,55 @@ size_t inverse_bytes(int n, int prec) {
 }
 
 // Y[0:bs, stripe] <- Inv[0:bs, 0:bs] Y[0:bs, stripe] for one diagonal block.
-// A workgroup owns a stripe of CW columns and stages all of it in LDS before
-// writing, so the product is in place.  The inverse is streamed through LDS
-// in 16-column chunks.
-constexpr int kApplyCW = 8;
-constexpr int kApplyKC = 16;
-template <typename T>
+// A workgroup owns a stripe of CW columns and stages all of it in LDS
+// before writing, so the product is in place.  The whole inverse is staged in
+// LDS first with 16-byte loads that are all in flight together (the block is
+// shared by every workgroup of the launch and comes from L2).
+constexpr int kApplyLd = kInvBlock + 2;  // keeps rows 16-byte aligned, spreads banks
+template <typename T, int CW>
 __global__ __launch_bounds__(256) void apply_inverse_kernel(int bs, int ncols, const cplx<T> *__restrict__ Inv,
                                                             cplx<T> *__restrict__ Y, long ldy) {
-  constexpr int CW = kApplyCW, KC = kApplyKC;
   constexpr int RPT = kInvBlock * CW / 256;  // output rows per thread
   constexpr int RSTEP = 256 / CW;
-  __shared__ cplx<T> Ys[kInvBlock][CW];
-  __shared__ cplx<T> Is[kInvBlock][KC + 1];
+  constexpr int EPV = 16 / sizeof(cplx<T>);  // complex elements per 16-byte vector
+  constexpr int NV = kInvBlock * kInvBlock / EPV / 256;
+  static_assert(NV % 8 == 0, "staging loop");
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T> *Is = reinterpret_cast<cplx<T> *>(smem_raw);  // [kInvBlock][kApplyLd]
+  cplx<T> *Ys = Is + kInvBlock * kApplyLd;               // [kInvBlock][CW]
   const int tid = threadIdx.x;
   const int c = tid % CW, r0 = tid / CW;
   const int col0 = blockIdx.x * CW;
   const bool colok = col0 + c < ncols;
   const cplx<T> zero{T(0), T(0)};
+  const uint4 *src = reinterpret_cast<const uint4 *>(Inv);
+  for (int v0 = 0; v0 < NV; v0 += 8) {
+    uint4 buf[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) buf[u] = src[(v0 + u) * 256 + tid];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = ((v0 + u) * 256 + tid) * EPV;
+      const int r = e / kInvBlock, k = e - r * kInvBlock;
+      *reinterpret_cast<uint4 *>(Is + r * kApplyLd + k) = buf[u];
+    }
+  }
   for (int q = 0; q < RPT; ++q) {
     const int r = r0 + q * RSTEP;
-    Ys[r][c] = (r < bs && colok) ? Y[(long)r * ldy + col0 + c] : zero;
+    Ys[r * CW + c] = (r < bs && colok) ? Y[(long)r * ldy + col0 + c] : zero;
   }
+  __syncthreads();
   cplx<T> acc[RPT];
+#pragma unroll
   for (int q = 0; q < RPT; ++q) acc[q] = zero;
-  for (int k0 = 0; k0 < bs; k0 += KC) {
-    __syncthreads();
-    for (int e = tid; e < kInvBlock * KC; e += 256) {
-      const int r = e / KC, kk = e - r * KC;
-      Is[r][kk] = (r < bs && k0 + kk < bs) ? Inv[(long)r * kInvBlock + k0 + kk] : zero;
-    }
-    __syncthreads();
+#pragma unroll 4
+  for (int k = 0; k < bs; ++k) {
+    const cplx<T> y = Ys[k * CW + c];
 #pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      const cplx<T> y = Ys[k0 + kk < kInvBlock ? k0 + kk : 0][c];
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const cplx<T> a = Is[r0 + q * RSTEP][kk];
-        acc[q].re += a.re * y.re - a.im * y.im;
-        acc[q].im += a.re * y.im + a.im * y.re;
-      }
+    for (int q = 0; q < RPT; ++q) {
+      const cplx<T> a = Is[(r0 + q * RSTEP) * kApplyLd + k];
+      acc[q].re += a.re * y.re - a.im * y.im;
+      acc[q].im += a.re * y.im + a.im * y.re;
     }
   }
   if (!colok) return;
@@ -694,14 +712,26 @@ __global__ __launch_bounds__(256) void apply_inverse_kernel(int bs, int ncols, c
   }
 }
 
+template <typename T, int CW>
+static int apply_inverse_launch(int bs, int ncols, const cplx<T> *inv, cplx<T> *Y, long ldy, hipStream_t st) {
+  const size_t shm = ((size_t)kInvBlock * kApplyLd + (size_t)kInvBlock * CW) * sizeof(cplx<T>);
+  int rc = ensure_dynamic_lds((const void *)apply_inverse_kernel<T, CW>, shm);
+  if (rc) return rc;
+  hipLaunchKernelGGL((apply_inverse_kernel<T, CW>), dim3((ncols + CW - 1) / CW), dim3(256), shm, st, bs, ncols,
+                     inv, Y, ldy);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+// 8-column stripes for the few right-hand sides of a solve (more
+// workgroups), 16-column ones for the U rows of the factorization (the
+// staged inverse serves more columns).
 template <typename T>
 static int apply_inverse(int bs, int ncols, const cplx<T> *inv, cplx<T> *Y, long ldy, hipStream_t st) {
   if (bs <= 0 || ncols <= 0) return HP_OK;
   TraceScope ts(TR_TRSM, st, 8.0 * bs * bs * (double)ncols, 0.0);
-  hipLaunchKernelGGL(apply_inverse_kernel<T>, dim3((ncols + kApplyCW - 1) / kApplyCW), dim3(256), 0, st, bs,
-                     ncols, inv, Y, ldy);
-  HP_CHECK_LAUNCH();
-  return HP_OK;
+  if (ncols <= 2048) return apply_inverse_launch<T, 8>(bs, ncols, inv, Y, ldy, st);
+  return apply_inverse_launch<T, 16>(bs, ncols, inv, Y, ldy, st);
 }
 
 // ------------------------------------------------------------ factorization --
@@ -818,7 +848,23 @@ int lu_factor(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *info, char
     if (rest > 0) {
       cplx<T> *L11 = A + (long)k * lda + k;
       cplx<T> *A12 = A + (long)k * lda + k + kb;
-      if ((rc = trsm<T, false>(kb, rest, L11, lda, A12, lda, st))) return rc;
+      if constexpr (std::is_same<T, float>::value) {
+        // U12 = L11^-1 A12 through the two inverted 128-row diagonal blocks of
+        // L11 (kb == 2 kInvBlock whenever columns remain)
+        static_assert(kOuterBlock == 2 * kInvBlock, "outer block = two inverted blocks");
+        cplx<T> *inv = (cplx<T> *)(work + ws.inv_off);
+        const int b = k / kInvBlock;
+        const size_t iblk = (size_t)kInvBlock * kInvBlock;
+        cplx<T> *A22 = A12 + (long)kInvBlock * lda;
+        if ((rc = tri_inverse<T>(n, A, lda, inv, b, 2, false, st))) return rc;
+        if ((rc = apply_inverse<T>(kInvBlock, rest, inv + b * iblk, A12, lda, st))) return rc;
+        if ((rc = gemm_sub<T>(kInvBlock, rest, kInvBlock, L11 + (long)kInvBlock * lda, lda, A12, lda, A22, lda,
+                              st)))
+          return rc;
+        if ((rc = apply_inverse<T>(kInvBlock, rest, inv + (b + 1) * iblk, A22, lda, st))) return rc;
+      } else {
+        if ((rc = trsm<T, false>(kb, rest, L11, lda, A12, lda, st))) return rc;
+      }
       if ((rc = gemm_sub<T>(rest, rest, kb, A + (long)(k + kb) * lda + k, lda, A12, lda,
                             A + (long)(k + kb) * lda + k + kb, lda, st)))
         return rc;
@@ -890,7 +936,7 @@ template <typename T>
 int solve_inverses(int n, const cplx<T> *LU, long lda, cplx<T> *inv, hipStream_t st);
 template <>
 int solve_inverses<float>(int n, const cplx<float> *LU, long lda, cplx<float> *inv, hipStream_t st) {
-  return tri_inverse<float>(n, LU, lda, inv, st);
+  return tri_inverse<float>(n, LU, lda, inv, 0, (n + kInvBlock - 1) / kInvBlock, true, st);
 }
 template <>
 int solve_inverses<double>(int, const cplx<double> *, long, cplx<double> *, hipStream_t) {
