@@ -19,6 +19,8 @@
 #include "common.h"
 
 #include <type_traits>
+#include <mutex>
+#include <map>
 
 #include <algorithm>
 #include <climits>
@@ -585,15 +587,20 @@ constexpr int kInvLd = kInvBlock + 1;  // LDS row stride (complex elements)
 // == 0 inverts the unit-lower block of L, blockIdx.y == 1 the upper block of
 // U.  Rows of the inverse are produced in substitution order, all columns of
 // a row at once (two threads per column, one per parity of the summation
-// index).  Output: dense kInvBlock x kInvBlock row-major blocks, the nbt lower
-// inverses first, then the nbt upper ones; entries outside a ragged last block
-// are zero.
+// index).  The factor's rows reach LDS through a two-chunk ring of
+// kInvChunk rows each: a chunk's loads are issued a whole chunk of rows ahead
+// of its use, so the row-by-row recurrence never waits on HBM.  Output: dense
+// kInvBlock x kInvBlock row-major blocks, the nbt lower inverses first, then
+// the nbt upper ones; entries outside a ragged last block are zero.
+constexpr int kInvChunk = 8;
 template <typename T>
 __global__ __launch_bounds__(256) void tri_inverse_kernel(int n, int blk0, int nbt, const cplx<T> *__restrict__ LU,
                                                           long lda, cplx<T> *__restrict__ Inv) {
+  constexpr int CH = kInvChunk;
+  constexpr int PER = CH * kInvBlock / 256;  // ring elements loaded per thread per chunk
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T> *Xs = reinterpret_cast<cplx<T> *>(smem_raw);  // [kInvBlock][kInvLd]
-  cplx<T> *Tr = Xs + kInvBlock * kInvLd;                // [2][kInvBlock]: rows of the factor
+  cplx<T> *Ring = Xs + kInvBlock * kInvLd;              // [2][CH][kInvBlock]: rows in use order
   const bool upper = blockIdx.y != 0;
   const int blk = blk0 + blockIdx.x;
   const int b0 = blk * kInvBlock;
@@ -602,25 +609,56 @@ __global__ __launch_bounds__(256) void tri_inverse_kernel(int n, int blk0, int n
   const int tid = threadIdx.x;
   const int j = tid >> 1, half = tid & 1;
   const cplx<T> zero{T(0), T(0)};
-  for (int e = tid; e < kInvBlock * kInvLd; e += 256) Xs[e] = zero;
-  if (tid < bs) Tr[tid] = Tb[(long)(upper ? bs - 1 : 0) * lda + tid];
-  __syncthreads();
-  for (int s = 0; s < bs; ++s) {
-    const int i = upper ? bs - 1 - s : s;
-    const cplx<T> *trow = Tr + (s & 1) * kInvBlock;
-    if (s + 1 < bs && tid < bs) Tr[((s + 1) & 1) * kInvBlock + tid] = Tb[(long)(upper ? i - 1 : i + 1) * lda + tid];
-    const bool active = j < bs && (upper ? j >= i : j <= i);
-    cplx<T> acc = (active && half == 0 && i == j) ? cplx<T>{T(1), T(0)} : zero;
-    if (active) {
-      if (!upper) {
-        for (int k = j + half; k < i; k += 2) acc = cfms(acc, trow[k], Xs[k * kInvLd + j]);
-      } else {
-        for (int k = i + 1 + half; k <= j; k += 2) acc = cfms(acc, trow[k], Xs[k * kInvLd + j]);
-      }
+  // the row used at step s (rows outside the block read as zero)
+  auto row_of = [&](int s) { return upper ? bs - 1 - s : s; };
+  cplx<T> pre[PER];
+  auto load_chunk = [&](int c) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
+      const int u = e / kInvBlock, col = e - u * kInvBlock;
+      const int st = c * CH + u;
+      pre[q] = (st < bs && col < bs) ? Tb[(long)row_of(st) * lda + col] : zero;
     }
-    acc.re += __shfl_xor(acc.re, 1);
-    acc.im += __shfl_xor(acc.im, 1);
-    if (active && half == 0) Xs[i * kInvLd + j] = upper ? cmul(acc, crcp(trow[i])) : acc;
+  };
+  auto store_chunk = [&](int c) {
+    cplx<T> *slot = Ring + (c & 1) * CH * kInvBlock;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) slot[tid + 256 * q] = pre[q];
+  };
+  for (int e = tid; e < kInvBlock * kInvLd; e += 256) Xs[e] = zero;
+  const int nch = (bs + CH - 1) / CH;
+  load_chunk(0);
+  store_chunk(0);
+  if (nch > 1) load_chunk(1);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const cplx<T> *slot = Ring + (c & 1) * CH * kInvBlock;
+    for (int u = 0; u < CH; ++u) {
+      const int s = c * CH + u;
+      if (s >= bs) break;
+      const int i = row_of(s);
+      const cplx<T> *trow = slot + u * kInvBlock;
+      const bool active = j < bs && (upper ? j >= i : j <= i);
+      cplx<T> acc = (active && half == 0 && i == j) ? cplx<T>{T(1), T(0)} : zero;
+      if (active) {
+        if (!upper) {
+          for (int k = j + half; k < i; k += 2) acc = cfms(acc, trow[k], Xs[k * kInvLd + j]);
+        } else {
+          for (int k = i + 1 + half; k <= j; k += 2) acc = cfms(acc, trow[k], Xs[k * kInvLd + j]);
+        }
+      }
+      acc.re += __shfl_xor(acc.re, 1);
+      acc.im += __shfl_xor(acc.im, 1);
+      if (active && half == 0) Xs[i * kInvLd + j] = upper ? cmul(acc, crcp(trow[i])) : acc;
+      __syncthreads();
+    }
+    // chunk c + 1 (loaded during chunk c) into the slot chunk c - 1 used;
+    // then the loads of chunk c + 2
+    if (c + 1 < nch) {
+      store_chunk(c + 1);
+      if (c + 2 < nch) load_chunk(c + 2);
+    }
     __syncthreads();
   }
   cplx<T> *out = Inv + ((size_t)blockIdx.y * nbt + blk) * kInvBlock * kInvBlock;
@@ -635,7 +673,7 @@ template <typename T>
 static int tri_inverse(int n, const cplx<T> *LU, long lda, cplx<T> *inv, int blk0, int nblk, bool both,
                        hipStream_t st) {
   if (nblk <= 0) return HP_OK;
-  const size_t shm = ((size_t)kInvBlock * kInvLd + 2 * kInvBlock) * sizeof(cplx<T>);
+  const size_t shm = ((size_t)kInvBlock * kInvLd + 2 * kInvChunk * kInvBlock) * sizeof(cplx<T>);
   int rc = ensure_dynamic_lds((const void *)tri_inverse_kernel<T>, shm);
   if (rc) return rc;
   const int nbt = (n + kInvBlock - 1) / kInvBlock;
@@ -788,6 +826,15 @@ static void panel_grid(int m, int &G, int &rpw) {
   }
 }
 
+// The panel grid must fit the device at once: at most one workgroup per CU.
+static int check_resident(int G, size_t shm) {
+  int dev = 0, cus = 0;
+  HP_CHECK_HIP(hipGetDevice(&dev));
+  HP_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (G > cus || shm > 160 * 1024) return HP_ERR_UNSUPPORTED;
+  return HP_OK;
+}
+
 template <typename T>
 static int panel(int n, int j0, int w, cplx<T> *A, long lda, int *ipiv, int *info, unsigned *bar,
                  const PanelSlots<T> &s, hipStream_t st) {
@@ -805,16 +852,108 @@ static int panel(int n, int j0, int w, cplx<T> *A, long lda, int *ipiv, int *inf
   int *srow = s.row;
   cplx<T> *sdiag = s.diag;
   void *args[] = {&nn, &jj0, &ww, &A, &ld, &ipiv, &info, &bar, &srows, &sval, &srow, &sdiag, &rp};
+  // All G workgroups must become resident together (they meet at grid
+  // barriers).  G is at most one per CU and the kernel fits a CU on its own, so
+  // on an idle device they are; beside a running trailing update they become
+  // resident as its workgroups retire, which the barriers' bounded waits cover.
+  if ((rc = check_resident(G, shm))) return rc;
   TraceScope ts(TR_PANEL, st, 4.0 * (double)m * w * w, 2.0 * sizeof(cplx<T>) * (double)m * w);
-  HP_CHECK_HIP(hipLaunchCooperativeKernel((const void *)panel_kernel<T>, dim3(G), dim3(256), args,
-                                          (unsigned)shm, st));
+  HP_CHECK_HIP(hipLaunchKernel((const void *)panel_kernel<T>, dim3(G), dim3(256), args, shm, st));
   return HP_OK;
 }
 
+// Second stream and events for the look-ahead, one set per device, created on
+// first use (default priority).  Factorizations on one device are enqueued
+// one at a time (g_la_mu), so the shared stream only serializes them.
+namespace {
+struct LookAhead {
+  hipStream_t panel = nullptr;
+  hipEvent_t ready = nullptr, done = nullptr;
+};
+std::mutex g_la_mu;
+std::map<int, LookAhead> g_la;
+
+int lookahead_for_device(LookAhead **out) {
+  int dev = 0;
+  HP_CHECK_HIP(hipGetDevice(&dev));
+  LookAhead &la = g_la[dev];
+  if (!la.panel) {
+    HP_CHECK_HIP(hipStreamCreateWithFlags(&la.panel, hipStreamNonBlocking));
+    HP_CHECK_HIP(hipEventCreateWithFlags(&la.ready, hipEventDisableTiming));
+    HP_CHECK_HIP(hipEventCreateWithFlags(&la.done, hipEventDisableTiming));
+  }
+  *out = &la;
+  return HP_OK;
+}
+}  // namespace
+
+// Factors the columns [k, k + kb) of the rows below k: kPanelWidth-wide
+// panels, each followed by its interchanges on the block's other columns and
+// by the update of the block's columns to its right.
+template <typename T>
+static int factor_block(int n, int k, int kb, cplx<T> *A, long lda, int *ipiv, int *info, unsigned *bars,
+                        const PanelSlots<T> &slots, int *plan, hipStream_t st) {
+  int rc;
+  const size_t per_panel = barrier_words(kMaxPanelGroups);
+  for (int j = k; j < k + kb; j += kPanelWidth) {
+    const int jb = std::min(kPanelWidth, k + kb - j);
+    if ((rc = panel<T>(n, j, jb, A, lda, ipiv, info, bars + per_panel * (j / kPanelWidth), slots, st)))
+      return rc;
+    if ((rc = laswp<T>(A, lda, ipiv, j, j + jb, k, j, j + jb, k + kb, nullptr, n, plan, info, st))) return rc;
+    const int rest = k + kb - (j + jb);
+    if (rest > 0) {
+      cplx<T> *L11 = A + (long)j * lda + j;
+      cplx<T> *A12 = A + (long)j * lda + j + jb;
+      if ((rc = trsm<T, false>(jb, rest, L11, lda, A12, lda, st))) return rc;
+      if ((rc = gemm_sub<T>(n - j - jb, rest, jb, A + (long)(j + jb) * lda + j, lda, A12, lda,
+                            A + (long)(j + jb) * lda + j + jb, lda, st)))
+        return rc;
+    }
+  }
+  return HP_OK;
+}
+
+// U12 = L11^-1 A12 for the kb rows of block k and the ncols columns right of it.
+template <typename T>
+static int block_row_solve(int n, int k, int kb, int ncols, cplx<T> *A, long lda, char *work, const Workspace &ws,
+                           hipStream_t st) {
+  int rc;
+  cplx<T> *L11 = A + (long)k * lda + k;
+  cplx<T> *A12 = A + (long)k * lda + k + kb;
+  if constexpr (std::is_same<T, float>::value) {
+    // through the two inverted 128-row diagonal blocks of L11 (kb == 2
+    // kInvBlock whenever columns remain)
+    static_assert(kOuterBlock == 2 * kInvBlock, "outer block = two inverted blocks");
+    if (kb != 2 * kInvBlock) return HP_ERR_ARG;
+    cplx<T> *inv = (cplx<T> *)(work + ws.inv_off);
+    const int b = k / kInvBlock;
+    const size_t iblk = (size_t)kInvBlock * kInvBlock;
+    cplx<T> *A22 = A12 + (long)kInvBlock * lda;
+    if ((rc = tri_inverse<T>(n, A, lda, inv, b, 2, false, st))) return rc;
+    if ((rc = apply_inverse<T>(kInvBlock, ncols, inv + b * iblk, A12, lda, st))) return rc;
+    if ((rc = gemm_sub<T>(kInvBlock, ncols, kInvBlock, L11 + (long)kInvBlock * lda, lda, A12, lda, A22, lda, st)))
+      return rc;
+    return apply_inverse<T>(kInvBlock, ncols, inv + (b + 1) * iblk, A22, lda, st);
+  } else {
+    (void)work;
+    (void)ws;
+    return trsm<T, false>(kb, ncols, L11, lda, A12, lda, st);
+  }
+}
+
+// Blocked right-looking LU with a one-block look-ahead: once the columns of
+// block k+1 have received the update from block k, block k+1 is factored on a
+// second stream while the rest of the trailing matrix is updated on the
+// caller's stream; the two meet before block k+1's interchanges are applied
+// to the other columns.  The panel's latency-bound column steps thus run under
+// the MFMA-bound update.
 template <typename T>
 int lu_factor(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *info, char *work, const Workspace &ws,
               hipStream_t st) {
   int rc;
+  std::lock_guard<std::mutex> lk(g_la_mu);
+  LookAhead *la = nullptr;
+  if ((rc = lookahead_for_device(&la))) return rc;
   unsigned *bars = (unsigned *)(work + ws.sync_off);
   const size_t per_panel = barrier_words(kMaxPanelGroups);
   const int npanels = (n + kPanelWidth - 1) / kPanelWidth;
@@ -824,50 +963,30 @@ int lu_factor(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *info, char
   HP_CHECK_LAUNCH();
   PanelSlots<T> slots = carve_slots<T>(work + ws.slot_off);
   int *plan = (int *)(work + ws.slot_off + slot_bytes_max());
+  if ((rc = factor_block<T>(n, 0, std::min(kOuterBlock, n), A, lda, ipiv, info, bars, slots, plan, st))) return rc;
   for (int k = 0; k < n; k += kOuterBlock) {
     const int kb = std::min(kOuterBlock, n - k);
-    for (int j = k; j < k + kb; j += kPanelWidth) {
-      const int jb = std::min(kPanelWidth, k + kb - j);
-      if ((rc = panel<T>(n, j, jb, A, lda, ipiv, info, bars + per_panel * (j / kPanelWidth), slots, st)))
-        return rc;
-      // the panel's swaps on the other columns of the outer block
-      if ((rc = laswp<T>(A, lda, ipiv, j, j + jb, k, j, j + jb, k + kb, nullptr, n, plan, info, st))) return rc;
-      const int rest = k + kb - (j + jb);
-      if (rest > 0) {
-        cplx<T> *L11 = A + (long)j * lda + j;
-        cplx<T> *A12 = A + (long)j * lda + j + jb;
-        if ((rc = trsm<T, false>(jb, rest, L11, lda, A12, lda, st))) return rc;
-        if ((rc = gemm_sub<T>(n - j - jb, rest, jb, A + (long)(j + jb) * lda + j, lda, A12, lda,
-                              A + (long)(j + jb) * lda + j + jb, lda, st)))
-          return rc;
-      }
-    }
-    // the block's swaps on all columns outside the block, and on perm
+    // the block's interchanges on all columns outside the block, and on perm
     if ((rc = laswp<T>(A, lda, ipiv, k, k + kb, 0, k, k + kb, n, perm, n, plan, info, st))) return rc;
     const int rest = n - k - kb;
-    if (rest > 0) {
-      cplx<T> *L11 = A + (long)k * lda + k;
-      cplx<T> *A12 = A + (long)k * lda + k + kb;
-      if constexpr (std::is_same<T, float>::value) {
-        // U12 = L11^-1 A12 through the two inverted 128-row diagonal blocks of
-        // L11 (kb == 2 kInvBlock whenever columns remain)
-        static_assert(kOuterBlock == 2 * kInvBlock, "outer block = two inverted blocks");
-        cplx<T> *inv = (cplx<T> *)(work + ws.inv_off);
-        const int b = k / kInvBlock;
-        const size_t iblk = (size_t)kInvBlock * kInvBlock;
-        cplx<T> *A22 = A12 + (long)kInvBlock * lda;
-        if ((rc = tri_inverse<T>(n, A, lda, inv, b, 2, false, st))) return rc;
-        if ((rc = apply_inverse<T>(kInvBlock, rest, inv + b * iblk, A12, lda, st))) return rc;
-        if ((rc = gemm_sub<T>(kInvBlock, rest, kInvBlock, L11 + (long)kInvBlock * lda, lda, A12, lda, A22, lda,
-                              st)))
-          return rc;
-        if ((rc = apply_inverse<T>(kInvBlock, rest, inv + (b + 1) * iblk, A22, lda, st))) return rc;
-      } else {
-        if ((rc = trsm<T, false>(kb, rest, L11, lda, A12, lda, st))) return rc;
-      }
-      if ((rc = gemm_sub<T>(rest, rest, kb, A + (long)(k + kb) * lda + k, lda, A12, lda,
-                            A + (long)(k + kb) * lda + k + kb, lda, st)))
-        return rc;
+    if (rest <= 0) break;
+    const int k2 = k + kb;
+    const int kb2 = std::min(kOuterBlock, rest);
+    cplx<T> *L21 = A + (long)k2 * lda + k;
+    cplx<T> *U12 = A + (long)k * lda + k2;
+    cplx<T> *A22 = A + (long)k2 * lda + k2;
+    if ((rc = block_row_solve<T>(n, k, kb, rest, A, lda, work, ws, st))) return rc;
+    // the next block's columns first
+    if ((rc = gemm_sub<T>(rest, kb2, kb, L21, lda, U12, lda, A22, lda, st))) return rc;
+    if (rest > kb2) {
+      HP_CHECK_HIP(hipEventRecord(la->ready, st));
+      HP_CHECK_HIP(hipStreamWaitEvent(la->panel, la->ready, 0));
+      if ((rc = factor_block<T>(n, k2, kb2, A, lda, ipiv, info, bars, slots, plan, la->panel))) return rc;
+      HP_CHECK_HIP(hipEventRecord(la->done, la->panel));
+      if ((rc = gemm_sub<T>(rest, rest - kb2, kb, L21, lda, U12 + kb2, lda, A22 + kb2, lda, st))) return rc;
+      HP_CHECK_HIP(hipStreamWaitEvent(st, la->done, 0));
+    } else {
+      if ((rc = factor_block<T>(n, k2, kb2, A, lda, ipiv, info, bars, slots, plan, st))) return rc;
     }
   }
   return HP_OK;
