@@ -1,10 +1,14 @@
 // Complex GEMM C -= A B on the matrix cores (the trailing update of the LU,
 // Sec. 3.1 / 3.4, and every block update of the triangular solves).
 //
-// Row-major interleaved complex operands.  Each complex product is four real
-// MFMA products ("4M"):  Cr += Ar Br - Ai Bi,  Ci += Ar Bi + Ai Br,  with
-// v_mfma_f64_16x16x4f64 (FP64 accumulation) or v_mfma_f32_16x16x4f32 (FP32
-// accumulation).
+// Row-major interleaved complex operands.  FP64 forms each complex product
+// from four real MFMA products ("4M"):  Cr += Ar Br - Ai Bi,
+// Ci += Ar Bi + Ai Br  (v_mfma_f64_16x16x4f64).  FP32 uses three ("3M"):
+// P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), then Cr += P1 - P2,
+// Ci += P3 - P1 - P2  (v_mfma_f32_16x16x4f32): a quarter fewer matrix-core
+// cycles, with the imaginary part's rounding error bounded by |A||B| instead
+// of its own terms -- the FP32 factors feed the FP64 refinement, which
+// absorbs that; the FP64 factorization keeps the 4M product.
 //
 // Tiling for CDNA4: 256 threads = 4 wavefronts in a 2 x 2 grid; a wavefront
 // owns WTM x WTN MFMA tiles of 16 x 16 complex outputs.  K advances in stages
@@ -117,8 +121,10 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
         ra[q] = *reinterpret_cast<const Vec16<T> *>(p);
       } else {
 #pragma unroll
-        for (int e = 0; e < EV; ++e)
-          ra[q].v[e] = (gr < M && gk + e < K) ? p[e] : cplx<T>{T(0), T(0)};
+        for (int e = 0; e < EV; ++e) {
+          ra[q].v[e] = cplx<T>{T(0), T(0)};
+          if (gr < M && gk + e < K) ra[q].v[e] = p[e];
+        }
       }
     }
 #pragma unroll
@@ -131,8 +137,10 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
         rb[q] = *reinterpret_cast<const Vec16<T> *>(p);
       } else {
 #pragma unroll
-        for (int e = 0; e < EV; ++e)
-          rb[q].v[e] = (gk < K && gc + e < N) ? p[e] : cplx<T>{T(0), T(0)};
+        for (int e = 0; e < EV; ++e) {
+          rb[q].v[e] = cplx<T>{T(0), T(0)};
+          if (gk < K && gc + e < N) rb[q].v[e] = p[e];
+        }
       }
     }
   };
@@ -154,13 +162,16 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
     }
   };
 
-  v4 acc_re[WTM][WTN], acc_im[WTM][WTN];
+  // 4M: acc_re, acc_im; 3M: acc_re = P1, acc_im = P3, acc_p2 = P2
+  constexpr bool M3 = sizeof(T) == 4;
+  v4 acc_re[WTM][WTN], acc_im[WTM][WTN], acc_p2[WTM][WTN];
 #pragma unroll
   for (int i = 0; i < WTM; ++i)
 #pragma unroll
     for (int j = 0; j < WTN; ++j) {
       acc_re[i][j] = v4{0, 0, 0, 0};
       acc_im[i][j] = v4{0, 0, 0, 0};
+      acc_p2[i][j] = v4{0, 0, 0, 0};
     }
 
   const int nk = (K + BK - 1) / BK;
@@ -181,15 +192,31 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
       for (int i = 0; i < WTM; ++i) af[i] = as[kk * PA + wm + i * 16 + fr];
 #pragma unroll
       for (int j = 0; j < WTN; ++j) bf[j] = bs[kk * PB + wn + j * 16 + fr];
+      if constexpr (M3) {
+        T bs_[WTN];
 #pragma unroll
-      for (int i = 0; i < WTM; ++i) {
-        const T nai = -af[i].im;
+        for (int j = 0; j < WTN; ++j) bs_[j] = bf[j].re + bf[j].im;
 #pragma unroll
-        for (int j = 0; j < WTN; ++j) {
-          acc_re[i][j] = Mfma<T>::mac(af[i].re, bf[j].re, acc_re[i][j]);
-          acc_im[i][j] = Mfma<T>::mac(af[i].re, bf[j].im, acc_im[i][j]);
-          acc_re[i][j] = Mfma<T>::mac(nai, bf[j].im, acc_re[i][j]);
-          acc_im[i][j] = Mfma<T>::mac(af[i].im, bf[j].re, acc_im[i][j]);
+        for (int i = 0; i < WTM; ++i) {
+          const T as_ = af[i].re + af[i].im;
+#pragma unroll
+          for (int j = 0; j < WTN; ++j) {
+            acc_re[i][j] = Mfma<T>::mac(af[i].re, bf[j].re, acc_re[i][j]);
+            acc_p2[i][j] = Mfma<T>::mac(af[i].im, bf[j].im, acc_p2[i][j]);
+            acc_im[i][j] = Mfma<T>::mac(as_, bs_[j], acc_im[i][j]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < WTM; ++i) {
+          const T nai = -af[i].im;
+#pragma unroll
+          for (int j = 0; j < WTN; ++j) {
+            acc_re[i][j] = Mfma<T>::mac(af[i].re, bf[j].re, acc_re[i][j]);
+            acc_im[i][j] = Mfma<T>::mac(af[i].re, bf[j].im, acc_im[i][j]);
+            acc_re[i][j] = Mfma<T>::mac(nai, bf[j].im, acc_re[i][j]);
+            acc_im[i][j] = Mfma<T>::mac(af[i].im, bf[j].re, acc_im[i][j]);
+          }
         }
       }
     }
@@ -208,8 +235,14 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
         const int gc = n0 + wn + j * 16 + fr;
         if (gc < N) {
           cplx<T> c = crow[gc];
-          c.re -= acc_re[i][j][r];
-          c.im -= acc_im[i][j][r];
+          if constexpr (M3) {
+            const T p1 = acc_re[i][j][r], p2 = acc_p2[i][j][r], p3 = acc_im[i][j][r];
+            c.re -= p1 - p2;
+            c.im -= p3 - p1 - p2;
+          } else {
+            c.re -= acc_re[i][j][r];
+            c.im -= acc_im[i][j][r];
+          }
           crow[gc] = c;
         }
       }
@@ -251,7 +284,8 @@ template <typename T>
 int gemm_sub_batched(int M, int N, int K, const cplx<T> *A, long lda, long sa, const cplx<T> *B, long ldb, long sb,
                      cplx<T> *C, long ldc, long sc, int batch, hipStream_t st) {
   if (M <= 0 || N <= 0 || K <= 0 || batch <= 0) return HP_OK;
-  TraceScope ts(sizeof(T) == 8 ? TR_GEMM64 : TR_GEMM32, st, 8.0 * M * (double)N * K * batch,
+  // real matrix-core flops of the product: 8 M N K (4M, FP64) or 6 M N K (3M, FP32)
+  TraceScope ts(sizeof(T) == 8 ? TR_GEMM64 : TR_GEMM32, st, (sizeof(T) == 8 ? 8.0 : 6.0) * M * (double)N * K * batch,
                 2.0 * sizeof(cplx<T>) * (double)M * N * batch);
   // 64 x 64 tiles: measured on MI355X (12800^2 x 256 update) at 120 TF/s in
   // FP32 and 57 TF/s in FP64, against 79-110 TF/s and 45 TF/s for the 128-wide

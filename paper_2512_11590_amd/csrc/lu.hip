@@ -494,7 +494,9 @@ __global__ __launch_bounds__(256) void trsm_kernel(int m, int ncols, const cplx<
   const int ncw = min(CW, ncols - col0);
   for (int e = tid; e < m * CW; e += 256) {
     const int rr = e / CW, cc = e - rr * CW;
-    Xs[e] = (cc < ncw) ? X[(long)rr * ldx + col0 + cc] : cplx<T>{T(0), T(0)};
+    cplx<T> v{T(0), T(0)};
+    if (cc < ncw) v = X[(long)rr * ldx + col0 + cc];
+    Xs[e] = v;
   }
   const int nblk = (m + BS - 1) / BS;
   for (int bi = 0; bi < nblk; ++bi) {
@@ -585,86 +587,154 @@ constexpr int kInvLd = kInvBlock + 1;  // LDS row stride (complex elements)
 
 // One workgroup per diagonal block: block index blk0 + blockIdx.x; blockIdx.y
 // == 0 inverts the unit-lower block of L, blockIdx.y == 1 the upper block of
-// U.  Rows of the inverse are produced in substitution order, all columns of
-// a row at once (two threads per column, one per parity of the summation
-// index).  The factor's rows reach LDS through a two-chunk ring of
-// kInvChunk rows each: a chunk's loads are issued a whole chunk of rows ahead
-// of its use, so the row-by-row recurrence never waits on HBM.  Output: dense
-// kInvBlock x kInvBlock row-major blocks, the nbt lower inverses first, then
-// the nbt upper ones; entries outside a ragged last block are zero.
-constexpr int kInvChunk = 8;
+// U.  The block is staged in LDS (extended by the identity past a ragged
+// edge) and inverted by recursive doubling: first its eight 16 x 16 diagonal
+// blocks (one thread per column, substitution in registers), then for
+// s = 16, 32, 64 every 2s-block from its two inverted s-blocks,
+//   [A 0; C D]^-1 = [A^-1 0; -D^-1 C A^-1  D^-1]   (lower),
+//   [A B; 0 D]^-1 = [A^-1  -A^-1 B D^-1; 0 D^-1]   (upper),
+// each off-diagonal product formed by all threads in two in-place passes.
+// Output: dense kInvBlock x kInvBlock row-major blocks, the nbt lower inverses
+// first, then the nbt upper ones; entries outside a ragged last block are zero.
+constexpr int kInvBase = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void tri_inverse_kernel(int n, int blk0, int nbt, const cplx<T> *__restrict__ LU,
                                                           long lda, cplx<T> *__restrict__ Inv) {
-  constexpr int CH = kInvChunk;
-  constexpr int PER = CH * kInvBlock / 256;  // ring elements loaded per thread per chunk
+  constexpr int NB = kInvBlock, LD = kInvLd, B0 = kInvBase;
+  constexpr int ND = NB / B0;  // diagonal base blocks
   extern __shared__ __align__(16) char smem_raw[];
-  cplx<T> *Xs = reinterpret_cast<cplx<T> *>(smem_raw);  // [kInvBlock][kInvLd]
-  cplx<T> *Ring = Xs + kInvBlock * kInvLd;              // [2][CH][kInvBlock]: rows in use order
+  cplx<T> *X = reinterpret_cast<cplx<T> *>(smem_raw);  // [NB][LD]
+  cplx<T> *Dg = X + NB * LD;                           // [ND][B0][B0 + 1]
   const bool upper = blockIdx.y != 0;
   const int blk = blk0 + blockIdx.x;
-  const int b0 = blk * kInvBlock;
-  const int bs = min(kInvBlock, n - b0);
+  const int b0 = blk * NB;
+  const int bs = min(NB, n - b0);
   const cplx<T> *Tb = LU + (long)b0 * lda + b0;
   const int tid = threadIdx.x;
-  const int j = tid >> 1, half = tid & 1;
   const cplx<T> zero{T(0), T(0)};
-  // the row used at step s (rows outside the block read as zero)
-  auto row_of = [&](int s) { return upper ? bs - 1 - s : s; };
-  cplx<T> pre[PER];
-  auto load_chunk = [&](int c) {
+  // stage the triangle (strict lower of L, upper of U incl. its diagonal)
+  for (int e0 = 0; e0 < NB * NB; e0 += 8 * 256) {
+    cplx<T> v[8];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + 256 * q;
-      const int u = e / kInvBlock, col = e - u * kInvBlock;
-      const int st = c * CH + u;
-      pre[q] = (st < bs && col < bs) ? Tb[(long)row_of(st) * lda + col] : zero;
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256 + tid;
+      const int r = e / NB, c = e - r * NB;
+      v[u] = zero;
+      if (r < bs && c < bs) {
+        if (upper ? (r <= c) : (r > c)) v[u] = Tb[(long)r * lda + c];
+      } else if (r == c) {
+        v[u].re = T(1);
+      }
     }
-  };
-  auto store_chunk = [&](int c) {
-    cplx<T> *slot = Ring + (c & 1) * CH * kInvBlock;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) slot[tid + 256 * q] = pre[q];
-  };
-  for (int e = tid; e < kInvBlock * kInvLd; e += 256) Xs[e] = zero;
-  const int nch = (bs + CH - 1) / CH;
-  load_chunk(0);
-  store_chunk(0);
-  if (nch > 1) load_chunk(1);
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256 + tid;
+      const int r = e / NB, c = e - r * NB;
+      X[r * LD + c] = v[u];
+    }
+  }
   __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    const cplx<T> *slot = Ring + (c & 1) * CH * kInvBlock;
-    for (int u = 0; u < CH; ++u) {
-      const int s = c * CH + u;
-      if (s >= bs) break;
-      const int i = row_of(s);
-      const cplx<T> *trow = slot + u * kInvBlock;
-      const bool active = j < bs && (upper ? j >= i : j <= i);
-      cplx<T> acc = (active && half == 0 && i == j) ? cplx<T>{T(1), T(0)} : zero;
-      if (active) {
-        if (!upper) {
-          for (int k = j + half; k < i; k += 2) acc = cfms(acc, trow[k], Xs[k * kInvLd + j]);
-        } else {
-          for (int k = i + 1 + half; k <= j; k += 2) acc = cfms(acc, trow[k], Xs[k * kInvLd + j]);
+  // inverses of the diagonal 16 x 16 blocks: thread (d, jj) solves for column jj of block d
+  if (tid < ND * B0) {
+    const int d = tid / B0, jj = tid - d * B0, o = d * B0;
+    cplx<T> x[B0];
+    if (!upper) {
+#pragma unroll
+      for (int ii = 0; ii < B0; ++ii) {
+        cplx<T> acc{T(ii == jj ? 1 : 0), T(0)};
+#pragma unroll
+        for (int k = 0; k < ii; ++k) acc = cfms(acc, X[(o + ii) * LD + o + k], x[k]);
+        x[ii] = acc;
+      }
+    } else {
+#pragma unroll
+      for (int ii = B0 - 1; ii >= 0; --ii) {
+        cplx<T> acc{T(ii == jj ? 1 : 0), T(0)};
+#pragma unroll
+        for (int k = ii + 1; k < B0; ++k) acc = cfms(acc, X[(o + ii) * LD + o + k], x[k]);
+        x[ii] = cmul(acc, crcp(X[(o + ii) * LD + o + ii]));
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < B0; ++ii) Dg[(d * B0 + ii) * (B0 + 1) + jj] = x[ii];
+  }
+  __syncthreads();
+  for (int e = tid; e < ND * B0 * B0; e += 256) {
+    const int d = e / (B0 * B0), ii = (e / B0) % B0, jj = e % B0;
+    X[(d * B0 + ii) * LD + d * B0 + jj] = Dg[(d * B0 + ii) * (B0 + 1) + jj];
+  }
+  __syncthreads();
+  // doubling: level s combines pairs of inverted s-blocks
+  for (int s = B0; s < NB; s *= 2) {
+    const int per = (NB / 2) * s / 256;  // elements per thread: 4, 8, 16
+    cplx<T> t[NB / 8];
+    // pass 1: T = C A (lower) or T = B D (upper), into registers
+#pragma unroll
+    for (int q = 0; q < NB / 8; ++q) {
+      if (q >= per) break;
+      const int e = tid + 256 * q;
+      const int p = e / (s * s), rem = e - p * s * s, r = rem / s, c = rem - r * s, o = 2 * s * p;
+      cplx<T> acc = zero;
+      if (!upper) {
+        for (int k = c; k < s; ++k) acc = cfms(acc, X[(o + s + r) * LD + o + k], X[(o + k) * LD + o + c]);
+      } else {
+        for (int k = 0; k <= c; ++k) acc = cfms(acc, X[(o + r) * LD + o + s + k], X[(o + s + k) * LD + o + s + c]);
+      }
+      t[q] = acc;  // holds -T
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB / 8; ++q) {
+      if (q >= per) break;
+      const int e = tid + 256 * q;
+      const int p = e / (s * s), rem = e - p * s * s, r = rem / s, c = rem - r * s, o = 2 * s * p;
+      if (!upper)
+        X[(o + s + r) * LD + o + c] = t[q];
+      else
+        X[(o + r) * LD + o + s + c] = t[q];
+    }
+    __syncthreads();
+    // pass 2: D^-1 (-T) (lower) or A^-1 (-T) (upper), in place of T
+#pragma unroll
+    for (int q = 0; q < NB / 8; ++q) {
+      if (q >= per) break;
+      const int e = tid + 256 * q;
+      const int p = e / (s * s), rem = e - p * s * s, r = rem / s, c = rem - r * s, o = 2 * s * p;
+      cplx<T> acc = zero;
+      if (!upper) {
+        for (int k = 0; k <= r; ++k) {
+          const cplx<T> a = X[(o + s + r) * LD + o + s + k], b = X[(o + s + k) * LD + o + c];
+          acc.re += a.re * b.re - a.im * b.im;
+          acc.im += a.re * b.im + a.im * b.re;
+        }
+      } else {
+        for (int k = r; k < s; ++k) {
+          const cplx<T> a = X[(o + r) * LD + o + k], b = X[(o + k) * LD + o + s + c];
+          acc.re += a.re * b.re - a.im * b.im;
+          acc.im += a.re * b.im + a.im * b.re;
         }
       }
-      acc.re += __shfl_xor(acc.re, 1);
-      acc.im += __shfl_xor(acc.im, 1);
-      if (active && half == 0) Xs[i * kInvLd + j] = upper ? cmul(acc, crcp(trow[i])) : acc;
-      __syncthreads();
+      t[q] = acc;
     }
-    // chunk c + 1 (loaded during chunk c) into the slot chunk c - 1 used;
-    // then the loads of chunk c + 2
-    if (c + 1 < nch) {
-      store_chunk(c + 1);
-      if (c + 2 < nch) load_chunk(c + 2);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB / 8; ++q) {
+      if (q >= per) break;
+      const int e = tid + 256 * q;
+      const int p = e / (s * s), rem = e - p * s * s, r = rem / s, c = rem - r * s, o = 2 * s * p;
+      if (!upper)
+        X[(o + s + r) * LD + o + c] = t[q];
+      else
+        X[(o + r) * LD + o + s + c] = t[q];
     }
     __syncthreads();
   }
-  cplx<T> *out = Inv + ((size_t)blockIdx.y * nbt + blk) * kInvBlock * kInvBlock;
-  for (int e = tid; e < kInvBlock * kInvBlock; e += 256) {
-    const int r = e / kInvBlock, c = e - r * kInvBlock;
-    out[e] = Xs[r * kInvLd + c];
+  cplx<T> *out = Inv + ((size_t)blockIdx.y * nbt + blk) * NB * NB;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e / NB, c = e - r * NB;
+    cplx<T> v = zero;
+    if (r < bs && c < bs) v = X[r * LD + c];
+    out[e] = v;
   }
 }
 
@@ -673,7 +743,7 @@ template <typename T>
 static int tri_inverse(int n, const cplx<T> *LU, long lda, cplx<T> *inv, int blk0, int nblk, bool both,
                        hipStream_t st) {
   if (nblk <= 0) return HP_OK;
-  const size_t shm = ((size_t)kInvBlock * kInvLd + 2 * kInvChunk * kInvBlock) * sizeof(cplx<T>);
+  const size_t shm = ((size_t)kInvBlock * kInvLd + (size_t)kInvBlock * (kInvBase + 1)) * sizeof(cplx<T>);
   int rc = ensure_dynamic_lds((const void *)tri_inverse_kernel<T>, shm);
   if (rc) return rc;
   const int nbt = (n + kInvBlock - 1) / kInvBlock;
