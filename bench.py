@@ -31,6 +31,12 @@ sys.path.insert(0, ROOT)
 METRIC = "N=25600 complex solve s & TF/s, FP32-LU+IR vs FP64 LU; served solves/s, p99"
 PEAK_FP32_MFMA = 157.3  # TF/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6   # TF/s, MI355X dense FP64 matrix
+# HBM bytes per launch of the FP32 GEMM on this command, from FETCH_SIZE and
+# WRITE_SIZE counter runs scaled by a 1 GiB copy
+# (profiles/gemm_sub_kernel_fp32_large_N25600_traffic.md); valid only for the
+# GEMM source it was measured on.
+GEMM_TRAFFIC = {"bytes_per_launch": 150.67e6,
+                "gemm_source_sha256": "d86159250730e6e0c6c425132b9e3131ba139dbb07b1c46d179267daf4d7e194"}
 
 
 def parse():
@@ -43,6 +49,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-refine", type=int, default=30)
     ap.add_argument("--tol", type=float, default=0.0)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=24)
+    ap.add_argument("--served-rate", type=float, default=4.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--served-slots", type=int, default=4)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (a plain copy of known size, "
                          "to scale hardware traffic counters) and exit")
@@ -75,6 +85,50 @@ def timed_steps(solver, energies, steps, warmup, H, torch, gemm_stage, **run):
     stages = H.hp_trace_read()
     H.hp_trace_enable(False)
     return (t1 - t0) / steps, infos, gemm, stages
+
+
+def gemm_traffic():
+    """Measured HBM bytes per GEMM launch, or None if the GEMM source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2512_11590_amd", "csrc", "gemm.hip")
+    with open(path, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    return GEMM_TRAFFIC["bytes_per_launch"] if sha == GEMM_TRAFFIC["gemm_source_sha256"] else None
+
+
+def served_stream(args, H, torch):
+    """The served stream: Poisson arrivals, N log-uniform in [500, 16000],
+    1-8 energies each, continuous batching over a few slots; FP32 + IR, then
+    FP64 on the same arrivals.  Reports solves/s, p50/p99 latency and the
+    largest S difference between the two precisions per request."""
+    import numpy as np
+    from paper_2512_11590_amd import serve
+    from workload import served_requests
+    reqs = served_requests(args.served_requests, args.served_rate)
+    res = {"requests": len(reqs), "rate_hz": args.served_rate, "slots": args.served_slots,
+           "N_range": [min(sp.nc * sp.nr for _, sp in reqs), max(sp.nc * sp.nr for _, sp in reqs)],
+           "energies": int(sum(len(sp.energies) for _, sp in reqs))}
+    runs = {}
+    for name, prec in (("fp32_ir", H.HP_C64), ("fp64", H.HP_C128)):
+        print(f"[bench] served stream {name}: {len(reqs)} requests at {args.served_rate}/s", file=sys.stderr,
+              flush=True)
+        t0 = time.perf_counter()
+        done = []
+
+        def progress(req, name=name, t0=t0):
+            done.append(req.rid)
+            print(f"[bench]   {name}: request {req.rid} (N={req.n}, {len(req.energies)} energies) done, "
+                  f"{len(done)}/{len(reqs)} at {time.perf_counter() - t0:.1f} s"
+                  + (f" error {req.error}" if req.error else ""), file=sys.stderr, flush=True)
+
+        runs[name] = serve.Server(slots=args.served_slots, prec=prec).run(reqs, progress=progress)
+        torch.cuda.empty_cache()
+        res[name] = serve.summary(runs[name])
+    diffs = [float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+             for ra, rb in zip(runs["fp32_ir"], runs["fp64"]) if ra.error is None and rb.error is None
+             for a, b in zip(ra.S, rb.S)]
+    res["S_relerr_fp32ir_vs_fp64_max"] = max(diffs) if diffs else None
+    return res
 
 
 def cpu_baseline(n_full: int):
@@ -146,7 +200,7 @@ def main():
     out["roofline"] = {"bound": "mfma", "kernel": "gemm_sub_kernel<float> (complex 3M GEMM, FP32 MFMA; "
                                                   "achieved counts its 6MNK real flops per launch)",
                        "achieved": ach, "peak": PEAK_FP32_MFMA, "unit": "TF/s", "frac": ach / PEAK_FP32_MFMA,
-                       "traffic": None, "launches_per_step": g["launches"] / args.steps,
+                       "traffic": gemm_traffic(), "launches_per_step": g["launches"] / args.steps,
                        "avg_launch_us": g["ms"] * 1e3 / max(1, g["launches"])}
     S32 = s32.S.cpu().numpy().copy()
     last_e = float(sp.energies[(args.steps - 1) % len(sp.energies)])
@@ -168,6 +222,8 @@ def main():
                           "S_relerr_fp32ir_vs_fp64_at_E": [last_e, err]}
         del s64
         torch.cuda.empty_cache()
+    if not args.no_served:
+        out["served"] = served_stream(args, H, torch)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(n)

@@ -106,7 +106,10 @@ int hp_build_matrix(const hp_system *sys, double E, int prec, void *C, long ldc,
  * set to 0, or k+1 for the first exactly zero pivot column k, or -1 if a
  * bounded inter-workgroup wait expired.  work: device workspace of at least
  * hp_workspace_bytes(n, 0, prec) bytes.  Asynchronous: does not synchronize;
- * read *info after the stream completes.
+ * read *info after the stream completes.  Internally, block k+1 is factored
+ * on a second stream (one per device and caller stream, created on first
+ * use, default priority) while block k's trailing update runs on `stream`;
+ * all of it is ordered before work enqueued on `stream` afterwards.
  * Errors: HP_ERR_ARG, HP_ERR_WORKSPACE, HP_ERR_UNSUPPORTED (n too large for
  * the co-resident panel grid), HP_ERR_HIP. */
 int hp_factor(int n, int prec, void *A, long lda, int *ipiv, int *perm, int *info,
@@ -174,6 +177,23 @@ int hp_coulomb(int l, double eta, double rho, double *out);
  * eta[nch], rho[nch] -> out[nch*4]. */
 int hp_coulomb_device(int nch, const int *l, const double *eta, const double *rho,
                       double *out, void *stream);
+
+/* ---- concurrency ------------------------------------------------------- */
+
+/* Number of factorizations that may be requested at the same time on one
+ * device, from different streams (process-wide, default 1).  A panel grid's
+ * workgroups wait for each other at every column, so they must be resident
+ * together.  With 1, each factorization runs on its caller's stream (plus the
+ * look-ahead stream) with panel workgroups of up to ~150 KB of LDS.  With
+ * k > 1, factorizations are serialized on one device-wide stream (the
+ * caller's stream hands over and waits by events; its other work still
+ * overlaps with other streams), and panel workgroups hold at most 64 KB of
+ * rows so that they find room beside other streams' kernels: then a panel
+ * of more than 128 x 64 KB of rows (n > 32768 in FP32, n > 16384 in FP64)
+ * fails with HP_ERR_UNSUPPORTED.  Returns the previous setting, or HP_ERR_ARG
+ * if k is outside [1, 256].  Host-side setting; takes effect for
+ * factorizations enqueued afterwards. */
+int hp_set_concurrency(int k);
 
 /* ---- instrumentation ---------------------------------------------------- */
 

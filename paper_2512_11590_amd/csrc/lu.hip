@@ -19,6 +19,9 @@
 #include "common.h"
 
 #include <type_traits>
+#include <utility>
+#include <memory>
+#include <atomic>
 #include <mutex>
 #include <map>
 
@@ -130,7 +133,10 @@ __device__ __forceinline__ void grid_arrive(unsigned *bar, unsigned epoch) {
 
 __device__ __forceinline__ void grid_wait(unsigned *bar, unsigned ngroups, unsigned epoch, int *flag) {
   (void)ngroups;
-  for (unsigned g = threadIdx.x; g < gridDim.x; g += blockDim.x) {
+  // once a wait has expired anywhere in the grid, no workgroup waits again,
+  // so a failed factorization drains at memory speed
+  const bool failed = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == -1;
+  for (unsigned g = threadIdx.x; !failed && g < gridDim.x; g += blockDim.x) {
     unsigned spins = 0;
     while (__hip_atomic_load(bar + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
       __builtin_amdgcn_s_sleep(1);
@@ -873,12 +879,16 @@ static size_t slot_bytes_max() {
 }
 
 // Rows per workgroup of the panel grid, and the grid size.
+// Number of factorizations that may run at the same time on one device
+// (hp_set_concurrency).
+std::atomic<int> g_concurrency{1};
+
 template <typename T>
-static void panel_grid(int m, int &G, int &rpw) {
+static int panel_grid(int m, int lds_cap, int &G, int &rpw) {
   // at least 64 rows per workgroup, at most kMaxPanelGroups workgroups (one
   // per CU; a 25600-row panel: 128 groups factor ~9% faster than 64 with the
-  // per-group arrival flags), and at most ~150 KB of LDS per workgroup
-  const int rpw_max = (150 * 1024) / (int)(kPanelWidth * sizeof(cplx<T>));
+  // per-group arrival flags), and at most lds_cap bytes of rows per workgroup
+  const int rpw_max = lds_cap / (int)(kPanelWidth * sizeof(cplx<T>));
   const int rpw_min = 64;
   G = (m + rpw_min - 1) / rpw_min;
   G = std::min(G, kMaxPanelGroups);
@@ -893,15 +903,15 @@ static void panel_grid(int m, int &G, int &rpw) {
   if (rpw > rpw_max) {
     rpw = rpw_max;
     G = (m + rpw - 1) / rpw;
+    if (G > kMaxPanelGroups) return HP_ERR_UNSUPPORTED;  // the rows do not fit the workgroups' LDS
   }
+  return HP_OK;
 }
 
-// The panel grid must fit the device at once: at most one workgroup per CU.
-static int check_resident(int G, size_t shm) {
-  int dev = 0, cus = 0;
+static int device_cus(int *cus) {
+  int dev = 0;
   HP_CHECK_HIP(hipGetDevice(&dev));
-  HP_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  if (G > cus || shm > 160 * 1024) return HP_ERR_UNSUPPORTED;
+  HP_CHECK_HIP(hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev));
   return HP_OK;
 }
 
@@ -909,9 +919,14 @@ template <typename T>
 static int panel(int n, int j0, int w, cplx<T> *A, long lda, int *ipiv, int *info, unsigned *bar,
                  const PanelSlots<T> &s, hipStream_t st) {
   const int m = n - j0;
-  int G, rpw;
-  panel_grid<T>(m, G, rpw);
-  if (G > kMaxPanelGroups) return HP_ERR_UNSUPPORTED;
+  int cus = 0, G, rpw;
+  int rc0 = device_cus(&cus);
+  if (rc0) return rc0;
+  // with other streams' work on the device, small workgroups (<= 64 KB of
+  // rows) so that each finds room beside the kernels already resident
+  const int conc = g_concurrency.load(std::memory_order_relaxed);
+  if ((rc0 = panel_grid<T>(m, (conc > 1 ? 64 : 150) * 1024, G, rpw))) return rc0;
+  if (G > kMaxPanelGroups || G > cus) return HP_ERR_UNSUPPORTED;
   size_t shm = (size_t)rpw * kPanelWidth * sizeof(cplx<T>);
   int rc = ensure_dynamic_lds((const void *)panel_kernel<T>, shm);
   if (rc) return rc;
@@ -923,36 +938,43 @@ static int panel(int n, int j0, int w, cplx<T> *A, long lda, int *ipiv, int *inf
   cplx<T> *sdiag = s.diag;
   void *args[] = {&nn, &jj0, &ww, &A, &ld, &ipiv, &info, &bar, &srows, &sval, &srow, &sdiag, &rp};
   // All G workgroups must become resident together (they meet at grid
-  // barriers).  G is at most one per CU and the kernel fits a CU on its own, so
-  // on an idle device they are; beside a running trailing update they become
-  // resident as its workgroups retire, which the barriers' bounded waits cover.
-  if ((rc = check_resident(G, shm))) return rc;
+  // barriers).  G is at most one per CU and one workgroup fits a CU, so on an
+  // idle device they are; beside other kernels (this factorization's own
+  // trailing update, other streams' work) they become resident as those
+  // kernels' workgroups retire, which the barriers' bounded waits cover.
+  // Only one factorization's panels are on the device at any time (see
+  // lu_factor), so panel grids never wait for each other.
   TraceScope ts(TR_PANEL, st, 4.0 * (double)m * w * w, 2.0 * sizeof(cplx<T>) * (double)m * w);
   HP_CHECK_HIP(hipLaunchKernel((const void *)panel_kernel<T>, dim3(G), dim3(256), args, shm, st));
   return HP_OK;
 }
 
-// Second stream and events for the look-ahead, one set per device, created on
-// first use (default priority).  Factorizations on one device are enqueued
-// one at a time (g_la_mu), so the shared stream only serializes them.
+// Second stream and events for the look-ahead, one set per (device, caller
+// stream), created on first use (default priority).  A factorization holds
+// its set's lock while it enqueues, so two host threads that factor on one
+// stream serialize, and factorizations on different streams overlap.
 namespace {
 struct LookAhead {
+  std::mutex mu;
   hipStream_t panel = nullptr;
   hipEvent_t ready = nullptr, done = nullptr;
 };
 std::mutex g_la_mu;
-std::map<int, LookAhead> g_la;
+std::map<std::pair<int, hipStream_t>, std::unique_ptr<LookAhead>> g_la;
 
-int lookahead_for_device(LookAhead **out) {
+int lookahead_for(hipStream_t st, LookAhead **out) {
   int dev = 0;
   HP_CHECK_HIP(hipGetDevice(&dev));
-  LookAhead &la = g_la[dev];
-  if (!la.panel) {
-    HP_CHECK_HIP(hipStreamCreateWithFlags(&la.panel, hipStreamNonBlocking));
-    HP_CHECK_HIP(hipEventCreateWithFlags(&la.ready, hipEventDisableTiming));
-    HP_CHECK_HIP(hipEventCreateWithFlags(&la.done, hipEventDisableTiming));
+  std::lock_guard<std::mutex> lk(g_la_mu);
+  std::unique_ptr<LookAhead> &la = g_la[{dev, st}];
+  if (!la) {
+    auto fresh = std::make_unique<LookAhead>();
+    HP_CHECK_HIP(hipStreamCreateWithFlags(&fresh->panel, hipStreamNonBlocking));
+    HP_CHECK_HIP(hipEventCreateWithFlags(&fresh->ready, hipEventDisableTiming));
+    HP_CHECK_HIP(hipEventCreateWithFlags(&fresh->done, hipEventDisableTiming));
+    la = std::move(fresh);
   }
-  *out = &la;
+  *out = la.get();
   return HP_OK;
 }
 }  // namespace
@@ -1018,12 +1040,12 @@ static int block_row_solve(int n, int k, int kb, int ncols, cplx<T> *A, long lda
 // to the other columns.  The panel's latency-bound column steps thus run under
 // the MFMA-bound update.
 template <typename T>
-int lu_factor(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *info, char *work, const Workspace &ws,
-              hipStream_t st) {
+static int lu_factor_on(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *info, char *work,
+                        const Workspace &ws, hipStream_t st) {
   int rc;
-  std::lock_guard<std::mutex> lk(g_la_mu);
   LookAhead *la = nullptr;
-  if ((rc = lookahead_for_device(&la))) return rc;
+  if ((rc = lookahead_for(st, &la))) return rc;
+  std::lock_guard<std::mutex> lk(la->mu);
   unsigned *bars = (unsigned *)(work + ws.sync_off);
   const size_t per_panel = barrier_words(kMaxPanelGroups);
   const int npanels = (n + kPanelWidth - 1) / kPanelWidth;
@@ -1060,6 +1082,54 @@ int lu_factor(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *info, char
     }
   }
   return HP_OK;
+}
+
+// Several factorizations may be requested at once on different streams
+// (hp_set_concurrency > 1).  Their panel grids must not wait for each other,
+// so they are serialized on one device-wide factorization stream: the
+// caller's stream hands over with an event and waits for the result; the
+// caller's other work (assembly, solves of other systems) still overlaps.
+namespace {
+struct FactorQueue {
+  std::mutex mu;
+  hipStream_t st = nullptr;
+  hipEvent_t in = nullptr, out = nullptr;
+};
+std::mutex g_fq_mu;
+std::map<int, std::unique_ptr<FactorQueue>> g_fq;
+
+int factor_queue(FactorQueue **out) {
+  int dev = 0;
+  HP_CHECK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_fq_mu);
+  std::unique_ptr<FactorQueue> &fq = g_fq[dev];
+  if (!fq) {
+    auto fresh = std::make_unique<FactorQueue>();
+    HP_CHECK_HIP(hipStreamCreateWithFlags(&fresh->st, hipStreamNonBlocking));
+    HP_CHECK_HIP(hipEventCreateWithFlags(&fresh->in, hipEventDisableTiming));
+    HP_CHECK_HIP(hipEventCreateWithFlags(&fresh->out, hipEventDisableTiming));
+    fq = std::move(fresh);
+  }
+  *out = fq.get();
+  return HP_OK;
+}
+}  // namespace
+
+template <typename T>
+int lu_factor(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *info, char *work, const Workspace &ws,
+              hipStream_t st) {
+  if (g_concurrency.load(std::memory_order_relaxed) <= 1)
+    return lu_factor_on<T>(n, A, lda, ipiv, perm, info, work, ws, st);
+  FactorQueue *fq = nullptr;
+  int rc = factor_queue(&fq);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(fq->mu);
+  HP_CHECK_HIP(hipEventRecord(fq->in, st));
+  HP_CHECK_HIP(hipStreamWaitEvent(fq->st, fq->in, 0));
+  rc = lu_factor_on<T>(n, A, lda, ipiv, perm, info, work, ws, fq->st);
+  HP_CHECK_HIP(hipEventRecord(fq->out, fq->st));
+  HP_CHECK_HIP(hipStreamWaitEvent(st, fq->out, 0));
+  return rc;
 }
 
 // ------------------------------------------------------------------ solve --
@@ -1169,3 +1239,8 @@ size_t factor_sync_bytes(int n) {
 size_t factor_slot_bytes() { return slot_bytes_max() + align_up(sizeof(int) * (1 + 2 * kPlanMax), 256); }
 
 }  // namespace hp
+
+extern "C" int hp_set_concurrency(int factorizations) {
+  if (factorizations < 1 || factorizations > 256) return HP_ERR_ARG;
+  return hp::g_concurrency.exchange(factorizations);
+}

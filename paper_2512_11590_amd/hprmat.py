@@ -54,7 +54,7 @@ class HpSolveInfo(ctypes.Structure):
 EXPORTS = ["hp_mesh", "hp_workspace_bytes", "hp_build_matrix", "hp_factor", "hp_solve",
            "hp_lu_solve", "hp_rmatrix", "hp_smatrix", "hp_coulomb", "hp_coulomb_device",
            "hp_build_info", "hp_strerror", "hp_trace_enable", "hp_trace_read", "hp_last_error",
-           "hp_gemm_sub"]
+           "hp_gemm_sub", "hp_set_concurrency"]
 
 _lib = None
 
@@ -107,6 +107,8 @@ def lib() -> ctypes.CDLL:
     L.hp_coulomb.restype = c_int
     L.hp_coulomb_device.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.hp_coulomb_device.restype = c_int
+    L.hp_set_concurrency.argtypes = [c_int]
+    L.hp_set_concurrency.restype = c_int
     L.hp_trace_enable.argtypes = [c_int]
     L.hp_trace_enable.restype = c_int
     L.hp_trace_read.argtypes = [ctypes.POINTER(HpTraceStat), c_int]
@@ -221,6 +223,14 @@ def hp_smatrix(sys: HpSystem, E: float, R, S, work, stream=None) -> int:
 def hp_coulomb_device(l, eta, rho, out, stream=None) -> None:
     _check(lib().hp_coulomb_device(int(l.numel()), _ptr(l), _ptr(eta), _ptr(rho), _ptr(out),
                                    _stream(stream)), "hp_coulomb_device")
+
+
+def hp_set_concurrency(factorizations: int) -> int:
+    """Factorizations that may run at once on the device; returns the previous value."""
+    rc = lib().hp_set_concurrency(int(factorizations))
+    if rc < 0:
+        raise HprmatError(rc, "hp_set_concurrency")
+    return rc
 
 
 TRACE_STAGES = ("assemble", "panel", "laswp", "trsm", "gemm_c128", "gemm_c64", "residual", "refine",

@@ -1,0 +1,210 @@
+"""A served stream of R-matrix solve requests on one GPU (continuous batching).
+
+A request is one coupled-channel system (its potential, mesh and channel
+data) with 1-8 energies; it arrives at a given time.  The server owns a fixed
+number of slots, each a host thread with its own HIP stream.  A request is
+admitted, in arrival order, as soon as a slot is free and its device memory
+fits the HBM budget; requests that arrive while others are on the GPU are
+therefore admitted as slots and memory free up, and the device work of the
+slots overlaps (different streams).  Per request the slot uploads the system
+once and runs, per energy, the five entry points of the C ABI
+(hp_build_matrix -> hp_factor -> hp_solve -> hp_rmatrix -> hp_smatrix) in
+FP32 + FP64 refinement or in FP64.  Factors are not shared between requests:
+C(E) differs for every (system, energy).
+
+Panel grids must be resident as a whole, so the server declares its number
+of slots to the library (hp_set_concurrency), which then serializes the
+factorizations of all slots on one device-wide stream and keeps panel
+workgroups small; everything else of the slots overlaps.
+
+Latency of a request = completion time - arrival time (host clock, the
+request's S matrices copied back).  The summary reports p50 / p99 latency and
+solves (energies) per second over the makespan.  All device arithmetic runs
+in the HIP library; this module only schedules.
+"""
+from __future__ import annotations
+
+import contextlib
+import threading
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import hprmat as H
+from . import pipeline as P
+
+
+def request_bytes(nc: int, nr: int, prec: int) -> int:
+    """Device bytes one request holds while admitted (matrix, workspace, solution,
+    potential values, small buffers)."""
+    n = nc * nr
+    elt = 8 if prec == H.HP_C64 else 16
+    return (n * n * elt + H.hp_workspace_bytes(n, nc, prec) + H.hp_workspace_bytes(nc, nc, H.HP_C128)
+            + n * nc * 16 + 3 * nc * nc * 16 + nr * nc * nc * 16 + 64 * n)
+
+
+@dataclass
+class Served:
+    rid: int
+    n: int
+    nc: int
+    energies: np.ndarray
+    arrival: float
+    admitted: float = 0.0
+    done: float = 0.0
+    R: list = field(default_factory=list)
+    S: list = field(default_factory=list)
+    iterations: list = field(default_factory=list)
+    fallback: list = field(default_factory=list)
+    error: str | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class Server:
+    def __init__(self, slots: int = 4, prec: int = H.HP_C64, hbm_budget: int | None = None,
+                 max_refine: int = 30, tol: float = 0.0, device: str = "cuda", executor=None,
+                 bytes_of=None):
+        """executor(req, params) runs one admitted request (default: the HIP
+        pipeline on the slot's stream); bytes_of(params) its device bytes
+        (default: request_bytes).  Both are replaceable so the scheduling can be
+        tested without a device."""
+        if slots < 1:
+            raise ValueError("slots >= 1")
+        self.slots = slots
+        self.prec = prec
+        self.max_refine = max_refine
+        self.tol = tol
+        self._execute = executor or self._run_request
+        self._bytes_of = bytes_of or (lambda sp: request_bytes(int(sp.nc), int(sp.nr), self.prec))
+        dev = torch.device(device)
+        self.gpu = dev.type == "cuda"
+        if self.gpu:
+            self.device = dev if dev.index is not None else torch.device(dev.type, torch.cuda.current_device())
+            props = torch.cuda.get_device_properties(self.device)
+            self.cus = int(props.multi_processor_count)
+            total = props.total_memory
+        else:
+            if hbm_budget is None:
+                raise ValueError("a budget is needed without a device")
+            self.device, self.cus, total = dev, 256, hbm_budget
+        self.budget = int(hbm_budget if hbm_budget is not None else total * 0.6)
+        self._cv = threading.Condition()
+        self._pending: deque = deque()
+        self._in_use = 0
+        self._closed = False
+
+    # -- admission -----------------------------------------------------------
+    def _admit(self):
+        with self._cv:
+            while True:
+                if self._pending:
+                    req, params, need = self._pending[0]
+                    if need > self.budget:
+                        self._pending.popleft()
+                        req.error = f"needs {need} bytes, more than the HBM budget {self.budget}"
+                        req.admitted = req.done = time.perf_counter() - self._t0
+                        self._cv.notify_all()
+                        continue
+                    if self._in_use + need <= self.budget:
+                        self._pending.popleft()
+                        self._in_use += need
+                        req.admitted = time.perf_counter() - self._t0
+                        return req, params, need
+                elif self._closed:
+                    return None
+                self._cv.wait(timeout=0.05)
+
+    def _release(self, need: int) -> None:
+        with self._cv:
+            self._in_use -= need
+            self._cv.notify_all()
+
+    # -- one slot --------------------------------------------------------------
+    def _run_request(self, req: Served, params) -> None:
+        d = P.DeviceSystem(params, device=str(self.device))
+        s = P.Solver(d, self.prec)
+        for E in req.energies:
+            r = s.run(float(E), max_refine=self.max_refine, tol=self.tol)
+            req.R.append(r.R.cpu().numpy().copy())
+            req.S.append(r.S.cpu().numpy().copy())
+            req.iterations.append(r.iterations)
+            req.fallback.append(r.fallback)
+
+    def _slot(self, k: int, stream) -> None:
+        if self.gpu:
+            torch.cuda.set_device(self.device)
+        with (torch.cuda.stream(stream) if self.gpu else contextlib.nullcontext()):
+            while True:
+                item = self._admit()
+                if item is None:
+                    return
+                req, params, need = item
+                try:
+                    self._execute(req, params)
+                except Exception as exc:  # reported per request, the stream goes on
+                    req.error = f"{type(exc).__name__}: {exc}"
+                finally:
+                    if self.gpu:
+                        stream.synchronize()
+                    req.done = time.perf_counter() - self._t0
+                    self._release(need)
+                    if self._progress is not None:
+                        self._progress(req)
+
+    # -- the stream ----------------------------------------------------------
+    def run(self, requests, progress=None) -> list[Served]:
+        """requests: [(arrival_seconds, SystemParams)] in arrival order.  Blocks
+        until every request is done; returns one Served per request.
+        progress(req), if given, is called from a slot thread as each request
+        completes."""
+        self._progress = progress
+        prev = H.hp_set_concurrency(self.slots) if self.gpu else None
+        out: list[Served] = []
+        streams = [torch.cuda.Stream(device=self.device) if self.gpu else None for _ in range(self.slots)]
+        self._closed = False
+        self._t0 = time.perf_counter()
+        threads = [threading.Thread(target=self._slot, args=(k, streams[k]), daemon=True)
+                   for k in range(self.slots)]
+        for t in threads:
+            t.start()
+        try:
+            for rid, (t_arr, params) in enumerate(requests):
+                wait = t_arr - (time.perf_counter() - self._t0)
+                if wait > 0:
+                    time.sleep(wait)
+                req = Served(rid=rid, n=int(params.nc) * int(params.nr), nc=int(params.nc),
+                             energies=np.asarray(params.energies, dtype=np.float64), arrival=float(t_arr))
+                out.append(req)
+                with self._cv:
+                    self._pending.append((req, params, int(self._bytes_of(params))))
+                    self._cv.notify_all()
+        finally:
+            with self._cv:
+                self._closed = True
+                self._cv.notify_all()
+            for t in threads:
+                t.join()
+            if prev is not None:
+                H.hp_set_concurrency(prev)
+        for req in out:
+            if req.error is None and len(req.S) != len(req.energies):
+                req.error = "not processed (no slot left)"
+        return out
+
+
+def summary(results: list[Served]) -> dict:
+    ok = [r for r in results if r.error is None]
+    lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+    solves = sum(len(r.energies) for r in ok)
+    span = max((r.done for r in results), default=0.0) - min((r.arrival for r in results), default=0.0)
+    return {"requests": len(results), "failed": len(results) - len(ok), "solves": solves,
+            "makespan_s": span, "solves_per_s": solves / span if span > 0 else 0.0,
+            "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+            "refinement_steps_mean": float(np.mean([i for r in ok for i in r.iterations])) if ok else 0.0,
+            "fp64_fallbacks": int(sum(f for r in ok for f in r.fallback))}

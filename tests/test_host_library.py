@@ -96,3 +96,13 @@ def test_workspace_grows_with_size(H):
     # FP32 factors also hold their inverted 128 x 128 diagonal blocks (2 per block row)
     assert b - c >= 2 * 16 * 128 * 128 * 8 - 16 * 2000 * 10
     assert H.hp_workspace_bytes(25600, 256, H.HP_C64) < 1 << 30
+
+
+def test_concurrency_setter(H):
+    """The concurrency setting is host state: set, read back through the
+    return value, reject values outside [1, 256]."""
+    assert H.hp_set_concurrency(4) == 1
+    assert H.hp_set_concurrency(2) == 4
+    assert H.lib().hp_set_concurrency(0) == H.HP_ERR_ARG
+    assert H.lib().hp_set_concurrency(257) == H.HP_ERR_ARG
+    assert H.hp_set_concurrency(1) == 2
