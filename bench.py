@@ -35,8 +35,8 @@ PEAK_FP64_MFMA = 78.6   # TF/s, MI355X dense FP64 matrix
 # WRITE_SIZE counter runs scaled by a 1 GiB copy
 # (profiles/gemm_sub_kernel_fp32_large_N25600_traffic.md); valid only for the
 # GEMM source it was measured on.
-GEMM_TRAFFIC = {"bytes_per_launch": 150.67e6,
-                "gemm_source_sha256": "d86159250730e6e0c6c425132b9e3131ba139dbb07b1c46d179267daf4d7e194"}
+GEMM_TRAFFIC = {"bytes_per_launch": 1.3370e+08,
+                "gemm_source_sha256": "ea07cf4cbe094ba8480696f5096b1e26548e90b85d56fe329dd2d8dbe63e4f20"}
 
 
 def parse():

@@ -65,8 +65,11 @@ struct GemmCfg {
   static constexpr int BN = 32 * WTN;
   static constexpr int BK = 16;
   static constexpr int EV = 16 / (int)sizeof(cplx<T>);         // complex per 16-byte vector
-  static constexpr int PAD = sizeof(T) == 4 ? 16 : 1;          // LDS row padding (complex)
-  static constexpr int PA = BM + PAD, PB = BN + PAD;
+  // LDS row padding (complex): one element on the k-major A rows spreads the
+  // transposing stores over banks; the B rows stay 16-byte aligned for vector
+  // stores (FP32: 33 KB per workgroup, so three fit beside a panel workgroup)
+  static constexpr int PADA = 1, PADB = sizeof(T) == 4 ? 0 : 1;
+  static constexpr int PA = BM + PADA, PB = BN + PADB;
   static constexpr int NVA = BM * BK / EV / 256;               // A vectors per thread per stage
   static constexpr int NVB = BK * BN / EV / 256;               // B vectors per thread per stage
   static constexpr size_t lds_bytes = (size_t)2 * BK * (PA + PB) * sizeof(cplx<T>);

@@ -1152,8 +1152,45 @@ __global__ void copy_rows_kernel(int n, int nrhs, const cplx<T> *__restrict__ X,
   Y[(long)i * ldy + c] = X[(long)i * ldx + c];
 }
 
-constexpr int kSolveBlock = 128;
-static_assert(kSolveBlock == kInvBlock, "solve blocks are the inverted diagonal blocks");
+// Rows per trailing GEMM of the solves: two inverted diagonal blocks (K = 256
+// runs the GEMM ~20 % faster than K = 128 on the n_c right-hand sides).
+constexpr int kSolveBlock = 2 * kInvBlock;
+static_assert(kSolveBlock <= kTrsmMaxRows, "substitution handles a whole solve block");
+
+// Rows [b, b + bs) of L Y = P B, once the rows above have been eliminated.
+template <typename T>
+static int diag_forward(int n, int b, int bs, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, long ldy,
+                        const cplx<T> *inv, hipStream_t st) {
+  if (!inv) return trsm<T, false>(bs, nrhs, LU + (long)b * lda + b, lda, Y + (long)b * ldy, ldy, st);
+  (void)n;
+  const size_t iblk = (size_t)kInvBlock * kInvBlock;
+  const int bi = b / kInvBlock, b1 = std::min(kInvBlock, bs), b2 = bs - b1;
+  int rc = apply_inverse<T>(b1, nrhs, inv + bi * iblk, Y + (long)b * ldy, ldy, st);
+  if (rc || b2 <= 0) return rc;
+  if ((rc = gemm_sub<T>(b2, nrhs, b1, LU + (long)(b + b1) * lda + b, lda, Y + (long)b * ldy, ldy,
+                        Y + (long)(b + b1) * ldy, ldy, st)))
+    return rc;
+  return apply_inverse<T>(b2, nrhs, inv + (bi + 1) * iblk, Y + (long)(b + b1) * ldy, ldy, st);
+}
+
+// Rows [b, b + bs) of U X = Y, once the rows below have been substituted.
+template <typename T>
+static int diag_backward(int n, int b, int bs, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, long ldy,
+                         const cplx<T> *inv, hipStream_t st) {
+  if (!inv) return trsm<T, true>(bs, nrhs, LU + (long)b * lda + b, lda, Y + (long)b * ldy, ldy, st);
+  const size_t iblk = (size_t)kInvBlock * kInvBlock;
+  const int nbt = (n + kInvBlock - 1) / kInvBlock;  // upper inverses follow the lower ones
+  const int bi = b / kInvBlock, b1 = std::min(kInvBlock, bs), b2 = bs - b1;
+  int rc;
+  if (b2 > 0) {
+    if ((rc = apply_inverse<T>(b2, nrhs, inv + (nbt + bi + 1) * iblk, Y + (long)(b + b1) * ldy, ldy, st)))
+      return rc;
+    if ((rc = gemm_sub<T>(b1, nrhs, b2, LU + (long)b * lda + b + b1, lda, Y + (long)(b + b1) * ldy, ldy,
+                          Y + (long)b * ldy, ldy, st)))
+      return rc;
+  }
+  return apply_inverse<T>(b1, nrhs, inv + (nbt + bi) * iblk, Y + (long)b * ldy, ldy, st);
+}
 
 // In-place solve on Y (n x nrhs, leading dimension ldy) that already holds P B.
 // With `inv` (the output of tri_inverse for this factor) the diagonal blocks
@@ -1163,15 +1200,10 @@ int lu_solve_permuted(int n, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, 
                       hipStream_t st) {
   int rc;
   const int nb = (n + kSolveBlock - 1) / kSolveBlock;
-  const size_t iblk = (size_t)kInvBlock * kInvBlock;
   for (int bi = 0; bi < nb; ++bi) {
     const int b = bi * kSolveBlock;
     const int bs = std::min(kSolveBlock, n - b);
-    if (inv)
-      rc = apply_inverse<T>(bs, nrhs, inv + bi * iblk, Y + (long)b * ldy, ldy, st);
-    else
-      rc = trsm<T, false>(bs, nrhs, LU + (long)b * lda + b, lda, Y + (long)b * ldy, ldy, st);
-    if (rc) return rc;
+    if ((rc = diag_forward<T>(n, b, bs, nrhs, LU, lda, Y, ldy, inv, st))) return rc;
     if (b + bs < n)
       if ((rc = gemm_sub<T>(n - b - bs, nrhs, bs, LU + (long)(b + bs) * lda + b, lda, Y + (long)b * ldy, ldy,
                             Y + (long)(b + bs) * ldy, ldy, st)))
@@ -1180,11 +1212,7 @@ int lu_solve_permuted(int n, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, 
   for (int bi = nb - 1; bi >= 0; --bi) {
     const int b = bi * kSolveBlock;
     const int bs = std::min(kSolveBlock, n - b);
-    if (inv)
-      rc = apply_inverse<T>(bs, nrhs, inv + (nb + bi) * iblk, Y + (long)b * ldy, ldy, st);
-    else
-      rc = trsm<T, true>(bs, nrhs, LU + (long)b * lda + b, lda, Y + (long)b * ldy, ldy, st);
-    if (rc) return rc;
+    if ((rc = diag_backward<T>(n, b, bs, nrhs, LU, lda, Y, ldy, inv, st))) return rc;
     if (b > 0)
       if ((rc = gemm_sub<T>(b, nrhs, bs, LU + b, lda, Y + (long)b * ldy, ldy, Y, ldy, st))) return rc;
   }
