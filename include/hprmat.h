@@ -178,6 +178,75 @@ int hp_coulomb(int l, double eta, double rho, double *out);
 int hp_coulomb_device(int nch, const int *l, const double *eta, const double *rho,
                       double *out, void *stream);
 
+/* ---- batched uneven systems ---------------------------------------------- */
+
+/* Many independent systems (one per (J^pi, energy) label, n of a few hundred
+ * to a few thousand) solved side by side, one workgroup per system, with no
+ * inter-workgroup synchronisation.  The caller lays the systems out in shared
+ * device buffers and describes each by an hp_batch_item in DEVICE memory;
+ * listing the largest systems first balances the persistent grid.
+ * Offsets are in elements of the buffer they index. */
+typedef struct hp_batch_item {
+  hp_system sys;  /* this system's data (device pointers) */
+  double E;       /* its energy (MeV) */
+  long a_off;     /* its n x n matrix in A (leading dimension n) */
+  long x_off;     /* its n x nc block in X (leading dimension nc) */
+  long p_off;     /* its n entries of ipiv and perm */
+  long r_off;     /* its nc x nc block of R */
+  long c_off;     /* its nc entries of per-column arrays: sum of nc over the systems before it */
+} hp_batch_item;
+
+/* Workspace of the batched solves: sum_nc = sum of nc, sum_xn = sum of n*nc
+ * over the systems.  0 on bad arguments. */
+size_t hp_batch_workspace_bytes(int count, long sum_nc, long sum_xn, int prec);
+
+/* C(E) of every system into A (precision prec), as hp_build_matrix does for one
+ * (Eq. block_structure).  One workgroup per system. */
+int hp_batch_build(int count, const hp_batch_item *items, int prec, void *A, void *stream);
+
+/* LU with partial pivoting of every system (Sec. 3.1), in place, as
+ * hp_factor: ipiv/perm per system at p_off, info[s] = 0 or k+1 for the first
+ * exactly zero pivot column k.  A persistent grid of `groups` workgroups takes
+ * systems in list order from a counter in `work` (>= 256 bytes); each
+ * workgroup factors its system in panels of `panel` (1..32) columns: column
+ * steps with full-row interchanges, the panel's block row, and the trailing
+ * update as MFMA complex tiles (3M in FP32, 4M in FP64).
+ * Errors: HP_ERR_ARG, HP_ERR_HIP. */
+int hp_batch_factor(int count, const hp_batch_item *items, int prec, void *A, int *ipiv, int *perm,
+                    int *info, int panel, int groups, void *work, size_t work_bytes, void *stream);
+
+/* Solves every system for its nc surface right-hand sides with the factors:
+ * X (FP64, per system at x_off) = C^-1 B.  With refine != 0 (FP32 factors
+ * only), the per-system refinement state is reset for hp_batch_refine_step;
+ * systems with a zero pivot (info_factor) are marked and left alone.  No
+ * host synchronisation.  work: hp_batch_workspace_bytes(...) bytes. */
+int hp_batch_solve_init(int count, const hp_batch_item *items, int prec, const void *LU, const int *perm,
+                        const int *info_factor, double *X, int refine, long sum_nc, long sum_xn,
+                        void *work, size_t work_bytes, void *stream);
+
+/* One FP64 refinement step of FP32 factors for every system still refining
+ * (Sec. 3.2): r = B - C X from the block structure, d from the factors
+ * (column-scaled), X += d, and the stop rule of hp_solve per system (relative
+ * correction <= tol, tol <= 0: 2^-52; a correction larger than half the
+ * previous one: converged if the previous was <= 1e-6, else not converged;
+ * not converged after max_refine steps).  A fixed sequence of four launches,
+ * no host synchronisation: it may be captured in a graph and replayed. */
+int hp_batch_refine_step(int count, const hp_batch_item *items, const void *LU, const int *perm, double *X,
+                         int max_refine, double tol, long sum_nc, long sum_xn, void *work,
+                         size_t work_bytes, void *stream);
+
+/* Number of systems still refining after the last step (host *active);
+ * synchronizes the stream. */
+int hp_batch_active(const void *work, unsigned *active, void *stream);
+
+/* Per-system outcome (host arrays of count): status 1 converged (or no
+ * refinement), 2 not converged, 3 zero pivot, 0 still refining; iters =
+ * corrections applied (may be NULL).  Synchronizes the stream. */
+int hp_batch_status(int count, const void *work, int *status, int *iters, void *stream);
+
+/* R of every system (Sec. 3.1 step 4), FP64 complex at r_off of R. */
+int hp_batch_rmatrix(int count, const hp_batch_item *items, const double *X, double *R, void *stream);
+
 /* ---- concurrency ------------------------------------------------------- */
 
 /* Number of factorizations that may be requested at the same time on one

@@ -1,0 +1,278 @@
+"""Batched uneven systems: device layout, size buckets, autotuning, graphs.
+
+Many independent systems (one per (J^pi, energy) label, N = nc*nr from a
+few hundred to a few thousand) are laid out in shared device buffers and
+solved by the batched entry points of the C ABI, one workgroup per system:
+
+    hp_batch_build -> hp_batch_factor -> hp_batch_solve_init
+        -> [hp_batch_refine_step]* (FP32 factors) -> hp_batch_rmatrix
+
+Systems are split into size buckets; each bucket is one persistent
+batched-LU launch (systems largest first), with its panel width and grid
+size picked by `autotune` (timed on the bucket itself, cached per bucket
+and precision).  The refinement step is captured once in a HIP graph and
+replayed until no system of the bucket is still refining.  The collision
+matrix S of each system follows from its R through hp_smatrix.  All
+arithmetic runs in the HIP library; this module lays out memory and
+sequences the calls.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import hprmat as H
+
+E2 = 1.44  # e^2 in MeV fm
+BUCKET_EDGES = (1000, 2000)  # N boundaries of the size buckets
+PANELS = (8, 16, 32)
+GROUPS_PER_CU = (2, 3)
+
+
+@dataclass
+class BucketTuning:
+    panel: int
+    groups: int
+    ms: float
+
+
+_TUNED: dict = {}
+
+
+class Bucket:
+    """Systems of one size bucket in shared device buffers (largest first)."""
+
+    def __init__(self, systems, energies, index, prec: int, device="cuda"):
+        order = sorted(range(len(systems)), key=lambda k: -(systems[k].nc * systems[k].nr))
+        self.index = [index[k] for k in order]
+        self.systems = [systems[k] for k in order]
+        self.energies = [float(energies[k]) for k in order]
+        self.prec = prec
+        self.count = len(self.systems)
+        dev = torch.device(device)
+        self.device = dev
+        nc = np.array([s.nc for s in self.systems], dtype=np.int64)
+        nr = np.array([s.nr for s in self.systems], dtype=np.int64)
+        n = nc * nr
+        self.n, self.nc, self.nr = n, nc, nr
+        self.a_off = np.concatenate([[0], np.cumsum(n * n)[:-1]])
+        self.x_off = np.concatenate([[0], np.cumsum(n * nc)[:-1]])
+        self.p_off = np.concatenate([[0], np.cumsum(n)[:-1]])
+        self.r_off = np.concatenate([[0], np.cumsum(nc * nc)[:-1]])
+        self.c_off = np.concatenate([[0], np.cumsum(nc)[:-1]])
+        self.sum_nc, self.sum_xn = int(nc.sum()), int((n * nc).sum())
+        # per-system mesh, channel and potential data, concatenated
+        r_h, q_h, tl_h, l_h, eps_h, v_h = [], [], [], [], [], []
+        for s in self.systems:
+            r, w, q, tl = H.hp_mesh(int(s.nr), float(s.a))
+            r_h.append(r)
+            q_h.append(q)
+            tl_h.append(np.ascontiguousarray(tl).ravel())
+            l_h.append(np.asarray(s.l, dtype=np.int32))
+            eps_h.append(np.asarray(s.eps, dtype=np.float64))
+            v_h.append(np.ascontiguousarray(s.potential(r), dtype=np.complex128).ravel())
+        self.r = torch.from_numpy(np.concatenate(r_h)).to(dev)
+        self.q = torch.from_numpy(np.concatenate(q_h)).to(dev)
+        self.tl = torch.from_numpy(np.concatenate(tl_h)).to(dev)
+        self.l = torch.from_numpy(np.concatenate(l_h)).to(dev)
+        self.eps = torch.from_numpy(np.concatenate(eps_h)).to(dev)
+        self.v = torch.from_numpy(np.concatenate(v_h)).to(dev)
+        off_r = np.concatenate([[0], np.cumsum(nr)[:-1]])
+        off_tl = np.concatenate([[0], np.cumsum(nr * nr)[:-1]])
+        off_c = self.c_off
+        off_v = np.concatenate([[0], np.cumsum(nr * nc * nc)[:-1]])
+        self.sys = []
+        items = (H.HpBatchItem * self.count)()
+        for k, s in enumerate(self.systems):
+            sy = H.HpSystem(int(nc[k]), int(nr[k]), float(s.a), float(s.hbar2_2mu), float(s.z1z2) * E2,
+                            self.r.data_ptr() + 8 * int(off_r[k]), self.q.data_ptr() + 8 * int(off_r[k]),
+                            self.tl.data_ptr() + 8 * int(off_tl[k]), self.l.data_ptr() + 4 * int(off_c[k]),
+                            self.eps.data_ptr() + 8 * int(off_c[k]), self.v.data_ptr() + 16 * int(off_v[k]))
+            self.sys.append(sy)
+            items[k] = H.HpBatchItem(sy, self.energies[k], int(self.a_off[k]), int(self.x_off[k]),
+                                     int(self.p_off[k]), int(self.r_off[k]), int(self.c_off[k]))
+        raw = np.frombuffer(bytes(items), dtype=np.uint8).copy()
+        self.items = torch.from_numpy(raw).to(dev)
+        ctype = torch.complex64 if prec == H.HP_C64 else torch.complex128
+        self.A = torch.empty(int((n * n).sum()), dtype=ctype, device=dev)
+        self.ipiv = torch.empty(int(n.sum()), dtype=torch.int32, device=dev)
+        self.perm = torch.empty(int(n.sum()), dtype=torch.int32, device=dev)
+        self.info = torch.zeros(self.count, dtype=torch.int32, device=dev)
+        self.X = torch.empty(self.sum_xn, dtype=torch.complex128, device=dev)
+        self.R = torch.empty(int((nc * nc).sum()), dtype=torch.complex128, device=dev)
+        self.work = torch.empty(H.hp_batch_workspace_bytes(self.count, self.sum_nc, self.sum_xn, prec),
+                                dtype=torch.uint8, device=dev)
+        self.graph = None
+        self._steps = 0
+        self.flops = float((8.0 / 3.0) * (n.astype(np.float64) ** 3).sum())
+
+    @property
+    def key(self):
+        return (int(self.n.max()), int(self.n.min()), self.count, self.prec)
+
+    def factor(self, panel: int, groups: int) -> None:
+        H.hp_batch_build(self.count, self.items, self.prec, self.A)
+        H.hp_batch_factor(self.count, self.items, self.prec, self.A, self.ipiv, self.perm, self.info, panel,
+                          groups, self.work)
+
+    def solve_init(self, max_refine: int = 30) -> bool:
+        """Initial solve; True if FP32 refinement follows."""
+        refine = self.prec == H.HP_C64 and max_refine > 0
+        H.hp_batch_solve_init(self.count, self.items, self.prec, self.A, self.perm, self.info, self.X, refine,
+                              self.sum_nc, self.sum_xn, self.work)
+        self._steps = 0
+        return refine
+
+    def refine_step(self, max_refine: int = 30, tol: float = 0.0, use_graph: bool = True) -> None:
+        """Enqueue one refinement step (a graph replay after the first step)."""
+        args = (self.count, self.items, self.A, self.perm, self.X, max_refine, tol, self.sum_nc, self.sum_xn,
+                self.work)
+        if use_graph and self.graph is None and self._steps > 0:
+            # capture one step (every kernel's launch attributes are set by now);
+            # the capture runs nothing, the replay below does
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream(device=self.device)
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.graph(g, stream=side):
+                H.hp_batch_refine_step(*args)
+            torch.cuda.current_stream().wait_stream(side)
+            self.graph = (g, (max_refine, tol))
+        if use_graph and self.graph is not None and self.graph[1] == (max_refine, tol):
+            self.graph[0].replay()
+        else:
+            H.hp_batch_refine_step(*args)
+        self._steps += 1
+
+    def solve(self, max_refine: int = 30, tol: float = 0.0, use_graph: bool = True) -> int:
+        """Initial solve, then (FP32) refinement steps until every system has
+        stopped; returns the number of steps taken."""
+        if not self.solve_init(max_refine):
+            return 0
+        while self._steps < max_refine:
+            self.refine_step(max_refine, tol, use_graph)
+            if H.hp_batch_active(self.work) == 0:
+                break
+        return self._steps
+
+    def rmatrix(self) -> None:
+        H.hp_batch_rmatrix(self.count, self.items, self.X, self.R)
+
+    def status(self):
+        return H.hp_batch_status(self.count, self.work)
+
+    def R_of(self, k: int) -> np.ndarray:
+        """R of the k-th system of this bucket (host copy)."""
+        c = int(self.nc[k])
+        o = int(self.r_off[k])
+        return self.R[o:o + c * c].view(c, c).cpu().numpy()
+
+    def S_of(self, k: int, swork=None) -> np.ndarray:
+        c = int(self.nc[k])
+        o = int(self.r_off[k])
+        S = torch.empty((c, c), dtype=torch.complex128, device=self.device)
+        if swork is None:
+            swork = torch.empty(H.hp_workspace_bytes(c, c, H.HP_C128), dtype=torch.uint8, device=self.device)
+        Rk = self.R[o:o + c * c]
+        H.hp_smatrix(self.sys[k], self.energies[k], Rk, S, swork)
+        return S.cpu().numpy()
+
+
+def autotune(bucket: Bucket, cus: int, reps: int = 1) -> BucketTuning:
+    """Time the bucket's factorization for each panel width and grid size;
+    keep the fastest (cached per bucket shape and precision)."""
+    if bucket.key in _TUNED:
+        return _TUNED[bucket.key]
+    best = None
+    for panel in PANELS:
+        for gpc in GROUPS_PER_CU:
+            groups = gpc * cus
+            bucket.factor(panel, groups)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                bucket.factor(panel, groups)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            if best is None or ms < best.ms:
+                best = BucketTuning(panel, groups, ms)
+    _TUNED[bucket.key] = best
+    return best
+
+
+class Batch:
+    """An uneven batch split into size buckets (one persistent launch each)."""
+
+    def __init__(self, systems, energies, prec: int, device="cuda", edges=BUCKET_EDGES):
+        self.prec = prec
+        self.count = len(systems)
+        n = np.array([s.nc * s.nr for s in systems])
+        bounds = (0,) + tuple(edges) + (1 << 30,)
+        self.buckets = []
+        for lo, hi in zip(bounds, bounds[1:]):
+            idx = [k for k in range(len(systems)) if lo <= n[k] < hi]
+            if idx:
+                self.buckets.append(Bucket([systems[k] for k in idx], [energies[k] for k in idx], idx, prec,
+                                           device))
+        props = torch.cuda.get_device_properties(torch.device(device))
+        self.cus = int(props.multi_processor_count)
+        self.tuning = {}
+        self.flops = sum(b.flops for b in self.buckets)
+
+    def tune(self) -> dict:
+        for b in self.buckets:
+            self.tuning[b.key] = autotune(b, self.cus)
+        return {f"N {int(b.n.min())}-{int(b.n.max())} ({b.count})": vars(self.tuning[b.key]) for b in self.buckets}
+
+    def run(self, max_refine: int = 30, tol: float = 0.0, use_graph: bool = True) -> dict:
+        """Build, factor, solve (and refine), R for every system.  Each bucket
+        has its own stream: all factorizations are enqueued first, then the
+        refinement steps of the buckets still refining are interleaved."""
+        streams = [torch.cuda.Stream() for _ in self.buckets]
+        cur = torch.cuda.current_stream()
+        refining = []
+        for b, s in zip(self.buckets, streams):
+            s.wait_stream(cur)
+            t = self.tuning.get(b.key) or BucketTuning(16, 2 * self.cus, 0.0)
+            with torch.cuda.stream(s):
+                b.factor(t.panel, t.groups)
+                if b.solve_init(max_refine):
+                    refining.append((b, s))
+        while refining:
+            for b, s in refining:
+                with torch.cuda.stream(s):
+                    b.refine_step(max_refine, tol, use_graph)
+            still = []
+            for b, s in refining:
+                with torch.cuda.stream(s):
+                    if H.hp_batch_active(b.work) > 0 and b._steps < max_refine:
+                        still.append((b, s))
+            refining = still
+        for b, s in zip(self.buckets, streams):
+            with torch.cuda.stream(s):
+                b.rmatrix()
+            cur.wait_stream(s)
+        return {f"N {int(b.n.min())}-{int(b.n.max())}": b._steps for b in self.buckets}
+
+    def results(self):
+        """[(R, S)] in the original order of the systems."""
+        out = [None] * self.count
+        cmax = max(int(b.nc.max()) for b in self.buckets)
+        swork = torch.empty(H.hp_workspace_bytes(cmax, cmax, H.HP_C128), dtype=torch.uint8)
+        swork = swork.to(self.buckets[0].device)
+        for b in self.buckets:
+            for k in range(b.count):
+                out[b.index[k]] = (b.R_of(k), b.S_of(k, swork))
+        return out
+
+    def status(self):
+        st = np.zeros(self.count, dtype=np.int32)
+        it = np.zeros(self.count, dtype=np.int32)
+        for b in self.buckets:
+            s, i = b.status()
+            for k in range(b.count):
+                st[b.index[k]] = s[k]
+                it[b.index[k]] = i[k]
+        return st, it

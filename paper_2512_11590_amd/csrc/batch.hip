@@ -1,0 +1,720 @@
+// Batched uneven systems: many independent coupled-channel systems (one per
+// (J^pi, energy) label, N = nc*nr of a few hundred to a few thousand) solved
+// side by side, one workgroup per system.
+//
+// At these sizes one system cannot fill the device, and the full-size path's
+// per-column grid barrier would make every system latency-bound.  Here a
+// single workgroup owns a system for the whole factorization (no grid
+// synchronisation at all), and the device is filled by running hundreds of
+// systems at once; systems are taken largest first from an atomic counter,
+// so the persistent grid stays balanced.
+//
+//   hp_batch_build    assembly of C(E) for every system (Eq. block_structure)
+//   hp_batch_factor   persistent batched LU with partial pivoting (Sec. 3.1):
+//                     per panel of W columns, column steps with immediate row
+//                     interchanges, the panel's block row, and the trailing
+//                     update as MFMA complex tiles (3M in FP32, 4M in FP64)
+//   hp_batch_solve_init / hp_batch_refine_step
+//                     solves for the nc surface right-hand sides, and FP64
+//                     refinement of FP32 factors (Sec. 3.2) with a per-system
+//                     stop rule; one refinement step is a fixed sequence of
+//                     launches with no host synchronisation (capturable)
+//   hp_batch_rmatrix  R for every system (Sec. 3.1 step 4)
+#include "common.h"
+
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+namespace hp {
+
+namespace {
+
+template <typename T>
+struct BMfma;
+template <>
+struct BMfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator element r of lane l is row 4 r + l / 16 of the 16 x 16 tile
+  static __device__ __forceinline__ int d_row(int l, int r) { return 4 * r + (l >> 4); }
+};
+template <>
+struct BMfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator element r of lane l is row 4 (l / 16) + r
+  static __device__ __forceinline__ int d_row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+constexpr int kBK = 32;       // largest K of one workgroup GEMM (panel width, solve block)
+constexpr int kBLd = 64 + 1;  // LDS row stride of the staged 64-wide tiles (complex)
+
+// LDS of one workgroup GEMM: the A and B tiles (33 KB in FP32, 67 KB in FP64)
+template <typename T>
+constexpr size_t tile_lds_bytes() {
+  return (size_t)2 * kBK * kBLd * sizeof(cplx<T>);
+}
+
+// C[M x N] -= A[M x K] B[K x N] (K <= kBK) by one workgroup, in 64 x 64 output
+// tiles: A and B staged k-major in LDS, four wavefronts of 32 x 32 outputs,
+// MFMA 16x16x4.  FP32: three real products per complex product (3M), FP64:
+// four (4M).  A, B and C must not overlap.  Ends with a barrier.
+template <typename T>
+__device__ void wg_gemm_sub(int M, int N, int K, const cplx<T> *__restrict__ A, long lda,
+                            const cplx<T> *__restrict__ B, long ldb, cplx<T> *__restrict__ C, long ldc,
+                            cplx<T> *As, cplx<T> *Bs) {
+  typedef typename BMfma<T>::v4 v4;
+  constexpr bool M3 = sizeof(T) == 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int fr = lane & 15, fk = lane >> 4;
+  const int Kp = (K + 3) & ~3;
+  const int tm = (M + 63) / 64, tn = (N + 63) / 64;
+  const cplx<T> zero{T(0), T(0)};
+  for (int t = 0; t < tm * tn; ++t) {
+    const int m0 = (t / tn) * 64, n0 = (t % tn) * 64;
+    for (int e = tid; e < 64 * Kp; e += 256) {
+      const int r = e / Kp, k = e - r * Kp;
+      cplx<T> v = zero;
+      if (m0 + r < M && k < K) v = A[(long)(m0 + r) * lda + k];
+      As[k * kBLd + r] = v;
+    }
+    for (int e = tid; e < Kp * 64; e += 256) {
+      const int k = e >> 6, c = e & 63;
+      cplx<T> v = zero;
+      if (k < K && n0 + c < N) v = B[(long)k * ldb + n0 + c];
+      Bs[k * kBLd + c] = v;
+    }
+    __syncthreads();
+    v4 p1[2][2], p2[2][2], p3[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) p1[i][j] = p2[i][j] = p3[i][j] = v4{0, 0, 0, 0};
+    for (int ks = 0; ks < Kp; ks += 4) {
+      const int kk = ks + fk;
+      cplx<T> af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) af[i] = As[kk * kBLd + wm + i * 16 + fr];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = Bs[kk * kBLd + wn + j * 16 + fr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if constexpr (M3) {
+            // p1 = Ar Br, p2 = Ai Bi, p3 = (Ar + Ai)(Br + Bi)
+            p1[i][j] = BMfma<T>::mac(af[i].re, bf[j].re, p1[i][j]);
+            p2[i][j] = BMfma<T>::mac(af[i].im, bf[j].im, p2[i][j]);
+            p3[i][j] = BMfma<T>::mac(af[i].re + af[i].im, bf[j].re + bf[j].im, p3[i][j]);
+          } else {
+            // p1 = Ar Br - Ai Bi, p3 = Ar Bi + Ai Br
+            p1[i][j] = BMfma<T>::mac(af[i].re, bf[j].re, p1[i][j]);
+            p1[i][j] = BMfma<T>::mac(-af[i].im, bf[j].im, p1[i][j]);
+            p3[i][j] = BMfma<T>::mac(af[i].re, bf[j].im, p3[i][j]);
+            p3[i][j] = BMfma<T>::mac(af[i].im, bf[j].re, p3[i][j]);
+          }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = m0 + wm + i * 16 + BMfma<T>::d_row(lane, r);
+        if (gr >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int gc = n0 + wn + j * 16 + fr;
+          if (gc >= N) continue;
+          cplx<T> c = C[(long)gr * ldc + gc];
+          if constexpr (M3) {
+            c.re -= p1[i][j][r] - p2[i][j][r];
+            c.im -= p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
+          } else {
+            c.re -= p1[i][j][r];
+            c.im -= p3[i][j][r];
+          }
+          C[(long)gr * ldc + gc] = c;
+        }
+      }
+    __syncthreads();
+  }
+}
+
+// Workgroup argmax of (v, row): largest v, smallest row on ties; every
+// thread returns the result.
+template <typename T>
+__device__ __forceinline__ void wg_argmax(T &v, int &r, T *sv, int *sr) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const T ov = __shfl_xor(v, off);
+    const int orow = __shfl_xor(r, off);
+    if (ov > v || (ov == v && orow < r)) {
+      v = ov;
+      r = orow;
+    }
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) {
+    sv[wave] = v;
+    sr[wave] = r;
+  }
+  __syncthreads();
+  v = sv[0];
+  r = sr[0];
+  for (int w = 1; w < 4; ++w)
+    if (sv[w] > v || (sv[w] == v && sr[w] < r)) {
+      v = sv[w];
+      r = sr[w];
+    }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int item_n(const hp_batch_item &it) { return it.sys.nc * it.sys.nr; }
+
+// Next system of a persistent grid (all threads get the same index).
+__device__ __forceinline__ int next_item(unsigned *counter, int *s_idx) {
+  if (threadIdx.x == 0) *s_idx = (int)atomicAdd(counter, 1u);
+  __syncthreads();
+  const int idx = *s_idx;
+  __syncthreads();
+  return idx;
+}
+
+__global__ void batch_zero_kernel(unsigned *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------- assembly --
+template <typename T>
+__global__ __launch_bounds__(256) void batch_build_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                          cplx<T> *__restrict__ A) {
+  const int s = blockIdx.x;
+  if (s >= count) return;
+  const hp_batch_item it = items[s];
+  const int nc = it.sys.nc, nr = it.sys.nr, n = nc * nr;
+  const double h = it.sys.hbar2_2mu, E = it.E;
+  cplx<T> *a = A + it.a_off;
+  for (int row = 0; row < n; ++row) {
+    const int c = row / nr, i = row - c * nr;
+    const int lc = it.sys.l[c];
+    const double ri = it.sys.r[i];
+    const double diag = h * (double)lc * (double)(lc + 1) / (ri * ri) + it.sys.eps[c] - E;
+    const double *tl_row = it.sys.tl + (size_t)i * nr;
+    const double *v_row = it.sys.v + 2 * ((size_t)i * nc + c) * nc;
+    for (int col = threadIdx.x; col < n; col += 256) {
+      const int cp = col / nr, j = col - cp * nr;
+      double re = 0.0, im = 0.0;
+      if (cp == c) {
+        re = h * tl_row[j];
+        if (j == i) re += diag;
+      }
+      if (j == i) {
+        re += v_row[2 * cp];
+        im += v_row[2 * cp + 1];
+      }
+      a[(long)row * n + col] = cplx<T>{(T)re, (T)im};
+    }
+  }
+}
+
+// ----------------------------------------------------------- factorization --
+// One workgroup factors one system at a time, P A = L U with partial pivoting
+// (largest |Re|+|Im|, smallest row on ties), in panels of W columns:
+//   column steps: pivot search, full-row interchange, scaling of the column
+//   and update of the panel's remaining columns;
+//   block row: U12 = L11^-1 A12 (one thread per column);
+//   trailing update A22 -= L21 U12 (workgroup MFMA tiles).
+template <typename T>
+__global__ __launch_bounds__(256) void batch_lu_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                       cplx<T> *__restrict__ A, int *__restrict__ ipiv,
+                                                       int *__restrict__ perm, int *__restrict__ info,
+                                                       unsigned *counter, int W) {
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T> *As = reinterpret_cast<cplx<T> *>(smem_raw);
+  cplx<T> *Bs = As + kBK * kBLd;
+  __shared__ cplx<T> urow[kBK];
+  __shared__ T sv[4];
+  __shared__ int sr[4];
+  __shared__ int s_idx;
+  const int tid = threadIdx.x;
+  for (;;) {
+    const int s = next_item(counter, &s_idx);
+    if (s >= count) break;
+    const hp_batch_item it = items[s];
+    const int n = item_n(it);
+    cplx<T> *a = A + it.a_off;
+    int *piv = ipiv + it.p_off;
+    int first_zero = 0;
+    for (int j0 = 0; j0 < n; j0 += W) {
+      const int w = min(W, n - j0);
+      for (int jj = 0; jj < w; ++jj) {
+        const int j = j0 + jj;
+        T best = T(-1);
+        int brow = INT_MAX;
+        for (int r = j + tid; r < n; r += 256) {
+          const T v = cabs1(a[(long)r * n + j]);
+          if (v > best || (v == best && r < brow)) {
+            best = v;
+            brow = r;
+          }
+        }
+        wg_argmax(best, brow, sv, sr);
+        const int p = (brow >= j && brow < n) ? brow : j;
+        if (tid == 0) piv[j] = p;
+        const bool nz = best > T(0);
+        if (!nz && first_zero == 0) first_zero = j + 1;
+        if (p != j)
+          for (int c = tid; c < n; c += 256) {
+            const cplx<T> x = a[(long)j * n + c];
+            a[(long)j * n + c] = a[(long)p * n + c];
+            a[(long)p * n + c] = x;
+          }
+        __syncthreads();
+        if (tid < w) urow[tid] = a[(long)j * n + j0 + tid];
+        __syncthreads();
+        if (nz) {
+          const cplx<T> inv = crcp(urow[jj]);
+          for (int r = j + 1 + tid; r < n; r += 256) {
+            cplx<T> *row = a + (long)r * n + j0;
+            const cplx<T> l = cmul(row[jj], inv);
+            row[jj] = l;
+            for (int c = jj + 1; c < w; ++c) row[c] = cfms(row[c], l, urow[c]);
+          }
+        }
+        __syncthreads();
+      }
+      const int rest = n - j0 - w;
+      if (rest > 0) {
+        // U12 = L11^-1 A12
+        for (int c = j0 + w + tid; c < n; c += 256) {
+          for (int i = 1; i < w; ++i) {
+            cplx<T> sum = a[(long)(j0 + i) * n + c];
+            for (int k = 0; k < i; ++k) sum = cfms(sum, a[(long)(j0 + i) * n + j0 + k], a[(long)(j0 + k) * n + c]);
+            a[(long)(j0 + i) * n + c] = sum;
+          }
+        }
+        __syncthreads();
+        wg_gemm_sub<T>(rest, rest, w, a + (long)(j0 + w) * n + j0, n, a + (long)j0 * n + j0 + w, n,
+                       a + (long)(j0 + w) * n + j0 + w, n, As, Bs);
+      }
+    }
+    // perm = the composition of the interchanges; info
+    if (tid == 0) {
+      int *pm = perm + it.p_off;
+      for (int i = 0; i < n; ++i) pm[i] = i;
+      for (int k = 0; k < n; ++k) {
+        const int p = piv[k];
+        const int x = pm[k];
+        pm[k] = pm[p];
+        pm[p] = x;
+      }
+      info[s] = first_zero;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------- solves --
+// Y (n x nc, leading dimension nc) <- U^-1 L^-1 Y in place, blocks of kBK rows:
+// the diagonal block by substitution (one thread per column), the rows
+// beyond it by a workgroup GEMM.
+template <typename T>
+__device__ void wg_lu_solve(int n, int nc, const cplx<T> *__restrict__ lu, cplx<T> *__restrict__ y, cplx<T> *As,
+                            cplx<T> *Bs) {
+  const int tid = threadIdx.x;
+  for (int b = 0; b < n; b += kBK) {
+    const int bs = min(kBK, n - b);
+    for (int c = tid; c < nc; c += 256)
+      for (int i = 1; i < bs; ++i) {
+        cplx<T> sum = y[(long)(b + i) * nc + c];
+        for (int k = 0; k < i; ++k) sum = cfms(sum, lu[(long)(b + i) * n + b + k], y[(long)(b + k) * nc + c]);
+        y[(long)(b + i) * nc + c] = sum;
+      }
+    __syncthreads();
+    if (b + bs < n)
+      wg_gemm_sub<T>(n - b - bs, nc, bs, lu + (long)(b + bs) * n + b, n, y + (long)b * nc, nc,
+                     y + (long)(b + bs) * nc, nc, As, Bs);
+  }
+  const int nb = (n + kBK - 1) / kBK;
+  for (int bi = nb - 1; bi >= 0; --bi) {
+    const int b = bi * kBK, bs = min(kBK, n - b);
+    for (int c = tid; c < nc; c += 256)
+      for (int i = bs - 1; i >= 0; --i) {
+        cplx<T> sum = y[(long)(b + i) * nc + c];
+        for (int k = i + 1; k < bs; ++k) sum = cfms(sum, lu[(long)(b + i) * n + b + k], y[(long)(b + k) * nc + c]);
+        y[(long)(b + i) * nc + c] = cdiv(sum, lu[(long)(b + i) * n + b + i]);
+      }
+    __syncthreads();
+    if (b > 0)
+      wg_gemm_sub<T>(b, nc, bs, lu + b, n, y + (long)b * nc, nc, y, nc, As, Bs);
+  }
+}
+
+// Per-system refinement state.
+struct BatchState {
+  int status;  // 0 running, 1 converged, 2 not converged, 3 zero pivot
+  int iters;
+  double corr_prev;
+  double corr;
+};
+
+// mode 0: Y = P B (B[(c,i)][c'] = delta_cc' q_i) and solve; then X = Y (FP64)
+// mode 1: Y = P R / s (per column, R the FP64 residual, s its column max) and
+//         solve, for systems still refining.
+template <typename T>
+__global__ __launch_bounds__(256) void batch_solve_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                          const cplx<T> *__restrict__ LU,
+                                                          const int *__restrict__ perm, cplx<T> *__restrict__ Y,
+                                                          cplx<double> *__restrict__ X,
+                                                          const cplx<double> *__restrict__ Rr,
+                                                          const double *__restrict__ cscale,
+                                                          BatchState *state, int mode) {
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T> *As = reinterpret_cast<cplx<T> *>(smem_raw);
+  cplx<T> *Bs = As + kBK * kBLd;
+  const int s = blockIdx.x;
+  if (s >= count) return;
+  const hp_batch_item it = items[s];
+  if (mode == 1 && state[s].status != 0) return;
+  const int nc = it.sys.nc, nr = it.sys.nr, n = nc * nr;
+  const int *pm = perm + it.p_off;
+  cplx<T> *y = Y + it.x_off;
+  const long cnt = (long)n * nc;
+  for (long e = threadIdx.x; e < cnt; e += 256) {
+    const int i = (int)(e / nc), cc = (int)(e - (long)i * nc);
+    const int src = pm[i];
+    cplx<T> v{T(0), T(0)};
+    if (mode == 0) {
+      const int c = src / nr, ii = src - c * nr;
+      if (c == cc) v.re = (T)it.sys.q[ii];
+    } else {
+      const cplx<double> r = Rr[it.x_off + (long)src * nc + cc];
+      const double sc = cscale[it.c_off + cc];
+      v = cplx<T>{(T)(r.re / sc), (T)(r.im / sc)};
+    }
+    y[e] = v;
+  }
+  __syncthreads();
+  wg_lu_solve<T>(n, nc, LU + it.a_off, y, As, Bs);
+  if (mode == 0 && X)
+    for (long e = threadIdx.x; e < cnt; e += 256) X[it.x_off + e] = cplx<double>{(double)y[e].re, (double)y[e].im};
+}
+
+// R = B - C X in FP64 from the block structure, and per column s = max |R|
+// (|Re|+|Im|; 1 for an exactly zero column), for systems still refining.
+__global__ __launch_bounds__(256) void batch_residual_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                             const cplx<double> *__restrict__ X,
+                                                             cplx<double> *__restrict__ Rr, double *cscale,
+                                                             const BatchState *state) {
+  const int s = blockIdx.x;
+  if (s >= count || state[s].status != 0) return;
+  const hp_batch_item it = items[s];
+  const int nc = it.sys.nc, nr = it.sys.nr, n = nc * nr;
+  const double h = it.sys.hbar2_2mu, E = it.E;
+  const cplx<double> *x = X + it.x_off;
+  cplx<double> *rr = Rr + it.x_off;
+  for (long e = threadIdx.x; e < (long)n * nc; e += 256) {
+    const int row = (int)(e / nc), cc = (int)(e - (long)row * nc);
+    const int c = row / nr, i = row - c * nr;
+    const int lc = it.sys.l[c];
+    const double ri = it.sys.r[i];
+    const double dg = h * (double)lc * (double)(lc + 1) / (ri * ri) + it.sys.eps[c] - E;
+    double sr = 0.0, si = 0.0;
+    const double *trow = it.sys.tl + (size_t)i * nr;
+    for (int j = 0; j < nr; ++j) {
+      const cplx<double> xv = x[(long)(c * nr + j) * nc + cc];
+      sr += h * trow[j] * xv.re;
+      si += h * trow[j] * xv.im;
+    }
+    const cplx<double> xi = x[(long)row * nc + cc];
+    sr += dg * xi.re;
+    si += dg * xi.im;
+    const double *vrow = it.sys.v + 2 * ((size_t)i * nc + c) * nc;
+    for (int cp = 0; cp < nc; ++cp) {
+      const cplx<double> xv = x[(long)(cp * nr + i) * nc + cc];
+      const double vr = vrow[2 * cp], vi = vrow[2 * cp + 1];
+      sr += vr * xv.re - vi * xv.im;
+      si += vr * xv.im + vi * xv.re;
+    }
+    const double b = (c == cc) ? it.sys.q[i] : 0.0;
+    rr[e] = cplx<double>{b - sr, -si};
+  }
+  __syncthreads();
+  // column maxima: thread t scans column t, t + 256, ...
+  for (int cc = threadIdx.x; cc < nc; cc += 256) {
+    double m = 0.0;
+    for (int row = 0; row < n; ++row) m = fmax(m, cabs1(rr[(long)row * nc + cc]));
+    cscale[it.c_off + cc] = (m > 0.0) ? m : 1.0;
+  }
+}
+
+// X += s Y for systems still refining; relative correction
+// corr = max_c |d_c|_inf / |x_c|_inf and the stop rule of hp_solve; counts
+// the systems still refining in *active.
+template <typename T>
+__global__ __launch_bounds__(256) void batch_update_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                           const cplx<T> *__restrict__ Y,
+                                                           cplx<double> *__restrict__ X,
+                                                           const double *__restrict__ cscale, BatchState *state,
+                                                           double tol, int max_refine, unsigned *active) {
+  __shared__ double red[256];
+  const int s = blockIdx.x;
+  if (s >= count || state[s].status != 0) return;
+  const hp_batch_item it = items[s];
+  const int nc = it.sys.nc, n = nc * it.sys.nr;
+  const cplx<T> *y = Y + it.x_off;
+  cplx<double> *x = X + it.x_off;
+  double corr = 0.0;
+  for (int cc = threadIdx.x; cc < nc; cc += 256) {
+    const double sc = cscale[it.c_off + cc];
+    double dm = 0.0, xm = 0.0;
+    for (int row = 0; row < n; ++row) {
+      const long e = (long)row * nc + cc;
+      const cplx<double> d{(double)y[e].re * sc, (double)y[e].im * sc};
+      cplx<double> v = x[e];
+      v.re += d.re;
+      v.im += d.im;
+      x[e] = v;
+      dm = fmax(dm, cabs1(d));
+      xm = fmax(xm, cabs1(v));
+    }
+    corr = fmax(corr, xm > 0.0 ? dm / xm : dm);
+  }
+  red[threadIdx.x] = corr;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    BatchState st = state[s];
+    corr = red[0];
+    st.iters += 1;
+    const double corr_tol = tol > 0.0 ? tol : 2.220446049250313e-16;
+    if (corr <= corr_tol) {
+      st.status = 1;
+    } else if (st.iters > 1 && corr > 0.5 * st.corr_prev) {
+      st.status = (st.corr_prev <= 1e-6) ? 1 : 2;
+    } else if (st.iters >= max_refine) {
+      st.status = 2;
+    }
+    st.corr = corr;
+    st.corr_prev = corr;
+    state[s] = st;
+    if (st.status == 0) atomicAdd(active, 1u);
+  }
+}
+
+__global__ void batch_state_init_kernel(int count, const int *__restrict__ info, BatchState *state, int refine) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= count) return;
+  BatchState st;
+  st.status = (info && info[s] != 0) ? 3 : (refine ? 0 : 1);
+  st.iters = 0;
+  st.corr_prev = 0.0;
+  st.corr = 0.0;
+  state[s] = st;
+}
+
+__global__ void batch_rmatrix_kernel(int count, const hp_batch_item *__restrict__ items,
+                                     const cplx<double> *__restrict__ X, cplx<double> *__restrict__ R) {
+  const int s = blockIdx.x;
+  if (s >= count) return;
+  const hp_batch_item it = items[s];
+  const int nc = it.sys.nc, nr = it.sys.nr;
+  const double f = it.sys.hbar2_2mu / it.sys.a;
+  for (int e = threadIdx.x; e < nc * nc; e += 256) {
+    const int c = e / nc, cp = e - c * nc;
+    double re = 0.0, im = 0.0;
+    for (int i = 0; i < nr; ++i) {
+      const cplx<double> xv = X[it.x_off + (long)(c * nr + i) * nc + cp];
+      re += it.sys.q[i] * xv.re;
+      im += it.sys.q[i] * xv.im;
+    }
+    R[it.r_off + e] = cplx<double>{f * re, f * im};
+  }
+}
+
+struct BatchWork {
+  unsigned *counter;  // [2]: work queue, active count
+  BatchState *state;  // [count]
+  double *cscale;     // [sum nc]
+  cplx<double> *res;  // [sum n nc] FP64 residual
+  char *y;            // [sum n nc] working-precision right-hand sides
+};
+
+BatchWork carve(char *w, int count, long sum_nc, long sum_xn) {
+  BatchWork b;
+  size_t off = 0;
+  b.counter = (unsigned *)(w + off);
+  off += 256;
+  b.state = (BatchState *)(w + off);
+  off += align_up(sizeof(BatchState) * (size_t)count, 256);
+  b.cscale = (double *)(w + off);
+  off += align_up(sizeof(double) * (size_t)sum_nc, 256);
+  b.res = (cplx<double> *)(w + off);
+  off += align_up(sizeof(cplx<double>) * (size_t)sum_xn, 256);
+  b.y = w + off;
+  return b;
+}
+
+size_t batch_bytes(int count, long sum_nc, long sum_xn, int prec) {
+  const size_t elt = prec == HP_C64 ? sizeof(cplx<float>) : sizeof(cplx<double>);
+  return 256 + align_up(sizeof(BatchState) * (size_t)count, 256) + align_up(sizeof(double) * (size_t)sum_nc, 256) +
+         align_up(sizeof(cplx<double>) * (size_t)sum_xn, 256) + align_up(elt * (size_t)sum_xn, 256);
+}
+
+}  // namespace
+
+}  // namespace hp
+
+using namespace hp;
+
+extern "C" size_t hp_batch_workspace_bytes(int count, long sum_nc, long sum_xn, int prec) {
+  if (count < 1 || sum_nc < 1 || sum_xn < 1 || (prec != HP_C64 && prec != HP_C128)) return 0;
+  return batch_bytes(count, sum_nc, sum_xn, prec);
+}
+
+extern "C" int hp_batch_build(int count, const hp_batch_item *items, int prec, void *A, void *stream) {
+  if (count < 1 || !items || !A) return HP_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  TraceScope ts(TR_ASSEMBLE, st, 0.0, 0.0);
+  if (prec == HP_C64)
+    hipLaunchKernelGGL(batch_build_kernel<float>, dim3(count), dim3(256), 0, st, count, items, (cplx<float> *)A);
+  else if (prec == HP_C128)
+    hipLaunchKernelGGL(batch_build_kernel<double>, dim3(count), dim3(256), 0, st, count, items, (cplx<double> *)A);
+  else
+    return HP_ERR_ARG;
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+extern "C" int hp_batch_factor(int count, const hp_batch_item *items, int prec, void *A, int *ipiv, int *perm,
+                               int *info, int panel, int groups, void *work, size_t work_bytes, void *stream) {
+  if (count < 1 || !items || !A || !ipiv || !perm || !info || !work || work_bytes < 256) return HP_ERR_ARG;
+  if (panel < 1 || panel > kBK || groups < 1) return HP_ERR_ARG;
+  if (prec != HP_C64 && prec != HP_C128) return HP_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned *counter = (unsigned *)work;
+  hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(64), 0, st, counter, 2);
+  HP_CHECK_LAUNCH();
+  const int grid = std::min(count, groups);
+  TraceScope ts(TR_PANEL, st, 0.0, 0.0);
+  int rc;
+  if (prec == HP_C64) {
+    const size_t shm = tile_lds_bytes<float>();
+    if ((rc = ensure_dynamic_lds((const void *)batch_lu_kernel<float>, shm))) return rc;
+    hipLaunchKernelGGL(batch_lu_kernel<float>, dim3(grid), dim3(256), shm, st, count, items, (cplx<float> *)A, ipiv,
+                       perm, info, counter, panel);
+  } else {
+    const size_t shm = tile_lds_bytes<double>();
+    if ((rc = ensure_dynamic_lds((const void *)batch_lu_kernel<double>, shm))) return rc;
+    hipLaunchKernelGGL(batch_lu_kernel<double>, dim3(grid), dim3(256), shm, st, count, items, (cplx<double> *)A,
+                       ipiv, perm, info, counter, panel);
+  }
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+extern "C" int hp_batch_solve_init(int count, const hp_batch_item *items, int prec, const void *LU, const int *perm,
+                                   const int *info_factor, double *X, int refine, long sum_nc, long sum_xn,
+                                   void *work, size_t work_bytes, void *stream) {
+  if (count < 1 || !items || !LU || !perm || !X || !work) return HP_ERR_ARG;
+  if (prec != HP_C64 && prec != HP_C128) return HP_ERR_ARG;
+  if (work_bytes < batch_bytes(count, sum_nc, sum_xn, prec)) return HP_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  BatchWork w = carve((char *)work, count, sum_nc, sum_xn);
+  hipLaunchKernelGGL(batch_state_init_kernel, dim3((count + 255) / 256), dim3(256), 0, st, count, info_factor,
+                     w.state, refine);
+  HP_CHECK_LAUNCH();
+  TraceScope ts(TR_TRSM, st, 0.0, 0.0);
+  int rc;
+  if (prec == HP_C64) {
+    const size_t shm = tile_lds_bytes<float>();
+    if ((rc = ensure_dynamic_lds((const void *)batch_solve_kernel<float>, shm))) return rc;
+    hipLaunchKernelGGL(batch_solve_kernel<float>, dim3(count), dim3(256), shm, st, count, items,
+                       (const cplx<float> *)LU, perm, (cplx<float> *)w.y, (cplx<double> *)X,
+                       (const cplx<double> *)nullptr, (const double *)nullptr, w.state, 0);
+  } else {
+    const size_t shm = tile_lds_bytes<double>();
+    if ((rc = ensure_dynamic_lds((const void *)batch_solve_kernel<double>, shm))) return rc;
+    hipLaunchKernelGGL(batch_solve_kernel<double>, dim3(count), dim3(256), shm, st, count, items,
+                       (const cplx<double> *)LU, perm, (cplx<double> *)X, (cplx<double> *)nullptr,
+                       (const cplx<double> *)nullptr, (const double *)nullptr, w.state, 0);
+  }
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+extern "C" int hp_batch_refine_step(int count, const hp_batch_item *items, const void *LU, const int *perm,
+                                    double *X, int max_refine, double tol, long sum_nc, long sum_xn, void *work,
+                                    size_t work_bytes, void *stream) {
+  if (count < 1 || !items || !LU || !perm || !X || !work) return HP_ERR_ARG;
+  if (work_bytes < batch_bytes(count, sum_nc, sum_xn, HP_C64)) return HP_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  BatchWork w = carve((char *)work, count, sum_nc, sum_xn);
+  hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(64), 0, st, w.counter + 1, 1);
+  HP_CHECK_LAUNCH();
+  {
+    TraceScope ts(TR_RESIDUAL, st, 0.0, 0.0);
+    hipLaunchKernelGGL(batch_residual_kernel, dim3(count), dim3(256), 0, st, count, items, (const cplx<double> *)X,
+                       w.res, w.cscale, w.state);
+    HP_CHECK_LAUNCH();
+  }
+  {
+    TraceScope ts(TR_TRSM, st, 0.0, 0.0);
+    const size_t shm = tile_lds_bytes<float>();
+    int rc;
+    if ((rc = ensure_dynamic_lds((const void *)batch_solve_kernel<float>, shm))) return rc;
+    hipLaunchKernelGGL(batch_solve_kernel<float>, dim3(count), dim3(256), shm, st, count, items,
+                       (const cplx<float> *)LU, perm, (cplx<float> *)w.y, (cplx<double> *)nullptr, w.res, w.cscale,
+                       w.state, 1);
+    HP_CHECK_LAUNCH();
+  }
+  TraceScope ts(TR_REFINE, st, 0.0, 0.0);
+  hipLaunchKernelGGL(batch_update_kernel<float>, dim3(count), dim3(256), 0, st, count, items,
+                     (const cplx<float> *)w.y, (cplx<double> *)X, w.cscale, w.state, tol, max_refine,
+                     w.counter + 1);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+extern "C" int hp_batch_active(const void *work, unsigned *active, void *stream) {
+  if (!work || !active) return HP_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  HP_CHECK_HIP(hipMemcpyAsync(active, (const unsigned *)work + 1, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  HP_CHECK_HIP(hipStreamSynchronize(st));
+  return HP_OK;
+}
+
+extern "C" int hp_batch_status(int count, const void *work, int *status, int *iters, void *stream) {
+  if (count < 1 || !work || !status) return HP_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  // the state array follows the 256-byte counter block
+  std::vector<BatchState> host((size_t)count);
+  HP_CHECK_HIP(hipMemcpyAsync(host.data(), (const char *)work + 256, sizeof(BatchState) * (size_t)count,
+                              hipMemcpyDeviceToHost, st));
+  HP_CHECK_HIP(hipStreamSynchronize(st));
+  for (int s = 0; s < count; ++s) {
+    status[s] = host[(size_t)s].status;
+    if (iters) iters[s] = host[(size_t)s].iters;
+  }
+  return HP_OK;
+}
+
+extern "C" int hp_batch_rmatrix(int count, const hp_batch_item *items, const double *X, double *R, void *stream) {
+  if (count < 1 || !items || !X || !R) return HP_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  TraceScope ts(TR_RMATRIX, st, 0.0, 0.0);
+  hipLaunchKernelGGL(batch_rmatrix_kernel, dim3(count), dim3(256), 0, st, count, items, (const cplx<double> *)X,
+                     (cplx<double> *)R);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}

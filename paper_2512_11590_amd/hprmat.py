@@ -38,6 +38,11 @@ class HpSystem(ctypes.Structure):
                 ("l", c_void_p), ("eps", c_void_p), ("v", c_void_p)]
 
 
+class HpBatchItem(ctypes.Structure):
+    _fields_ = [("sys", HpSystem), ("E", c_double), ("a_off", c_long), ("x_off", c_long),
+                ("p_off", c_long), ("r_off", c_long), ("c_off", c_long)]
+
+
 class HpTraceStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("launches", c_long), ("ms", c_double), ("flops", c_double),
                 ("bytes", c_double)]
@@ -54,7 +59,9 @@ class HpSolveInfo(ctypes.Structure):
 EXPORTS = ["hp_mesh", "hp_workspace_bytes", "hp_build_matrix", "hp_factor", "hp_solve",
            "hp_lu_solve", "hp_rmatrix", "hp_smatrix", "hp_coulomb", "hp_coulomb_device",
            "hp_build_info", "hp_strerror", "hp_trace_enable", "hp_trace_read", "hp_last_error",
-           "hp_gemm_sub", "hp_set_concurrency"]
+           "hp_gemm_sub", "hp_set_concurrency", "hp_batch_workspace_bytes", "hp_batch_build",
+           "hp_batch_factor", "hp_batch_solve_init", "hp_batch_refine_step", "hp_batch_active",
+           "hp_batch_status", "hp_batch_rmatrix"]
 
 _lib = None
 
@@ -107,6 +114,25 @@ def lib() -> ctypes.CDLL:
     L.hp_coulomb.restype = c_int
     L.hp_coulomb_device.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.hp_coulomb_device.restype = c_int
+    L.hp_batch_workspace_bytes.argtypes = [c_int, c_long, c_long, c_int]
+    L.hp_batch_workspace_bytes.restype = c_size_t
+    L.hp_batch_build.argtypes = [c_int, c_void_p, c_int, c_void_p, c_void_p]
+    L.hp_batch_build.restype = c_int
+    L.hp_batch_factor.argtypes = [c_int, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int,
+                                  c_void_p, c_size_t, c_void_p]
+    L.hp_batch_factor.restype = c_int
+    L.hp_batch_solve_init.argtypes = [c_int, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                      c_long, c_long, c_void_p, c_size_t, c_void_p]
+    L.hp_batch_solve_init.restype = c_int
+    L.hp_batch_refine_step.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_double, c_long,
+                                       c_long, c_void_p, c_size_t, c_void_p]
+    L.hp_batch_refine_step.restype = c_int
+    L.hp_batch_active.argtypes = [c_void_p, P(ctypes.c_uint), c_void_p]
+    L.hp_batch_active.restype = c_int
+    L.hp_batch_status.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.hp_batch_status.restype = c_int
+    L.hp_batch_rmatrix.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.hp_batch_rmatrix.restype = c_int
     L.hp_set_concurrency.argtypes = [c_int]
     L.hp_set_concurrency.restype = c_int
     L.hp_trace_enable.argtypes = [c_int]
@@ -223,6 +249,50 @@ def hp_smatrix(sys: HpSystem, E: float, R, S, work, stream=None) -> int:
 def hp_coulomb_device(l, eta, rho, out, stream=None) -> None:
     _check(lib().hp_coulomb_device(int(l.numel()), _ptr(l), _ptr(eta), _ptr(rho), _ptr(out),
                                    _stream(stream)), "hp_coulomb_device")
+
+
+# ---- batched uneven systems (device item array: a uint8 tensor of HpBatchItem records)
+
+def hp_batch_workspace_bytes(count: int, sum_nc: int, sum_xn: int, prec: int) -> int:
+    return int(lib().hp_batch_workspace_bytes(count, sum_nc, sum_xn, prec))
+
+
+def hp_batch_build(count, items, prec, A, stream=None) -> None:
+    _check(lib().hp_batch_build(count, _ptr(items), prec, _ptr(A), _stream(stream)), "hp_batch_build")
+
+
+def hp_batch_factor(count, items, prec, A, ipiv, perm, info, panel, groups, work, stream=None) -> None:
+    _check(lib().hp_batch_factor(count, _ptr(items), prec, _ptr(A), _ptr(ipiv), _ptr(perm), _ptr(info), panel,
+                                 groups, _ptr(work), work.numel(), _stream(stream)), "hp_batch_factor")
+
+
+def hp_batch_solve_init(count, items, prec, LU, perm, info, X, refine, sum_nc, sum_xn, work, stream=None) -> None:
+    _check(lib().hp_batch_solve_init(count, _ptr(items), prec, _ptr(LU), _ptr(perm), _ptr(info), _ptr(X),
+                                     int(bool(refine)), sum_nc, sum_xn, _ptr(work), work.numel(), _stream(stream)),
+           "hp_batch_solve_init")
+
+
+def hp_batch_refine_step(count, items, LU, perm, X, max_refine, tol, sum_nc, sum_xn, work, stream=None) -> None:
+    _check(lib().hp_batch_refine_step(count, _ptr(items), _ptr(LU), _ptr(perm), _ptr(X), max_refine, tol, sum_nc,
+                                      sum_xn, _ptr(work), work.numel(), _stream(stream)), "hp_batch_refine_step")
+
+
+def hp_batch_active(work, stream=None) -> int:
+    v = ctypes.c_uint(0)
+    _check(lib().hp_batch_active(_ptr(work), ctypes.byref(v), _stream(stream)), "hp_batch_active")
+    return int(v.value)
+
+
+def hp_batch_status(count, work, stream=None):
+    st = np.zeros(count, dtype=np.int32)
+    it = np.zeros(count, dtype=np.int32)
+    _check(lib().hp_batch_status(count, _ptr(work), st.ctypes.data, it.ctypes.data, _stream(stream)),
+           "hp_batch_status")
+    return st, it
+
+
+def hp_batch_rmatrix(count, items, X, R, stream=None) -> None:
+    _check(lib().hp_batch_rmatrix(count, _ptr(items), _ptr(X), _ptr(R), _stream(stream)), "hp_batch_rmatrix")
 
 
 def hp_set_concurrency(factorizations: int) -> int:
