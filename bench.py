@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--max-refine", type=int, default=30)
     ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-systems", type=int, default=512)
     ap.add_argument("--served-requests", type=int, default=24)
     ap.add_argument("--served-rate", type=float, default=4.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--served-slots", type=int, default=4)
@@ -94,6 +96,35 @@ def gemm_traffic():
     with open(path, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     return GEMM_TRAFFIC["bytes_per_launch"] if sha == GEMM_TRAFFIC["gemm_source_sha256"] else None
+
+
+def batched(args, H, torch):
+    """The uneven batch: nc ~ U{5..80}, nr ~ U{40..50}, one energy per system,
+    one workgroup per system in size buckets (autotuned on each bucket's 8
+    largest systems), FP32 + IR and FP64.  Rate: (8/3) sum N^3 / time of
+    build + factor + solve (+ refinement) + R for the whole batch."""
+    import numpy as np
+    from paper_2512_11590_amd import batch as B
+    from workload import batch_systems
+    sps = batch_systems(args.batched_systems)
+    res = {"systems": len(sps), "N_range": [min(s.nc * s.nr for s in sps), max(s.nc * s.nr for s in sps)]}
+    for name, prec in (("fp32_ir", H.HP_C64), ("fp64", H.HP_C128)):
+        print(f"[bench] batched {name}: {len(sps)} systems", file=sys.stderr, flush=True)
+        bt = B.Batch(sps, [s.energies[0] for s in sps], prec)
+        tuned = bt.tune(sample=8, panels=(16, 32))
+        bt.run()  # warm (captures the refinement graphs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = bt.run()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        st, it = bt.status()
+        res[name] = {"ms": t * 1e3, "tflops": bt.flops / t / 1e12, "systems_per_s": len(sps) / t,
+                     "buckets": tuned, "refinement_steps": steps,
+                     "converged": int(np.sum(st == 1)), "mean_corrections": float(it.mean())}
+        del bt
+        torch.cuda.empty_cache()
+    return res
 
 
 def served_stream(args, H, torch):
@@ -222,6 +253,8 @@ def main():
                           "S_relerr_fp32ir_vs_fp64_at_E": [last_e, err]}
         del s64
         torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = batched(args, H, torch)
     if not args.no_served:
         out["served"] = served_stream(args, H, torch)
     if not args.no_cpu:

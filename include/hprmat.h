@@ -215,6 +215,18 @@ int hp_batch_build(int count, const hp_batch_item *items, int prec, void *A, voi
 int hp_batch_factor(int count, const hp_batch_item *items, int prec, void *A, int *ipiv, int *perm,
                     int *info, int panel, int groups, void *work, size_t work_bytes, void *stream);
 
+/* The same factorization in steps, for batches of larger systems: per panel
+ * step one launch for the column steps of every system still factoring and
+ * one launch of all their trailing-update tiles, so the device is filled by
+ * tiles rather than by systems.  n_host: HOST array of the systems' n, which
+ * must be listed largest first (HP_ERR_ARG otherwise).  work: at least 256 +
+ * 4 * ceil(nmax / panel) * (count + 1) bytes (the batch workspace of
+ * hp_batch_workspace_bytes is enough).  Errors: HP_ERR_ARG,
+ * HP_ERR_WORKSPACE, HP_ERR_HIP. */
+int hp_batch_factor_stepped(int count, const hp_batch_item *items, const int *n_host, int prec, void *A,
+                            int *ipiv, int *perm, int *info, int panel, void *work, size_t work_bytes,
+                            void *stream);
+
 /* Solves every system for its nc surface right-hand sides with the factors:
  * X (FP64, per system at x_off) = C^-1 B.  With refine != 0 (FP32 factors
  * only), the per-system refinement state is reset for hp_batch_refine_step;

@@ -8,8 +8,11 @@ solved by the batched entry points of the C ABI, one workgroup per system:
         -> [hp_batch_refine_step]* (FP32 factors) -> hp_batch_rmatrix
 
 Systems are split into size buckets; each bucket is one persistent
-batched-LU launch (systems largest first), with its panel width and grid
-size picked by `autotune` (timed on the bucket itself, cached per bucket
+batched-LU launch (systems largest first, one workgroup per system) or, for
+buckets of larger systems, the stepped form (per panel step one launch of
+every system's column steps and one of all their trailing-update tiles).
+The form, panel width and grid size of each bucket are picked by
+`autotune` (timed on the bucket or its largest systems, cached per bucket
 and precision).  The refinement step is captured once in a HIP graph and
 replayed until no system of the bucket is still refining.  The collision
 matrix S of each system follows from its R through hp_smatrix.  All
@@ -35,7 +38,7 @@ GROUPS_PER_CU = (2, 3)
 @dataclass
 class BucketTuning:
     panel: int
-    groups: int
+    groups: int  # workgroups of the persistent grid; 0: the stepped form
     ms: float
 
 
@@ -114,9 +117,15 @@ class Bucket:
         return (int(self.n.max()), int(self.n.min()), self.count, self.prec)
 
     def factor(self, panel: int, groups: int) -> None:
+        """Build and factor; groups > 0: persistent grid of that many
+        workgroups, groups == 0: the stepped form."""
         H.hp_batch_build(self.count, self.items, self.prec, self.A)
-        H.hp_batch_factor(self.count, self.items, self.prec, self.A, self.ipiv, self.perm, self.info, panel,
-                          groups, self.work)
+        if groups > 0:
+            H.hp_batch_factor(self.count, self.items, self.prec, self.A, self.ipiv, self.perm, self.info, panel,
+                              groups, self.work)
+        else:
+            H.hp_batch_factor_stepped(self.count, self.items, self.n, self.prec, self.A, self.ipiv, self.perm,
+                                      self.info, panel, self.work)
 
     def solve_init(self, max_refine: int = 30) -> bool:
         """Initial solve; True if FP32 refinement follows."""
@@ -180,20 +189,26 @@ class Bucket:
         return S.cpu().numpy()
 
 
-def autotune(bucket: Bucket, cus: int, reps: int = 1) -> BucketTuning:
-    """Time the bucket's factorization for each panel width and grid size;
-    keep the fastest (cached per bucket shape and precision)."""
+def autotune(bucket: Bucket, cus: int, reps: int = 1, sample: int | None = None, panels=PANELS,
+             groups_per_cu=GROUPS_PER_CU) -> BucketTuning:
+    """Time the factorization for each panel width and grid size, on the
+    bucket itself or on a bucket of its `sample` largest systems; keep the
+    fastest (cached per bucket shape and precision)."""
     if bucket.key in _TUNED:
         return _TUNED[bucket.key]
+    probe = bucket
+    if sample is not None and sample < bucket.count:
+        probe = Bucket(bucket.systems[:sample], bucket.energies[:sample], list(range(sample)), bucket.prec,
+                       bucket.device)
     best = None
-    for panel in PANELS:
-        for gpc in GROUPS_PER_CU:
+    for panel in panels:
+        for gpc in tuple(groups_per_cu) + (0,):
             groups = gpc * cus
-            bucket.factor(panel, groups)  # warm
+            probe.factor(panel, groups)  # warm
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(reps):
-                bucket.factor(panel, groups)
+                probe.factor(panel, groups)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) / reps * 1e3
             if best is None or ms < best.ms:
@@ -221,9 +236,9 @@ class Batch:
         self.tuning = {}
         self.flops = sum(b.flops for b in self.buckets)
 
-    def tune(self) -> dict:
+    def tune(self, **kw) -> dict:
         for b in self.buckets:
-            self.tuning[b.key] = autotune(b, self.cus)
+            self.tuning[b.key] = autotune(b, self.cus, **kw)
         return {f"N {int(b.n.min())}-{int(b.n.max())} ({b.count})": vars(self.tuning[b.key]) for b in self.buckets}
 
     def run(self, max_refine: int = 30, tol: float = 0.0, use_graph: bool = True) -> dict:

@@ -60,90 +60,96 @@ constexpr size_t tile_lds_bytes() {
   return (size_t)2 * kBK * kBLd * sizeof(cplx<T>);
 }
 
-// C[M x N] -= A[M x K] B[K x N] (K <= kBK) by one workgroup, in 64 x 64 output
-// tiles: A and B staged k-major in LDS, four wavefronts of 32 x 32 outputs,
-// MFMA 16x16x4.  FP32: three real products per complex product (3M), FP64:
-// four (4M).  A, B and C must not overlap.  Ends with a barrier.
+// One 64 x 64 output tile (m0, n0) of C[M x N] -= A[M x K] B[K x N]
+// (K <= kBK) by one workgroup: A and B staged k-major in LDS, four
+// wavefronts of 32 x 32 outputs, MFMA 16x16x4.  FP32: three real products
+// per complex product (3M), FP64: four (4M).  A, B and C must not overlap.
+// Ends with a barrier.
 template <typename T>
-__device__ void wg_gemm_sub(int M, int N, int K, const cplx<T> *__restrict__ A, long lda,
-                            const cplx<T> *__restrict__ B, long ldb, cplx<T> *__restrict__ C, long ldc,
-                            cplx<T> *As, cplx<T> *Bs) {
+__device__ void tile_gemm_sub(int m0, int n0, int M, int N, int K, const cplx<T> *__restrict__ A, long lda,
+                              const cplx<T> *__restrict__ B, long ldb, cplx<T> *__restrict__ C, long ldc,
+                              cplx<T> *As, cplx<T> *Bs) {
   typedef typename BMfma<T>::v4 v4;
   constexpr bool M3 = sizeof(T) == 4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int fr = lane & 15, fk = lane >> 4;
   const int Kp = (K + 3) & ~3;
-  const int tm = (M + 63) / 64, tn = (N + 63) / 64;
   const cplx<T> zero{T(0), T(0)};
-  for (int t = 0; t < tm * tn; ++t) {
-    const int m0 = (t / tn) * 64, n0 = (t % tn) * 64;
-    for (int e = tid; e < 64 * Kp; e += 256) {
-      const int r = e / Kp, k = e - r * Kp;
-      cplx<T> v = zero;
-      if (m0 + r < M && k < K) v = A[(long)(m0 + r) * lda + k];
-      As[k * kBLd + r] = v;
-    }
-    for (int e = tid; e < Kp * 64; e += 256) {
-      const int k = e >> 6, c = e & 63;
-      cplx<T> v = zero;
-      if (k < K && n0 + c < N) v = B[(long)k * ldb + n0 + c];
-      Bs[k * kBLd + c] = v;
-    }
-    __syncthreads();
-    v4 p1[2][2], p2[2][2], p3[2][2];
+  for (int e = tid; e < 64 * Kp; e += 256) {
+    const int r = e / Kp, k = e - r * Kp;
+    cplx<T> v = zero;
+    if (m0 + r < M && k < K) v = A[(long)(m0 + r) * lda + k];
+    As[k * kBLd + r] = v;
+  }
+  for (int e = tid; e < Kp * 64; e += 256) {
+    const int k = e >> 6, c = e & 63;
+    cplx<T> v = zero;
+    if (k < K && n0 + c < N) v = B[(long)k * ldb + n0 + c];
+    Bs[k * kBLd + c] = v;
+  }
+  __syncthreads();
+  v4 p1[2][2], p2[2][2], p3[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) p1[i][j] = p2[i][j] = p3[i][j] = v4{0, 0, 0, 0};
+  for (int ks = 0; ks < Kp; ks += 4) {
+    const int kk = ks + fk;
+    cplx<T> af[2], bf[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) af[i] = As[kk * kBLd + wm + i * 16 + fr];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bf[j] = Bs[kk * kBLd + wn + j * 16 + fr];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) p1[i][j] = p2[i][j] = p3[i][j] = v4{0, 0, 0, 0};
-    for (int ks = 0; ks < Kp; ks += 4) {
-      const int kk = ks + fk;
-      cplx<T> af[2], bf[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) af[i] = As[kk * kBLd + wm + i * 16 + fr];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) bf[j] = Bs[kk * kBLd + wn + j * 16 + fr];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          if constexpr (M3) {
-            // p1 = Ar Br, p2 = Ai Bi, p3 = (Ar + Ai)(Br + Bi)
-            p1[i][j] = BMfma<T>::mac(af[i].re, bf[j].re, p1[i][j]);
-            p2[i][j] = BMfma<T>::mac(af[i].im, bf[j].im, p2[i][j]);
-            p3[i][j] = BMfma<T>::mac(af[i].re + af[i].im, bf[j].re + bf[j].im, p3[i][j]);
-          } else {
-            // p1 = Ar Br - Ai Bi, p3 = Ar Bi + Ai Br
-            p1[i][j] = BMfma<T>::mac(af[i].re, bf[j].re, p1[i][j]);
-            p1[i][j] = BMfma<T>::mac(-af[i].im, bf[j].im, p1[i][j]);
-            p3[i][j] = BMfma<T>::mac(af[i].re, bf[j].im, p3[i][j]);
-            p3[i][j] = BMfma<T>::mac(af[i].im, bf[j].re, p3[i][j]);
-          }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gr = m0 + wm + i * 16 + BMfma<T>::d_row(lane, r);
-        if (gr >= M) continue;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int gc = n0 + wn + j * 16 + fr;
-          if (gc >= N) continue;
-          cplx<T> c = C[(long)gr * ldc + gc];
-          if constexpr (M3) {
-            c.re -= p1[i][j][r] - p2[i][j][r];
-            c.im -= p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
-          } else {
-            c.re -= p1[i][j][r];
-            c.im -= p3[i][j][r];
-          }
-          C[(long)gr * ldc + gc] = c;
+      for (int j = 0; j < 2; ++j) {
+        if constexpr (M3) {
+          // p1 = Ar Br, p2 = Ai Bi, p3 = (Ar + Ai)(Br + Bi)
+          p1[i][j] = BMfma<T>::mac(af[i].re, bf[j].re, p1[i][j]);
+          p2[i][j] = BMfma<T>::mac(af[i].im, bf[j].im, p2[i][j]);
+          p3[i][j] = BMfma<T>::mac(af[i].re + af[i].im, bf[j].re + bf[j].im, p3[i][j]);
+        } else {
+          // p1 = Ar Br - Ai Bi, p3 = Ar Bi + Ai Br
+          p1[i][j] = BMfma<T>::mac(af[i].re, bf[j].re, p1[i][j]);
+          p1[i][j] = BMfma<T>::mac(-af[i].im, bf[j].im, p1[i][j]);
+          p3[i][j] = BMfma<T>::mac(af[i].re, bf[j].im, p3[i][j]);
+          p3[i][j] = BMfma<T>::mac(af[i].im, bf[j].re, p3[i][j]);
         }
       }
-    __syncthreads();
   }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = m0 + wm + i * 16 + BMfma<T>::d_row(lane, r);
+      if (gr >= M) continue;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int gc = n0 + wn + j * 16 + fr;
+        if (gc >= N) continue;
+        cplx<T> c = C[(long)gr * ldc + gc];
+        if constexpr (M3) {
+          c.re -= p1[i][j][r] - p2[i][j][r];
+          c.im -= p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
+        } else {
+          c.re -= p1[i][j][r];
+          c.im -= p3[i][j][r];
+        }
+        C[(long)gr * ldc + gc] = c;
+      }
+    }
+  __syncthreads();
+}
+
+// All of C[M x N] -= A[M x K] B[K x N] by one workgroup, tile after tile.
+template <typename T>
+__device__ void wg_gemm_sub(int M, int N, int K, const cplx<T> *__restrict__ A, long lda,
+                            const cplx<T> *__restrict__ B, long ldb, cplx<T> *__restrict__ C, long ldc,
+                            cplx<T> *As, cplx<T> *Bs) {
+  const int tm = (M + 63) / 64, tn = (N + 63) / 64;
+  for (int t = 0; t < tm * tn; ++t) tile_gemm_sub<T>((t / tn) * 64, (t % tn) * 64, M, N, K, A, lda, B, ldb, C, ldc, As, Bs);
 }
 
 // Workgroup argmax of (v, row): largest v, smallest row on ties; every
@@ -225,12 +231,81 @@ __global__ __launch_bounds__(256) void batch_build_kernel(int count, const hp_ba
 }
 
 // ----------------------------------------------------------- factorization --
-// One workgroup factors one system at a time, P A = L U with partial pivoting
-// (largest |Re|+|Im|, smallest row on ties), in panels of W columns:
+// P A = L U with partial pivoting (largest |Re|+|Im|, smallest row on ties),
+// in panels of W columns:
 //   column steps: pivot search, full-row interchange, scaling of the column
 //   and update of the panel's remaining columns;
 //   block row: U12 = L11^-1 A12 (one thread per column);
-//   trailing update A22 -= L21 U12 (workgroup MFMA tiles).
+//   trailing update A22 -= L21 U12 (MFMA tiles).
+
+// Column steps and block row of the panel [j0, j0 + w) of one n x n system,
+// by one workgroup.  Records the pivots, and the first exactly zero pivot
+// column (1-based) in *first_zero if it is still 0.
+template <typename T>
+__device__ void panel_steps(cplx<T> *a, int n, int j0, int w, int *piv, int *first_zero, cplx<T> *urow, T *sv,
+                            int *sr) {
+  const int tid = threadIdx.x;
+  for (int jj = 0; jj < w; ++jj) {
+    const int j = j0 + jj;
+    T best = T(-1);
+    int brow = INT_MAX;
+    for (int r = j + tid; r < n; r += 256) {
+      const T v = cabs1(a[(long)r * n + j]);
+      if (v > best || (v == best && r < brow)) {
+        best = v;
+        brow = r;
+      }
+    }
+    wg_argmax(best, brow, sv, sr);
+    const int p = (brow >= j && brow < n) ? brow : j;
+    const bool nz = best > T(0);
+    if (tid == 0) {
+      piv[j] = p;
+      if (!nz && *first_zero == 0) *first_zero = j + 1;
+    }
+    if (p != j)
+      for (int c = tid; c < n; c += 256) {
+        const cplx<T> x = a[(long)j * n + c];
+        a[(long)j * n + c] = a[(long)p * n + c];
+        a[(long)p * n + c] = x;
+      }
+    __syncthreads();
+    if (tid < w) urow[tid] = a[(long)j * n + j0 + tid];
+    __syncthreads();
+    if (nz) {
+      const cplx<T> inv = crcp(urow[jj]);
+      for (int r = j + 1 + tid; r < n; r += 256) {
+        cplx<T> *row = a + (long)r * n + j0;
+        const cplx<T> l = cmul(row[jj], inv);
+        row[jj] = l;
+        for (int c = jj + 1; c < w; ++c) row[c] = cfms(row[c], l, urow[c]);
+      }
+    }
+    __syncthreads();
+  }
+  // U12 = L11^-1 A12
+  for (int c = j0 + w + tid; c < n; c += 256) {
+    for (int i = 1; i < w; ++i) {
+      cplx<T> sum = a[(long)(j0 + i) * n + c];
+      for (int k = 0; k < i; ++k) sum = cfms(sum, a[(long)(j0 + i) * n + j0 + k], a[(long)(j0 + k) * n + c]);
+      a[(long)(j0 + i) * n + c] = sum;
+    }
+  }
+  __syncthreads();
+}
+
+// perm = the composition of the interchanges (one thread).
+__device__ void compose_perm(const int *piv, int *pm, int n) {
+  for (int i = 0; i < n; ++i) pm[i] = i;
+  for (int k = 0; k < n; ++k) {
+    const int p = piv[k];
+    const int x = pm[k];
+    pm[k] = pm[p];
+    pm[p] = x;
+  }
+}
+
+// Persistent form: one workgroup factors one system at a time.
 template <typename T>
 __global__ __launch_bounds__(256) void batch_lu_kernel(int count, const hp_batch_item *__restrict__ items,
                                                        cplx<T> *__restrict__ A, int *__restrict__ ipiv,
@@ -243,6 +318,7 @@ __global__ __launch_bounds__(256) void batch_lu_kernel(int count, const hp_batch
   __shared__ T sv[4];
   __shared__ int sr[4];
   __shared__ int s_idx;
+  __shared__ int s_zero;
   const int tid = threadIdx.x;
   for (;;) {
     const int s = next_item(counter, &s_idx);
@@ -251,74 +327,99 @@ __global__ __launch_bounds__(256) void batch_lu_kernel(int count, const hp_batch
     const int n = item_n(it);
     cplx<T> *a = A + it.a_off;
     int *piv = ipiv + it.p_off;
-    int first_zero = 0;
+    if (tid == 0) s_zero = 0;
+    __syncthreads();
     for (int j0 = 0; j0 < n; j0 += W) {
       const int w = min(W, n - j0);
-      for (int jj = 0; jj < w; ++jj) {
-        const int j = j0 + jj;
-        T best = T(-1);
-        int brow = INT_MAX;
-        for (int r = j + tid; r < n; r += 256) {
-          const T v = cabs1(a[(long)r * n + j]);
-          if (v > best || (v == best && r < brow)) {
-            best = v;
-            brow = r;
-          }
-        }
-        wg_argmax(best, brow, sv, sr);
-        const int p = (brow >= j && brow < n) ? brow : j;
-        if (tid == 0) piv[j] = p;
-        const bool nz = best > T(0);
-        if (!nz && first_zero == 0) first_zero = j + 1;
-        if (p != j)
-          for (int c = tid; c < n; c += 256) {
-            const cplx<T> x = a[(long)j * n + c];
-            a[(long)j * n + c] = a[(long)p * n + c];
-            a[(long)p * n + c] = x;
-          }
-        __syncthreads();
-        if (tid < w) urow[tid] = a[(long)j * n + j0 + tid];
-        __syncthreads();
-        if (nz) {
-          const cplx<T> inv = crcp(urow[jj]);
-          for (int r = j + 1 + tid; r < n; r += 256) {
-            cplx<T> *row = a + (long)r * n + j0;
-            const cplx<T> l = cmul(row[jj], inv);
-            row[jj] = l;
-            for (int c = jj + 1; c < w; ++c) row[c] = cfms(row[c], l, urow[c]);
-          }
-        }
-        __syncthreads();
-      }
+      panel_steps<T>(a, n, j0, w, piv, &s_zero, urow, sv, sr);
       const int rest = n - j0 - w;
-      if (rest > 0) {
-        // U12 = L11^-1 A12
-        for (int c = j0 + w + tid; c < n; c += 256) {
-          for (int i = 1; i < w; ++i) {
-            cplx<T> sum = a[(long)(j0 + i) * n + c];
-            for (int k = 0; k < i; ++k) sum = cfms(sum, a[(long)(j0 + i) * n + j0 + k], a[(long)(j0 + k) * n + c]);
-            a[(long)(j0 + i) * n + c] = sum;
-          }
-        }
-        __syncthreads();
+      if (rest > 0)
         wg_gemm_sub<T>(rest, rest, w, a + (long)(j0 + w) * n + j0, n, a + (long)j0 * n + j0 + w, n,
                        a + (long)(j0 + w) * n + j0 + w, n, As, Bs);
-      }
     }
-    // perm = the composition of the interchanges; info
     if (tid == 0) {
-      int *pm = perm + it.p_off;
-      for (int i = 0; i < n; ++i) pm[i] = i;
-      for (int k = 0; k < n; ++k) {
-        const int p = piv[k];
-        const int x = pm[k];
-        pm[k] = pm[p];
-        pm[p] = x;
-      }
-      info[s] = first_zero;
+      compose_perm(piv, perm + it.p_off, n);
+      info[s] = s_zero;
     }
     __syncthreads();
   }
+}
+
+// Stepped form, for buckets of larger systems: one launch per panel step for
+// the column steps of every system still factoring (systems listed largest
+// first, so they are items [0, active)), then one launch of all their
+// trailing-update tiles.
+template <typename T>
+__global__ __launch_bounds__(256) void batch_panel_kernel(const hp_batch_item *__restrict__ items,
+                                                          cplx<T> *__restrict__ A, int *__restrict__ ipiv,
+                                                          int *__restrict__ perm, int *__restrict__ info, int j0,
+                                                          int W) {
+  __shared__ cplx<T> urow[kBK];
+  __shared__ T sv[4];
+  __shared__ int sr[4];
+  __shared__ int s_zero;
+  const int s = blockIdx.x;
+  const hp_batch_item it = items[s];
+  const int n = item_n(it);
+  if (j0 >= n) return;
+  const int w = min(W, n - j0);
+  int *piv = ipiv + it.p_off;
+  if (threadIdx.x == 0) s_zero = info[s];
+  __syncthreads();
+  panel_steps<T>(A + it.a_off, n, j0, w, piv, &s_zero, urow, sv, sr);
+  if (threadIdx.x == 0) {
+    info[s] = s_zero;
+    if (j0 + w == n) compose_perm(piv, perm + it.p_off, n);
+  }
+}
+
+// Tile offsets of every panel step: offs[t * (count + 1) + s] = number of
+// trailing-update tiles of systems [0, s) at step t (exclusive prefix sum).
+__global__ void batch_tiles_kernel(int count, const hp_batch_item *__restrict__ items, int W, int *offs) {
+  const int t = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const int j0 = t * W;
+  int acc = 0;
+  int *o = offs + (long)t * (count + 1);
+  for (int s = 0; s < count; ++s) {
+    o[s] = acc;
+    const int n = item_n(items[s]);
+    if (j0 < n) {
+      const int rest = n - j0 - min(W, n - j0);
+      const int tt = (rest + 63) / 64;
+      acc += tt * tt;
+    }
+  }
+  o[count] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void batch_trail_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                          cplx<T> *__restrict__ A, const int *__restrict__ offs,
+                                                          int j0, int W) {
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T> *As = reinterpret_cast<cplx<T> *>(smem_raw);
+  cplx<T> *Bs = As + kBK * kBLd;
+  const int g = blockIdx.x;
+  if (g >= offs[count]) return;
+  // the system owning tile g: offs[s] <= g < offs[s + 1]
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (offs[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const hp_batch_item it = items[lo];
+  const int n = item_n(it);
+  const int w = min(W, n - j0);
+  const int rest = n - j0 - w;
+  const int tn = (rest + 63) / 64;
+  const int l = g - offs[lo];
+  cplx<T> *a = A + it.a_off;
+  tile_gemm_sub<T>((l / tn) * 64, (l % tn) * 64, rest, rest, w, a + (long)(j0 + w) * n + j0, n,
+                   a + (long)j0 * n + j0 + w, n, a + (long)(j0 + w) * n + j0 + w, n, As, Bs);
 }
 
 // ------------------------------------------------------------------- solves --
@@ -620,6 +721,60 @@ extern "C" int hp_batch_factor(int count, const hp_batch_item *items, int prec, 
                        ipiv, perm, info, counter, panel);
   }
   HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+extern "C" int hp_batch_factor_stepped(int count, const hp_batch_item *items, const int *n_host, int prec,
+                                       void *A, int *ipiv, int *perm, int *info, int panel, void *work,
+                                       size_t work_bytes, void *stream) {
+  if (count < 1 || !items || !n_host || !A || !ipiv || !perm || !info || !work) return HP_ERR_ARG;
+  if (panel < 1 || panel > kBK || (prec != HP_C64 && prec != HP_C128)) return HP_ERR_ARG;
+  int nmax = 0;
+  for (int s = 0; s < count; ++s) {
+    if (n_host[s] < 1 || (s > 0 && n_host[s] > n_host[s - 1])) return HP_ERR_ARG;  // largest first
+    nmax = std::max(nmax, n_host[s]);
+  }
+  const int steps = (nmax + panel - 1) / panel;
+  const size_t tbl = 256 + sizeof(int) * (size_t)steps * (count + 1);
+  if (work_bytes < tbl) return HP_ERR_WORKSPACE;
+  int *offs = (int *)((char *)work + 256);
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(batch_zero_kernel, dim3((count + 255) / 256), dim3(256), 0, st, (unsigned *)info, count);
+  HP_CHECK_LAUNCH();
+  hipLaunchKernelGGL(batch_tiles_kernel, dim3(steps), dim3(64), 0, st, count, items, panel, offs);
+  HP_CHECK_LAUNCH();
+  const size_t shm = prec == HP_C64 ? tile_lds_bytes<float>() : tile_lds_bytes<double>();
+  int rc = prec == HP_C64 ? ensure_dynamic_lds((const void *)batch_trail_kernel<float>, shm)
+                          : ensure_dynamic_lds((const void *)batch_trail_kernel<double>, shm);
+  if (rc) return rc;
+  TraceScope ts(TR_PANEL, st, 0.0, 0.0);
+  for (int t = 0; t < steps; ++t) {
+    const int j0 = t * panel;
+    int active = 0;
+    long tiles = 0;
+    for (int s = 0; s < count && n_host[s] > j0; ++s) {
+      ++active;
+      const long rest = n_host[s] - j0 - std::min(panel, n_host[s] - j0);
+      const long tt = (rest + 63) / 64;
+      tiles += tt * tt;
+    }
+    if (prec == HP_C64)
+      hipLaunchKernelGGL(batch_panel_kernel<float>, dim3(active), dim3(256), 0, st, items, (cplx<float> *)A, ipiv,
+                         perm, info, j0, panel);
+    else
+      hipLaunchKernelGGL(batch_panel_kernel<double>, dim3(active), dim3(256), 0, st, items, (cplx<double> *)A,
+                         ipiv, perm, info, j0, panel);
+    HP_CHECK_LAUNCH();
+    if (tiles == 0) continue;
+    if (tiles > (1L << 30)) return HP_ERR_UNSUPPORTED;
+    if (prec == HP_C64)
+      hipLaunchKernelGGL(batch_trail_kernel<float>, dim3((unsigned)tiles), dim3(256), shm, st, active, items,
+                         (cplx<float> *)A, offs + (long)t * (count + 1), j0, panel);
+    else
+      hipLaunchKernelGGL(batch_trail_kernel<double>, dim3((unsigned)tiles), dim3(256), shm, st, active, items,
+                         (cplx<double> *)A, offs + (long)t * (count + 1), j0, panel);
+    HP_CHECK_LAUNCH();
+  }
   return HP_OK;
 }
 

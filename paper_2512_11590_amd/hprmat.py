@@ -60,7 +60,7 @@ EXPORTS = ["hp_mesh", "hp_workspace_bytes", "hp_build_matrix", "hp_factor", "hp_
            "hp_lu_solve", "hp_rmatrix", "hp_smatrix", "hp_coulomb", "hp_coulomb_device",
            "hp_build_info", "hp_strerror", "hp_trace_enable", "hp_trace_read", "hp_last_error",
            "hp_gemm_sub", "hp_set_concurrency", "hp_batch_workspace_bytes", "hp_batch_build",
-           "hp_batch_factor", "hp_batch_solve_init", "hp_batch_refine_step", "hp_batch_active",
+           "hp_batch_factor", "hp_batch_factor_stepped", "hp_batch_solve_init", "hp_batch_refine_step", "hp_batch_active",
            "hp_batch_status", "hp_batch_rmatrix"]
 
 _lib = None
@@ -121,6 +121,9 @@ def lib() -> ctypes.CDLL:
     L.hp_batch_factor.argtypes = [c_int, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int,
                                   c_void_p, c_size_t, c_void_p]
     L.hp_batch_factor.restype = c_int
+    L.hp_batch_factor_stepped.argtypes = [c_int, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p,
+                                          c_void_p, c_int, c_void_p, c_size_t, c_void_p]
+    L.hp_batch_factor_stepped.restype = c_int
     L.hp_batch_solve_init.argtypes = [c_int, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                                       c_long, c_long, c_void_p, c_size_t, c_void_p]
     L.hp_batch_solve_init.restype = c_int
@@ -264,6 +267,13 @@ def hp_batch_build(count, items, prec, A, stream=None) -> None:
 def hp_batch_factor(count, items, prec, A, ipiv, perm, info, panel, groups, work, stream=None) -> None:
     _check(lib().hp_batch_factor(count, _ptr(items), prec, _ptr(A), _ptr(ipiv), _ptr(perm), _ptr(info), panel,
                                  groups, _ptr(work), work.numel(), _stream(stream)), "hp_batch_factor")
+
+
+def hp_batch_factor_stepped(count, items, n_host, prec, A, ipiv, perm, info, panel, work, stream=None) -> None:
+    n = np.ascontiguousarray(n_host, dtype=np.int32)
+    _check(lib().hp_batch_factor_stepped(count, _ptr(items), n.ctypes.data, prec, _ptr(A), _ptr(ipiv), _ptr(perm),
+                                         _ptr(info), panel, _ptr(work), work.numel(), _stream(stream)),
+           "hp_batch_factor_stepped")
 
 
 def hp_batch_solve_init(count, items, prec, LU, perm, info, X, refine, sum_nc, sum_xn, work, stream=None) -> None:

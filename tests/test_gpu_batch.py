@@ -1,7 +1,8 @@
 """Batched uneven systems on the GPU (one workgroup per system).
 
 * small systems of the batch family (N <= 600) against the oracle: R and S
-  within 1e-10, FP64 and FP32 + refinement, for every panel width;
+  within 1e-10, FP64 and FP32 + refinement, for every panel width, in the
+  persistent and the stepped form of the factorization;
 * larger systems (N up to ~2500) against the single-system path of the
   library: S within 1e-10;
 * refinement steps replayed from a captured graph give bit-identical X to
@@ -50,15 +51,16 @@ def small():
     return sps, refs
 
 
+@pytest.mark.parametrize("form", ["persistent", "stepped"])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("panel", [8, 16, 32])
-def test_small_batch_against_oracle(mods, small, prec, panel):
+def test_small_batch_against_oracle(mods, small, prec, panel, form):
     H, B, P = mods
     sps, refs = small
-    say("batch vs oracle", "prec", prec, "panel", panel, [sp.nc * sp.nr for sp in sps])
+    say("batch vs oracle", "prec", prec, "panel", panel, form, [sp.nc * sp.nr for sp in sps])
     bt = B.Batch(sps, [sp.energies[0] for sp in sps], prec)
     for b in bt.buckets:
-        bt.tuning[b.key] = B.BucketTuning(panel, 2 * bt.cus, 0.0)
+        bt.tuning[b.key] = B.BucketTuning(panel, 2 * bt.cus if form == "persistent" else 0, 0.0)
     bt.run()
     st, it = bt.status()
     assert np.all(st == 1), (st, it)
@@ -90,7 +92,7 @@ def test_graph_replay_matches_eager(mods):
     xs = []
     for use_graph in (False, True, True):
         bk = B.Bucket(sps, [sp.energies[0] for sp in sps], list(range(len(sps))), H.HP_C64)
-        bk.factor(16, 512)
+        bk.factor(16, 0 if use_graph else 512)
         steps = bk.solve(max_refine=30, use_graph=use_graph)
         torch.cuda.synchronize()
         xs.append((steps, bk.X.cpu().numpy().copy()))
