@@ -197,8 +197,8 @@ typedef struct hp_batch_item {
 } hp_batch_item;
 
 /* Workspace of the batched solves: sum_nc = sum of nc, sum_xn = sum of n*nc
- * over the systems.  0 on bad arguments. */
-size_t hp_batch_workspace_bytes(int count, long sum_nc, long sum_xn, int prec);
+ * over the systems, nmax = the largest n.  0 on bad arguments. */
+size_t hp_batch_workspace_bytes(int count, long sum_nc, long sum_xn, int nmax, int prec);
 
 /* C(E) of every system into A (precision prec), as hp_build_matrix does for one
  * (Eq. block_structure).  One workgroup per system. */
@@ -230,22 +230,26 @@ int hp_batch_factor_stepped(int count, const hp_batch_item *items, const int *n_
 /* Solves every system for its nc surface right-hand sides with the factors:
  * X (FP64, per system at x_off) = C^-1 B.  With refine != 0 (FP32 factors
  * only), the per-system refinement state is reset for hp_batch_refine_step;
- * systems with a zero pivot (info_factor) are marked and left alone.  No
- * host synchronisation.  work: hp_batch_workspace_bytes(...) bytes. */
-int hp_batch_solve_init(int count, const hp_batch_item *items, int prec, const void *LU, const int *perm,
-                        const int *info_factor, double *X, int refine, long sum_nc, long sum_xn,
-                        void *work, size_t work_bytes, void *stream);
+ * systems with a zero pivot (info_factor) are marked and left alone.
+ * shape_host: NULL (one workgroup solves each system) or the HOST (n, nc)
+ * pairs of the systems, largest n first, for the stepped form (per block of
+ * 32 rows one launch of every system's diagonal block and one of all update
+ * tiles).  No host synchronisation.  work: hp_batch_workspace_bytes(...). */
+int hp_batch_solve_init(int count, const hp_batch_item *items, const int *shape_host, int prec, const void *LU,
+                        const int *perm, const int *info_factor, double *X, int refine, long sum_nc,
+                        long sum_xn, void *work, size_t work_bytes, void *stream);
 
 /* One FP64 refinement step of FP32 factors for every system still refining
  * (Sec. 3.2): r = B - C X from the block structure, d from the factors
- * (column-scaled), X += d, and the stop rule of hp_solve per system (relative
- * correction <= tol, tol <= 0: 2^-52; a correction larger than half the
- * previous one: converged if the previous was <= 1e-6, else not converged;
- * not converged after max_refine steps).  A fixed sequence of four launches,
- * no host synchronisation: it may be captured in a graph and replayed. */
-int hp_batch_refine_step(int count, const hp_batch_item *items, const void *LU, const int *perm, double *X,
-                         int max_refine, double tol, long sum_nc, long sum_xn, void *work,
-                         size_t work_bytes, void *stream);
+ * (column-scaled; solves as chosen by shape_host), X += d, and the stop rule
+ * of hp_solve per system (relative correction <= tol, tol <= 0: 2^-52; a
+ * correction larger than half the previous one: converged if the previous
+ * was <= 1e-6, else not converged; not converged after max_refine steps).  A
+ * fixed sequence of launches, no host synchronisation: it may be captured
+ * in a graph and replayed. */
+int hp_batch_refine_step(int count, const hp_batch_item *items, const int *shape_host, const void *LU,
+                         const int *perm, double *X, int max_refine, double tol, long sum_nc, long sum_xn,
+                         void *work, size_t work_bytes, void *stream);
 
 /* Number of systems still refining after the last step (host *active);
  * synchronizes the stream. */

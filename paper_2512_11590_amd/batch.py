@@ -106,8 +106,10 @@ class Bucket:
         self.info = torch.zeros(self.count, dtype=torch.int32, device=dev)
         self.X = torch.empty(self.sum_xn, dtype=torch.complex128, device=dev)
         self.R = torch.empty(int((nc * nc).sum()), dtype=torch.complex128, device=dev)
-        self.work = torch.empty(H.hp_batch_workspace_bytes(self.count, self.sum_nc, self.sum_xn, prec),
-                                dtype=torch.uint8, device=dev)
+        self.work = torch.empty(H.hp_batch_workspace_bytes(self.count, self.sum_nc, self.sum_xn, int(n.max()),
+                                                           prec), dtype=torch.uint8, device=dev)
+        self.shape = np.stack([n, nc], axis=1).astype(np.int32)  # (n, nc), largest n first
+        self.stepped = False  # solves in the stepped form (set with the factorization form)
         self.graph = None
         self._steps = 0
         self.flops = float((8.0 / 3.0) * (n.astype(np.float64) ** 3).sum())
@@ -120,6 +122,7 @@ class Bucket:
         """Build and factor; groups > 0: persistent grid of that many
         workgroups, groups == 0: the stepped form."""
         H.hp_batch_build(self.count, self.items, self.prec, self.A)
+        self.stepped = groups == 0
         if groups > 0:
             H.hp_batch_factor(self.count, self.items, self.prec, self.A, self.ipiv, self.perm, self.info, panel,
                               groups, self.work)
@@ -130,15 +133,15 @@ class Bucket:
     def solve_init(self, max_refine: int = 30) -> bool:
         """Initial solve; True if FP32 refinement follows."""
         refine = self.prec == H.HP_C64 and max_refine > 0
-        H.hp_batch_solve_init(self.count, self.items, self.prec, self.A, self.perm, self.info, self.X, refine,
-                              self.sum_nc, self.sum_xn, self.work)
+        H.hp_batch_solve_init(self.count, self.items, self.shape if self.stepped else None, self.prec, self.A,
+                              self.perm, self.info, self.X, refine, self.sum_nc, self.sum_xn, self.work)
         self._steps = 0
         return refine
 
     def refine_step(self, max_refine: int = 30, tol: float = 0.0, use_graph: bool = True) -> None:
         """Enqueue one refinement step (a graph replay after the first step)."""
-        args = (self.count, self.items, self.A, self.perm, self.X, max_refine, tol, self.sum_nc, self.sum_xn,
-                self.work)
+        args = (self.count, self.items, self.shape if self.stepped else None, self.A, self.perm, self.X, max_refine,
+                tol, self.sum_nc, self.sum_xn, self.work)
         if use_graph and self.graph is None and self._steps > 0:
             # capture one step (every kernel's launch attributes are set by now);
             # the capture runs nothing, the replay below does
@@ -148,8 +151,8 @@ class Bucket:
             with torch.cuda.graph(g, stream=side):
                 H.hp_batch_refine_step(*args)
             torch.cuda.current_stream().wait_stream(side)
-            self.graph = (g, (max_refine, tol))
-        if use_graph and self.graph is not None and self.graph[1] == (max_refine, tol):
+            self.graph = (g, (max_refine, tol, self.stepped))
+        if use_graph and self.graph is not None and self.graph[1] == (max_refine, tol, self.stepped):
             self.graph[0].replay()
         else:
             H.hp_batch_refine_step(*args)

@@ -643,15 +643,153 @@ __global__ void batch_rmatrix_kernel(int count, const hp_batch_item *__restrict_
   }
 }
 
+// ------------------------------------------------------- stepped solves --
+// The solves of a bucket of larger systems, in steps of kBK rows: per step
+// one launch of every system's diagonal block (one thread per right-hand
+// column) and one launch of all update tiles of the rows beyond it.
+
+// P B (mode 0) or P R / s (mode 1, systems still refining) into Y.
+template <typename T>
+__global__ __launch_bounds__(256) void batch_rhs_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                        const int *__restrict__ perm, cplx<T> *__restrict__ Y,
+                                                        const cplx<double> *__restrict__ Rr,
+                                                        const double *__restrict__ cscale,
+                                                        const BatchState *state, int mode) {
+  const int s = blockIdx.x;
+  if (s >= count) return;
+  if (mode == 1 && state[s].status != 0) return;
+  const hp_batch_item it = items[s];
+  const int nc = it.sys.nc, nr = it.sys.nr, n = nc * nr;
+  const int *pm = perm + it.p_off;
+  cplx<T> *y = Y + it.x_off;
+  for (long e = threadIdx.x; e < (long)n * nc; e += 256) {
+    const int i = (int)(e / nc), cc = (int)(e - (long)i * nc);
+    const int src = pm[i];
+    cplx<T> v{T(0), T(0)};
+    if (mode == 0) {
+      const int c = src / nr, ii = src - c * nr;
+      if (c == cc) v.re = (T)it.sys.q[ii];
+    } else {
+      const cplx<double> r = Rr[it.x_off + (long)src * nc + cc];
+      const double sc = cscale[it.c_off + cc];
+      v = cplx<T>{(T)(r.re / sc), (T)(r.im / sc)};
+    }
+    y[e] = v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void batch_widen_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                          const cplx<T> *__restrict__ Y, cplx<double> *__restrict__ X) {
+  const int s = blockIdx.x;
+  if (s >= count) return;
+  const hp_batch_item it = items[s];
+  const long cnt = (long)it.sys.nc * it.sys.nr * it.sys.nc;
+  for (long e = threadIdx.x; e < cnt; e += 256)
+    X[it.x_off + e] = cplx<double>{(double)Y[it.x_off + e].re, (double)Y[it.x_off + e].im};
+}
+
+// Tile offsets of every solve step (exclusive prefix sums, count + 1 per step):
+// forward: the rows below the step's block; backward: the rows above it.
+__global__ void batch_solve_tiles_kernel(int count, const hp_batch_item *__restrict__ items, int *fwd, int *bwd) {
+  const int t = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const int b0 = t * kBK;
+  int af = 0, ab = 0;
+  int *of = fwd + (long)t * (count + 1), *ob = bwd + (long)t * (count + 1);
+  for (int s = 0; s < count; ++s) {
+    of[s] = af;
+    ob[s] = ab;
+    const int nc = items[s].sys.nc, n = item_n(items[s]);
+    if (b0 < n) {
+      const int below = n - b0 - min(kBK, n - b0);
+      const int tn = (nc + 63) / 64;
+      af += ((below + 63) / 64) * tn;
+      ab += ((b0 + 63) / 64) * tn;
+    }
+  }
+  of[count] = af;
+  ob[count] = ab;
+}
+
+// Diagonal block [b0, b0 + bs) of every system (state: skip systems not refining).
+template <typename T>
+__global__ __launch_bounds__(256) void batch_sdiag_kernel(const hp_batch_item *__restrict__ items,
+                                                          const cplx<T> *__restrict__ LU, cplx<T> *__restrict__ Y,
+                                                          int b0, int upper, const BatchState *state) {
+  const int s = blockIdx.x;
+  if (state && state[s].status != 0) return;
+  const hp_batch_item it = items[s];
+  const int nc = it.sys.nc, n = item_n(it);
+  if (b0 >= n) return;
+  const int bs = min(kBK, n - b0);
+  const cplx<T> *lu = LU + it.a_off;
+  cplx<T> *y = Y + it.x_off;
+  for (int c = threadIdx.x; c < nc; c += 256) {
+    if (!upper) {
+      for (int i = 1; i < bs; ++i) {
+        cplx<T> sum = y[(long)(b0 + i) * nc + c];
+        for (int k = 0; k < i; ++k) sum = cfms(sum, lu[(long)(b0 + i) * n + b0 + k], y[(long)(b0 + k) * nc + c]);
+        y[(long)(b0 + i) * nc + c] = sum;
+      }
+    } else {
+      for (int i = bs - 1; i >= 0; --i) {
+        cplx<T> sum = y[(long)(b0 + i) * nc + c];
+        for (int k = i + 1; k < bs; ++k) sum = cfms(sum, lu[(long)(b0 + i) * n + b0 + k], y[(long)(b0 + k) * nc + c]);
+        y[(long)(b0 + i) * nc + c] = cdiv(sum, lu[(long)(b0 + i) * n + b0 + i]);
+      }
+    }
+  }
+}
+
+// Update tiles of a solve step: forward Y[b0+bs:n] -= L[b0+bs:n, b0:b0+bs] Y[b0:b0+bs],
+// backward Y[0:b0] -= U[0:b0, b0:b0+bs] Y[b0:b0+bs].
+template <typename T>
+__global__ __launch_bounds__(256) void batch_strail_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                           const cplx<T> *__restrict__ LU, cplx<T> *__restrict__ Y,
+                                                           const int *__restrict__ offs, int b0, int upper,
+                                                           const BatchState *state) {
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T> *As = reinterpret_cast<cplx<T> *>(smem_raw);
+  cplx<T> *Bs = As + kBK * kBLd;
+  const int g = blockIdx.x;
+  if (g >= offs[count]) return;
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (offs[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  if (state && state[lo].status != 0) return;
+  const hp_batch_item it = items[lo];
+  const int nc = it.sys.nc, n = item_n(it);
+  const int bs = min(kBK, n - b0);
+  const int tn = (nc + 63) / 64;
+  const int l = g - offs[lo];
+  const cplx<T> *lu = LU + it.a_off;
+  cplx<T> *y = Y + it.x_off;
+  if (!upper)
+    tile_gemm_sub<T>((l / tn) * 64, (l % tn) * 64, n - b0 - bs, nc, bs, lu + (long)(b0 + bs) * n + b0, n,
+                     y + (long)b0 * nc, nc, y + (long)(b0 + bs) * nc, nc, As, Bs);
+  else
+    tile_gemm_sub<T>((l / tn) * 64, (l % tn) * 64, b0, nc, bs, lu + b0, n, y + (long)b0 * nc, nc, y, nc, As, Bs);
+}
+
 struct BatchWork {
   unsigned *counter;  // [2]: work queue, active count
   BatchState *state;  // [count]
   double *cscale;     // [sum nc]
   cplx<double> *res;  // [sum n nc] FP64 residual
   char *y;            // [sum n nc] working-precision right-hand sides
+  int *fwd, *bwd;     // [steps][count + 1] tile offsets of the stepped solves
 };
 
-BatchWork carve(char *w, int count, long sum_nc, long sum_xn) {
+int solve_steps(int nmax) { return (nmax + kBK - 1) / kBK; }
+
+BatchWork carve(char *w, int count, long sum_nc, long sum_xn, int prec) {
+  const size_t elt = prec == HP_C64 ? sizeof(cplx<float>) : sizeof(cplx<double>);
   BatchWork b;
   size_t off = 0;
   b.counter = (unsigned *)(w + off);
@@ -663,13 +801,70 @@ BatchWork carve(char *w, int count, long sum_nc, long sum_xn) {
   b.res = (cplx<double> *)(w + off);
   off += align_up(sizeof(cplx<double>) * (size_t)sum_xn, 256);
   b.y = w + off;
+  off += align_up(elt * (size_t)sum_xn, 256);
+  b.fwd = (int *)(w + off);
+  b.bwd = nullptr;
   return b;
 }
 
-size_t batch_bytes(int count, long sum_nc, long sum_xn, int prec) {
+size_t batch_bytes(int count, long sum_nc, long sum_xn, int nmax, int prec) {
   const size_t elt = prec == HP_C64 ? sizeof(cplx<float>) : sizeof(cplx<double>);
   return 256 + align_up(sizeof(BatchState) * (size_t)count, 256) + align_up(sizeof(double) * (size_t)sum_nc, 256) +
-         align_up(sizeof(cplx<double>) * (size_t)sum_xn, 256) + align_up(elt * (size_t)sum_xn, 256);
+         align_up(sizeof(cplx<double>) * (size_t)sum_xn, 256) + align_up(elt * (size_t)sum_xn, 256) +
+         align_up(sizeof(int) * 2 * (size_t)solve_steps(std::max(nmax, 1)) * (count + 1), 256);
+}
+
+// shape_host: HOST (n, nc) pairs of the systems, largest n first.
+int check_shapes(int count, const int *shape_host, int *nmax) {
+  *nmax = 0;
+  for (int s = 0; s < count; ++s) {
+    const int n = shape_host[2 * s], nc = shape_host[2 * s + 1];
+    if (n < 1 || nc < 1 || (s > 0 && n > shape_host[2 * s - 2])) return HP_ERR_ARG;
+    *nmax = std::max(*nmax, n);
+  }
+  return HP_OK;
+}
+
+// One stepped solve of every system (mode 0: of P B, then X = Y; mode 1: of
+// the scaled residuals of the systems still refining).
+template <typename T>
+int stepped_solve(int count, const hp_batch_item *items, const int *shape_host, int nmax, const cplx<T> *LU,
+                  const int *perm, cplx<T> *Y, cplx<double> *X, const BatchWork &w, int mode, hipStream_t st) {
+  const int steps = solve_steps(nmax);
+  const BatchState *state = mode == 1 ? w.state : nullptr;
+  const int *fwd = w.fwd, *bwd = w.fwd + (long)steps * (count + 1);
+  const size_t shm = tile_lds_bytes<T>();
+  int rc;
+  if ((rc = ensure_dynamic_lds((const void *)batch_strail_kernel<T>, shm))) return rc;
+  hipLaunchKernelGGL(batch_rhs_kernel<T>, dim3(count), dim3(256), 0, st, count, items, perm, Y,
+                     (const cplx<double> *)w.res, (const double *)w.cscale, (const BatchState *)w.state, mode);
+  HP_CHECK_LAUNCH();
+  for (int pass = 0; pass < 2; ++pass) {
+    const int upper = pass;
+    for (int q = 0; q < steps; ++q) {
+      const int t = upper ? steps - 1 - q : q;
+      const int b0 = t * kBK;
+      int active = 0;
+      long tiles = 0;
+      for (int s = 0; s < count && shape_host[2 * s] > b0; ++s) {
+        ++active;
+        const int n = shape_host[2 * s], nc = shape_host[2 * s + 1];
+        const long rows = upper ? b0 : n - b0 - std::min(kBK, n - b0);
+        tiles += ((rows + 63) / 64) * ((nc + 63) / 64);
+      }
+      hipLaunchKernelGGL(batch_sdiag_kernel<T>, dim3(active), dim3(256), 0, st, items, LU, Y, b0, upper, state);
+      HP_CHECK_LAUNCH();
+      if (tiles == 0) continue;
+      hipLaunchKernelGGL(batch_strail_kernel<T>, dim3((unsigned)tiles), dim3(256), shm, st, active, items, LU, Y,
+                         (upper ? bwd : fwd) + (long)t * (count + 1), b0, upper, state);
+      HP_CHECK_LAUNCH();
+    }
+  }
+  if (X) {
+    hipLaunchKernelGGL(batch_widen_kernel<T>, dim3(count), dim3(256), 0, st, count, items, Y, X);
+    HP_CHECK_LAUNCH();
+  }
+  return HP_OK;
 }
 
 }  // namespace
@@ -678,9 +873,9 @@ size_t batch_bytes(int count, long sum_nc, long sum_xn, int prec) {
 
 using namespace hp;
 
-extern "C" size_t hp_batch_workspace_bytes(int count, long sum_nc, long sum_xn, int prec) {
-  if (count < 1 || sum_nc < 1 || sum_xn < 1 || (prec != HP_C64 && prec != HP_C128)) return 0;
-  return batch_bytes(count, sum_nc, sum_xn, prec);
+extern "C" size_t hp_batch_workspace_bytes(int count, long sum_nc, long sum_xn, int nmax, int prec) {
+  if (count < 1 || sum_nc < 1 || sum_xn < 1 || nmax < 1 || (prec != HP_C64 && prec != HP_C128)) return 0;
+  return batch_bytes(count, sum_nc, sum_xn, nmax, prec);
 }
 
 extern "C" int hp_batch_build(int count, const hp_batch_item *items, int prec, void *A, void *stream) {
@@ -778,19 +973,31 @@ extern "C" int hp_batch_factor_stepped(int count, const hp_batch_item *items, co
   return HP_OK;
 }
 
-extern "C" int hp_batch_solve_init(int count, const hp_batch_item *items, int prec, const void *LU, const int *perm,
-                                   const int *info_factor, double *X, int refine, long sum_nc, long sum_xn,
-                                   void *work, size_t work_bytes, void *stream) {
+extern "C" int hp_batch_solve_init(int count, const hp_batch_item *items, const int *shape_host, int prec,
+                                   const void *LU, const int *perm, const int *info_factor, double *X, int refine,
+                                   long sum_nc, long sum_xn, void *work, size_t work_bytes, void *stream) {
   if (count < 1 || !items || !LU || !perm || !X || !work) return HP_ERR_ARG;
   if (prec != HP_C64 && prec != HP_C128) return HP_ERR_ARG;
-  if (work_bytes < batch_bytes(count, sum_nc, sum_xn, prec)) return HP_ERR_WORKSPACE;
+  int nmax = 1, rc;
+  if (shape_host && (rc = check_shapes(count, shape_host, &nmax))) return rc;
+  if (work_bytes < batch_bytes(count, sum_nc, sum_xn, nmax, prec)) return HP_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
-  BatchWork w = carve((char *)work, count, sum_nc, sum_xn);
+  BatchWork w = carve((char *)work, count, sum_nc, sum_xn, prec);
   hipLaunchKernelGGL(batch_state_init_kernel, dim3((count + 255) / 256), dim3(256), 0, st, count, info_factor,
                      w.state, refine);
   HP_CHECK_LAUNCH();
   TraceScope ts(TR_TRSM, st, 0.0, 0.0);
-  int rc;
+  if (shape_host) {
+    const int steps = solve_steps(nmax);
+    hipLaunchKernelGGL(batch_solve_tiles_kernel, dim3(steps), dim3(64), 0, st, count, items, w.fwd,
+                       w.fwd + (long)steps * (count + 1));
+    HP_CHECK_LAUNCH();
+    if (prec == HP_C64)
+      return stepped_solve<float>(count, items, shape_host, nmax, (const cplx<float> *)LU, perm, (cplx<float> *)w.y,
+                                  (cplx<double> *)X, w, 0, st);
+    return stepped_solve<double>(count, items, shape_host, nmax, (const cplx<double> *)LU, perm,
+                                 (cplx<double> *)X, nullptr, w, 0, st);
+  }
   if (prec == HP_C64) {
     const size_t shm = tile_lds_bytes<float>();
     if ((rc = ensure_dynamic_lds((const void *)batch_solve_kernel<float>, shm))) return rc;
@@ -808,13 +1015,15 @@ extern "C" int hp_batch_solve_init(int count, const hp_batch_item *items, int pr
   return HP_OK;
 }
 
-extern "C" int hp_batch_refine_step(int count, const hp_batch_item *items, const void *LU, const int *perm,
-                                    double *X, int max_refine, double tol, long sum_nc, long sum_xn, void *work,
-                                    size_t work_bytes, void *stream) {
+extern "C" int hp_batch_refine_step(int count, const hp_batch_item *items, const int *shape_host, const void *LU,
+                                    const int *perm, double *X, int max_refine, double tol, long sum_nc,
+                                    long sum_xn, void *work, size_t work_bytes, void *stream) {
   if (count < 1 || !items || !LU || !perm || !X || !work) return HP_ERR_ARG;
-  if (work_bytes < batch_bytes(count, sum_nc, sum_xn, HP_C64)) return HP_ERR_WORKSPACE;
+  int nmax = 1, rc;
+  if (shape_host && (rc = check_shapes(count, shape_host, &nmax))) return rc;
+  if (work_bytes < batch_bytes(count, sum_nc, sum_xn, nmax, HP_C64)) return HP_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
-  BatchWork w = carve((char *)work, count, sum_nc, sum_xn);
+  BatchWork w = carve((char *)work, count, sum_nc, sum_xn, HP_C64);
   hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(64), 0, st, w.counter + 1, 1);
   HP_CHECK_LAUNCH();
   {
@@ -825,13 +1034,18 @@ extern "C" int hp_batch_refine_step(int count, const hp_batch_item *items, const
   }
   {
     TraceScope ts(TR_TRSM, st, 0.0, 0.0);
-    const size_t shm = tile_lds_bytes<float>();
-    int rc;
-    if ((rc = ensure_dynamic_lds((const void *)batch_solve_kernel<float>, shm))) return rc;
-    hipLaunchKernelGGL(batch_solve_kernel<float>, dim3(count), dim3(256), shm, st, count, items,
-                       (const cplx<float> *)LU, perm, (cplx<float> *)w.y, (cplx<double> *)nullptr, w.res, w.cscale,
-                       w.state, 1);
-    HP_CHECK_LAUNCH();
+    if (shape_host) {
+      if ((rc = stepped_solve<float>(count, items, shape_host, nmax, (const cplx<float> *)LU, perm,
+                                     (cplx<float> *)w.y, nullptr, w, 1, st)))
+        return rc;
+    } else {
+      const size_t shm = tile_lds_bytes<float>();
+      if ((rc = ensure_dynamic_lds((const void *)batch_solve_kernel<float>, shm))) return rc;
+      hipLaunchKernelGGL(batch_solve_kernel<float>, dim3(count), dim3(256), shm, st, count, items,
+                         (const cplx<float> *)LU, perm, (cplx<float> *)w.y, (cplx<double> *)nullptr, w.res,
+                         w.cscale, w.state, 1);
+      HP_CHECK_LAUNCH();
+    }
   }
   TraceScope ts(TR_REFINE, st, 0.0, 0.0);
   hipLaunchKernelGGL(batch_update_kernel<float>, dim3(count), dim3(256), 0, st, count, items,

@@ -114,7 +114,7 @@ def lib() -> ctypes.CDLL:
     L.hp_coulomb.restype = c_int
     L.hp_coulomb_device.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.hp_coulomb_device.restype = c_int
-    L.hp_batch_workspace_bytes.argtypes = [c_int, c_long, c_long, c_int]
+    L.hp_batch_workspace_bytes.argtypes = [c_int, c_long, c_long, c_int, c_int]
     L.hp_batch_workspace_bytes.restype = c_size_t
     L.hp_batch_build.argtypes = [c_int, c_void_p, c_int, c_void_p, c_void_p]
     L.hp_batch_build.restype = c_int
@@ -124,11 +124,11 @@ def lib() -> ctypes.CDLL:
     L.hp_batch_factor_stepped.argtypes = [c_int, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p,
                                           c_void_p, c_int, c_void_p, c_size_t, c_void_p]
     L.hp_batch_factor_stepped.restype = c_int
-    L.hp_batch_solve_init.argtypes = [c_int, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
-                                      c_long, c_long, c_void_p, c_size_t, c_void_p]
+    L.hp_batch_solve_init.argtypes = [c_int, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_int, c_long, c_long, c_void_p, c_size_t, c_void_p]
     L.hp_batch_solve_init.restype = c_int
-    L.hp_batch_refine_step.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_double, c_long,
-                                       c_long, c_void_p, c_size_t, c_void_p]
+    L.hp_batch_refine_step.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_double,
+                                       c_long, c_long, c_void_p, c_size_t, c_void_p]
     L.hp_batch_refine_step.restype = c_int
     L.hp_batch_active.argtypes = [c_void_p, P(ctypes.c_uint), c_void_p]
     L.hp_batch_active.restype = c_int
@@ -256,8 +256,8 @@ def hp_coulomb_device(l, eta, rho, out, stream=None) -> None:
 
 # ---- batched uneven systems (device item array: a uint8 tensor of HpBatchItem records)
 
-def hp_batch_workspace_bytes(count: int, sum_nc: int, sum_xn: int, prec: int) -> int:
-    return int(lib().hp_batch_workspace_bytes(count, sum_nc, sum_xn, prec))
+def hp_batch_workspace_bytes(count: int, sum_nc: int, sum_xn: int, nmax: int, prec: int) -> int:
+    return int(lib().hp_batch_workspace_bytes(count, sum_nc, sum_xn, nmax, prec))
 
 
 def hp_batch_build(count, items, prec, A, stream=None) -> None:
@@ -276,15 +276,24 @@ def hp_batch_factor_stepped(count, items, n_host, prec, A, ipiv, perm, info, pan
            "hp_batch_factor_stepped")
 
 
-def hp_batch_solve_init(count, items, prec, LU, perm, info, X, refine, sum_nc, sum_xn, work, stream=None) -> None:
-    _check(lib().hp_batch_solve_init(count, _ptr(items), prec, _ptr(LU), _ptr(perm), _ptr(info), _ptr(X),
-                                     int(bool(refine)), sum_nc, sum_xn, _ptr(work), work.numel(), _stream(stream)),
-           "hp_batch_solve_init")
+def _shape(shape):
+    return None if shape is None else np.ascontiguousarray(shape, dtype=np.int32)
 
 
-def hp_batch_refine_step(count, items, LU, perm, X, max_refine, tol, sum_nc, sum_xn, work, stream=None) -> None:
-    _check(lib().hp_batch_refine_step(count, _ptr(items), _ptr(LU), _ptr(perm), _ptr(X), max_refine, tol, sum_nc,
-                                      sum_xn, _ptr(work), work.numel(), _stream(stream)), "hp_batch_refine_step")
+def hp_batch_solve_init(count, items, shape, prec, LU, perm, info, X, refine, sum_nc, sum_xn, work,
+                        stream=None) -> None:
+    sh = _shape(shape)
+    _check(lib().hp_batch_solve_init(count, _ptr(items), None if sh is None else sh.ctypes.data, prec, _ptr(LU),
+                                     _ptr(perm), _ptr(info), _ptr(X), int(bool(refine)), sum_nc, sum_xn, _ptr(work),
+                                     work.numel(), _stream(stream)), "hp_batch_solve_init")
+
+
+def hp_batch_refine_step(count, items, shape, LU, perm, X, max_refine, tol, sum_nc, sum_xn, work,
+                         stream=None) -> None:
+    sh = _shape(shape)
+    _check(lib().hp_batch_refine_step(count, _ptr(items), None if sh is None else sh.ctypes.data, _ptr(LU),
+                                      _ptr(perm), _ptr(X), max_refine, tol, sum_nc, sum_xn, _ptr(work), work.numel(),
+                                      _stream(stream)), "hp_batch_refine_step")
 
 
 def hp_batch_active(work, stream=None) -> int:
