@@ -1154,6 +1154,141 @@ __global__ void copy_rows_kernel(int n, int nrhs, const cplx<T> *__restrict__ X,
 
 // Rows per trailing GEMM of the solves: two inverted diagonal blocks (K = 256
 // runs the GEMM ~20 % faster than K = 128 on the n_c right-hand sides).
+// A 256-row diagonal block of a solve in one launch.  With the first 128-row
+// sub-block f and the second s (forward: f above s; backward: f below s):
+//   Y_f <- Inv_f Y_f;   Y_s -= M Y_f;   Y_s <- Inv_s Y_s,
+// M the off-diagonal block of L (forward) or U (backward), bsec x bf.  A
+// workgroup owns a stripe of CW right-hand columns (both sub-blocks in LDS);
+// each 128 x 128 operand is staged whole in LDS in turn.  Every staging
+// issues all of a thread's loads (in-bounds addresses, out-of-range values
+// replaced by zero afterwards) before its first LDS store, so the loads are
+// in flight together.
+constexpr int kDiagNV = kInvBlock * kInvBlock * 8 / 16 / 256;  // 16-byte vectors of an FP32 block per thread
+
+template <typename T>
+__device__ __forceinline__ void stage_block(cplx<T> *__restrict__ S, const uint4 *__restrict__ src, int tid) {
+  constexpr int EPV = 16 / sizeof(cplx<T>);
+  constexpr int NV = kInvBlock * kInvBlock / EPV / 256;
+  uint4 buf[NV];
+#pragma unroll
+  for (int u = 0; u < NV; ++u) buf[u] = src[u * 256 + tid];
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const int e = (u * 256 + tid) * EPV;
+    const int r = e / kInvBlock, k = e - r * kInvBlock;
+    *reinterpret_cast<uint4 *>(S + r * kApplyLd + k) = buf[u];
+  }
+}
+
+template <typename T, int CW>
+__global__ __launch_bounds__(256) void diag256_kernel(int bf, int bsec, const cplx<T> *__restrict__ invf,
+                                                      const cplx<T> *__restrict__ M, long ldm,
+                                                      const cplx<T> *__restrict__ invs, cplx<T> *__restrict__ Yf,
+                                                      cplx<T> *__restrict__ Ysec, long ldy, int ncols) {
+  constexpr int RPT = kInvBlock * CW / 256;
+  constexpr int RSTEP = 256 / CW;
+  constexpr int NE = kInvBlock * kInvBlock / 256;  // elements of M per thread
+  constexpr int MB = 16;                           // M loads in flight per batch
+  static_assert(NE % MB == 0, "staging loop");
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T> *__restrict__ S = reinterpret_cast<cplx<T> *>(smem_raw);  // [kInvBlock][kApplyLd]
+  cplx<T> *__restrict__ Fs = S + kInvBlock * kApplyLd;               // [kInvBlock][CW]
+  cplx<T> *__restrict__ Ss = Fs + kInvBlock * CW;                     // [kInvBlock][CW]
+  const int tid = threadIdx.x;
+  const int c = tid % CW, r0 = tid / CW;
+  const int col0 = blockIdx.x * CW;
+  const bool colok = col0 + c < ncols;
+  const int gc = min(col0 + c, ncols - 1);
+  const cplx<T> zero{T(0), T(0)};
+  {
+    cplx<T> vf[RPT], vs[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = r0 + q * RSTEP;
+      vf[q] = Yf[(long)min(r, bf - 1) * ldy + gc];
+      vs[q] = bsec > 0 ? Ysec[(long)min(r, bsec - 1) * ldy + gc] : zero;
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = r0 + q * RSTEP;
+      Fs[r * CW + c] = (r < bf && colok) ? vf[q] : zero;
+      Ss[r * CW + c] = (r < bsec && colok) ? vs[q] : zero;
+    }
+  }
+  cplx<T> acc[RPT];
+  auto product = [&](const cplx<T> *__restrict__ Y, int kmax) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) acc[q] = zero;
+#pragma unroll 4
+    for (int k = 0; k < kmax; ++k) {
+      const cplx<T> y = Y[k * CW + c];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const cplx<T> a = S[(r0 + q * RSTEP) * kApplyLd + k];
+        acc[q].re += a.re * y.re - a.im * y.im;
+        acc[q].im += a.re * y.im + a.im * y.re;
+      }
+    }
+  };
+  stage_block<T>(S, reinterpret_cast<const uint4 *>(invf), tid);
+  __syncthreads();
+  product(Fs, bf);
+  __syncthreads();
+  for (int q = 0; q < RPT; ++q) Fs[(r0 + q * RSTEP) * CW + c] = acc[q];
+  if (bsec > 0) {
+    // M (bsec x bf) with 8-byte loads: its rows need not be 16-byte aligned
+    for (int e0 = 0; e0 < NE; e0 += MB) {
+      cplx<T> buf[MB];
+#pragma unroll
+      for (int u = 0; u < MB; ++u) {
+        const int e = (e0 + u) * 256 + tid;
+        const int r = e / kInvBlock, k = e - r * kInvBlock;
+        buf[u] = M[(long)min(r, bsec - 1) * ldm + min(k, bf - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < MB; ++u) {
+        const int e = (e0 + u) * 256 + tid;
+        const int r = e / kInvBlock, k = e - r * kInvBlock;
+        S[r * kApplyLd + k] = (r < bsec && k < bf) ? buf[u] : zero;
+      }
+    }
+    __syncthreads();
+    product(Fs, bf);
+    __syncthreads();
+    for (int q = 0; q < RPT; ++q) {
+      const int r = r0 + q * RSTEP;
+      const cplx<T> v = Ss[r * CW + c];
+      Ss[r * CW + c] = cplx<T>{v.re - acc[q].re, v.im - acc[q].im};
+    }
+    stage_block<T>(S, reinterpret_cast<const uint4 *>(invs), tid);
+    __syncthreads();
+    product(Ss, bsec);
+    __syncthreads();
+    for (int q = 0; q < RPT; ++q) Ss[(r0 + q * RSTEP) * CW + c] = acc[q];
+  }
+  __syncthreads();
+  if (!colok) return;
+  for (int q = 0; q < RPT; ++q) {
+    const int r = r0 + q * RSTEP;
+    if (r < bf) Yf[(long)r * ldy + col0 + c] = Fs[r * CW + c];
+    if (r < bsec) Ysec[(long)r * ldy + col0 + c] = Ss[r * CW + c];
+  }
+}
+
+template <typename T>
+static int diag256(int bf, int bsec, const cplx<T> *invf, const cplx<T> *M, long ldm, const cplx<T> *invs,
+                   cplx<T> *Yf, cplx<T> *Ysec, long ldy, int ncols, hipStream_t st) {
+  constexpr int CW = 8;
+  const size_t shm = ((size_t)kInvBlock * kApplyLd + (size_t)2 * kInvBlock * CW) * sizeof(cplx<T>);
+  int rc = ensure_dynamic_lds((const void *)diag256_kernel<T, CW>, shm);
+  if (rc) return rc;
+  TraceScope ts(TR_TRSM, st, 8.0 * ((double)bf * bf + (double)bsec * bf + (double)bsec * bsec) * ncols, 0.0);
+  hipLaunchKernelGGL((diag256_kernel<T, CW>), dim3((ncols + CW - 1) / CW), dim3(256), shm, st, bf, bsec, invf, M,
+                     ldm, invs, Yf, Ysec, ldy, ncols);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
 constexpr int kSolveBlock = 2 * kInvBlock;
 static_assert(kSolveBlock <= kTrsmMaxRows, "substitution handles a whole solve block");
 
@@ -1165,12 +1300,8 @@ static int diag_forward(int n, int b, int bs, int nrhs, const cplx<T> *LU, long 
   (void)n;
   const size_t iblk = (size_t)kInvBlock * kInvBlock;
   const int bi = b / kInvBlock, b1 = std::min(kInvBlock, bs), b2 = bs - b1;
-  int rc = apply_inverse<T>(b1, nrhs, inv + bi * iblk, Y + (long)b * ldy, ldy, st);
-  if (rc || b2 <= 0) return rc;
-  if ((rc = gemm_sub<T>(b2, nrhs, b1, LU + (long)(b + b1) * lda + b, lda, Y + (long)b * ldy, ldy,
-                        Y + (long)(b + b1) * ldy, ldy, st)))
-    return rc;
-  return apply_inverse<T>(b2, nrhs, inv + (bi + 1) * iblk, Y + (long)(b + b1) * ldy, ldy, st);
+  return diag256<T>(b1, std::max(b2, 0), inv + bi * iblk, LU + (long)(b + b1) * lda + b, lda,
+                    inv + (bi + 1) * iblk, Y + (long)b * ldy, Y + (long)(b + b1) * ldy, ldy, nrhs, st);
 }
 
 // Rows [b, b + bs) of U X = Y, once the rows below have been substituted.
@@ -1181,15 +1312,12 @@ static int diag_backward(int n, int b, int bs, int nrhs, const cplx<T> *LU, long
   const size_t iblk = (size_t)kInvBlock * kInvBlock;
   const int nbt = (n + kInvBlock - 1) / kInvBlock;  // upper inverses follow the lower ones
   const int bi = b / kInvBlock, b1 = std::min(kInvBlock, bs), b2 = bs - b1;
-  int rc;
-  if (b2 > 0) {
-    if ((rc = apply_inverse<T>(b2, nrhs, inv + (nbt + bi + 1) * iblk, Y + (long)(b + b1) * ldy, ldy, st)))
-      return rc;
-    if ((rc = gemm_sub<T>(b1, nrhs, b2, LU + (long)b * lda + b + b1, lda, Y + (long)(b + b1) * ldy, ldy,
-                          Y + (long)b * ldy, ldy, st)))
-      return rc;
-  }
-  return apply_inverse<T>(b1, nrhs, inv + (nbt + bi) * iblk, Y + (long)b * ldy, ldy, st);
+  if (b2 <= 0)
+    return diag256<T>(b1, 0, inv + (nbt + bi) * iblk, nullptr, 0, nullptr, Y + (long)b * ldy, nullptr, ldy, nrhs,
+                      st);
+  // the lower sub-block first, then the upper one through U_ab (b1 x b2)
+  return diag256<T>(b2, b1, inv + (nbt + bi + 1) * iblk, LU + (long)b * lda + b + b1, lda,
+                    inv + (nbt + bi) * iblk, Y + (long)(b + b1) * ldy, Y + (long)b * ldy, ldy, nrhs, st);
 }
 
 // In-place solve on Y (n x nrhs, leading dimension ldy) that already holds P B.
