@@ -66,7 +66,7 @@ constexpr size_t tile_lds_bytes() {
 // per complex product (3M), FP64: four (4M).  A, B and C must not overlap.
 // Ends with a barrier.
 template <typename T>
-__device__ void tile_gemm_sub(int m0, int n0, int M, int N, int K, const cplx<T> *__restrict__ A, long lda,
+__device__ __forceinline__ void tile_gemm_sub(int m0, int n0, int M, int N, int K, const cplx<T> *__restrict__ A, long lda,
                               const cplx<T> *__restrict__ B, long ldb, cplx<T> *__restrict__ C, long ldc,
                               cplx<T> *As, cplx<T> *Bs) {
   typedef typename BMfma<T>::v4 v4;
@@ -76,17 +76,29 @@ __device__ void tile_gemm_sub(int m0, int n0, int M, int N, int K, const cplx<T>
   const int fr = lane & 15, fk = lane >> 4;
   const int Kp = (K + 3) & ~3;
   const cplx<T> zero{T(0), T(0)};
-  for (int e = tid; e < 64 * Kp; e += 256) {
-    const int r = e / Kp, k = e - r * Kp;
-    cplx<T> v = zero;
-    if (m0 + r < M && k < K) v = A[(long)(m0 + r) * lda + k];
-    As[k * kBLd + r] = v;
-  }
-  for (int e = tid; e < Kp * 64; e += 256) {
-    const int k = e >> 6, c = e & 63;
-    cplx<T> v = zero;
-    if (k < K && n0 + c < N) v = B[(long)k * ldb + n0 + c];
-    Bs[k * kBLd + c] = v;
+  {
+    // all of a thread's loads first (clamped addresses: in bounds, no branch
+    // to wait on), then the stores with out-of-range values masked to zero
+    constexpr int NS = 64 * kBK / 256;
+    cplx<T> ra[NS], rb[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / Kp, k = e - r * Kp;
+      ra[u] = A[(long)min(m0 + r, M - 1) * lda + min(k, K - 1)];
+      const int kb = e >> 6, c = e & 63;
+      rb[u] = B[(long)min(kb, K - 1) * ldb + min(n0 + c, N - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + 256 * u;
+      if (e < 64 * Kp) {
+        const int r = e / Kp, k = e - r * Kp;
+        As[k * kBLd + r] = (m0 + r < M && k < K) ? ra[u] : zero;
+        const int kb = e >> 6, c = e & 63;
+        Bs[kb * kBLd + c] = (kb < K && n0 + c < N) ? rb[u] : zero;
+      }
+    }
   }
   __syncthreads();
   v4 p1[2][2], p2[2][2], p3[2][2];
@@ -119,17 +131,26 @@ __device__ void tile_gemm_sub(int m0, int n0, int M, int N, int K, const cplx<T>
         }
       }
   }
+  // C: all eight loads of the thread in flight at once (clamped addresses),
+  // then the updates, stored where in range
+  cplx<T> cv[2][4][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = min(m0 + wm + i * 16 + BMfma<T>::d_row(lane, r), M - 1);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) cv[i][r][j] = C[(long)gr * ldc + min(n0 + wn + j * 16 + fr, N - 1)];
+    }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gr = m0 + wm + i * 16 + BMfma<T>::d_row(lane, r);
-      if (gr >= M) continue;
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int gc = n0 + wn + j * 16 + fr;
-        if (gc >= N) continue;
-        cplx<T> c = C[(long)gr * ldc + gc];
+        cplx<T> c = cv[i][r][j];
         if constexpr (M3) {
           c.re -= p1[i][j][r] - p2[i][j][r];
           c.im -= p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
@@ -137,7 +158,7 @@ __device__ void tile_gemm_sub(int m0, int n0, int M, int N, int K, const cplx<T>
           c.re -= p1[i][j][r];
           c.im -= p3[i][j][r];
         }
-        C[(long)gr * ldc + gc] = c;
+        if (gr < M && gc < N) C[(long)gr * ldc + gc] = c;
       }
     }
   __syncthreads();

@@ -226,28 +226,36 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
     if (kt + 1 < nk) store_stage(cur ^ 1);
     __syncthreads();
   }
+  // Epilogue: every C element this thread owns is loaded (at a clamped, always
+  // valid address) before the first one is used, so the loads are in flight
+  // together; out-of-range elements are then skipped on the store.
+  cplx<T> cv[WTM][4][WTN];
+#pragma unroll
+  for (int i = 0; i < WTM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = min(m0 + wm + i * 16 + MfmaLayout<T>::d_row(lane, r), M - 1);
+#pragma unroll
+      for (int j = 0; j < WTN; ++j) cv[i][r][j] = C[(long)gr * ldc + min(n0 + wn + j * 16 + fr, N - 1)];
+    }
 #pragma unroll
   for (int i = 0; i < WTM; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gr = m0 + wm + i * 16 + MfmaLayout<T>::d_row(lane, r);
-      if (gr >= M) continue;
-      cplx<T> *crow = C + (long)gr * ldc;
 #pragma unroll
       for (int j = 0; j < WTN; ++j) {
         const int gc = n0 + wn + j * 16 + fr;
-        if (gc < N) {
-          cplx<T> c = crow[gc];
-          if constexpr (M3) {
-            const T p1 = acc_re[i][j][r], p2 = acc_p2[i][j][r], p3 = acc_im[i][j][r];
-            c.re -= p1 - p2;
-            c.im -= p3 - p1 - p2;
-          } else {
-            c.re -= acc_re[i][j][r];
-            c.im -= acc_im[i][j][r];
-          }
-          crow[gc] = c;
+        cplx<T> c = cv[i][r][j];
+        if constexpr (M3) {
+          const T p1 = acc_re[i][j][r], p2 = acc_p2[i][j][r], p3 = acc_im[i][j][r];
+          c.re -= p1 - p2;
+          c.im -= p3 - p1 - p2;
+        } else {
+          c.re -= acc_re[i][j][r];
+          c.im -= acc_im[i][j][r];
         }
+        if (gr < M && gc < N) C[(long)gr * ldc + gc] = c;
       }
     }
 }

@@ -191,9 +191,24 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
   const int nrow = max(0, rend - rbeg);
   const int ncand = G * W;  // slot values held in registers per column
 
-  for (int e = tid; e < nrow * w; e += 256) {
-    const int rr = e / w, cc = e - rr * w;
-    Ls[rr * W + cc] = A[(long)(rbeg + rr) * lda + j0 + cc];
+  // rows into LDS, eight loads per thread in flight at a time (clamped
+  // addresses, so every load is in bounds and none waits on a branch)
+  for (int e0 = 0; e0 < nrow * w; e0 += 8 * 256) {
+    cplx<T> buf[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = min(e0 + u * 256 + tid, nrow * w - 1);
+      const int rr = e / w, cc = e - rr * w;
+      buf[u] = A[(long)(rbeg + rr) * lda + j0 + cc];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256 + tid;
+      if (e < nrow * w) {
+        const int rr = e / w, cc = e - rr * w;
+        Ls[rr * W + cc] = buf[u];
+      }
+    }
   }
   __syncthreads();
 
@@ -622,21 +637,19 @@ __global__ __launch_bounds__(256) void tri_inverse_kernel(int n, int blk0, int n
   for (int e0 = 0; e0 < NB * NB; e0 += 8 * 256) {
     cplx<T> v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 8; ++u) {  // all loads first (clamped addresses), then the masks
       const int e = e0 + u * 256 + tid;
       const int r = e / NB, c = e - r * NB;
-      v[u] = zero;
-      if (r < bs && c < bs) {
-        if (upper ? (r <= c) : (r > c)) v[u] = Tb[(long)r * lda + c];
-      } else if (r == c) {
-        v[u].re = T(1);
-      }
+      v[u] = Tb[(long)min(r, bs - 1) * lda + min(c, bs - 1)];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + u * 256 + tid;
       const int r = e / NB, c = e - r * NB;
-      X[r * LD + c] = v[u];
+      const bool in = r < bs && c < bs && (upper ? (r <= c) : (r > c));
+      cplx<T> x = in ? v[u] : zero;
+      if (!(r < bs && c < bs) && r == c) x.re = T(1);
+      X[r * LD + c] = x;
     }
   }
   __syncthreads();
