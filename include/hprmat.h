@@ -84,7 +84,10 @@ int hp_mesh(int nr, double a, double *r, double *w, double *q, double *tl);
 
 /* Device workspace (bytes) that hp_factor, hp_solve and hp_smatrix need for
  * an n x n factorization with nrhs right-hand sides in precision prec.  One
- * workspace may serve all three calls on one stream in sequence. */
+ * workspace may serve all three calls on one stream in sequence.  With
+ * prec == HP_C64 and nrhs > 0 it includes the transformed FP32 L factor
+ * that hp_solve's refinement solves use (about 4 n^2 bytes); hp_factor alone
+ * needs only hp_workspace_bytes(n, 0, prec). */
 size_t hp_workspace_bytes(int n, int nrhs, int prec);
 
 /* ---- the hot path ----------------------------------------------------- */
@@ -129,7 +132,11 @@ int hp_factor(int n, int prec, void *A, long lda, int *ipiv, int *perm, int *inf
  * stops shrinking above that (Sec. 6: the single-precision factor is then too
  * inaccurate to contract) or after max_refine corrections.  info (host, may
  * be NULL) receives the outcome, including the normwise backward error.
- * Synchronizes the stream once per refinement pass.
+ * Synchronizes the stream once per refinement pass.  With FP32 factors the
+ * call first multiplies every block column of L below the diagonal by the
+ * inverse of its 256-row diagonal block (kept in work, the factors are not
+ * modified), so that the forward substitution of each solve of the
+ * refinement is a chain of GEMMs.
  * Errors: HP_ERR_ARG, HP_ERR_WORKSPACE, HP_ERR_NOCONV (X holds the last
  * iterate), HP_ERR_SINGULAR (zero pivot reported by hp_factor), HP_ERR_SYNC,
  * HP_ERR_HIP. */

@@ -60,6 +60,20 @@ Workspace plan_workspace(int n, int nrhs, int prec) {
   w.inv_off = off;
   w.inv_bytes = align_up(inverse_bytes(n, prec), A);
   off += w.inv_bytes;
+  if (prec == HP_C64 && nrhs > 0) {
+    w.wv_off = off;
+    w.wv_bytes = align_up(wform_bytes(n), A);
+    off += w.wv_bytes;
+    w.inv2_off = off;
+    w.inv2_bytes = align_up(wform_inv_bytes(n), A);
+    off += w.inv2_bytes;
+    w.z_off = off;
+    w.z_bytes = align_up((size_t)n * nrhs * sizeof(cplx<float>), A);
+    off += w.z_bytes;
+    w.wtmp_off = off;
+    w.wtmp_bytes = align_up(wform_tmp_bytes(n), A);
+    off += w.wtmp_bytes;
+  }
   w.total = off;
   return w;
 }

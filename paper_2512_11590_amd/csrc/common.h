@@ -74,6 +74,7 @@ class TraceScope {
 // ------------------------------------------------------------ constants --
 constexpr int kPanelWidth = 32;     // columns factored by one cooperative panel launch
 constexpr int kOuterBlock = 256;    // columns per trailing-update step (GEMM K)
+constexpr int kInvBlock = 128;      // rows of an inverted diagonal block of an FP32 factor
 constexpr int kMaxPanelGroups = 128;  // candidate slots held in registers: 16 per thread
 constexpr unsigned kSpinLimit = 1u << 22;  // bounded grid-barrier wait (a few seconds)
 
@@ -89,6 +90,9 @@ struct Workspace {
   size_t aux_off, aux_bytes;        // nrhs x nrhs complex128 (collision-matrix solve)
   size_t red_off, red_bytes;        // reductions, Coulomb values, small index arrays
   size_t inv_off, inv_bytes;        // inverted diagonal blocks of an FP32 factor
+  // FP32 solves with nrhs > 0 only: the transformed L, its 256-row
+  // diagonal-block inverses, a second n x nrhs buffer and build scratch
+  size_t wv_off, wv_bytes, inv2_off, inv2_bytes, z_off, z_bytes, wtmp_off, wtmp_bytes;
   size_t total;
 };
 Workspace plan_workspace(int n, int nrhs, int prec);
@@ -105,6 +109,10 @@ int lu_solve(int n, int nrhs, const cplx<T> *LU, long lda, const int *perm, cplx
 template <typename T>
 int lu_solve_permuted(int n, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, long ldy, const cplx<T> *inv,
                       hipStream_t st);
+// The backward half of lu_solve_permuted: Y <- U^-1 Y in place.
+template <typename T>
+int lu_solve_upper(int n, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, long ldy, const cplx<T> *inv,
+                   hipStream_t st);
 // Inverts the diagonal blocks of an FP32 factor into `inv` (inverse_bytes(n, HP_C64) bytes).
 template <typename T>
 int solve_inverses(int n, const cplx<T> *LU, long lda, cplx<T> *inv, hipStream_t st);
@@ -116,8 +124,20 @@ int gemm_sub(int M, int N, int K, const cplx<T> *A, long lda, const cplx<T> *B, 
 template <typename T>
 int gemm_sub_batched(int M, int N, int K, const cplx<T> *A, long lda, long sa, const cplx<T> *B, long ldb,
                      long sb, cplx<T> *C, long ldc, long sc, int batch, hipStream_t st);
+// batched C = alpha A B (C is written, never read; it must not overlap A or B)
+template <typename T>
+int gemm_set_batched(int M, int N, int K, T alpha, const cplx<T> *A, long lda, long sa, const cplx<T> *B, long ldb,
+                     long sb, cplx<T> *C, long ldc, long sc, int batch, hipStream_t st);
 size_t factor_sync_bytes(int n);
 size_t factor_slot_bytes();
+// Transformed form of an FP32 factor for repeated solves (wsolve.hip)
+size_t wform_bytes(int n);
+size_t wform_inv_bytes(int n);
+size_t wform_tmp_bytes(int n);
+int wform_build(int n, const cplx<float> *LU, long lda, const cplx<float> *inv, cplx<float> *inv2, cplx<float> *tmp,
+                cplx<float> *W, hipStream_t st);
+int wform_solve(int n, int nrhs, const cplx<float> *LU, long lda, const cplx<float> *inv, const cplx<float> *W,
+                const cplx<float> *inv2, cplx<float> *Y, long ldy, cplx<float> *Z, long ldz, hipStream_t st);
 
 }  // namespace hp
 

@@ -78,11 +78,12 @@ struct GemmCfg {
 
 constexpr int kGroupM = 8;
 
-template <typename T, int WTM, int WTN, bool VEC>
+// SET = false: C -= A B.  SET = true: C = alpha A B (C is not read).
+template <typename T, int WTM, int WTN, bool VEC, bool SET>
 __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, const cplx<T> *__restrict__ A, long lda,
                                                        long sa, const cplx<T> *__restrict__ B, long ldb, long sb,
                                                        cplx<T> *__restrict__ C, long ldc, long sc, int tm, int tn,
-                                                       int total, int per_xcd) {
+                                                       int total, int per_xcd, T alpha) {
   typedef GemmCfg<T, WTM, WTN> G;
   typedef typename Mfma<T>::v4 v4;
   constexpr int BM = G::BM, BN = G::BN, BK = G::BK, EV = G::EV, PA = G::PA, PB = G::PB;
@@ -236,7 +237,12 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
     for (int r = 0; r < 4; ++r) {
       const int gr = min(m0 + wm + i * 16 + MfmaLayout<T>::d_row(lane, r), M - 1);
 #pragma unroll
-      for (int j = 0; j < WTN; ++j) cv[i][r][j] = C[(long)gr * ldc + min(n0 + wn + j * 16 + fr, N - 1)];
+      for (int j = 0; j < WTN; ++j) {
+        if constexpr (SET)
+          cv[i][r][j] = cplx<T>{T(0), T(0)};
+        else
+          cv[i][r][j] = C[(long)gr * ldc + min(n0 + wn + j * 16 + fr, N - 1)];
+      }
     }
 #pragma unroll
   for (int i = 0; i < WTM; ++i)
@@ -255,14 +261,15 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
           c.re -= acc_re[i][j][r];
           c.im -= acc_im[i][j][r];
         }
+        if constexpr (SET) c = cplx<T>{-alpha * c.re, -alpha * c.im};
         if (gr < M && gc < N) C[(long)gr * ldc + gc] = c;
       }
     }
 }
 
-template <typename T, int WTM, int WTN>
+template <typename T, int WTM, int WTN, bool SET>
 static int launch_gemm(int M, int N, int K, const cplx<T> *A, long lda, long sa, const cplx<T> *B, long ldb,
-                       long sb, cplx<T> *C, long ldc, long sc, int batch, hipStream_t st) {
+                       long sb, cplx<T> *C, long ldc, long sc, int batch, T alpha, hipStream_t st) {
   typedef GemmCfg<T, WTM, WTN> G;
   const int tm = (M + G::BM - 1) / G::BM, tn = (N + G::BN - 1) / G::BN;
   const long total_l = (long)tm * tn * batch;
@@ -276,17 +283,17 @@ static int launch_gemm(int M, int N, int K, const cplx<T> *A, long lda, long sa,
           (sa % 2 == 0) && (sb % 2 == 0);
   }
   const size_t shm = G::lds_bytes;
-  const void *fn = vec ? (const void *)gemm_sub_kernel<T, WTM, WTN, true>
-                       : (const void *)gemm_sub_kernel<T, WTM, WTN, false>;
+  const void *fn = vec ? (const void *)gemm_sub_kernel<T, WTM, WTN, true, SET>
+                       : (const void *)gemm_sub_kernel<T, WTM, WTN, false, SET>;
   int rc = ensure_dynamic_lds(fn, shm);
   if (rc) return rc;
   dim3 grid((unsigned)(8 * per_xcd));
   if (vec)
-    hipLaunchKernelGGL((gemm_sub_kernel<T, WTM, WTN, true>), grid, dim3(256), shm, st, M, N, K, A, lda, sa, B, ldb,
-                       sb, C, ldc, sc, tm, tn, total, per_xcd);
+    hipLaunchKernelGGL((gemm_sub_kernel<T, WTM, WTN, true, SET>), grid, dim3(256), shm, st, M, N, K, A, lda, sa, B,
+                       ldb, sb, C, ldc, sc, tm, tn, total, per_xcd, alpha);
   else
-    hipLaunchKernelGGL((gemm_sub_kernel<T, WTM, WTN, false>), grid, dim3(256), shm, st, M, N, K, A, lda, sa, B,
-                       ldb, sb, C, ldc, sc, tm, tn, total, per_xcd);
+    hipLaunchKernelGGL((gemm_sub_kernel<T, WTM, WTN, false, SET>), grid, dim3(256), shm, st, M, N, K, A, lda, sa,
+                       B, ldb, sb, C, ldc, sc, tm, tn, total, per_xcd, alpha);
   HP_CHECK_LAUNCH();
   return HP_OK;
 }
@@ -298,10 +305,22 @@ int gemm_sub_batched(int M, int N, int K, const cplx<T> *A, long lda, long sa, c
   // real matrix-core flops of the product: 8 M N K (4M, FP64) or 6 M N K (3M, FP32)
   TraceScope ts(sizeof(T) == 8 ? TR_GEMM64 : TR_GEMM32, st, (sizeof(T) == 8 ? 8.0 : 6.0) * M * (double)N * K * batch,
                 2.0 * sizeof(cplx<T>) * (double)M * N * batch);
-  // 64 x 64 tiles: measured on MI355X (12800^2 x 256 update) at 120 TF/s in
-  // FP32 and 57 TF/s in FP64, against 79-110 TF/s and 45 TF/s for the 128-wide
-  // tiles, whose register footprint leaves one wavefront per SIMD.
-  return launch_gemm<T, 2, 2>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, batch, st);
+  // 64 x 64 tiles: measured on MI355X (12800^2 x 256 update, complex rate
+  // 8MNK / t) at 120 TF/s in FP32 (90 TF/s of 3M matrix-core flops then, 104
+  // since the epilogue loads were batched) and 57 TF/s in FP64, against
+  // 79-110 TF/s and 45 TF/s for the 128-wide tiles, whose register footprint
+  // leaves one wavefront per SIMD.  A variant that loads C during the last K
+  // stage was 1 % faster alone but slower beside the panel (more registers).
+  return launch_gemm<T, 2, 2, false>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, batch, T(1), st);
+}
+
+template <typename T>
+int gemm_set_batched(int M, int N, int K, T alpha, const cplx<T> *A, long lda, long sa, const cplx<T> *B, long ldb,
+                     long sb, cplx<T> *C, long ldc, long sc, int batch, hipStream_t st) {
+  if (M <= 0 || N <= 0 || K <= 0 || batch <= 0) return HP_OK;
+  TraceScope ts(sizeof(T) == 8 ? TR_GEMM64 : TR_GEMM32, st, (sizeof(T) == 8 ? 8.0 : 6.0) * M * (double)N * K * batch,
+                1.0 * sizeof(cplx<T>) * (double)M * N * batch);
+  return launch_gemm<T, 2, 2, true>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, batch, alpha, st);
 }
 
 template <typename T>
@@ -318,6 +337,10 @@ template int gemm_sub_batched<double>(int, int, int, const cplx<double> *, long,
                                       long, cplx<double> *, long, long, int, hipStream_t);
 template int gemm_sub_batched<float>(int, int, int, const cplx<float> *, long, long, const cplx<float> *, long,
                                      long, cplx<float> *, long, long, int, hipStream_t);
+template int gemm_set_batched<float>(int, int, int, float, const cplx<float> *, long, long, const cplx<float> *,
+                                     long, long, cplx<float> *, long, long, int, hipStream_t);
+template int gemm_set_batched<double>(int, int, int, double, const cplx<double> *, long, long,
+                                      const cplx<double> *, long, long, cplx<double> *, long, long, int, hipStream_t);
 
 }  // namespace hp
 

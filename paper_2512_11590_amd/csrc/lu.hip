@@ -603,7 +603,6 @@ static int trsm(int m, int ncols, const cplx<T> *L, long ldl, cplx<T> *X, long l
 // followed by the trailing GEMM, instead of a latency-bound substitution.
 // The refinement corrects the slightly larger rounding error of the products.
 // FP64 keeps the substitution (its single solve sets the accuracy).
-constexpr int kInvBlock = 128;
 constexpr int kInvLd = kInvBlock + 1;  // LDS row stride (complex elements)
 
 // One workgroup per diagonal block: block index blk0 + blockIdx.x; blockIdx.y
@@ -1018,7 +1017,19 @@ static int factor_block(int n, int k, int kb, cplx<T> *A, long lda, int *ipiv, i
   return HP_OK;
 }
 
-// U12 = L11^-1 A12 for the kb rows of block k and the ncols columns right of it.
+// Inverts the two 128-row diagonal blocks of L11 of the (factored) block at
+// k into the workspace (FP32 only; FP64 substitutes).
+template <typename T>
+static int invert_block(int n, int k, const cplx<T> *A, long lda, char *work, const Workspace &ws,
+                        hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value)
+    return tri_inverse<T>(n, A, lda, (cplx<T> *)(work + ws.inv_off), k / kInvBlock, 2, false, st);
+  (void)n, (void)k, (void)A, (void)lda, (void)work, (void)ws, (void)st;
+  return HP_OK;
+}
+
+// U12 = L11^-1 A12 for the kb rows of block k and the ncols columns right of
+// it (FP32: through the inverses invert_block made).
 template <typename T>
 static int block_row_solve(int n, int k, int kb, int ncols, cplx<T> *A, long lda, char *work, const Workspace &ws,
                            hipStream_t st) {
@@ -1034,7 +1045,7 @@ static int block_row_solve(int n, int k, int kb, int ncols, cplx<T> *A, long lda
     const int b = k / kInvBlock;
     const size_t iblk = (size_t)kInvBlock * kInvBlock;
     cplx<T> *A22 = A12 + (long)kInvBlock * lda;
-    if ((rc = tri_inverse<T>(n, A, lda, inv, b, 2, false, st))) return rc;
+    (void)n;
     if ((rc = apply_inverse<T>(kInvBlock, ncols, inv + b * iblk, A12, lda, st))) return rc;
     if ((rc = gemm_sub<T>(kInvBlock, ncols, kInvBlock, L11 + (long)kInvBlock * lda, lda, A12, lda, A22, lda, st)))
       return rc;
@@ -1080,6 +1091,10 @@ static int lu_factor_on(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *
     cplx<T> *L21 = A + (long)k2 * lda + k;
     cplx<T> *U12 = A + (long)k * lda + k2;
     cplx<T> *A22 = A + (long)k2 * lda + k2;
+    // L11's diagonal blocks inverted on this stream: beside the trailing
+    // update, the inversion's whole-CU LDS footprint waits for GEMM
+    // workgroups to drain (10x slower there than here)
+    if ((rc = invert_block<T>(n, k, A, lda, work, ws, st))) return rc;
     if ((rc = block_row_solve<T>(n, k, kb, rest, A, lda, work, ws, st))) return rc;
     // the next block's columns first
     if ((rc = gemm_sub<T>(rest, kb2, kb, L21, lda, U12, lda, A22, lda, st))) return rc;
@@ -1291,7 +1306,10 @@ __global__ __launch_bounds__(256) void diag256_kernel(int bf, int bsec, const cp
 template <typename T>
 static int diag256(int bf, int bsec, const cplx<T> *invf, const cplx<T> *M, long ldm, const cplx<T> *invs,
                    cplx<T> *Yf, cplx<T> *Ysec, long ldy, int ncols, hipStream_t st) {
-  constexpr int CW = 8;
+  // two columns per workgroup: 128 workgroups for 256 right-hand sides,
+  // one output row per thread (22 us per launch on MI355X against 35 us with
+  // eight columns, whose four dependent rows per thread lengthen each phase)
+  constexpr int CW = 2;
   const size_t shm = ((size_t)kInvBlock * kApplyLd + (size_t)2 * kInvBlock * CW) * sizeof(cplx<T>);
   int rc = ensure_dynamic_lds((const void *)diag256_kernel<T, CW>, shm);
   if (rc) return rc;
@@ -1337,6 +1355,21 @@ static int diag_backward(int n, int b, int bs, int nrhs, const cplx<T> *LU, long
 // With `inv` (the output of tri_inverse for this factor) the diagonal blocks
 // are applied as products with their inverses, otherwise by substitution.
 template <typename T>
+int lu_solve_upper(int n, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, long ldy, const cplx<T> *inv,
+                   hipStream_t st) {
+  int rc;
+  const int nb = (n + kSolveBlock - 1) / kSolveBlock;
+  for (int bi = nb - 1; bi >= 0; --bi) {
+    const int b = bi * kSolveBlock;
+    const int bs = std::min(kSolveBlock, n - b);
+    if ((rc = diag_backward<T>(n, b, bs, nrhs, LU, lda, Y, ldy, inv, st))) return rc;
+    if (b > 0)
+      if ((rc = gemm_sub<T>(b, nrhs, bs, LU + b, lda, Y + (long)b * ldy, ldy, Y, ldy, st))) return rc;
+  }
+  return HP_OK;
+}
+
+template <typename T>
 int lu_solve_permuted(int n, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, long ldy, const cplx<T> *inv,
                       hipStream_t st) {
   int rc;
@@ -1350,14 +1383,7 @@ int lu_solve_permuted(int n, int nrhs, const cplx<T> *LU, long lda, cplx<T> *Y, 
                             Y + (long)(b + bs) * ldy, ldy, st)))
         return rc;
   }
-  for (int bi = nb - 1; bi >= 0; --bi) {
-    const int b = bi * kSolveBlock;
-    const int bs = std::min(kSolveBlock, n - b);
-    if ((rc = diag_backward<T>(n, b, bs, nrhs, LU, lda, Y, ldy, inv, st))) return rc;
-    if (b > 0)
-      if ((rc = gemm_sub<T>(b, nrhs, bs, LU + b, lda, Y + (long)b * ldy, ldy, Y, ldy, st))) return rc;
-  }
-  return HP_OK;
+  return lu_solve_upper<T>(n, nrhs, LU, lda, Y, ldy, inv, st);
 }
 
 template <typename T>
@@ -1400,6 +1426,8 @@ template int lu_solve_permuted<double>(int, int, const cplx<double> *, long, cpl
                                        const cplx<double> *, hipStream_t);
 template int lu_solve_permuted<float>(int, int, const cplx<float> *, long, cplx<float> *, long,
                                       const cplx<float> *, hipStream_t);
+template int lu_solve_upper<float>(int, int, const cplx<float> *, long, cplx<float> *, long, const cplx<float> *,
+                                   hipStream_t);
 
 size_t factor_sync_bytes(int n) {
   const int npanels = (n + kPanelWidth - 1) / kPanelWidth;

@@ -246,17 +246,31 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
   unsigned long long *xmax = smax + nc;
   unsigned long long *dmax = xmax + nc;
   unsigned long long *norms = dmax + nc;  // |C|_inf, |B|_inf
-  // FP32 factors are applied through their inverted diagonal blocks
-  cplx<T> *inv = nullptr;
-  if (sizeof(T) == sizeof(float)) {
-    inv = (cplx<T> *)(work + ws.inv_off);
-    if ((rc = solve_inverses<T>((int)n, LU, lda, inv, st))) return rc;
+  // FP32 factors: the forward substitution in the transformed form (its
+  // chain is GEMMs only), built once here for all the solves of the
+  // refinement; the solution lands in a second buffer (Ysol)
+  cplx<T> *Ysol = Y;
+  if constexpr (sizeof(T) == sizeof(float)) {
+    cplx<float> *inv = (cplx<float> *)(work + ws.inv_off);
+    if ((rc = solve_inverses<float>((int)n, LU, lda, inv, st))) return rc;
+    if ((rc = wform_build((int)n, LU, lda, inv, (cplx<float> *)(work + ws.inv2_off), (cplx<float> *)(work + ws.wtmp_off),
+                          (cplx<float> *)(work + ws.wv_off), st)))
+      return rc;
+    Ysol = (cplx<float> *)(work + ws.z_off);
   }
+  auto solve_y = [&]() -> int {
+    if constexpr (sizeof(T) == sizeof(float))
+      return wform_solve((int)n, nc, LU, lda, (const cplx<float> *)(work + ws.inv_off),
+                         (const cplx<float> *)(work + ws.wv_off), (const cplx<float> *)(work + ws.inv2_off), Y, nc,
+                         Ysol, nc, st);
+    else
+      return lu_solve_permuted<T>((int)n, nc, LU, lda, Y, nc, nullptr, st);
+  };
   // initial solve
   hipLaunchKernelGGL(rhs_from_perm_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, nc, nr, perm, sys->q, Y);
   HP_CHECK_LAUNCH();
-  if ((rc = lu_solve_permuted<T>((int)n, nc, LU, lda, Y, nc, inv, st))) return rc;
-  hipLaunchKernelGGL(widen_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, cnt, Y, X);
+  if ((rc = solve_y())) return rc;
+  hipLaunchKernelGGL(widen_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, cnt, Ysol, X);
   HP_CHECK_LAUNCH();
   int hinfo = 0;
   if (finfo) {
@@ -324,12 +338,12 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
       hipLaunchKernelGGL(scale_perm_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, n, nc, perm, Rr, smax, Y);
       HP_CHECK_LAUNCH();
     }
-    if ((rc = lu_solve_permuted<T>((int)n, nc, LU, lda, Y, nc, inv, st))) return rc;
+    if ((rc = solve_y())) return rc;
     {
       TraceScope ts(TR_REFINE, st, 0.0, (sizeof(cplx<T>) + 32.0) * (double)cnt);
       hipLaunchKernelGGL(zero_u64_kernel, dim3(nblk(nc)), dim3(256), 0, st, dmax, nc);
       HP_CHECK_LAUNCH();
-      hipLaunchKernelGGL(update_kernel<T>, dim3(cm_blocks), dim3(256), 0, st, n, nc, Y, smax, X, dmax);
+      hipLaunchKernelGGL(update_kernel<T>, dim3(cm_blocks), dim3(256), 0, st, n, nc, Ysol, smax, X, dmax);
       HP_CHECK_LAUNCH();
     }
   }

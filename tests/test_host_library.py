@@ -95,7 +95,13 @@ def test_workspace_grows_with_size(H):
     assert 0 < a < b and 0 < c < d
     # FP32 factors also hold their inverted 128 x 128 diagonal blocks (2 per block row)
     assert b - c >= 2 * 16 * 128 * 128 * 8 - 16 * 2000 * 10
-    assert H.hp_workspace_bytes(25600, 256, H.HP_C64) < 1 << 30
+    # and, with right-hand sides, the transformed L (about half of an n x n
+    # complex64 matrix) of the refinement solves; a factorization alone does
+    # not need it
+    f = H.hp_workspace_bytes(2000, 0, H.HP_C64)
+    assert b - f >= 0.8 * 2000 * 2000 * 8 / 2
+    assert f < 1 << 24
+    assert H.hp_workspace_bytes(25600, 256, H.HP_C64) < 25600 * 25600 * 8 / 2 + (1 << 30)
 
 
 def test_concurrency_setter(H):
