@@ -35,8 +35,8 @@ PEAK_FP64_MFMA = 78.6   # TF/s, MI355X dense FP64 matrix
 # WRITE_SIZE counter runs scaled by a 1 GiB copy
 # (profiles/gemm_sub_kernel_fp32_large_N25600_traffic.md); valid only for the
 # GEMM source it was measured on.
-GEMM_TRAFFIC = {"bytes_per_launch": 1.3370e+08,
-                "gemm_source_sha256": "ea07cf4cbe094ba8480696f5096b1e26548e90b85d56fe329dd2d8dbe63e4f20"}
+GEMM_TRAFFIC = {"bytes_per_launch": 2.1815e+08,
+                "gemm_source_sha256": "264a744c8acf7612bc56183415b3317e9d26b504020882f69af7755f50044824"}
 
 
 def parse():
