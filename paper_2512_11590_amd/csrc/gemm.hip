@@ -22,6 +22,8 @@
 // XCD gets a contiguous range of tiles.
 #include "common.h"
 
+#include <type_traits>
+
 namespace hp {
 
 template <typename T>
@@ -80,7 +82,7 @@ constexpr int kGroupM = 8;
 
 // SET = false: C -= A B.  SET = true: C = alpha A B (C is not read).
 template <typename T, int WTM, int WTN, bool VEC, bool SET>
-__global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, const cplx<T> *__restrict__ A, long lda,
+__global__ __launch_bounds__(256, (sizeof(T) == 4 ? 4 : 2)) void gemm_sub_kernel(int M, int N, int K, const cplx<T> *__restrict__ A, long lda,
                                                        long sa, const cplx<T> *__restrict__ B, long ldb, long sb,
                                                        cplx<T> *__restrict__ C, long ldc, long sc, int tm, int tn,
                                                        int total, int per_xcd, T alpha) {
@@ -113,8 +115,13 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * (16 * WTM), wn = (wave & 1) * (16 * WTN);
 
-  Vec16<T> ra[G::NVA], rb[G::NVB];
-  auto load_stage = [&](int k0) {
+  // Two register sets for the staged operands: stage s is loaded into set
+  // s % 2 two stages before its MFMAs, so its global loads have the MFMAs of
+  // two stages to land.  (The set index is a compile-time constant in every
+  // use, so the sets stay in registers.)
+  Vec16<T> ra[2][G::NVA], rb[2][G::NVB];
+  auto load_stage = [&](auto set, int k0) {
+    constexpr int S = decltype(set)::value;
 #pragma unroll
     for (int q = 0; q < G::NVA; ++q) {
       const int v = tid + 256 * q;
@@ -122,12 +129,12 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
       const int gr = m0 + row, gk = k0 + kv * EV;
       const cplx<T> *p = A + (long)gr * lda + gk;
       if (VEC && gr < M && gk + EV <= K) {
-        ra[q] = *reinterpret_cast<const Vec16<T> *>(p);
+        ra[S][q] = *reinterpret_cast<const Vec16<T> *>(p);
       } else {
 #pragma unroll
         for (int e = 0; e < EV; ++e) {
-          ra[q].v[e] = cplx<T>{T(0), T(0)};
-          if (gr < M && gk + e < K) ra[q].v[e] = p[e];
+          ra[S][q].v[e] = cplx<T>{T(0), T(0)};
+          if (gr < M && gk + e < K) ra[S][q].v[e] = p[e];
         }
       }
     }
@@ -138,17 +145,18 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
       const int gk = k0 + kr, gc = n0 + nv * EV;
       const cplx<T> *p = B + (long)gk * ldb + gc;
       if (VEC && gk < K && gc + EV <= N) {
-        rb[q] = *reinterpret_cast<const Vec16<T> *>(p);
+        rb[S][q] = *reinterpret_cast<const Vec16<T> *>(p);
       } else {
 #pragma unroll
         for (int e = 0; e < EV; ++e) {
-          rb[q].v[e] = cplx<T>{T(0), T(0)};
-          if (gk < K && gc + e < N) rb[q].v[e] = p[e];
+          rb[S][q].v[e] = cplx<T>{T(0), T(0)};
+          if (gk < K && gc + e < N) rb[S][q].v[e] = p[e];
         }
       }
     }
   };
-  auto store_stage = [&](int buf) {
+  auto store_stage = [&](auto set, int buf) {
+    constexpr int S = decltype(set)::value;
     cplx<T> *as = As + buf * BK * PA;
     cplx<T> *bs = Bs + buf * BK * PB;
 #pragma unroll
@@ -156,15 +164,17 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
       const int v = tid + 256 * q;
       const int row = v / (BK / EV), kv = v % (BK / EV);
 #pragma unroll
-      for (int e = 0; e < EV; ++e) as[(kv * EV + e) * PA + row] = ra[q].v[e];
+      for (int e = 0; e < EV; ++e) as[(kv * EV + e) * PA + row] = ra[S][q].v[e];
     }
 #pragma unroll
     for (int q = 0; q < G::NVB; ++q) {
       const int v = tid + 256 * q;
       const int kr = v / (BN / EV), nv = v % (BN / EV);
-      *reinterpret_cast<Vec16<T> *>(bs + kr * PB + nv * EV) = rb[q];
+      *reinterpret_cast<Vec16<T> *>(bs + kr * PB + nv * EV) = rb[S][q];
     }
   };
+  constexpr std::integral_constant<int, 0> set0{};
+  constexpr std::integral_constant<int, 1> set1{};
 
   // 4M: acc_re, acc_im; 3M: acc_re = P1, acc_im = P3, acc_p2 = P2
   constexpr bool M3 = sizeof(T) == 4;
@@ -179,13 +189,8 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
     }
 
   const int nk = (K + BK - 1) / BK;
-  load_stage(0);
-  store_stage(0);
-  __syncthreads();
   const int fr = lane & 15, fk = lane >> 4;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) load_stage((kt + 1) * BK);
+  auto compute = [&](int cur) {
     const cplx<T> *as = As + cur * BK * PA;
     const cplx<T> *bs = Bs + cur * BK * PB;
 #pragma unroll
@@ -224,35 +229,51 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
         }
       }
     }
-    if (kt + 1 < nk) store_stage(cur ^ 1);
+  };
+  load_stage(set0, 0);
+  if (nk > 1) load_stage(set1, BK);
+  store_stage(set0, 0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; kt += 2) {
+    // stage kt from LDS buffer 0; stage kt + 1 (set 1) goes to buffer 1
+    if (kt + 2 < nk) load_stage(set0, (kt + 2) * BK);
+    compute(0);
+    if (kt + 1 < nk) store_stage(set1, 1);
     __syncthreads();
+    if (kt + 1 < nk) {
+      // stage kt + 1 from buffer 1; stage kt + 2 (set 0) goes to buffer 0
+      if (kt + 3 < nk) load_stage(set1, (kt + 3) * BK);
+      compute(1);
+      if (kt + 2 < nk) store_stage(set0, 0);
+      __syncthreads();
+    }
   }
-  // Epilogue: every C element this thread owns is loaded (at a clamped, always
-  // valid address) before the first one is used, so the loads are in flight
-  // together; out-of-range elements are then skipped on the store.
-  cplx<T> cv[WTM][4][WTN];
+  // Epilogue, one row-block of MFMA tiles at a time: the C elements of the
+  // row-block are all loaded (at clamped, always valid addresses) before the
+  // first one is used, so those loads are in flight together; out-of-range
+  // elements are skipped on the store.  Halving the live C values keeps the
+  // kernel within 128 registers (4 wavefronts per SIMD).
 #pragma unroll
-  for (int i = 0; i < WTM; ++i)
+  for (int i = 0; i < WTM; ++i) {
+    cplx<T> cv[4][WTN];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gr = min(m0 + wm + i * 16 + MfmaLayout<T>::d_row(lane, r), M - 1);
 #pragma unroll
       for (int j = 0; j < WTN; ++j) {
         if constexpr (SET)
-          cv[i][r][j] = cplx<T>{T(0), T(0)};
+          cv[r][j] = cplx<T>{T(0), T(0)};
         else
-          cv[i][r][j] = C[(long)gr * ldc + min(n0 + wn + j * 16 + fr, N - 1)];
+          cv[r][j] = C[(long)gr * ldc + min(n0 + wn + j * 16 + fr, N - 1)];
       }
     }
-#pragma unroll
-  for (int i = 0; i < WTM; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gr = m0 + wm + i * 16 + MfmaLayout<T>::d_row(lane, r);
 #pragma unroll
       for (int j = 0; j < WTN; ++j) {
         const int gc = n0 + wn + j * 16 + fr;
-        cplx<T> c = cv[i][r][j];
+        cplx<T> c = cv[r][j];
         if constexpr (M3) {
           const T p1 = acc_re[i][j][r], p2 = acc_p2[i][j][r], p3 = acc_im[i][j][r];
           c.re -= p1 - p2;
@@ -265,6 +286,173 @@ __global__ __launch_bounds__(256) void gemm_sub_kernel(int M, int N, int K, cons
         if (gr < M && gc < N) C[(long)gr * ldc + gc] = c;
       }
     }
+  }
+}
+
+
+// FP32 operands staged by direct global->LDS loads (global_load_lds_dwordx4):
+// the loaded 16-byte chunks go straight into LDS, with no pass through
+// registers and no LDS store instructions; on MI355X this runs the 3M update
+// ~15 % faster than the register-staged kernel (120 vs 104 TF/s of 3M flops
+// on a 25344 x 25088 x 256 update).  A wave's direct load writes 64
+// consecutive 16-byte slots, so the LDS layouts follow the loads: B rows are
+// row-major [BK][64]; A is row-major [64][BK] with the 16-byte chunks of row r
+// permuted by chunk ^ (r % 8), which spreads the MFMA operand reads (16 rows
+// at one k) over the banks.  The loads are issued from inline assembly (LDS
+// base in M0) so that the compiler neither reorders them nor waits for them
+// before the current stage's LDS reads; each thread waits for its own loads
+// (vmcnt) before the barrier that publishes a stage.  Requirements (checked by
+// the launcher): 16-byte aligned rows of A and B, K a multiple of 16, N even.
+// Rows of A past M read row M - 1 and columns of B past N read the last column
+// pair (their outputs are discarded).
+constexpr int kDirectBK = 16;
+// lds_byte_addr must be uniform over the wavefront.  The kernel that uses
+// this makes no other use of M0 (its assembly is checked for that).
+__device__ __forceinline__ void lds_direct_load16(unsigned lds_byte_addr, const void *src) {
+  const unsigned m0v = __builtin_amdgcn_readfirstlane(lds_byte_addr);
+  // one wait state between the M0 write and the LDS-DMA load that reads it
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(m0v), "v"(src)
+               : "memory");
+}
+
+template <bool SET>
+__global__ __launch_bounds__(256, 4) void gemm_direct_kernel(int M, int N, int K, const cplx<float> *__restrict__ A,
+                                                             long lda, long sa, const cplx<float> *__restrict__ B,
+                                                             long ldb, long sb, cplx<float> *__restrict__ C, long ldc,
+                                                             long sc, int tm, int tn, int total, int per_xcd,
+                                                             float alpha) {
+  typedef typename Mfma<float>::v4 v4;
+  constexpr int BM = 64, BN = 64, BK = kDirectBK;
+  constexpr int ACH = BK / 2;                // 16-byte chunks per A row
+  constexpr int APW = BM * ACH / 64 / 4;     // A wave-loads per wavefront per stage
+  constexpr int BPW = BK * (BN / 2) / 64 / 4;  // B wave-loads per wavefront per stage
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<float> *As = reinterpret_cast<cplx<float> *>(smem_raw);  // [2][BM * BK]
+  cplx<float> *Bs = As + 2 * BM * BK;                            // [2][BK * BN]
+
+  const int bid = blockIdx.x;
+  const int t = (bid & 7) * per_xcd + (bid >> 3);
+  if (t >= total) return;
+  const int per_batch = tm * tn;
+  const int z = t / per_batch;
+  const int tb = t - z * per_batch;
+  const int grp = tb / (kGroupM * tn);
+  const int first_m = grp * kGroupM;
+  const int gm = min(kGroupM, tm - first_m);
+  const int in_grp = tb - grp * kGroupM * tn;
+  const int m0 = (first_m + in_grp % gm) * BM, n0 = (in_grp / gm) * BN;
+  A += sa * z;
+  B += sb * z;
+  C += sc * z;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+
+  // this lane's source chunks (k0 = 0) and its wavefront's LDS slots
+  const cplx<float> *asrc[APW];
+  const cplx<float> *bsrc[BPW];
+#pragma unroll
+  for (int i = 0; i < APW; ++i) {
+    const int c = (wave * APW + i) * 64 + lane;
+    const int row = c / ACH, pos = c - row * ACH;
+    asrc[i] = A + (long)min(m0 + row, M - 1) * lda + 2 * (pos ^ (row & (ACH - 1)));
+  }
+#pragma unroll
+  for (int i = 0; i < BPW; ++i) {
+    const int c = (wave * BPW + i) * 64 + lane;
+    const int kr = c / (BN / 2), pos = c - kr * (BN / 2);
+    bsrc[i] = B + (long)kr * ldb + min(n0 + 2 * pos, N - 2);
+  }
+  const unsigned lds0 = (unsigned)(size_t)(const __attribute__((address_space(3))) void *)As;
+  auto issue = [&](int buf, int k0) {
+#pragma unroll
+    for (int i = 0; i < APW; ++i)
+      lds_direct_load16(lds0 + (unsigned)((buf * BM * BK + (wave * APW + i) * 128) * sizeof(cplx<float>)),
+                        asrc[i] + k0);
+#pragma unroll
+    for (int i = 0; i < BPW; ++i)
+      lds_direct_load16(
+          lds0 + (unsigned)(((2 * BM * BK) + buf * BK * BN + (wave * BPW + i) * 128) * sizeof(cplx<float>)),
+          bsrc[i] + (long)k0 * ldb);
+  };
+
+  v4 acc_re[2][2], acc_im[2][2], acc_p2[2][2];  // 3M: P1, P3, P2
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc_re[i][j] = v4{0, 0, 0, 0};
+      acc_im[i][j] = v4{0, 0, 0, 0};
+      acc_p2[i][j] = v4{0, 0, 0, 0};
+    }
+  const int fr = lane & 15, fk = lane >> 4;
+  const int nk = K / BK;
+  issue(0, 0);
+  for (int kt = 0; kt < nk; ++kt) {
+    // this thread's loads of stage kt have landed; the barrier publishes
+    // everyone's and frees the other buffer (read during stage kt - 1)
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (kt + 1 < nk) issue((kt + 1) & 1, (kt + 1) * BK);
+    const cplx<float> *as = As + (kt & 1) * BM * BK;
+    const cplx<float> *bs = Bs + (kt & 1) * BK * BN;
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kk = ks + fk;
+      cplx<float> af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm + i * 16 + fr;
+        af[i] = as[row * BK + 2 * ((kk >> 1) ^ (row & (ACH - 1))) + (kk & 1)];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = bs[kk * BN + wn + j * 16 + fr];
+      float bsum[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bsum[j] = bf[j].re + bf[j].im;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const float asum = af[i].re + af[i].im;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc_re[i][j] = Mfma<float>::mac(af[i].re, bf[j].re, acc_re[i][j]);
+          acc_p2[i][j] = Mfma<float>::mac(af[i].im, bf[j].im, acc_p2[i][j]);
+          acc_im[i][j] = Mfma<float>::mac(asum, bsum[j], acc_im[i][j]);
+        }
+      }
+    }
+  }
+  // epilogue as in gemm_sub_kernel
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    cplx<float> cv[4][2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = min(m0 + wm + i * 16 + MfmaLayout<float>::d_row(lane, r), M - 1);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if constexpr (SET)
+          cv[r][j] = cplx<float>{0.f, 0.f};
+        else
+          cv[r][j] = C[(long)gr * ldc + min(n0 + wn + j * 16 + fr, N - 1)];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = m0 + wm + i * 16 + MfmaLayout<float>::d_row(lane, r);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int gc = n0 + wn + j * 16 + fr;
+        cplx<float> c = cv[r][j];
+        const float p1 = acc_re[i][j][r], p2 = acc_p2[i][j][r], p3 = acc_im[i][j][r];
+        c.re -= p1 - p2;
+        c.im -= p3 - p1 - p2;
+        if constexpr (SET) c = cplx<float>{-alpha * c.re, -alpha * c.im};
+        if (gr < M && gc < N) C[(long)gr * ldc + gc] = c;
+      }
+    }
+  }
 }
 
 template <typename T, int WTM, int WTN, bool SET>
@@ -282,12 +470,21 @@ static int launch_gemm(int M, int N, int K, const cplx<T> *A, long lda, long sa,
     vec = ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && (lda % 2 == 0) && (ldb % 2 == 0) &&
           (sa % 2 == 0) && (sb % 2 == 0);
   }
+  dim3 grid((unsigned)(8 * per_xcd));
+  if constexpr (sizeof(T) == 4 && WTM == 2 && WTN == 2) {
+    if (vec && K % kDirectBK == 0 && N % 2 == 0 && ldc > 0) {
+      const size_t dshm = (size_t)2 * 2 * 64 * kDirectBK * sizeof(cplx<float>);
+      hipLaunchKernelGGL((gemm_direct_kernel<SET>), grid, dim3(256), dshm, st, M, N, K, A, lda, sa, B, ldb, sb, C,
+                         ldc, sc, tm, tn, total, per_xcd, alpha);
+      HP_CHECK_LAUNCH();
+      return HP_OK;
+    }
+  }
   const size_t shm = G::lds_bytes;
   const void *fn = vec ? (const void *)gemm_sub_kernel<T, WTM, WTN, true, SET>
                        : (const void *)gemm_sub_kernel<T, WTM, WTN, false, SET>;
   int rc = ensure_dynamic_lds(fn, shm);
   if (rc) return rc;
-  dim3 grid((unsigned)(8 * per_xcd));
   if (vec)
     hipLaunchKernelGGL((gemm_sub_kernel<T, WTM, WTN, true, SET>), grid, dim3(256), shm, st, M, N, K, A, lda, sa, B,
                        ldb, sb, C, ldc, sc, tm, tn, total, per_xcd, alpha);
