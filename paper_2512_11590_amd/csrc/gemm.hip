@@ -297,8 +297,9 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 4 : 2)) void gemm_sub_kernel
 // on a 25344 x 25088 x 256 update).  A wave's direct load writes 64
 // consecutive 16-byte slots, so the LDS layouts follow the loads: B rows are
 // row-major [BK][64]; A is row-major [64][BK] with the 16-byte chunks of row r
-// permuted by chunk ^ (r % 8), which spreads the MFMA operand reads (16 rows
-// at one k) over the banks.  The loads are issued from inline assembly (LDS
+// permuted by chunk ^ ((r / 2) % 8): a row spans half the banks, so rows r and
+// r + 1 sit in different halves and the permutation separates the 8 pairs,
+// and the MFMA operand reads (16 rows at one k) touch distinct banks.  The loads are issued from inline assembly (LDS
 // base in M0) so that the compiler neither reorders them nor waits for them
 // before the current stage's LDS reads; each thread waits for its own loads
 // (vmcnt) before the barrier that publishes a stage.  Requirements (checked by
@@ -363,7 +364,7 @@ __global__ __launch_bounds__(256, 4) void gemm_direct_kernel(int M, int N, int K
   for (int i = 0; i < APW; ++i) {
     const int c = (wave * APW + i) * 64 + lane;
     const int row = c / ACH, pos = c - row * ACH;
-    asrc[i] = A + (long)min(m0 + row, M - 1) * lda + 2 * (pos ^ (row & (ACH - 1)));
+    asrc[i] = A + (long)min(m0 + row, M - 1) * lda + 2 * (pos ^ ((row >> 1) & (ACH - 1)));
   }
 #pragma unroll
   for (int i = 0; i < BPW; ++i) {
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(256, 4) void gemm_direct_kernel(int M, int N, int K
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int row = wm + i * 16 + fr;
-        af[i] = as[row * BK + 2 * ((kk >> 1) ^ (row & (ACH - 1))) + (kk & 1)];
+        af[i] = as[row * BK + 2 * ((kk >> 1) ^ ((row >> 1) & (ACH - 1))) + (kk & 1)];
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) bf[j] = bs[kk * BN + wn + j * 16 + fr];

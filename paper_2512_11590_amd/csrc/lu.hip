@@ -171,6 +171,7 @@ static size_t barrier_words(int G) { return (size_t)G * kBarStride; }
 // Slots alternate between two buffers, so a slow reader never sees the next
 // column's writes.
 constexpr int kMaxCandPerThread = kMaxPanelGroups * kPanelWidth / 256;
+constexpr int kPanelLd = kPanelWidth + 1;  // LDS row stride of the panel rows (complex elements)
 
 template <typename T>
 __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T> *__restrict__ A,
@@ -179,11 +180,12 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
                                                     cplx<T> *slot_rows, T *slot_val, int *slot_row,
                                                     cplx<T> *diag_rows, int rpw) {
   extern __shared__ __align__(16) char smem_raw[];
-  cplx<T> *Ls = reinterpret_cast<cplx<T> *>(smem_raw);  // [rpw][kPanelWidth]
+  cplx<T> *Ls = reinterpret_cast<cplx<T> *>(smem_raw);  // [rpw][kPanelLd]
   __shared__ cplx<T> urow[kPanelWidth], drow[kPanelWidth];
   __shared__ T red_v[4];
   __shared__ int red_r[4];
   constexpr int W = kPanelWidth;
+  constexpr int LW = kPanelLd;  // padded row stride: rows 2 banks apart, so a column's elements spread over the banks
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const unsigned ngroups = (unsigned)G;
   const int rbeg = j0 + g * rpw;
@@ -206,7 +208,7 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
       const int e = e0 + u * 256 + tid;
       if (e < nrow * w) {
         const int rr = e / w, cc = e - rr * w;
-        Ls[rr * W + cc] = buf[u];
+        Ls[rr * LW + cc] = buf[u];
       }
     }
   }
@@ -221,17 +223,17 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
     }
     if (brow != INT_MAX)
       for (int cc = tid; cc < w; cc += 256)
-        st_agent(&slot_rows[((size_t)par * G + g) * W + cc], Ls[(brow - rbeg) * W + cc]);
+        st_agent(&slot_rows[((size_t)par * G + g) * W + cc], Ls[(brow - rbeg) * LW + cc]);
     const int jd = j0 + jj;
     if (jd >= rbeg && jd < rend)
-      for (int cc = tid; cc < w; cc += 256) st_agent(&diag_rows[par * W + cc], Ls[(jd - rbeg) * W + cc]);
+      for (int cc = tid; cc < w; cc += 256) st_agent(&diag_rows[par * W + cc], Ls[(jd - rbeg) * LW + cc]);
   };
 
   // prologue: candidate for the first column
   {
     T best = T(-1);
     int brow = INT_MAX;
-    for (int rr = tid; rr < nrow; rr += 256) argmax_combine(best, brow, cabs1(Ls[rr * W]), rbeg + rr);
+    for (int rr = tid; rr < nrow; rr += 256) argmax_combine(best, brow, cabs1(Ls[rr * LW]), rbeg + rr);
     block_argmax(best, brow, red_v, red_r);
     publish(0, best, brow);
     grid_arrive(bar, 1u);
@@ -271,9 +273,9 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
       if (!(wv > T(0))) atomicCAS(info, 0, jc + 1);
     }
     if (jc >= rbeg && jc < rend)
-      for (int cc = tid; cc < w; cc += 256) Ls[(jc - rbeg) * W + cc] = urow[cc];
+      for (int cc = tid; cc < w; cc += 256) Ls[(jc - rbeg) * LW + cc] = urow[cc];
     if (p != jc && p >= rbeg && p < rend)
-      for (int cc = tid; cc < w; cc += 256) Ls[(p - rbeg) * W + cc] = drow[cc];
+      for (int cc = tid; cc < w; cc += 256) Ls[(p - rbeg) * LW + cc] = drow[cc];
     __syncthreads();
     // -- eliminate: scale column j below the pivot (an exactly zero pivot
     //    column is left as it is, and nothing is subtracted)
@@ -282,7 +284,7 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
     if (j == w - 1) {
       if (nz)
         for (int rr = tid; rr < nrow; rr += 256)
-          if (rbeg + rr > jc) Ls[rr * W + j] = cmul(Ls[rr * W + j], inv);
+          if (rbeg + rr > jc) Ls[rr * LW + j] = cmul(Ls[rr * LW + j], inv);
       __syncthreads();
       break;
     }
@@ -293,11 +295,11 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
       const int gr = rbeg + rr;
       if (gr > jc) {
         if (nz) {
-          const cplx<T> lv = cmul(Ls[rr * W + j], inv);
-          Ls[rr * W + j] = lv;
-          Ls[rr * W + j + 1] = cfms(Ls[rr * W + j + 1], lv, urow[j + 1]);
+          const cplx<T> lv = cmul(Ls[rr * LW + j], inv);
+          Ls[rr * LW + j] = lv;
+          Ls[rr * LW + j + 1] = cfms(Ls[rr * LW + j + 1], lv, urow[j + 1]);
         }
-        argmax_combine(best, brow, cabs1(Ls[rr * W + j + 1]), gr);
+        argmax_combine(best, brow, cabs1(Ls[rr * LW + j + 1]), gr);
       }
     }
     block_argmax(best, brow, red_v, red_r);
@@ -306,8 +308,8 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
     const int r2 = (jc + 1 >= rbeg && jc + 1 < rend) ? jc + 1 - rbeg : -1;
     if (nz) {
       for (int cc = j + 2 + tid; cc < w; cc += 256) {
-        if (r1 >= 0) Ls[r1 * W + cc] = cfms(Ls[r1 * W + cc], Ls[r1 * W + j], urow[cc]);
-        if (r2 >= 0 && r2 != r1) Ls[r2 * W + cc] = cfms(Ls[r2 * W + cc], Ls[r2 * W + j], urow[cc]);
+        if (r1 >= 0) Ls[r1 * LW + cc] = cfms(Ls[r1 * LW + cc], Ls[r1 * LW + j], urow[cc]);
+        if (r2 >= 0 && r2 != r1) Ls[r2 * LW + cc] = cfms(Ls[r2 * LW + cc], Ls[r2 * LW + j], urow[cc]);
       }
     }
     __syncthreads();
@@ -317,15 +319,15 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
     if (nz && j + 2 < w) {
       for (int rr = tid; rr < nrow; rr += 256) {
         if (rbeg + rr > jc && rr != r1 && rr != r2) {
-          const cplx<T> lv = Ls[rr * W + j];
-          for (int cc = j + 2; cc < w; ++cc) Ls[rr * W + cc] = cfms(Ls[rr * W + cc], lv, urow[cc]);
+          const cplx<T> lv = Ls[rr * LW + j];
+          for (int cc = j + 2; cc < w; ++cc) Ls[rr * LW + cc] = cfms(Ls[rr * LW + cc], lv, urow[cc]);
         }
       }
     }
   }
   for (int e = tid; e < nrow * w; e += 256) {
     const int rr = e / w, cc = e - rr * w;
-    A[(long)(rbeg + rr) * lda + j0 + cc] = Ls[rr * W + cc];
+    A[(long)(rbeg + rr) * lda + j0 + cc] = Ls[rr * LW + cc];
   }
 }
 
@@ -900,7 +902,7 @@ static int panel_grid(int m, int lds_cap, int &G, int &rpw) {
   // at least 64 rows per workgroup, at most kMaxPanelGroups workgroups (one
   // per CU; a 25600-row panel: 128 groups factor ~9% faster than 64 with the
   // per-group arrival flags), and at most lds_cap bytes of rows per workgroup
-  const int rpw_max = lds_cap / (int)(kPanelWidth * sizeof(cplx<T>));
+  const int rpw_max = lds_cap / (int)(kPanelLd * sizeof(cplx<T>));
   const int rpw_min = 64;
   G = (m + rpw_min - 1) / rpw_min;
   G = std::min(G, kMaxPanelGroups);
@@ -939,7 +941,7 @@ static int panel(int n, int j0, int w, cplx<T> *A, long lda, int *ipiv, int *inf
   const int conc = g_concurrency.load(std::memory_order_relaxed);
   if ((rc0 = panel_grid<T>(m, (conc > 1 ? 64 : 150) * 1024, G, rpw))) return rc0;
   if (G > kMaxPanelGroups || G > cus) return HP_ERR_UNSUPPORTED;
-  size_t shm = (size_t)rpw * kPanelWidth * sizeof(cplx<T>);
+  size_t shm = (size_t)rpw * kPanelLd * sizeof(cplx<T>);
   int rc = ensure_dynamic_lds((const void *)panel_kernel<T>, shm);
   if (rc) return rc;
   int nn = n, jj0 = j0, ww = w, rp = rpw;
