@@ -35,8 +35,8 @@ PEAK_FP64_MFMA = 78.6   # TF/s, MI355X dense FP64 matrix
 # WRITE_SIZE counter runs scaled by a 1 GiB copy
 # (profiles/gemm_sub_kernel_fp32_large_N25600_traffic.md); valid only for the
 # GEMM source it was measured on.
-GEMM_TRAFFIC = {"bytes_per_launch": 2.1815e+08,
-                "gemm_source_sha256": "264a744c8acf7612bc56183415b3317e9d26b504020882f69af7755f50044824"}
+GEMM_TRAFFIC = {"bytes_per_launch": 2.1457e+08,
+                "gemm_source_sha256": "a59b431c811e42fafe6a67ae1e94aa145b0e9314941c434d7c22160023424ee2"}
 
 
 def parse():
@@ -228,8 +228,9 @@ def main():
     out["refinement"] = [{"steps": it, "backward_error": c, "fp64_fallback": fb} for it, c, fb in info32]
     out["stages_ms_one_step"] = {k: round(v["ms"], 3) for k, v in st32.items() if v["launches"]}
     ach = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
-    out["roofline"] = {"bound": "mfma", "kernel": "gemm_sub_kernel<float> (complex 3M GEMM, FP32 MFMA; "
-                                                  "achieved counts its 6MNK real flops per launch)",
+    out["roofline"] = {"bound": "mfma", "kernel": "FP32 complex 3M GEMM (gemm_direct_kernel, with "
+                                                  "gemm_sub_kernel<float> for ragged shapes; achieved counts the "
+                                                  "6MNK real flops per launch)",
                        "achieved": ach, "peak": PEAK_FP32_MFMA, "unit": "TF/s", "frac": ach / PEAK_FP32_MFMA,
                        "traffic": gemm_traffic(), "launches_per_step": g["launches"] / args.steps,
                        "avg_launch_us": g["ms"] * 1e3 / max(1, g["launches"])}
