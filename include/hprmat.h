@@ -287,6 +287,14 @@ int hp_batch_rmatrix(int count, const hp_batch_item *items, const double *X, dou
  * factorizations enqueued afterwards. */
 int hp_set_concurrency(int k);
 
+/* Whether hp_solve replays the refinement solves of FP32 factors from a HIP
+ * graph (1, the default) or launches them one by one (0).  The graph is
+ * captured on an internal stream at the first refinement solve of each call
+ * and replayed on the caller's stream; the results are identical.  Launches
+ * inside the graph are not timed by hp_trace.  Returns the previous setting,
+ * or HP_ERR_ARG if on is not 0 or 1.  Host-side setting. */
+int hp_set_solve_graphs(int on);
+
 /* ---- instrumentation ---------------------------------------------------- */
 
 /* Per-stage device timers.  hp_trace_enable(mask) clears the record and starts

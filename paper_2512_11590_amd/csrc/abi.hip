@@ -60,6 +60,11 @@ Workspace plan_workspace(int n, int nrhs, int prec) {
   w.inv_off = off;
   w.inv_bytes = align_up(inverse_bytes(n, prec), A);
   off += w.inv_bytes;
+  if (prec == HP_C64) {
+    w.u12_off = off;
+    w.u12_bytes = align_up((size_t)kInvBlock * n * sizeof(cplx<float>), A);
+    off += w.u12_bytes;
+  }
   if (prec == HP_C64 && nrhs > 0) {
     w.wv_off = off;
     w.wv_bytes = align_up(wform_bytes(n), A);

@@ -93,6 +93,8 @@ struct Workspace {
   // FP32 solves with nrhs > 0 only: the transformed L, its 256-row
   // diagonal-block inverses, a second n x nrhs buffer and build scratch
   size_t wv_off, wv_bytes, inv2_off, inv2_bytes, z_off, z_bytes, wtmp_off, wtmp_bytes;
+  // FP32 factorizations: one 128-row half of the U12 block row (128 x n)
+  size_t u12_off, u12_bytes;
   size_t total;
 };
 Workspace plan_workspace(int n, int nrhs, int prec);

@@ -781,86 +781,9 @@ size_t inverse_bytes(int n, int prec) {
   return 2 * nb * kInvBlock * kInvBlock * sizeof(cplx<float>);
 }
 
-// Y[0:bs, stripe] <- Inv[0:bs, 0:bs] Y[0:bs, stripe] for one diagonal block.
-// A workgroup owns a stripe of CW columns and stages all of it in LDS
-// before writing, so the product is in place.  The whole inverse is staged in
-// LDS first with 16-byte loads that are all in flight together (the block is
-// shared by every workgroup of the launch and comes from L2).
-constexpr int kApplyLd = kInvBlock + 2;  // keeps rows 16-byte aligned, spreads banks
-template <typename T, int CW>
-__global__ __launch_bounds__(256) void apply_inverse_kernel(int bs, int ncols, const cplx<T> *__restrict__ Inv,
-                                                            cplx<T> *__restrict__ Y, long ldy) {
-  constexpr int RPT = kInvBlock * CW / 256;  // output rows per thread
-  constexpr int RSTEP = 256 / CW;
-  constexpr int EPV = 16 / sizeof(cplx<T>);  // complex elements per 16-byte vector
-  constexpr int NV = kInvBlock * kInvBlock / EPV / 256;
-  static_assert(NV % 8 == 0, "staging loop");
-  extern __shared__ __align__(16) char smem_raw[];
-  cplx<T> *Is = reinterpret_cast<cplx<T> *>(smem_raw);  // [kInvBlock][kApplyLd]
-  cplx<T> *Ys = Is + kInvBlock * kApplyLd;               // [kInvBlock][CW]
-  const int tid = threadIdx.x;
-  const int c = tid % CW, r0 = tid / CW;
-  const int col0 = blockIdx.x * CW;
-  const bool colok = col0 + c < ncols;
-  const cplx<T> zero{T(0), T(0)};
-  const uint4 *src = reinterpret_cast<const uint4 *>(Inv);
-  for (int v0 = 0; v0 < NV; v0 += 8) {
-    uint4 buf[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) buf[u] = src[(v0 + u) * 256 + tid];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = ((v0 + u) * 256 + tid) * EPV;
-      const int r = e / kInvBlock, k = e - r * kInvBlock;
-      *reinterpret_cast<uint4 *>(Is + r * kApplyLd + k) = buf[u];
-    }
-  }
-  for (int q = 0; q < RPT; ++q) {
-    const int r = r0 + q * RSTEP;
-    Ys[r * CW + c] = (r < bs && colok) ? Y[(long)r * ldy + col0 + c] : zero;
-  }
-  __syncthreads();
-  cplx<T> acc[RPT];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) acc[q] = zero;
-#pragma unroll 4
-  for (int k = 0; k < bs; ++k) {
-    const cplx<T> y = Ys[k * CW + c];
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const cplx<T> a = Is[(r0 + q * RSTEP) * kApplyLd + k];
-      acc[q].re += a.re * y.re - a.im * y.im;
-      acc[q].im += a.re * y.im + a.im * y.re;
-    }
-  }
-  if (!colok) return;
-  for (int q = 0; q < RPT; ++q) {
-    const int r = r0 + q * RSTEP;
-    if (r < bs) Y[(long)r * ldy + col0 + c] = acc[q];
-  }
-}
-
-template <typename T, int CW>
-static int apply_inverse_launch(int bs, int ncols, const cplx<T> *inv, cplx<T> *Y, long ldy, hipStream_t st) {
-  const size_t shm = ((size_t)kInvBlock * kApplyLd + (size_t)kInvBlock * CW) * sizeof(cplx<T>);
-  int rc = ensure_dynamic_lds((const void *)apply_inverse_kernel<T, CW>, shm);
-  if (rc) return rc;
-  hipLaunchKernelGGL((apply_inverse_kernel<T, CW>), dim3((ncols + CW - 1) / CW), dim3(256), shm, st, bs, ncols,
-                     inv, Y, ldy);
-  HP_CHECK_LAUNCH();
-  return HP_OK;
-}
-
-// 8-column stripes for the few right-hand sides of a solve (more
-// workgroups), 16-column ones for the U rows of the factorization (the
-// staged inverse serves more columns).
-template <typename T>
-static int apply_inverse(int bs, int ncols, const cplx<T> *inv, cplx<T> *Y, long ldy, hipStream_t st) {
-  if (bs <= 0 || ncols <= 0) return HP_OK;
-  TraceScope ts(TR_TRSM, st, 8.0 * bs * bs * (double)ncols, 0.0);
-  if (ncols <= 2048) return apply_inverse_launch<T, 8>(bs, ncols, inv, Y, ldy, st);
-  return apply_inverse_launch<T, 16>(bs, ncols, inv, Y, ldy, st);
-}
+// LDS row stride of a staged 128 x 128 inverse (diag256_kernel): keeps rows
+// 16-byte aligned and spreads the banks.
+constexpr int kApplyLd = kInvBlock + 2;
 
 // ------------------------------------------------------------ factorization --
 
@@ -1030,6 +953,10 @@ static int invert_block(int n, int k, const cplx<T> *A, long lda, char *work, co
   return HP_OK;
 }
 
+template <typename T>
+__global__ void copy_rows_kernel(int n, int nrhs, const cplx<T> *__restrict__ X, long ldx, cplx<T> *__restrict__ Y,
+                                 long ldy);
+
 // U12 = L11^-1 A12 for the kb rows of block k and the ncols columns right of
 // it (FP32: through the inverses invert_block made).
 template <typename T>
@@ -1048,10 +975,25 @@ static int block_row_solve(int n, int k, int kb, int ncols, cplx<T> *A, long lda
     const size_t iblk = (size_t)kInvBlock * kInvBlock;
     cplx<T> *A22 = A12 + (long)kInvBlock * lda;
     (void)n;
-    if ((rc = apply_inverse<T>(kInvBlock, ncols, inv + b * iblk, A12, lda, st))) return rc;
+    // each inverse applied as an MFMA product into scratch, then copied back
+    // (a product cannot run in place: every output tile reads its whole
+    // column panel)
+    cplx<T> *tmp = (cplx<T> *)(work + ws.u12_off);
+    const long cnt = (long)kInvBlock * ncols;
+    const dim3 cgrid((unsigned)((cnt + 255) / 256));
+    if ((rc = gemm_set_batched<T>(kInvBlock, ncols, kInvBlock, T(1), inv + b * iblk, kInvBlock, 0, A12, lda, 0, tmp,
+                                  ncols, 0, 1, st)))
+      return rc;
+    hipLaunchKernelGGL(copy_rows_kernel<T>, cgrid, dim3(256), 0, st, kInvBlock, ncols, tmp, (long)ncols, A12, lda);
+    HP_CHECK_LAUNCH();
     if ((rc = gemm_sub<T>(kInvBlock, ncols, kInvBlock, L11 + (long)kInvBlock * lda, lda, A12, lda, A22, lda, st)))
       return rc;
-    return apply_inverse<T>(kInvBlock, ncols, inv + (b + 1) * iblk, A22, lda, st);
+    if ((rc = gemm_set_batched<T>(kInvBlock, ncols, kInvBlock, T(1), inv + (b + 1) * iblk, kInvBlock, 0, A22, lda, 0,
+                                  tmp, ncols, 0, 1, st)))
+      return rc;
+    hipLaunchKernelGGL(copy_rows_kernel<T>, cgrid, dim3(256), 0, st, kInvBlock, ncols, tmp, (long)ncols, A22, lda);
+    HP_CHECK_LAUNCH();
+    return HP_OK;
   } else {
     (void)work;
     (void)ws;

@@ -16,6 +16,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -214,6 +215,24 @@ static double u64_as_double(unsigned long long u) {
   return d;
 }
 
+// Whether hp_solve replays its FP32 refinement solves from a captured graph.
+std::atomic<int> g_solve_graphs{1};
+
+// A captured solve: capture stream, graph and executable, released on scope exit.
+struct SolveGraph {
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  SolveGraph() = default;
+  SolveGraph(const SolveGraph &) = delete;
+  SolveGraph &operator=(const SolveGraph &) = delete;
+  ~SolveGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
 // Refinement loop (Sec. 3.2).  Each pass forms the FP64 residual of the
 // current X, solves for the correction with the working-precision factors and
 // adds it in FP64.  The size of the correction, max_c |d_c| / |x_c|, measures
@@ -258,18 +277,42 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
       return rc;
     Ysol = (cplx<float> *)(work + ws.z_off);
   }
-  auto solve_y = [&]() -> int {
-    if constexpr (sizeof(T) == sizeof(float))
-      return wform_solve((int)n, nc, LU, lda, (const cplx<float> *)(work + ws.inv_off),
-                         (const cplx<float> *)(work + ws.wv_off), (const cplx<float> *)(work + ws.inv2_off), Y, nc,
-                         Ysol, nc, st);
-    else
+  // The refinement solves are the same ~300 launches on the same buffers each
+  // time: with FP32 factors they are captured once (at the first refinement
+  // solve, after the initial solve has run eagerly) into a HIP graph that is
+  // replayed on the caller's stream, which removes the per-launch gaps.
+  SolveGraph sg;
+  const bool graphs = g_solve_graphs.load(std::memory_order_relaxed) != 0;
+  auto solve_y = [&](bool eager) -> int {
+    if constexpr (sizeof(T) == sizeof(float)) {
+      auto run = [&](hipStream_t s) {
+        return wform_solve((int)n, nc, LU, lda, (const cplx<float> *)(work + ws.inv_off),
+                           (const cplx<float> *)(work + ws.wv_off), (const cplx<float> *)(work + ws.inv2_off), Y, nc,
+                           Ysol, nc, s);
+      };
+      if (eager || !graphs) return run(st);
+      if (!sg.exec) {
+        HP_CHECK_HIP(hipStreamCreateWithFlags(&sg.cap, hipStreamNonBlocking));
+        HP_CHECK_HIP(hipStreamBeginCapture(sg.cap, hipStreamCaptureModeThreadLocal));
+        const int rc1 = run(sg.cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(sg.cap, &g);
+        sg.graph = g;
+        if (rc1) return rc1;
+        HP_CHECK_HIP(e);
+        HP_CHECK_HIP(hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0));
+      }
+      HP_CHECK_HIP(hipGraphLaunch(sg.exec, st));
+      return HP_OK;
+    } else {
+      (void)eager;
       return lu_solve_permuted<T>((int)n, nc, LU, lda, Y, nc, nullptr, st);
+    }
   };
   // initial solve
   hipLaunchKernelGGL(rhs_from_perm_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, nc, nr, perm, sys->q, Y);
   HP_CHECK_LAUNCH();
-  if ((rc = solve_y())) return rc;
+  if ((rc = solve_y(true))) return rc;
   hipLaunchKernelGGL(widen_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, cnt, Ysol, X);
   HP_CHECK_LAUNCH();
   int hinfo = 0;
@@ -338,7 +381,7 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
       hipLaunchKernelGGL(scale_perm_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, n, nc, perm, Rr, smax, Y);
       HP_CHECK_LAUNCH();
     }
-    if ((rc = solve_y())) return rc;
+    if ((rc = solve_y(false))) return rc;
     {
       TraceScope ts(TR_REFINE, st, 0.0, (sizeof(cplx<T>) + 32.0) * (double)cnt);
       hipLaunchKernelGGL(zero_u64_kernel, dim3(nblk(nc)), dim3(256), 0, st, dmax, nc);
@@ -387,6 +430,11 @@ extern "C" int hp_solve(const hp_system *sys, double E, int prec, const void *LU
                               max_refine, tol, (char *)work, ws, info, st);
   return solve_impl<float>(sys, E, (const cplx<float> *)LU, lda, perm, info_factor, (cplx<double> *)X,
                            max_refine, tol, (char *)work, ws, info, st);
+}
+
+extern "C" int hp_set_solve_graphs(int on) {
+  if (on != 0 && on != 1) return HP_ERR_ARG;
+  return g_solve_graphs.exchange(on);
 }
 
 extern "C" int hp_rmatrix(const hp_system *sys, const double *X, double *R, void *stream) {

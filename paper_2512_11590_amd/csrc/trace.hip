@@ -45,6 +45,10 @@ bool trace_on() { return g_on; }
 TraceScope::TraceScope(int cat, hipStream_t st, double flops, double bytes)
     : cat_(cat), st_(st), flops_(flops), bytes_(bytes), a_(nullptr) {
   if (!g_on || !((g_mask >> cat) & 1u)) return;
+  // launches recorded into a graph are not timed (their events would be
+  // replayed many times under one record)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> lk(g_mu);
   a_ = get_event();
   if (a_) hipEventRecord((hipEvent_t)a_, st_);

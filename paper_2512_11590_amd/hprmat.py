@@ -59,7 +59,7 @@ class HpSolveInfo(ctypes.Structure):
 EXPORTS = ["hp_mesh", "hp_workspace_bytes", "hp_build_matrix", "hp_factor", "hp_solve",
            "hp_lu_solve", "hp_rmatrix", "hp_smatrix", "hp_coulomb", "hp_coulomb_device",
            "hp_build_info", "hp_strerror", "hp_trace_enable", "hp_trace_read", "hp_last_error",
-           "hp_gemm_sub", "hp_set_concurrency", "hp_batch_workspace_bytes", "hp_batch_build",
+           "hp_gemm_sub", "hp_set_concurrency", "hp_set_solve_graphs", "hp_batch_workspace_bytes", "hp_batch_build",
            "hp_batch_factor", "hp_batch_factor_stepped", "hp_batch_solve_init", "hp_batch_refine_step", "hp_batch_active",
            "hp_batch_status", "hp_batch_rmatrix"]
 
@@ -138,6 +138,8 @@ def lib() -> ctypes.CDLL:
     L.hp_batch_rmatrix.restype = c_int
     L.hp_set_concurrency.argtypes = [c_int]
     L.hp_set_concurrency.restype = c_int
+    L.hp_set_solve_graphs.argtypes = [c_int]
+    L.hp_set_solve_graphs.restype = c_int
     L.hp_trace_enable.argtypes = [c_int]
     L.hp_trace_enable.restype = c_int
     L.hp_trace_read.argtypes = [ctypes.POINTER(HpTraceStat), c_int]
@@ -320,6 +322,15 @@ def hp_set_concurrency(factorizations: int) -> int:
     if rc < 0:
         raise HprmatError(rc, "hp_set_concurrency")
     return rc
+
+
+def hp_set_solve_graphs(on: bool) -> bool:
+    """Replay hp_solve's FP32 refinement solves from a HIP graph (default) or
+    launch them one by one; returns the previous setting."""
+    rc = lib().hp_set_solve_graphs(1 if on else 0)
+    if rc < 0:
+        raise HprmatError(rc, "hp_set_solve_graphs")
+    return bool(rc)
 
 
 TRACE_STAGES = ("assemble", "panel", "laswp", "trsm", "gemm_c128", "gemm_c64", "residual", "refine",
