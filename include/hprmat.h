@@ -127,8 +127,10 @@ int hp_factor(int n, int prec, void *A, long lda, int *ipiv, int *perm, int *inf
  * structure of sys (no N x N FP64 matrix), correction from the factors,
  * X += d in FP64.  The relative correction max_c |d_c| / |x_c| tracks the
  * forward error: refinement stops converged when it is <= tol (tol <= 0:
- * 2^-52) or when it stops shrinking (a correction larger than half the
- * previous one) while already <= 1e-6, and reports non-convergence when it
+ * 2^-29 = u64/u32: the error left after such a correction, about kappa u32
+ * times it, is below the FP64 floor kappa u64) or when it stops shrinking (a
+ * correction larger than half the previous one) while already <= 1e-6, and
+ * reports non-convergence when it
  * stops shrinking above that (Sec. 6: the single-precision factor is then too
  * inaccurate to contract) or after max_refine corrections.  info (host, may
  * be NULL) receives the outcome, including the normwise backward error.
@@ -249,7 +251,7 @@ int hp_batch_solve_init(int count, const hp_batch_item *items, const int *shape_
 /* One FP64 refinement step of FP32 factors for every system still refining
  * (Sec. 3.2): r = B - C X from the block structure, d from the factors
  * (column-scaled; solves as chosen by shape_host), X += d, and the stop rule
- * of hp_solve per system (relative correction <= tol, tol <= 0: 2^-52; a
+ * of hp_solve per system (relative correction <= tol, tol <= 0: 2^-29; a
  * correction larger than half the previous one: converged if the previous
  * was <= 1e-6, else not converged; not converged after max_refine steps).  A
  * fixed sequence of launches, no host synchronisation: it may be captured

@@ -619,7 +619,7 @@ __global__ __launch_bounds__(256) void batch_update_kernel(int count, const hp_b
     BatchState st = state[s];
     corr = red[0];
     st.iters += 1;
-    const double corr_tol = tol > 0.0 ? tol : 2.220446049250313e-16;
+    const double corr_tol = tol > 0.0 ? tol : kRefineTol;
     if (corr <= corr_tol) {
       st.status = 1;
     } else if (st.iters > 1 && corr > 0.5 * st.corr_prev) {

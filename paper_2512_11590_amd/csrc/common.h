@@ -75,6 +75,14 @@ class TraceScope {
 constexpr int kPanelWidth = 32;     // columns factored by one cooperative panel launch
 constexpr int kOuterBlock = 256;    // columns per trailing-update step (GEMM K)
 constexpr int kInvBlock = 128;      // rows of an inverted diagonal block of an FP32 factor
+// Default convergence threshold of the FP64 refinement of FP32 factors on the
+// relative correction c = max_c |d_c| / |x_c|.  Each step contracts the error
+// by rho ~ kappa u32, and c estimates the error before the step, so the error
+// left after applying a correction c is ~ rho c <= kappa u32 c; once
+// c <= u64 / u32 = 2^-53 / 2^-24 it is below kappa u64, the accuracy of a
+// backward-stable FP64 solve.  Further steps only move the iterate within
+// that floor.
+constexpr double kRefineTol = 0x1p-29;
 constexpr int kMaxPanelGroups = 128;  // candidate slots held in registers: 16 per thread
 constexpr unsigned kSpinLimit = 1u << 22;  // bounded grid-barrier wait (a few seconds)
 

@@ -237,9 +237,10 @@ struct SolveGraph {
 // current X, solves for the correction with the working-precision factors and
 // adds it in FP64.  The size of the correction, max_c |d_c| / |x_c|, measures
 // the forward error of the iterate before it; the loop stops
-//  * converged when it is <= tol (tol <= 0: 2^-52), or when it stops
-//    shrinking (a correction larger than half the previous one: the iterate is
-//    at the accuracy an FP64 residual can resolve) while already <= 1e-6;
+//  * converged when it is <= tol (tol <= 0: kRefineTol = 2^-29, after which
+//    the remaining error is below the FP64 floor), or when it stops shrinking
+//    (a correction larger than half the previous one: the iterate is at the
+//    accuracy an FP64 residual can resolve) while already <= 1e-6;
 //  * not converged when it stops shrinking above that level (the factors are
 //    too inaccurate for the refinement to contract, Sec. 6) or after
 //    max_refine corrections.
@@ -326,7 +327,7 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
     if (info) info->converged = 1;
     return HP_OK;
   }
-  const double corr_tol = (tol > 0.0) ? tol : 2.220446049250313e-16;
+  const double corr_tol = (tol > 0.0) ? tol : kRefineTol;
   const double stagnation_ok = 1e-6;
   hipLaunchKernelGGL(zero_u64_kernel, dim3(nblk(3 * nc + 2)), dim3(256), 0, st, smax, 3 * nc + 2);
   HP_CHECK_LAUNCH();
