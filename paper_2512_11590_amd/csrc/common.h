@@ -83,7 +83,7 @@ constexpr int kInvBlock = 128;      // rows of an inverted diagonal block of an 
 // backward-stable FP64 solve.  Further steps only move the iterate within
 // that floor.
 constexpr double kRefineTol = 0x1p-29;
-constexpr int kMaxPanelGroups = 128;  // candidate slots held in registers: 16 per thread
+constexpr int kMaxPanelGroups = 128;  // workgroups of one cooperative panel grid
 constexpr unsigned kSpinLimit = 1u << 22;  // bounded grid-barrier wait (a few seconds)
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }

@@ -161,16 +161,16 @@ static size_t barrier_words(int G) { return (size_t)G * kBarStride; }
 // LDS for the whole panel.  Per column j: every workgroup publishes its
 // candidate pivot for column j (largest |Re|+|Im|, smallest row on ties)
 // together with that row's panel values in a slot, and the owner of row j
-// publishes row j; a grid barrier; every workgroup reads all slots in one
-// round trip (the candidate rows go to registers), picks the same winner,
-// the owners of the two rows exchange them, and each workgroup eliminates in
-// its own rows.  The elimination is split so the barrier wait hides most of
+// publishes row j; a grid barrier; every workgroup reads all candidate
+// values, picks the same winner and then reads only the winner's row (two
+// short round trips cost less than one that moves every candidate row to
+// every workgroup), the owners of the two rows exchange them, and each
+// workgroup eliminates in its own rows.  The elimination is split so the barrier wait hides most of
 // it: column j+1 is updated first (it decides the next pivot), the next
 // candidate row and the next diagonal row are finished and published, and
 // the remaining columns are updated while the other workgroups arrive.
 // Slots alternate between two buffers, so a slow reader never sees the next
 // column's writes.
-constexpr int kMaxCandPerThread = kMaxPanelGroups * kPanelWidth / 256;
 constexpr int kPanelLd = kPanelWidth + 1;  // LDS row stride of the panel rows (complex elements)
 
 template <typename T>
@@ -191,7 +191,6 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
   const int rbeg = j0 + g * rpw;
   const int rend = min(n, rbeg + rpw);
   const int nrow = max(0, rend - rbeg);
-  const int ncand = G * W;  // slot values held in registers per column
 
   // rows into LDS, eight loads per thread in flight at a time (clamped
   // addresses, so every load is in bounds and none waits on a branch)
@@ -243,13 +242,8 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
     const int jc = j0 + j;
     const int par = j & 1;
     grid_wait(bar, ngroups, (unsigned)(j + 1), info);
-    // -- one round trip: all candidate values, rows and panel rows, and row jc
-    cplx<T> cand[kMaxCandPerThread];
-#pragma unroll
-    for (int q = 0; q < kMaxCandPerThread; ++q) {
-      const int e = tid + 256 * q;
-      if (e < ncand) cand[q] = ld_agent(&slot_rows[(size_t)par * G * W + e]);
-    }
+    // -- two round trips: every candidate's value and row (and row jc), then
+    //    the winner's panel row from the slot of the workgroup that owns it
     T wv = T(-1);
     int wr = INT_MAX;
     for (int e = tid; e < G; e += 256) argmax_combine(wv, wr, ld_agent(&slot_val[par * G + e]), ld_agent(&slot_row[par * G + e]));
@@ -260,13 +254,8 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
       if (g == 0 && tid == 0) atomicExch(info, -1);
       p = jc;
     }
-    // the winning row's values sit in the slot of the workgroup that owns row p
     const int wg = min(G - 1, (p - j0) / rpw);
-#pragma unroll
-    for (int q = 0; q < kMaxCandPerThread; ++q) {
-      const int e = tid + 256 * q;
-      if (e < ncand && e / W == wg && (e % W) < w) urow[e % W] = cand[q];
-    }
+    if (tid < w) urow[tid] = ld_agent(&slot_rows[((size_t)par * G + wg) * W + tid]);
     __syncthreads();
     if (g == 0 && tid == 0) {
       ipiv[jc] = p;
