@@ -8,8 +8,8 @@
 //
 // Structure of hp_factor for an outer block of kOuterBlock columns at k:
 //   for each inner panel of kPanelWidth columns j inside the block:
-//     panel_kernel       cooperative grid, one grid barrier per column: pivot
-//                        search (wavefront shuffles + slot exchange), row swap,
+//     panel_kernel       cooperative grid, one grid-wide exchange per column:
+//                        pivot search (wavefront reductions + slot exchange), row swap,
 //                        scaling and rank-1 update of the panel held in LDS
 //     laswp_kernel       the panel's swaps on the other columns of the block
 //     trsm + gemm_sub    U rows of the panel and update of the rest of the block
@@ -114,6 +114,44 @@ __device__ __forceinline__ void block_argmax(T &v, int &r, T *sv, int *sr) {
   for (int w = 1; w < 4; ++w) argmax_combine(v, r, sv[w], sr[w]);
 }
 
+// FP32 wavefront argmax on the DPP and readlane paths (no LDS round trips):
+// butterflies inside each row of 16 lanes, then the four row results
+// combined; every lane returns the wave's (value, row).
+template <int kCtrl>
+__device__ __forceinline__ void dpp_argmax_step(float &v, int &r) {
+  const float ov = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xF, 0xF, false));
+  const int orow = __builtin_amdgcn_update_dpp(0, r, kCtrl, 0xF, 0xF, false);
+  argmax_combine(v, r, ov, orow);
+}
+__device__ __forceinline__ void wave_argmax_dpp(float &v, int &r) {
+  dpp_argmax_step<0xB1>(v, r);   // quad_perm [1,0,3,2]: lane ^ 1
+  dpp_argmax_step<0x4E>(v, r);   // quad_perm [2,3,0,1]: lane ^ 2
+  dpp_argmax_step<0x141>(v, r);  // row_half_mirror: the other quad of each 8
+  dpp_argmax_step<0x140>(v, r);  // row_mirror: the other 8 of each 16
+  float bv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  int br = __builtin_amdgcn_readlane(r, 0);
+#pragma unroll
+  for (int l = 16; l < 64; l += 16)
+    argmax_combine(bv, br, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)), __builtin_amdgcn_readlane(r, l));
+  v = bv;
+  r = br;
+}
+// Whole-workgroup FP32 argmax with one barrier.  Two calls that use the same
+// sv/sr must have a __syncthreads between them (the callers' other barriers).
+__device__ __forceinline__ void block_argmax_dpp(float &v, int &r, float *sv, int *sr) {
+  wave_argmax_dpp(v, r);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    sv[wave] = v;
+    sr[wave] = r;
+  }
+  __syncthreads();
+  v = sv[0];
+  r = sr[0];
+#pragma unroll
+  for (int w = 1; w < 4; ++w) argmax_combine(v, r, sv[w], sr[w]);
+}
+
 // Grid synchronisation of the cooperative panel grid without atomics: every
 // workgroup owns one flag word and publishes the epoch it has reached there
 // (after its slot data is globally visible); a workgroup waits by polling all
@@ -154,6 +192,39 @@ __device__ __forceinline__ void grid_wait(unsigned *bar, unsigned ngroups, unsig
 
 static size_t barrier_words(int G) { return (size_t)G * kBarStride; }
 
+// FP32 panels publish each workgroup's pivot candidate as one 64-bit word:
+// the candidate value's bits above the column's epoch (global column + 1,
+// 19 bits) and the candidate's row offset inside its workgroup (13 bits; all
+// ones for "no candidate").  A reader polls the word until it carries the
+// epoch it waits for, so the arrival flag and the value read are one round
+// trip.  The word is stored after the workgroup's slot rows are visible.
+constexpr int kKeyRowBits = 13;
+constexpr unsigned kKeyNoRow = (1u << kKeyRowBits) - 1;
+constexpr int kKeyMaxColumns = 1 << (32 - kKeyRowBits);
+
+__device__ __forceinline__ unsigned long long make_key(float v, unsigned epoch, unsigned rowoff) {
+  return ((unsigned long long)__float_as_uint(v) << 32) | (epoch << kKeyRowBits) | rowoff;
+}
+
+// Bounded wait for the key word at p to carry epoch; returns the last word
+// read (on expiry -1 is recorded in *flag, as in grid_wait).
+__device__ __forceinline__ unsigned long long wait_key(const unsigned long long *p, unsigned epoch, bool failed,
+                                                       int *flag) {
+  unsigned long long v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned spins = 0;
+  while (!failed && ((unsigned)v >> kKeyRowBits) != epoch) {
+    __builtin_amdgcn_s_sleep(1);
+    if (((++spins) & 1023u) == 0) {
+      if (spins > kSpinLimit || __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == -1) {
+        atomicExch(flag, -1);
+        break;
+      }
+    }
+    v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return v;
+}
+
 // ------------------------------------------------------------ panel (LU) --
 //
 // Factor columns [j0, j0+w) of rows [j0, n) with partial pivoting.  The rows
@@ -161,16 +232,17 @@ static size_t barrier_words(int G) { return (size_t)G * kBarStride; }
 // LDS for the whole panel.  Per column j: every workgroup publishes its
 // candidate pivot for column j (largest |Re|+|Im|, smallest row on ties)
 // together with that row's panel values in a slot, and the owner of row j
-// publishes row j; a grid barrier; every workgroup reads all candidate
-// values, picks the same winner and then reads only the winner's row (two
-// short round trips cost less than one that moves every candidate row to
-// every workgroup), the owners of the two rows exchange them, and each
-// workgroup eliminates in its own rows.  The elimination is split so the barrier wait hides most of
-// it: column j+1 is updated first (it decides the next pivot), the next
-// candidate row and the next diagonal row are finished and published, and
-// the remaining columns are updated while the other workgroups arrive.
-// Slots alternate between two buffers, so a slow reader never sees the next
-// column's writes.
+// publishes row j; every workgroup waits for all candidates (FP32: polls the
+// candidates' epoch-tagged key words, which carry the values; FP64: a flag
+// barrier, then the value slots), picks the same winner and then reads only
+// the winner's row (a second short round trip costs less than moving every
+// candidate row to every workgroup), the owners of the two rows exchange
+// them, and each workgroup eliminates in its own rows.  The elimination is
+// split so the wait hides most of it: column j+1 is updated first (it
+// decides the next pivot), the next candidate row and the next diagonal row
+// are finished and published, and the remaining columns are updated while
+// the other workgroups arrive.  Slots alternate between two buffers, so a
+// slow reader never sees the next column's writes.
 constexpr int kPanelLd = kPanelWidth + 1;  // LDS row stride of the panel rows (complex elements)
 
 template <typename T>
@@ -178,12 +250,21 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
                                                     long lda, int *__restrict__ ipiv,
                                                     int *__restrict__ info, unsigned *bar,
                                                     cplx<T> *slot_rows, T *slot_val, int *slot_row,
-                                                    cplx<T> *diag_rows, int rpw) {
+                                                    cplx<T> *diag_rows, unsigned long long *slot_key, int rpw) {
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T> *Ls = reinterpret_cast<cplx<T> *>(smem_raw);  // [rpw][kPanelLd]
   __shared__ cplx<T> urow[kPanelWidth], drow[kPanelWidth];
-  __shared__ T red_v[4];
-  __shared__ int red_r[4];
+  __shared__ T red_v[4], red_v2[4];  // read-side and elimination-side argmax exchange
+  __shared__ int red_r[4], red_r2[4];
+  // FP32: candidates as epoch-tagged key words (slot_key); FP64: value and
+  // row slots behind the flag barrier (the value leaves no room for a tag)
+  constexpr bool kKeyed = std::is_same<T, float>::value;
+  auto argmax_all = [&](T &v, int &r, T *sv, int *sr) {
+    if constexpr (kKeyed)
+      block_argmax_dpp(v, r, sv, sr);
+    else
+      block_argmax(v, r, sv, sr);
+  };
   constexpr int W = kPanelWidth;
   constexpr int LW = kPanelLd;  // padded row stride: rows 2 banks apart, so a column's elements spread over the banks
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
@@ -213,12 +294,16 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
   }
   __syncthreads();
 
-  // publish the candidate of column jj (slot buffer jj & 1) and row j0+jj
+  // publish the candidate of column jj (slot buffer jj & 1) and row j0+jj,
+  // then arrive: the key word (FP32) or the arrival flag, once the rows are
+  // visible
   auto publish = [&](int jj, T best, int brow) {
     const int par = jj & 1;
-    if (tid == 0) {
-      st_agent(&slot_val[par * G + g], best);
-      st_agent(&slot_row[par * G + g], brow);
+    if constexpr (!kKeyed) {
+      if (tid == 0) {
+        st_agent(&slot_val[par * G + g], best);
+        st_agent(&slot_row[par * G + g], brow);
+      }
     }
     if (brow != INT_MAX)
       for (int cc = tid; cc < w; cc += 256)
@@ -226,6 +311,18 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
     const int jd = j0 + jj;
     if (jd >= rbeg && jd < rend)
       for (int cc = tid; cc < w; cc += 256) st_agent(&diag_rows[par * W + cc], Ls[(jd - rbeg) * LW + cc]);
+    if constexpr (kKeyed) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (tid == 0) {
+        const unsigned off = brow == INT_MAX ? kKeyNoRow : (unsigned)(brow - rbeg);
+        __hip_atomic_store(&slot_key[par * G + g], make_key(best, (unsigned)(jd + 1), off), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+    } else {
+      grid_arrive(bar, (unsigned)(jj + 1));
+    }
   };
 
   // prologue: candidate for the first column
@@ -233,22 +330,30 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
     T best = T(-1);
     int brow = INT_MAX;
     for (int rr = tid; rr < nrow; rr += 256) argmax_combine(best, brow, cabs1(Ls[rr * LW]), rbeg + rr);
-    block_argmax(best, brow, red_v, red_r);
+    argmax_all(best, brow, red_v2, red_r2);
     publish(0, best, brow);
-    grid_arrive(bar, 1u);
   }
 
   for (int j = 0; j < w; ++j) {
     const int jc = j0 + j;
     const int par = j & 1;
-    grid_wait(bar, ngroups, (unsigned)(j + 1), info);
-    // -- two round trips: every candidate's value and row (and row jc), then
-    //    the winner's panel row from the slot of the workgroup that owns it
+    // -- every candidate's value and row, then the winner's panel row from
+    //    the slot of the workgroup that owns it (and row jc)
     T wv = T(-1);
     int wr = INT_MAX;
-    for (int e = tid; e < G; e += 256) argmax_combine(wv, wr, ld_agent(&slot_val[par * G + e]), ld_agent(&slot_row[par * G + e]));
-    if (tid < w) drow[tid] = ld_agent(&diag_rows[par * W + tid]);
-    block_argmax(wv, wr, red_v, red_r);
+    if constexpr (kKeyed) {
+      const bool failed = __hip_atomic_load(info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == -1;
+      for (int e = tid; e < G; e += 256) {
+        const unsigned long long key = wait_key(&slot_key[par * G + e], (unsigned)(jc + 1), failed, info);
+        const unsigned off = (unsigned)key & kKeyNoRow;
+        argmax_combine(wv, wr, __uint_as_float((unsigned)(key >> 32)), off == kKeyNoRow ? INT_MAX : j0 + e * rpw + (int)off);
+      }
+    } else {
+      grid_wait(bar, ngroups, (unsigned)(j + 1), info);
+      for (int e = tid; e < G; e += 256) argmax_combine(wv, wr, ld_agent(&slot_val[par * G + e]), ld_agent(&slot_row[par * G + e]));
+      if (tid < w) drow[tid] = ld_agent(&diag_rows[par * W + tid]);
+    }
+    argmax_all(wv, wr, red_v, red_r);
     int p = wr;
     if (p < jc || p >= n) {  // cannot happen unless the exchange failed; never index out of range
       if (g == 0 && tid == 0) atomicExch(info, -1);
@@ -256,6 +361,9 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
     }
     const int wg = min(G - 1, (p - j0) / rpw);
     if (tid < w) urow[tid] = ld_agent(&slot_rows[((size_t)par * G + wg) * W + tid]);
+    if constexpr (kKeyed) {
+      if (tid >= 64 && tid < 64 + w) drow[tid - 64] = ld_agent(&diag_rows[par * W + tid - 64]);
+    }
     __syncthreads();
     if (g == 0 && tid == 0) {
       ipiv[jc] = p;
@@ -291,7 +399,7 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
         argmax_combine(best, brow, cabs1(Ls[rr * LW + j + 1]), gr);
       }
     }
-    block_argmax(best, brow, red_v, red_r);
+    argmax_all(best, brow, red_v2, red_r2);
     // finish the two rows that are published next: the candidate and row jc+1
     const int r1 = (brow != INT_MAX) ? brow - rbeg : -1;
     const int r2 = (jc + 1 >= rbeg && jc + 1 < rend) ? jc + 1 - rbeg : -1;
@@ -303,7 +411,6 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
     }
     __syncthreads();
     publish(j + 1, best, brow);
-    grid_arrive(bar, (unsigned)(j + 2));
     // the remaining columns of the other rows, while the grid arrives
     if (nz && j + 2 < w) {
       for (int rr = tid; rr < nrow; rr += 256) {
@@ -782,6 +889,7 @@ struct PanelSlots {
   T *val;         // [2][G]
   int *row;       // [2][G]
   cplx<T> *diag;  // [2][W]
+  unsigned long long *key;  // [2][G] (FP32 panels)
 };
 
 template <typename T>
@@ -795,14 +903,18 @@ static PanelSlots<T> carve_slots(char *base) {
   s.row = (int *)(base + off);
   off += align_up(sizeof(int) * 2 * kMaxPanelGroups, 256);
   s.diag = (cplx<T> *)(base + off);
+  off += align_up(sizeof(cplx<T>) * 2 * kPanelWidth, 256);
+  s.key = (unsigned long long *)(base + off);
   return s;
 }
 
 static size_t slot_bytes_max() {
   return align_up(sizeof(cplx<double>) * 2 * kMaxPanelGroups * kPanelWidth, 256) +
          align_up(sizeof(double) * 2 * kMaxPanelGroups, 256) + align_up(sizeof(int) * 2 * kMaxPanelGroups, 256) +
-         align_up(sizeof(cplx<double>) * 2 * kPanelWidth, 256);
+         align_up(sizeof(cplx<double>) * 2 * kPanelWidth, 256) +
+         align_up(sizeof(unsigned long long) * 2 * kMaxPanelGroups, 256);
 }
+static size_t slot_key_words() { return 2 * 2 * kMaxPanelGroups; }  // 32-bit words of PanelSlots::key
 
 // Rows per workgroup of the panel grid, and the grid size.
 // Number of factorizations that may run at the same time on one device
@@ -853,6 +965,8 @@ static int panel(int n, int j0, int w, cplx<T> *A, long lda, int *ipiv, int *inf
   const int conc = g_concurrency.load(std::memory_order_relaxed);
   if ((rc0 = panel_grid<T>(m, (conc > 1 ? 64 : 150) * 1024, G, rpw))) return rc0;
   if (G > kMaxPanelGroups || G > cus) return HP_ERR_UNSUPPORTED;
+  // the FP32 key word holds the row offset and the column epoch in 32 bits
+  if (std::is_same<T, float>::value && (rpw >= (int)kKeyNoRow || n >= kKeyMaxColumns)) return HP_ERR_UNSUPPORTED;
   size_t shm = (size_t)rpw * kPanelLd * sizeof(cplx<T>);
   int rc = ensure_dynamic_lds((const void *)panel_kernel<T>, shm);
   if (rc) return rc;
@@ -862,7 +976,8 @@ static int panel(int n, int j0, int w, cplx<T> *A, long lda, int *ipiv, int *inf
   T *sval = s.val;
   int *srow = s.row;
   cplx<T> *sdiag = s.diag;
-  void *args[] = {&nn, &jj0, &ww, &A, &ld, &ipiv, &info, &bar, &srows, &sval, &srow, &sdiag, &rp};
+  unsigned long long *skey = s.key;
+  void *args[] = {&nn, &jj0, &ww, &A, &ld, &ipiv, &info, &bar, &srows, &sval, &srow, &sdiag, &skey, &rp};
   // All G workgroups must become resident together (they meet at grid
   // barriers).  G is at most one per CU and one workgroup fits a CU, so on an
   // idle device they are; beside other kernels (this factorization's own
@@ -1011,6 +1126,8 @@ static int lu_factor_on(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *
   hipLaunchKernelGGL(iota_kernel, dim3((n + 255) / 256), dim3(256), 0, st, perm, n);
   HP_CHECK_LAUNCH();
   PanelSlots<T> slots = carve_slots<T>(work + ws.slot_off);
+  // key words from an earlier factorization must not match this one's epochs
+  if ((rc = fill_u32((unsigned *)slots.key, slot_key_words(), 0u, st))) return rc;
   int *plan = (int *)(work + ws.slot_off + slot_bytes_max());
   if ((rc = factor_block<T>(n, 0, std::min(kOuterBlock, n), A, lda, ipiv, info, bars, slots, plan, st))) return rc;
   for (int k = 0; k < n; k += kOuterBlock) {
