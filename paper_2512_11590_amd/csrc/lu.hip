@@ -251,6 +251,9 @@ __global__ __launch_bounds__(256) void panel_kernel(int n, int j0, int w, cplx<T
                                                     int *__restrict__ info, unsigned *bar,
                                                     cplx<T> *slot_rows, T *slot_val, int *slot_row,
                                                     cplx<T> *diag_rows, unsigned long long *slot_key, int rpw) {
+  // the panel chain is latency-bound and shares its SIMDs with the
+  // MFMA-bound trailing update: its waves go first in instruction issue
+  __builtin_amdgcn_s_setprio(3);
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T> *Ls = reinterpret_cast<cplx<T> *>(smem_raw);  // [rpw][kPanelLd]
   __shared__ cplx<T> urow[kPanelWidth], drow[kPanelWidth];
@@ -693,6 +696,184 @@ static int trsm(int m, int ncols, const cplx<T> *L, long ldl, cplx<T> *X, long l
   return trsm_launch<T, UPPER, TrsmCfg<T>::CW>(m, ncols, L, ldl, X, ldx, st);
 }
 
+// --------------------------------------------------------- panel finish --
+//
+// After the panel of jb <= kPanelWidth columns at j inside the outer block
+// [k, kend): the panel's interchanges on the block's other columns ([k, j)
+// and [j + jb, kend)) and the panel's U rows U12 = L11^-1 A12 on the columns
+// right of it, in one launch.  One workgroup per stripe of CW columns:
+//  1. the net row permutation of the jb interchanges, worked out by one
+//     wavefront: the jb block rows and the distinct pivot rows below the
+//     block are the slots (at most 2 jb); lane s tracks which original row's
+//     content sits in slot s while the interchanges are replayed in order;
+//  2. every slot's source row of the stripe into LDS (all reads before any
+//     write), then the rows that move below the block, and the block rows
+//     of the columns left of the panel, written back;
+//  3. right of the panel, forward substitution with the panel's unit lower
+//     L11 on the block rows (one thread per column; FP32 columns held in
+//     registers), written back.
+template <typename T>
+struct FinishCfg {
+  static constexpr int CW = 32;  // 2 kPanelWidth x CW must be a multiple of 256
+};
+template <>
+struct FinishCfg<float> {
+  static constexpr int CW = 64;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void panel_finish_kernel(int n, int k, int kend, int j, int jb,
+                                                           cplx<T> *__restrict__ A, long lda,
+                                                           const int *__restrict__ ipiv, int *__restrict__ info) {
+  constexpr int CW = FinishCfg<T>::CW;
+  constexpr int W = kPanelWidth;
+  constexpr int LP = W + 1;
+  __builtin_amdgcn_s_setprio(3);  // on the panel chain, like panel_kernel
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);  // [2 W][CW]: the stripe's slot contents
+  cplx<T> *Lt = buf + 2 * W * CW;                         // [W][LP]: L11
+  __shared__ int ps[W], src[2 * W], dst[2 * W];
+  __shared__ int nslot;
+  const int tid = threadIdx.x;
+  const int n1 = j - k;                   // stripe columns left of the panel
+  const int ntot = n1 + (kend - j - jb);  // and in total
+  const int q0 = blockIdx.x * CW;
+  if (tid < jb) {
+    int p = ipiv[j + tid];
+    if (p < j + tid || p >= n) {  // never expected; keep every index in range
+      atomicExch(info, -1);
+      p = j + tid;
+    }
+    ps[tid] = p;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int lane = tid;
+    const int p = lane < jb ? ps[lane] : 0;
+    const bool out = lane < jb && p >= j + jb;
+    int f = lane;  // first interchange that brings row p in
+    for (int i = 0; i < jb; ++i) {
+      const int pi = __builtin_amdgcn_readlane(p, i);
+      if (out && i < f && pi == p) f = i;
+    }
+    const unsigned long long firsts = __ballot(out && f == lane);
+    const int nout = __popcll(firsts);
+    // slot of this lane's pivot row, and the original row of slot `lane`
+    const int b = lane < jb ? (out ? jb + __popcll(firsts & ((1ull << f) - 1)) : p - j) : lane;
+    int row = lane < jb ? j + lane : -1;
+    for (int i = 0; i < jb; ++i) {
+      const int pi = __builtin_amdgcn_readlane(p, i);
+      if ((firsts >> i) & 1ull)
+        if (lane == jb + __popcll(firsts & ((1ull << i) - 1))) row = pi;
+    }
+    int content = row;
+    for (int i = 0; i < jb; ++i) {
+      const int bi = __builtin_amdgcn_readlane(b, i);
+      const int vi = __builtin_amdgcn_readlane(content, i);
+      const int vb = __builtin_amdgcn_readlane(content, bi);
+      if (lane == i) content = vb;
+      if (lane == bi) content = vi;
+    }
+    if (lane < jb + nout) {
+      src[lane] = content;
+      dst[lane] = row;
+    }
+    if (lane == 0) nslot = jb + nout;
+  }
+  __syncthreads();
+  const int ns = nslot;
+  const int ncw = min(CW, ntot - q0);
+  const bool right = q0 + ncw > n1;
+  if constexpr (sizeof(T) == 4) {
+    // every load of the stripe and of L11 in flight before the first LDS store
+    constexpr int kGather = 2 * W * CW / 256, kLoadL = W * W / 256;
+    cplx<T> gv[kGather], lv[kLoadL];
+#pragma unroll
+    for (int u = 0; u < kGather; ++u) {
+      const int e = tid + 256 * u, sl = e / CW, c = e - sl * CW, q = q0 + c;
+      cplx<T> v{T(0), T(0)};
+      if (sl < ns && c < ncw) v = A[(long)src[sl] * lda + (q < n1 ? k + q : j + jb + (q - n1))];
+      gv[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadL; ++u) {
+      const int e = tid + 256 * u, r = e / W, c = e - r * W;
+      cplx<T> v{T(0), T(0)};
+      if (right && r < jb && c < jb) v = A[(long)(j + r) * lda + j + c];
+      lv[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < kGather; ++u) {
+      const int e = tid + 256 * u, sl = e / CW, c = e - sl * CW;
+      if (sl < ns && c < ncw) buf[e] = gv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadL; ++u) {
+      const int e = tid + 256 * u, r = e / W, c = e - r * W;
+      Lt[r * LP + c] = lv[u];
+    }
+  } else {
+    if (right)
+      for (int e = tid; e < W * W; e += 256) {
+        const int r = e / W, c = e - r * W;
+        Lt[r * LP + c] = (r < jb && c < jb) ? A[(long)(j + r) * lda + j + c] : cplx<T>{T(0), T(0)};
+      }
+    for (int e = tid; e < ns * CW; e += 256) {
+      const int sl = e / CW, c = e - sl * CW, q = q0 + c;
+      if (c < ncw) buf[e] = A[(long)src[sl] * lda + (q < n1 ? k + q : j + jb + (q - n1))];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < ns * CW; e += 256) {
+    const int sl = e / CW, c = e - sl * CW, q = q0 + c;
+    if (c < ncw && src[sl] != dst[sl] && (sl >= jb || q < n1))
+      A[(long)dst[sl] * lda + (q < n1 ? k + q : j + jb + (q - n1))] = buf[e];
+  }
+  if (tid < ncw && q0 + tid >= n1) {
+    const int col = j + jb + (q0 + tid - n1);
+    if constexpr (sizeof(T) == 4) {
+      // the column in registers, every index static
+      cplx<T> x[W];
+#pragma unroll
+      for (int i = 0; i < W; ++i) x[i] = i < jb ? buf[i * CW + tid] : cplx<T>{T(0), T(0)};
+#pragma unroll
+      for (int i = 1; i < W; ++i)
+        if (i < jb) {
+#pragma unroll
+          for (int kk = 0; kk < i; ++kk) x[i] = cfms(x[i], Lt[i * LP + kk], x[kk]);
+        }
+#pragma unroll
+      for (int i = 0; i < W; ++i)
+        if (i < jb) A[(long)(j + i) * lda + col] = x[i];
+    } else {
+      for (int i = 1; i < jb; ++i) {
+        cplx<T> sum = buf[i * CW + tid];
+        for (int kk = 0; kk < i; ++kk) sum = cfms(sum, Lt[i * LP + kk], buf[kk * CW + tid]);
+        buf[i * CW + tid] = sum;
+      }
+      for (int i = 0; i < jb; ++i) A[(long)(j + i) * lda + col] = buf[i * CW + tid];
+    }
+  }
+}
+
+template <typename T>
+static int panel_finish(int n, int k, int kend, int j, int jb, cplx<T> *A, long lda, const int *ipiv, int *info,
+                        hipStream_t st) {
+  if (jb <= 0 || jb > kPanelWidth || j < k || j + jb > kend || kend > n) return HP_ERR_ARG;
+  const int ntot = (j - k) + (kend - j - jb);
+  if (ntot == 0) return HP_OK;
+  constexpr int CW = FinishCfg<T>::CW;
+  const size_t shm = ((size_t)2 * kPanelWidth * CW + (size_t)kPanelWidth * (kPanelWidth + 1)) * sizeof(cplx<T>);
+  int rc = ensure_dynamic_lds((const void *)panel_finish_kernel<T>, shm);
+  if (rc) return rc;
+  const int nright = kend - j - jb;
+  TraceScope ts(TR_TRSM, st, 4.0 * jb * jb * (double)nright, 4.0 * jb * ntot * sizeof(cplx<T>));
+  hipLaunchKernelGGL(panel_finish_kernel<T>, dim3((unsigned)((ntot + CW - 1) / CW)), dim3(256), shm, st, n, k, kend,
+                     j, jb, A, lda, ipiv, info);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
 // ------------------------------------------- inverted diagonal blocks --
 // The FP32 factor is applied many times per energy (once per refinement
 // step).  Its triangular solves are restructured for that reuse: the
@@ -1025,19 +1206,18 @@ int lookahead_for(hipStream_t st, LookAhead **out) {
 // by the update of the block's columns to its right.
 template <typename T>
 static int factor_block(int n, int k, int kb, cplx<T> *A, long lda, int *ipiv, int *info, unsigned *bars,
-                        const PanelSlots<T> &slots, int *plan, hipStream_t st) {
+                        const PanelSlots<T> &slots, hipStream_t st) {
   int rc;
   const size_t per_panel = barrier_words(kMaxPanelGroups);
   for (int j = k; j < k + kb; j += kPanelWidth) {
     const int jb = std::min(kPanelWidth, k + kb - j);
     if ((rc = panel<T>(n, j, jb, A, lda, ipiv, info, bars + per_panel * (j / kPanelWidth), slots, st)))
       return rc;
-    if ((rc = laswp<T>(A, lda, ipiv, j, j + jb, k, j, j + jb, k + kb, nullptr, n, plan, info, st))) return rc;
+    // the panel's interchanges on the block's other columns, and its U rows
+    if ((rc = panel_finish<T>(n, k, k + kb, j, jb, A, lda, ipiv, info, st))) return rc;
     const int rest = k + kb - (j + jb);
     if (rest > 0) {
-      cplx<T> *L11 = A + (long)j * lda + j;
       cplx<T> *A12 = A + (long)j * lda + j + jb;
-      if ((rc = trsm<T, false>(jb, rest, L11, lda, A12, lda, st))) return rc;
       if ((rc = gemm_sub<T>(n - j - jb, rest, jb, A + (long)(j + jb) * lda + j, lda, A12, lda,
                             A + (long)(j + jb) * lda + j + jb, lda, st)))
         return rc;
@@ -1129,7 +1309,7 @@ static int lu_factor_on(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *
   // key words from an earlier factorization must not match this one's epochs
   if ((rc = fill_u32((unsigned *)slots.key, slot_key_words(), 0u, st))) return rc;
   int *plan = (int *)(work + ws.slot_off + slot_bytes_max());
-  if ((rc = factor_block<T>(n, 0, std::min(kOuterBlock, n), A, lda, ipiv, info, bars, slots, plan, st))) return rc;
+  if ((rc = factor_block<T>(n, 0, std::min(kOuterBlock, n), A, lda, ipiv, info, bars, slots, st))) return rc;
   for (int k = 0; k < n; k += kOuterBlock) {
     const int kb = std::min(kOuterBlock, n - k);
     // the block's interchanges on all columns outside the block, and on perm
@@ -1151,12 +1331,12 @@ static int lu_factor_on(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *
     if (rest > kb2) {
       HP_CHECK_HIP(hipEventRecord(la->ready, st));
       HP_CHECK_HIP(hipStreamWaitEvent(la->panel, la->ready, 0));
-      if ((rc = factor_block<T>(n, k2, kb2, A, lda, ipiv, info, bars, slots, plan, la->panel))) return rc;
+      if ((rc = factor_block<T>(n, k2, kb2, A, lda, ipiv, info, bars, slots, la->panel))) return rc;
       HP_CHECK_HIP(hipEventRecord(la->done, la->panel));
       if ((rc = gemm_sub<T>(rest, rest - kb2, kb, L21, lda, U12 + kb2, lda, A22 + kb2, lda, st))) return rc;
       HP_CHECK_HIP(hipStreamWaitEvent(st, la->done, 0));
     } else {
-      if ((rc = factor_block<T>(n, k2, kb2, A, lda, ipiv, info, bars, slots, plan, st))) return rc;
+      if ((rc = factor_block<T>(n, k2, kb2, A, lda, ipiv, info, bars, slots, st))) return rc;
     }
   }
   return HP_OK;
@@ -1241,7 +1421,6 @@ __global__ void copy_rows_kernel(int n, int nrhs, const cplx<T> *__restrict__ X,
 // issues all of a thread's loads (in-bounds addresses, out-of-range values
 // replaced by zero afterwards) before its first LDS store, so the loads are
 // in flight together.
-constexpr int kDiagNV = kInvBlock * kInvBlock * 8 / 16 / 256;  // 16-byte vectors of an FP32 block per thread
 
 template <typename T>
 __device__ __forceinline__ void stage_block(cplx<T> *__restrict__ S, const uint4 *__restrict__ src, int tid) {
