@@ -31,11 +31,12 @@ sys.path.insert(0, ROOT)
 METRIC = "N=25600 complex solve s & TF/s, FP32-LU+IR vs FP64 LU; served solves/s, p99"
 PEAK_FP32_MFMA = 157.3  # TF/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6   # TF/s, MI355X dense FP64 matrix
-# HBM bytes per launch of the FP32 GEMM on this command, from FETCH_SIZE and
-# WRITE_SIZE counter runs scaled by a 1 GiB copy
-# (profiles/gemm_sub_kernel_fp32_large_N25600_traffic.md); valid only for the
-# GEMM source it was measured on.
-GEMM_TRAFFIC = {"bytes_per_launch": 2.1457e+08,
+# HBM bytes per launch of the FP32 GEMM on this command, over the launches
+# the roofline timers see (each step's factorization and first solve), from
+# FETCH_SIZE and WRITE_SIZE counter runs scaled by a 1 GiB copy
+# (profiles/gemm_direct_kernel_fp32_large_N25600_traffic.md); valid only for
+# the GEMM source it was measured on.
+GEMM_TRAFFIC = {"bytes_per_launch": 3.3396e+08,
                 "gemm_source_sha256": "a59b431c811e42fafe6a67ae1e94aa145b0e9314941c434d7c22160023424ee2"}
 
 

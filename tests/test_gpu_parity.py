@@ -80,6 +80,39 @@ def test_lu_fp64_matches_oracle_elimination(H, n):
     assert np.array_equal(perm.cpu().numpy(), pr)
 
 
+def row_scrambled(n, seed, kind):
+    """A diagonally dominant matrix with its rows moved, so that partial
+    pivoting has to fetch every pivot row from elsewhere: `reverse` puts row
+    j at n-1-j (pivots from far below the block); `shift` moves every row up
+    by one (the pivot of every column is the row the previous interchange
+    sent to the bottom, so one row is chosen many times within a panel)."""
+    B = rand_matrix(n, seed, diag=10.0 * np.sqrt(n))
+    if kind == "reverse":
+        return B[::-1].copy()
+    return np.roll(B, -1, axis=0)
+
+
+@pytest.mark.parametrize("kind", ["reverse", "shift"])
+@pytest.mark.parametrize("n", [45, 300, 600])
+def test_lu_interchanges_from_below(H, n, kind):
+    say("lu interchanges", kind, n)
+    A = row_scrambled(n, 3 * n + len(kind), kind)
+    _, LU, ipiv_o = ge.solve(A, np.ones((n, 1), complex))
+    if kind == "shift":  # the pivot rows repeat: every column takes row n-1
+        assert np.all(ipiv_o[:-1] == n - 1)
+    dA, ipiv, perm, info, _ = device_factor(H, A, H.HP_C128)
+    assert int(info.item()) == 0
+    assert np.array_equal(ipiv.cpu().numpy(), ipiv_o)
+    assert relerr(dA.cpu().numpy(), LU) < 1e-12
+    dA, ipiv, perm, info, _ = device_factor(H, A, H.HP_C64)
+    assert int(info.item()) == 0
+    assert np.array_equal(ipiv.cpu().numpy(), ipiv_o)
+    LU32 = dA.cpu().numpy().astype(np.complex128)
+    L = np.tril(LU32, -1) + np.eye(n)
+    U = np.triu(LU32)
+    assert relerr(L @ U, A[perm.cpu().numpy()]) < 1e-5
+
+
 @pytest.mark.parametrize("n", [5, 64, 257, 513])
 def test_lu_fp32_backward_error(H, n):
     say("lu fp32", n)
