@@ -1279,9 +1279,23 @@ static int block_row_solve(int n, int k, int kb, int ncols, cplx<T> *A, long lda
     HP_CHECK_LAUNCH();
     return HP_OK;
   } else {
+    (void)n;
     (void)work;
     (void)ws;
-    return trsm<T, false>(kb, ncols, L11, lda, A12, lda, st);
+    // blocked substitution: each 32-row diagonal block of L11 solved in
+    // place, the rows below it then updated by an MFMA product (one long
+    // substitution over 256 rows is latency-bound and sits on the
+    // factorization's critical path)
+    constexpr int kSub = kPanelWidth;
+    for (int i0 = 0; i0 < kb; i0 += kSub) {
+      const int ib = std::min(kSub, kb - i0);
+      cplx<T> *Xi = A12 + (long)i0 * lda;
+      if ((rc = trsm<T, false>(ib, ncols, L11 + (long)i0 * lda + i0, lda, Xi, lda, st))) return rc;
+      if (i0 + ib < kb && (rc = gemm_sub<T>(kb - i0 - ib, ncols, ib, L11 + (long)(i0 + ib) * lda + i0, lda, Xi, lda,
+                                            Xi + (long)ib * lda, lda, st)))
+        return rc;
+    }
+    return HP_OK;
   }
 }
 
