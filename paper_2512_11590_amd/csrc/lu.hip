@@ -710,8 +710,8 @@ static int trsm(int m, int ncols, const cplx<T> *L, long ldl, cplx<T> *X, long l
 //     write), then the rows that move below the block, and the block rows
 //     of the columns left of the panel, written back;
 //  3. right of the panel, forward substitution with the panel's unit lower
-//     L11 on the block rows (one thread per column; FP32 columns held in
-//     registers), written back.
+//     L11 on the block rows (one thread per column: FP32 columns held in
+//     registers, FP64 in 8-row register blocks), written back.
 template <typename T>
 struct FinishCfg {
   static constexpr int CW = 32;  // 2 kPanelWidth x CW must be a multiple of 256
@@ -764,7 +764,7 @@ __global__ __launch_bounds__(256) void panel_finish_kernel(int n, int k, int ken
     for (int i = 0; i < jb; ++i) {
       const int pi = __builtin_amdgcn_readlane(p, i);
       if ((firsts >> i) & 1ull)
-        if (lane == jb + __popcll(firsts & ((1ull << i) - 1))) row = pi;
+        if (lane == jb + (int)__popcll(firsts & ((1ull << i) - 1))) row = pi;
     }
     int content = row;
     for (int i = 0; i < jb; ++i) {
@@ -846,12 +846,31 @@ __global__ __launch_bounds__(256) void panel_finish_kernel(int n, int k, int ken
       for (int i = 0; i < W; ++i)
         if (i < jb) A[(long)(j + i) * lda + col] = x[i];
     } else {
-      for (int i = 1; i < jb; ++i) {
-        cplx<T> sum = buf[i * CW + tid];
-        for (int kk = 0; kk < i; ++kk) sum = cfms(sum, Lt[i * LP + kk], buf[kk * CW + tid]);
-        buf[i * CW + tid] = sum;
+      // 8 rows at a time in registers, the rows solved before them read back
+      // from LDS (rows past jb meet only zeros of L11 and are never stored)
+      constexpr int RB = 8;
+#pragma unroll 1
+      for (int r0 = 0; r0 < jb; r0 += RB) {
+        cplx<T> acc[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) acc[i] = buf[(r0 + i) * CW + tid];
+#pragma unroll 1
+        for (int kk = 0; kk < r0; ++kk) {
+          const cplx<T> xk = buf[kk * CW + tid];
+#pragma unroll
+          for (int i = 0; i < RB; ++i) acc[i] = cfms(acc[i], Lt[(r0 + i) * LP + kk], xk);
+        }
+#pragma unroll
+        for (int i = 1; i < RB; ++i)
+#pragma unroll
+          for (int kk = 0; kk < i; ++kk) acc[i] = cfms(acc[i], Lt[(r0 + i) * LP + r0 + kk], acc[kk]);
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+          if (r0 + i < jb) {
+            buf[(r0 + i) * CW + tid] = acc[i];
+            A[(long)(j + r0 + i) * lda + col] = acc[i];
+          }
       }
-      for (int i = 0; i < jb; ++i) A[(long)(j + i) * lda + col] = buf[i * CW + tid];
     }
   }
 }
