@@ -542,37 +542,94 @@ __global__ __launch_bounds__(256) void batch_residual_kernel(int count, const hp
   const double h = it.sys.hbar2_2mu, E = it.E;
   const cplx<double> *x = X + it.x_off;
   cplx<double> *rr = Rr + it.x_off;
-  for (long e = threadIdx.x; e < (long)n * nc; e += 256) {
-    const int row = (int)(e / nc), cc = (int)(e - (long)row * nc);
-    const int c = row / nr, i = row - c * nr;
-    const int lc = it.sys.l[c];
-    const double ri = it.sys.r[i];
-    const double dg = h * (double)lc * (double)(lc + 1) / (ri * ri) + it.sys.eps[c] - E;
-    double sr = 0.0, si = 0.0;
-    const double *trow = it.sys.tl + (size_t)i * nr;
+  // Each X element loaded feeds RB1 (RB2) outputs held in registers; every
+  // output element keeps the summation order of the definition (kinetic
+  // terms over j, the diagonal term, coupling terms over c').
+  constexpr int RB1 = 8, RB2 = 4, kMaxCols = 256;
+  __shared__ unsigned long long smax[kMaxCols];  // column maxima as the bits of non-negative doubles
+  smax[threadIdx.x] = 0ull;
+  // pass 1: h (T + L) X + diagonal, RB1 mesh rows of one channel per item,
+  // partial sums into R
+  const int nrb = (nr + RB1 - 1) / RB1;
+  const long n1 = (long)nc * nrb * nc;
+  for (long e = threadIdx.x; e < n1; e += 256) {
+    const int cc = (int)(e % nc);
+    const long t = e / nc;
+    const int ib = (int)(t % nrb), c = (int)(t / nrb);
+    const int i0 = ib * RB1;
+    const cplx<double> *xc = x + (long)c * nr * nc + cc;
+    double sr[RB1], si[RB1];
+#pragma unroll
+    for (int u = 0; u < RB1; ++u) sr[u] = si[u] = 0.0;
     for (int j = 0; j < nr; ++j) {
-      const cplx<double> xv = x[(long)(c * nr + j) * nc + cc];
-      sr += h * trow[j] * xv.re;
-      si += h * trow[j] * xv.im;
+      const cplx<double> xv = xc[(long)j * nc];
+#pragma unroll
+      for (int u = 0; u < RB1; ++u) {
+        const int i = min(i0 + u, nr - 1);  // rows past nr: computed, never stored
+        const double ht = h * it.sys.tl[(size_t)i * nr + j];
+        sr[u] += ht * xv.re;
+        si[u] += ht * xv.im;
+      }
     }
-    const cplx<double> xi = x[(long)row * nc + cc];
-    sr += dg * xi.re;
-    si += dg * xi.im;
-    const double *vrow = it.sys.v + 2 * ((size_t)i * nc + c) * nc;
-    for (int cp = 0; cp < nc; ++cp) {
-      const cplx<double> xv = x[(long)(cp * nr + i) * nc + cc];
-      const double vr = vrow[2 * cp], vi = vrow[2 * cp + 1];
-      sr += vr * xv.re - vi * xv.im;
-      si += vr * xv.im + vi * xv.re;
+    const int lc = it.sys.l[c];
+#pragma unroll
+    for (int u = 0; u < RB1; ++u) {
+      const int i = i0 + u;
+      if (i < nr) {
+        const double ri = it.sys.r[i];
+        const double dg = h * (double)lc * (double)(lc + 1) / (ri * ri) + it.sys.eps[c] - E;
+        const cplx<double> xi = xc[(long)i * nc];
+        rr[((long)c * nr + i) * nc + cc] = cplx<double>{sr[u] + dg * xi.re, si[u] + dg * xi.im};
+      }
     }
-    const double b = (c == cc) ? it.sys.q[i] : 0.0;
-    rr[e] = cplx<double>{b - sr, -si};
   }
   __syncthreads();
-  // column maxima: thread t scans column t, t + 256, ...
+  // pass 2: + V_i X_i, RB2 channels at one mesh point per item; R = B - sum
+  const int ncb = (nc + RB2 - 1) / RB2;
+  const long n2 = (long)nr * ncb * nc;
+  for (long e = threadIdx.x; e < n2; e += 256) {
+    const int cc = (int)(e % nc);
+    const long t = e / nc;
+    const int cb = (int)(t % ncb), i = (int)(t / ncb);
+    const int c0 = cb * RB2;
+    const double *vi_ = it.sys.v + 2 * (size_t)i * nc * nc;  // V_i[c][c']
+    double sr[RB2], si[RB2];
+#pragma unroll
+    for (int u = 0; u < RB2; ++u) {
+      const int c = min(c0 + u, nc - 1);  // channels past nc: computed, never stored
+      const cplx<double> p = rr[((long)c * nr + i) * nc + cc];
+      sr[u] = p.re;
+      si[u] = p.im;
+    }
+    for (int cp = 0; cp < nc; ++cp) {
+      const cplx<double> xv = x[((long)cp * nr + i) * nc + cc];
+#pragma unroll
+      for (int u = 0; u < RB2; ++u) {
+        const int c = min(c0 + u, nc - 1);
+        const double vr = vi_[2 * ((size_t)c * nc + cp)], vim = vi_[2 * ((size_t)c * nc + cp) + 1];
+        sr[u] += vr * xv.re - vim * xv.im;
+        si[u] += vr * xv.im + vim * xv.re;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RB2; ++u) {
+      const int c = c0 + u;
+      if (c < nc) {
+        const double b = (c == cc) ? it.sys.q[i] : 0.0;
+        const cplx<double> out{b - sr[u], -si[u]};
+        rr[((long)c * nr + i) * nc + cc] = out;
+        if (cc < kMaxCols) atomicMax(&smax[cc], (unsigned long long)__double_as_longlong(cabs1(out)));
+      }
+    }
+  }
+  __syncthreads();
+  // column maxima (1 for an exactly zero column); columns past kMaxCols scan R
   for (int cc = threadIdx.x; cc < nc; cc += 256) {
     double m = 0.0;
-    for (int row = 0; row < n; ++row) m = fmax(m, cabs1(rr[(long)row * nc + cc]));
+    if (cc < kMaxCols)
+      m = __longlong_as_double((long long)smax[cc]);
+    else
+      for (int row = 0; row < n; ++row) m = fmax(m, cabs1(rr[(long)row * nc + cc]));
     cscale[it.c_off + cc] = (m > 0.0) ? m : 1.0;
   }
 }
