@@ -447,18 +447,75 @@ __global__ __launch_bounds__(256) void batch_trail_kernel(int count, const hp_ba
 // Y (n x nc, leading dimension nc) <- U^-1 L^-1 Y in place, blocks of kBK rows:
 // the diagonal block by substitution (one thread per column), the rows
 // beyond it by a workgroup GEMM.
+// Substitution on one diagonal block [b0, b0 + bs) of an LU factor for the
+// right-hand column c of y (leading dimension nc): unit lower (forward) or
+// upper (backward, dividing by the diagonal).  D: the block in LDS at
+// stride kBK + 1, zero past bs.  Rows are taken 8 at a time in registers;
+// the rows solved before such a group (above it forward, below it backward)
+// are read back from y.  Both solve forms of the batch use this routine, so
+// their results agree bit for bit.
+template <typename T>
+__device__ __forceinline__ void diag_block_solve(const cplx<T> *D, cplx<T> *__restrict__ y, int nc, int b0, int bs,
+                                                 int c, bool upper) {
+  constexpr int RB = 8, LP = kBK + 1;
+  const cplx<T> zero{T(0), T(0)};
+  const int nb = (bs + RB - 1) / RB;
+#pragma unroll 1
+  for (int q = 0; q < nb; ++q) {
+    const int r0 = (upper ? nb - 1 - q : q) * RB;
+    cplx<T> acc[RB];
+#pragma unroll
+    for (int u = 0; u < RB; ++u) acc[u] = r0 + u < bs ? y[(long)(b0 + r0 + u) * nc + c] : zero;
+    const int k0 = upper ? r0 + RB : 0, k1 = upper ? bs : r0;
+#pragma unroll 4
+    for (int kk = k0; kk < k1; ++kk) {
+      const cplx<T> xk = y[(long)(b0 + kk) * nc + c];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) acc[u] = cfms(acc[u], D[(r0 + u) * LP + kk], xk);
+    }
+    if (!upper) {
+#pragma unroll
+      for (int u = 1; u < RB; ++u)
+#pragma unroll
+        for (int v = 0; v < u; ++v) acc[u] = cfms(acc[u], D[(r0 + u) * LP + r0 + v], acc[v]);
+    } else {
+#pragma unroll
+      for (int u = RB - 1; u >= 0; --u)
+        if (r0 + u < bs) {
+#pragma unroll
+          for (int v = u + 1; v < RB; ++v)
+            if (r0 + v < bs) acc[u] = cfms(acc[u], D[(r0 + u) * LP + r0 + v], acc[v]);
+          acc[u] = cdiv(acc[u], D[(r0 + u) * LP + r0 + u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u)
+      if (r0 + u < bs) y[(long)(b0 + r0 + u) * nc + c] = acc[u];
+  }
+}
+
+// The diagonal block [b0, b0 + bs) of lu (leading dimension n) into D
+// (stride kBK + 1, zero-padded to kBK x kBK); the caller synchronizes.
+template <typename T>
+__device__ __forceinline__ void stage_diag_block(cplx<T> *D, const cplx<T> *__restrict__ lu, int n, int b0, int bs) {
+  constexpr int B = kBK, LP = kBK + 1;
+  for (int e = threadIdx.x; e < B * B; e += blockDim.x) {
+    const int r = e / B, k = e - r * B;
+    D[r * LP + k] = (r < bs && k < bs) ? lu[(long)(b0 + r) * n + b0 + k] : cplx<T>{T(0), T(0)};
+  }
+}
+
 template <typename T>
 __device__ void wg_lu_solve(int n, int nc, const cplx<T> *__restrict__ lu, cplx<T> *__restrict__ y, cplx<T> *As,
                             cplx<T> *Bs) {
   const int tid = threadIdx.x;
+  static_assert(kBK * kBLd >= kBK * (kBK + 1), "the diagonal block fits the A tile");
   for (int b = 0; b < n; b += kBK) {
     const int bs = min(kBK, n - b);
-    for (int c = tid; c < nc; c += 256)
-      for (int i = 1; i < bs; ++i) {
-        cplx<T> sum = y[(long)(b + i) * nc + c];
-        for (int k = 0; k < i; ++k) sum = cfms(sum, lu[(long)(b + i) * n + b + k], y[(long)(b + k) * nc + c]);
-        y[(long)(b + i) * nc + c] = sum;
-      }
+    __syncthreads();  // As is free (the previous step's product is done with it)
+    stage_diag_block<T>(As, lu, n, b, bs);
+    __syncthreads();
+    for (int c = tid; c < nc; c += 256) diag_block_solve<T>(As, y, nc, b, bs, c, false);
     __syncthreads();
     if (b + bs < n)
       wg_gemm_sub<T>(n - b - bs, nc, bs, lu + (long)(b + bs) * n + b, n, y + (long)b * nc, nc,
@@ -467,12 +524,10 @@ __device__ void wg_lu_solve(int n, int nc, const cplx<T> *__restrict__ lu, cplx<
   const int nb = (n + kBK - 1) / kBK;
   for (int bi = nb - 1; bi >= 0; --bi) {
     const int b = bi * kBK, bs = min(kBK, n - b);
-    for (int c = tid; c < nc; c += 256)
-      for (int i = bs - 1; i >= 0; --i) {
-        cplx<T> sum = y[(long)(b + i) * nc + c];
-        for (int k = i + 1; k < bs; ++k) sum = cfms(sum, lu[(long)(b + i) * n + b + k], y[(long)(b + k) * nc + c]);
-        y[(long)(b + i) * nc + c] = cdiv(sum, lu[(long)(b + i) * n + b + i]);
-      }
+    __syncthreads();
+    stage_diag_block<T>(As, lu, n, b, bs);
+    __syncthreads();
+    for (int c = tid; c < nc; c += 256) diag_block_solve<T>(As, y, nc, b, bs, c, true);
     __syncthreads();
     if (b > 0)
       wg_gemm_sub<T>(b, nc, bs, lu + b, n, y + (long)b * nc, nc, y, nc, As, Bs);
@@ -790,34 +845,24 @@ __global__ void batch_solve_tiles_kernel(int count, const hp_batch_item *__restr
   ob[count] = ab;
 }
 
-// Diagonal block [b0, b0 + bs) of every system (state: skip systems not refining).
+// Diagonal block [b0, b0 + bs) of every system (state: skip systems not
+// refining): the block of LU staged in LDS, one right-hand column per thread
+// (diag_block_solve).
 template <typename T>
 __global__ __launch_bounds__(256) void batch_sdiag_kernel(const hp_batch_item *__restrict__ items,
                                                           const cplx<T> *__restrict__ LU, cplx<T> *__restrict__ Y,
                                                           int b0, int upper, const BatchState *state) {
+  __shared__ cplx<T> D[kBK * (kBK + 1)];
   const int s = blockIdx.x;
   if (state && state[s].status != 0) return;
   const hp_batch_item it = items[s];
   const int nc = it.sys.nc, n = item_n(it);
   if (b0 >= n) return;
   const int bs = min(kBK, n - b0);
-  const cplx<T> *lu = LU + it.a_off;
+  stage_diag_block<T>(D, LU + it.a_off, n, b0, bs);
+  __syncthreads();
   cplx<T> *y = Y + it.x_off;
-  for (int c = threadIdx.x; c < nc; c += 256) {
-    if (!upper) {
-      for (int i = 1; i < bs; ++i) {
-        cplx<T> sum = y[(long)(b0 + i) * nc + c];
-        for (int k = 0; k < i; ++k) sum = cfms(sum, lu[(long)(b0 + i) * n + b0 + k], y[(long)(b0 + k) * nc + c]);
-        y[(long)(b0 + i) * nc + c] = sum;
-      }
-    } else {
-      for (int i = bs - 1; i >= 0; --i) {
-        cplx<T> sum = y[(long)(b0 + i) * nc + c];
-        for (int k = i + 1; k < bs; ++k) sum = cfms(sum, lu[(long)(b0 + i) * n + b0 + k], y[(long)(b0 + k) * nc + c]);
-        y[(long)(b0 + i) * nc + c] = cdiv(sum, lu[(long)(b0 + i) * n + b0 + i]);
-      }
-    }
-  }
+  for (int c = threadIdx.x; c < nc; c += 256) diag_block_solve<T>(D, y, nc, b0, bs, c, upper != 0);
 }
 
 // Update tiles of a solve step: forward Y[b0+bs:n] -= L[b0+bs:n, b0:b0+bs] Y[b0:b0+bs],
