@@ -259,12 +259,70 @@ __global__ __launch_bounds__(256) void batch_build_kernel(int count, const hp_ba
 //   block row: U12 = L11^-1 A12 (one thread per column);
 //   trailing update A22 -= L21 U12 (MFMA tiles).
 
+// Substitution on one diagonal block [b0, b0 + bs) of an LU factor for the
+// right-hand column c of y (leading dimension nc): unit lower (forward) or
+// upper (backward, dividing by the diagonal).  D: the block in LDS at
+// stride kBK + 1, zero past bs.  Rows are taken 8 at a time in registers;
+// the rows solved before such a group (above it forward, below it backward)
+// are read back from y.  Both solve forms of the batch use this routine, so
+// their results agree bit for bit.
+template <typename T>
+__device__ __forceinline__ void diag_block_solve(const cplx<T> *D, cplx<T> *__restrict__ y, int nc, int b0, int bs,
+                                                 int c, bool upper) {
+  constexpr int RB = 8, LP = kBK + 1;
+  const cplx<T> zero{T(0), T(0)};
+  const int nb = (bs + RB - 1) / RB;
+#pragma unroll 1
+  for (int q = 0; q < nb; ++q) {
+    const int r0 = (upper ? nb - 1 - q : q) * RB;
+    cplx<T> acc[RB];
+#pragma unroll
+    for (int u = 0; u < RB; ++u) acc[u] = r0 + u < bs ? y[(long)(b0 + r0 + u) * nc + c] : zero;
+    const int k0 = upper ? r0 + RB : 0, k1 = upper ? bs : r0;
+#pragma unroll 4
+    for (int kk = k0; kk < k1; ++kk) {
+      const cplx<T> xk = y[(long)(b0 + kk) * nc + c];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) acc[u] = cfms(acc[u], D[(r0 + u) * LP + kk], xk);
+    }
+    if (!upper) {
+#pragma unroll
+      for (int u = 1; u < RB; ++u)
+#pragma unroll
+        for (int v = 0; v < u; ++v) acc[u] = cfms(acc[u], D[(r0 + u) * LP + r0 + v], acc[v]);
+    } else {
+#pragma unroll
+      for (int u = RB - 1; u >= 0; --u)
+        if (r0 + u < bs) {
+#pragma unroll
+          for (int v = u + 1; v < RB; ++v)
+            if (r0 + v < bs) acc[u] = cfms(acc[u], D[(r0 + u) * LP + r0 + v], acc[v]);
+          acc[u] = cdiv(acc[u], D[(r0 + u) * LP + r0 + u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u)
+      if (r0 + u < bs) y[(long)(b0 + r0 + u) * nc + c] = acc[u];
+  }
+}
+
+// The diagonal block [b0, b0 + bs) of lu (leading dimension n) into D
+// (stride kBK + 1, zero-padded to kBK x kBK); the caller synchronizes.
+template <typename T>
+__device__ __forceinline__ void stage_diag_block(cplx<T> *D, const cplx<T> *__restrict__ lu, int n, int b0, int bs) {
+  constexpr int B = kBK, LP = kBK + 1;
+  for (int e = threadIdx.x; e < B * B; e += blockDim.x) {
+    const int r = e / B, k = e - r * B;
+    D[r * LP + k] = (r < bs && k < bs) ? lu[(long)(b0 + r) * n + b0 + k] : cplx<T>{T(0), T(0)};
+  }
+}
+
 // Column steps and block row of the panel [j0, j0 + w) of one n x n system,
 // by one workgroup.  Records the pivots, and the first exactly zero pivot
 // column (1-based) in *first_zero if it is still 0.
 template <typename T>
 __device__ void panel_steps(cplx<T> *a, int n, int j0, int w, int *piv, int *first_zero, cplx<T> *urow, T *sv,
-                            int *sr) {
+                            int *sr, cplx<T> *D) {
   const int tid = threadIdx.x;
   for (int jj = 0; jj < w; ++jj) {
     const int j = j0 + jj;
@@ -304,14 +362,12 @@ __device__ void panel_steps(cplx<T> *a, int n, int j0, int w, int *piv, int *fir
     }
     __syncthreads();
   }
-  // U12 = L11^-1 A12
-  for (int c = j0 + w + tid; c < n; c += 256) {
-    for (int i = 1; i < w; ++i) {
-      cplx<T> sum = a[(long)(j0 + i) * n + c];
-      for (int k = 0; k < i; ++k) sum = cfms(sum, a[(long)(j0 + i) * n + j0 + k], a[(long)(j0 + k) * n + c]);
-      a[(long)(j0 + i) * n + c] = sum;
-    }
-  }
+  // U12 = L11^-1 A12: L11 staged in LDS (D: kBK x (kBK + 1)), each column
+  // of A12 by diag_block_solve (the terms in the same order as a plain
+  // substitution)
+  stage_diag_block<T>(D, a, n, j0, w);
+  __syncthreads();
+  for (int c = j0 + w + tid; c < n; c += 256) diag_block_solve<T>(D, a + (long)j0 * n, n, 0, w, c, false);
   __syncthreads();
 }
 
@@ -352,7 +408,7 @@ __global__ __launch_bounds__(256) void batch_lu_kernel(int count, const hp_batch
     __syncthreads();
     for (int j0 = 0; j0 < n; j0 += W) {
       const int w = min(W, n - j0);
-      panel_steps<T>(a, n, j0, w, piv, &s_zero, urow, sv, sr);
+      panel_steps<T>(a, n, j0, w, piv, &s_zero, urow, sv, sr, As);  // As is free until the product
       const int rest = n - j0 - w;
       if (rest > 0)
         wg_gemm_sub<T>(rest, rest, w, a + (long)(j0 + w) * n + j0, n, a + (long)j0 * n + j0 + w, n,
@@ -376,6 +432,7 @@ __global__ __launch_bounds__(256) void batch_panel_kernel(const hp_batch_item *_
                                                           int *__restrict__ perm, int *__restrict__ info, int j0,
                                                           int W) {
   __shared__ cplx<T> urow[kBK];
+  __shared__ cplx<T> D[kBK * (kBK + 1)];
   __shared__ T sv[4];
   __shared__ int sr[4];
   __shared__ int s_zero;
@@ -387,7 +444,7 @@ __global__ __launch_bounds__(256) void batch_panel_kernel(const hp_batch_item *_
   int *piv = ipiv + it.p_off;
   if (threadIdx.x == 0) s_zero = info[s];
   __syncthreads();
-  panel_steps<T>(A + it.a_off, n, j0, w, piv, &s_zero, urow, sv, sr);
+  panel_steps<T>(A + it.a_off, n, j0, w, piv, &s_zero, urow, sv, sr, D);
   if (threadIdx.x == 0) {
     info[s] = s_zero;
     if (j0 + w == n) compose_perm(piv, perm + it.p_off, n);
@@ -447,64 +504,6 @@ __global__ __launch_bounds__(256) void batch_trail_kernel(int count, const hp_ba
 // Y (n x nc, leading dimension nc) <- U^-1 L^-1 Y in place, blocks of kBK rows:
 // the diagonal block by substitution (one thread per column), the rows
 // beyond it by a workgroup GEMM.
-// Substitution on one diagonal block [b0, b0 + bs) of an LU factor for the
-// right-hand column c of y (leading dimension nc): unit lower (forward) or
-// upper (backward, dividing by the diagonal).  D: the block in LDS at
-// stride kBK + 1, zero past bs.  Rows are taken 8 at a time in registers;
-// the rows solved before such a group (above it forward, below it backward)
-// are read back from y.  Both solve forms of the batch use this routine, so
-// their results agree bit for bit.
-template <typename T>
-__device__ __forceinline__ void diag_block_solve(const cplx<T> *D, cplx<T> *__restrict__ y, int nc, int b0, int bs,
-                                                 int c, bool upper) {
-  constexpr int RB = 8, LP = kBK + 1;
-  const cplx<T> zero{T(0), T(0)};
-  const int nb = (bs + RB - 1) / RB;
-#pragma unroll 1
-  for (int q = 0; q < nb; ++q) {
-    const int r0 = (upper ? nb - 1 - q : q) * RB;
-    cplx<T> acc[RB];
-#pragma unroll
-    for (int u = 0; u < RB; ++u) acc[u] = r0 + u < bs ? y[(long)(b0 + r0 + u) * nc + c] : zero;
-    const int k0 = upper ? r0 + RB : 0, k1 = upper ? bs : r0;
-#pragma unroll 4
-    for (int kk = k0; kk < k1; ++kk) {
-      const cplx<T> xk = y[(long)(b0 + kk) * nc + c];
-#pragma unroll
-      for (int u = 0; u < RB; ++u) acc[u] = cfms(acc[u], D[(r0 + u) * LP + kk], xk);
-    }
-    if (!upper) {
-#pragma unroll
-      for (int u = 1; u < RB; ++u)
-#pragma unroll
-        for (int v = 0; v < u; ++v) acc[u] = cfms(acc[u], D[(r0 + u) * LP + r0 + v], acc[v]);
-    } else {
-#pragma unroll
-      for (int u = RB - 1; u >= 0; --u)
-        if (r0 + u < bs) {
-#pragma unroll
-          for (int v = u + 1; v < RB; ++v)
-            if (r0 + v < bs) acc[u] = cfms(acc[u], D[(r0 + u) * LP + r0 + v], acc[v]);
-          acc[u] = cdiv(acc[u], D[(r0 + u) * LP + r0 + u]);
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < RB; ++u)
-      if (r0 + u < bs) y[(long)(b0 + r0 + u) * nc + c] = acc[u];
-  }
-}
-
-// The diagonal block [b0, b0 + bs) of lu (leading dimension n) into D
-// (stride kBK + 1, zero-padded to kBK x kBK); the caller synchronizes.
-template <typename T>
-__device__ __forceinline__ void stage_diag_block(cplx<T> *D, const cplx<T> *__restrict__ lu, int n, int b0, int bs) {
-  constexpr int B = kBK, LP = kBK + 1;
-  for (int e = threadIdx.x; e < B * B; e += blockDim.x) {
-    const int r = e / B, k = e - r * B;
-    D[r * LP + k] = (r < bs && k < bs) ? lu[(long)(b0 + r) * n + b0 + k] : cplx<T>{T(0), T(0)};
-  }
-}
-
 template <typename T>
 __device__ void wg_lu_solve(int n, int nc, const cplx<T> *__restrict__ lu, cplx<T> *__restrict__ y, cplx<T> *As,
                             cplx<T> *Bs) {
