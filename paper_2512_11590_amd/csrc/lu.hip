@@ -534,17 +534,39 @@ __global__ __launch_bounds__(256) void row_permute_kernel(cplx<T> *__restrict__ 
   constexpr int CW = PermCfg<T>::CW;
   extern __shared__ __align__(16) char smem_raw[];
   cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);  // [nmove][CW]
-  const int nmove = plan[0];
+  __shared__ int psrc[kPlanMax], pdst[kPlanMax];
+  const int nmove = min(plan[0], kPlanMax);
   const int n1 = c1 - c0;
   const int ntot = n1 + (c3 - c2);
   const int cbase = blockIdx.x * CW;
   const int tid = threadIdx.x;
-  for (int e = tid; e < nmove * CW; e += 256) {
-    const int m = e / CW, cc = e - m * CW;
-    const int t = cbase + cc;
-    if (t < ntot) {
-      const int col = (t < n1) ? c0 + t : c2 + (t - n1);
-      buf[e] = A[(long)plan[1 + kPlanMax + m] * lda + col];
+  for (int m = tid; m < nmove; m += 256) {
+    psrc[m] = plan[1 + kPlanMax + m];
+    pdst[m] = plan[1 + m];
+  }
+  __syncthreads();
+  // every source element into LDS before any destination is written (FP32:
+  // eight loads per thread in flight; an FP64 batch would go to scratch)
+  if constexpr (sizeof(T) == 4) {
+    for (int e0 = 0; e0 < nmove * CW; e0 += 8 * 256) {
+      cplx<T> v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + tid;
+        const int m = e / CW, cc = e - m * CW, t = cbase + cc;
+        if (e < nmove * CW && t < ntot) v[u] = A[(long)psrc[m] * lda + ((t < n1) ? c0 + t : c2 + (t - n1))];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + tid;
+        const int m = e / CW, cc = e - m * CW, t = cbase + cc;
+        if (e < nmove * CW && t < ntot) buf[e] = v[u];
+      }
+    }
+  } else {
+    for (int e = tid; e < nmove * CW; e += 256) {
+      const int m = e / CW, cc = e - m * CW, t = cbase + cc;
+      if (t < ntot) buf[e] = A[(long)psrc[m] * lda + ((t < n1) ? c0 + t : c2 + (t - n1))];
     }
   }
   __syncthreads();
@@ -553,7 +575,7 @@ __global__ __launch_bounds__(256) void row_permute_kernel(cplx<T> *__restrict__ 
     const int t = cbase + cc;
     if (t < ntot) {
       const int col = (t < n1) ? c0 + t : c2 + (t - n1);
-      A[(long)plan[1 + m] * lda + col] = buf[e];
+      A[(long)pdst[m] * lda + col] = buf[e];
     }
   }
 }
