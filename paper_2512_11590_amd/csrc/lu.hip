@@ -445,9 +445,9 @@ constexpr int kPlanMax = 2 * kOuterBlock;
 __global__ __launch_bounds__(256) void swap_plan_kernel(const int *__restrict__ ipiv, int k0, int kb, int n,
                                                         int *__restrict__ plan, int *__restrict__ perm,
                                                         int *__restrict__ info) {
-  __shared__ int pp[kOuterBlock], firstj[kOuterBlock], isfirst[kOuterBlock], cidx[kOuterBlock];
+  __shared__ int pp[kOuterBlock], firstj[kOuterBlock], bsl[kOuterBlock], cidx[kOuterBlock];
   __shared__ int pos[kPlanMax], val[kPlanMax];
-  __shared__ int nout, nmove;
+  __shared__ int nout, nmove, wcnt[4];
   __shared__ int pv[kPlanMax], pd[kPlanMax];
   const int tid = threadIdx.x;
   if (tid < kb) {
@@ -459,45 +459,50 @@ __global__ __launch_bounds__(256) void swap_plan_kernel(const int *__restrict__ 
     pp[tid] = p;
   }
   __syncthreads();
+  // first interchange that brings each outside pivot row in
+  int isf = 0;
   if (tid < kb) {
     const int p = pp[tid];
     int f = tid;
     if (p >= k0 + kb)
       for (int j = 0; j < tid; ++j)
-        if (pp[j] == p) {
-          f = j;
-          break;
-        }
+        if (pp[j] == p && f == tid) f = j;
     firstj[tid] = f;
-    isfirst[tid] = (p >= k0 + kb && f == tid) ? 1 : 0;
+    isf = (p >= k0 + kb && f == tid) ? 1 : 0;
   }
+  // slot numbers of the outside rows: exclusive prefix count of the first
+  // appearances, from the wavefront ballots
+  const int lane = tid & 63, wave = tid >> 6;
+  const unsigned long long firsts = __ballot(isf);
+  if (lane == 0) wcnt[wave] = __popcll(firsts);
   __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wave; ++w) before += wcnt[w];
+  cidx[tid] = before + __popcll(firsts & ((1ull << lane) - 1));
   if (tid == 0) {
-    int c = 0;
-    for (int j = 0; j < kb; ++j) {
-      cidx[j] = c;
-      c += isfirst[j];
-    }
-    nout = c;
+    nout = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
     nmove = 0;
   }
   __syncthreads();
+  // the slot of each interchange's pivot row, and the row of each slot
   if (tid < kb) {
+    const int p = pp[tid];
+    bsl[tid] = (p < k0 + kb) ? (p - k0) : (kb + cidx[firstj[tid]]);
     pos[tid] = k0 + tid;
-    val[tid] = k0 + tid;
-    if (isfirst[tid]) {
-      pos[kb + cidx[tid]] = pp[tid];
-      val[kb + cidx[tid]] = pp[tid];
-    }
+    if (isf) pos[kb + cidx[tid]] = p;
   }
   __syncthreads();
-  if (tid == 0) {
-    for (int j = 0; j < kb; ++j) {
-      const int p = pp[j];
-      const int b = (p < k0 + kb) ? (p - k0) : (kb + cidx[firstj[j]]);
-      const int t = val[j];
-      val[j] = val[b];
-      val[b] = t;
+  // the row whose content ends in each slot: the slot traced back through
+  // the interchanges, last to first (one slot per thread, no serial replay)
+  {
+    const int ns = kb + nout;
+    for (int sl = tid; sl < ns; sl += 256) {
+      int q = sl;
+      for (int j = kb - 1; j >= 0; --j) {
+        const int bj = bsl[j];
+        q = (q == j) ? bj : (q == bj ? j : q);
+      }
+      val[sl] = pos[q];
     }
   }
   __syncthreads();
