@@ -129,10 +129,12 @@ int hp_factor(int n, int prec, void *A, long lda, int *ipiv, int *perm, int *inf
  * forward error: refinement stops converged when it is <= tol (tol <= 0:
  * 2^-29 = u64/u32: the error left after such a correction, about kappa u32
  * times it, is below the FP64 floor kappa u64) or when it stops shrinking (a
- * correction larger than half the previous one) while already <= 1e-6, and
- * reports non-convergence when it
- * stops shrinking above that (Sec. 6: the single-precision factor is then too
- * inaccurate to contract) or after max_refine corrections.  info (host, may
+ * correction larger than half the previous one) with that correction itself
+ * <= max(tol, 2^-26), and reports non-convergence (HP_ERR_NOCONV) when it
+ * stops shrinking above that (Performance Results, Accuracy Validation,
+ * Fig. illcond: the single-precision factor is then too inaccurate to
+ * contract; the caller then solves in FP64, the paper's fallback mechanism)
+ * or after max_refine corrections.  info (host, may
  * be NULL) receives the outcome, including the normwise backward error.
  * Synchronizes the stream once per refinement pass.  With FP32 factors the
  * call first multiplies every block column of L below the diagonal by the
@@ -252,8 +254,9 @@ int hp_batch_solve_init(int count, const hp_batch_item *items, const int *shape_
  * (Sec. 3.2): r = B - C X from the block structure, d from the factors
  * (column-scaled; solves as chosen by shape_host), X += d, and the stop rule
  * of hp_solve per system (relative correction <= tol, tol <= 0: 2^-29; a
- * correction larger than half the previous one: converged if the previous
- * was <= 1e-6, else not converged; not converged after max_refine steps).  A
+ * correction larger than half the previous one: converged if it is itself
+ * <= max(tol, 2^-26), else not converged; not converged after max_refine
+ * steps).  A
  * fixed sequence of launches, no host synchronisation: it may be captured
  * in a graph and replayed. */
 int hp_batch_refine_step(int count, const hp_batch_item *items, const int *shape_host, const void *LU,
@@ -279,12 +282,13 @@ int hp_batch_rmatrix(int count, const hp_batch_item *items, const double *X, dou
  * workgroups wait for each other at every column, so they must be resident
  * together.  With 1, each factorization runs on its caller's stream (plus the
  * look-ahead stream) with panel workgroups of up to ~150 KB of LDS.  With
- * k > 1, factorizations are serialized on one device-wide stream (the
+ * k > 1, factorizations of n > 256 are serialized on one device-wide stream (the
  * caller's stream hands over and waits by events; its other work still
- * overlaps with other streams), and panel workgroups hold at most 64 KB of
- * rows so that they find room beside other streams' kernels: then a panel
- * of more than 128 x 64 KB of rows (n > 32768 in FP32, n > 16384 in FP64)
- * fails with HP_ERR_UNSUPPORTED.  Returns the previous setting, or HP_ERR_ARG
+ * overlaps with other streams), and panel workgroups hold 64 KB of rows, or
+ * the ceil(n / 128) rows that a grid of 128 workgroups needs when that is
+ * more, so that they find room beside other streams' kernels (the same
+ * limit as with 1 applies: about 150 KB of rows per workgroup, beyond which
+ * hp_factor fails with HP_ERR_UNSUPPORTED).  Returns the previous setting, or HP_ERR_ARG
  * if k is outside [1, 256].  Host-side setting; takes effect for
  * factorizations enqueued afterwards. */
 int hp_set_concurrency(int k);

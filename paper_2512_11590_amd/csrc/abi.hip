@@ -136,6 +136,6 @@ extern "C" const char *hp_strerror(int code) {
 extern "C" const char *hp_last_error(void) { return g_last_error; }
 
 extern "C" const char *hp_build_info(void) {
-  return "hprmat gfx950: blocked right-looking complex LU (cooperative panel, MFMA 4M trailing update), "
-         "FP64/FP32 factors, device FP64 refinement";
+  return "hprmat gfx950: blocked right-looking complex LU (co-resident panel grid, MFMA trailing update: "
+         "4M in FP64, 3M in FP32), FP64/FP32 factors, device FP64 refinement";
 }

@@ -734,7 +734,7 @@ __global__ __launch_bounds__(256) void batch_update_kernel(int count, const hp_b
     if (corr <= corr_tol) {
       st.status = 1;
     } else if (st.iters > 1 && corr > 0.5 * st.corr_prev) {
-      st.status = (st.corr_prev <= 1e-6) ? 1 : 2;
+      st.status = (corr <= fmax(corr_tol, kStallTol)) ? 1 : 2;
     } else if (st.iters >= max_refine) {
       st.status = 2;
     }

@@ -83,6 +83,15 @@ constexpr int kInvBlock = 128;      // rows of an inverted diagonal block of an 
 // backward-stable FP64 solve.  Further steps only move the iterate within
 // that floor.
 constexpr double kRefineTol = 0x1p-29;
+// A correction that stops shrinking (more than half the previous one) means
+// the iterate sits at the accuracy an FP64 residual resolves.  That floor is
+// about kappa u64, and refinement of FP32 factors contracts only while
+// kappa u32 < 1, i.e. while kappa u64 < u64 / u32 = 2^-29.  A stall is
+// therefore accepted as converged only if the stalled correction itself is
+// within a factor 8 of that bound; a stall above it means the factor does not
+// contract (the ill-conditioned case of the paper's Fig. illcond) and is
+// reported as non-convergence, which sends the caller to the FP64 solve.
+constexpr double kStallTol = 0x1p-26;
 constexpr int kMaxPanelGroups = 128;  // workgroups of one cooperative panel grid
 constexpr unsigned kSpinLimit = 1u << 22;  // bounded grid-barrier wait (a few seconds)
 

@@ -307,13 +307,13 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 4 : 2)) void gemm_sub_kernel
 // Rows of A past M read row M - 1 and columns of B past N read the last column
 // pair (their outputs are discarded).
 constexpr int kDirectBK = 16;
-// lds_byte_addr must be uniform over the wavefront.  The kernel that uses
-// this makes no other use of M0 (its assembly is checked for that).
+// lds_byte_addr must be uniform over the wavefront.  M0 is declared clobbered,
+// so the compiler keeps nothing of its own in M0 across the load.
 __device__ __forceinline__ void lds_direct_load16(unsigned lds_byte_addr, const void *src) {
   const unsigned m0v = __builtin_amdgcn_readfirstlane(lds_byte_addr);
   // one wait state between the M0 write and the LDS-DMA load that reads it
   asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(m0v), "v"(src)
-               : "memory");
+               : "memory", "m0");
 }
 
 template <bool SET>

@@ -1187,10 +1187,13 @@ static int panel(int n, int j0, int w, cplx<T> *A, long lda, int *ipiv, int *inf
   int cus = 0, G, rpw;
   int rc0 = device_cus(&cus);
   if (rc0) return rc0;
-  // with other streams' work on the device, small workgroups (<= 64 KB of
-  // rows) so that each finds room beside the kernels already resident
+  // with other streams' work on the device, small workgroups (64 KB of rows,
+  // or just what a grid of kMaxPanelGroups needs when that is more) so that
+  // each finds room beside the kernels already resident
   const int conc = g_concurrency.load(std::memory_order_relaxed);
-  if ((rc0 = panel_grid<T>(m, (conc > 1 ? 64 : 150) * 1024, G, rpw))) return rc0;
+  const int rows_needed = (m + kMaxPanelGroups - 1) / kMaxPanelGroups;
+  const int small_cap = std::max(64 * 1024, rows_needed * kPanelLd * (int)sizeof(cplx<T>));
+  if ((rc0 = panel_grid<T>(m, conc > 1 ? std::min(small_cap, 150 * 1024) : 150 * 1024, G, rpw))) return rc0;
   if (G > kMaxPanelGroups || G > cus) return HP_ERR_UNSUPPORTED;
   // the FP32 key word holds the row offset and the column epoch in 32 bits
   if (std::is_same<T, float>::value && (rpw >= (int)kKeyNoRow || n >= kKeyMaxColumns)) return HP_ERR_UNSUPPORTED;
@@ -1355,9 +1358,14 @@ template <typename T>
 static int lu_factor_on(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *info, char *work,
                         const Workspace &ws, hipStream_t st) {
   int rc;
+  // the look-ahead stream is needed (and created on first use) only when a
+  // block is factored beside a trailing update, i.e. for n > 2 kOuterBlock
   LookAhead *la = nullptr;
-  if ((rc = lookahead_for(st, &la))) return rc;
-  std::lock_guard<std::mutex> lk(la->mu);
+  std::unique_lock<std::mutex> lk;
+  if (n > 2 * kOuterBlock) {
+    if ((rc = lookahead_for(st, &la))) return rc;
+    lk = std::unique_lock<std::mutex>(la->mu);
+  }
   unsigned *bars = (unsigned *)(work + ws.sync_off);
   const size_t per_panel = barrier_words(kMaxPanelGroups);
   const int npanels = (n + kPanelWidth - 1) / kPanelWidth;
@@ -1388,7 +1396,7 @@ static int lu_factor_on(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *
     if ((rc = block_row_solve<T>(n, k, kb, rest, A, lda, work, ws, st))) return rc;
     // the next block's columns first
     if ((rc = gemm_sub<T>(rest, kb2, kb, L21, lda, U12, lda, A22, lda, st))) return rc;
-    if (rest > kb2) {
+    if (rest > kb2) {  // here n > 2 kOuterBlock, so la is set
       HP_CHECK_HIP(hipEventRecord(la->ready, st));
       HP_CHECK_HIP(hipStreamWaitEvent(la->panel, la->ready, 0));
       if ((rc = factor_block<T>(n, k2, kb2, A, lda, ipiv, info, bars, slots, la->panel))) return rc;
@@ -1436,7 +1444,9 @@ int factor_queue(FactorQueue **out) {
 template <typename T>
 int lu_factor(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *info, char *work, const Workspace &ws,
               hipStream_t st) {
-  if (g_concurrency.load(std::memory_order_relaxed) <= 1)
+  // a factorization of one block (n <= kOuterBlock: a panel grid of at most
+  // four workgroups) runs on the caller's stream in either mode
+  if (g_concurrency.load(std::memory_order_relaxed) <= 1 || n <= kOuterBlock)
     return lu_factor_on<T>(n, A, lda, ipiv, perm, info, work, ws, st);
   FactorQueue *fq = nullptr;
   int rc = factor_queue(&fq);

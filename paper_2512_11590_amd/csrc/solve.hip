@@ -240,10 +240,11 @@ struct SolveGraph {
 //  * converged when it is <= tol (tol <= 0: kRefineTol = 2^-29, after which
 //    the remaining error is below the FP64 floor), or when it stops shrinking
 //    (a correction larger than half the previous one: the iterate is at the
-//    accuracy an FP64 residual can resolve) while already <= 1e-6;
+//    accuracy an FP64 residual can resolve) with the stalled correction
+//    itself <= max(tol, kStallTol = 2^-26);
 //  * not converged when it stops shrinking above that level (the factors are
-//    too inaccurate for the refinement to contract, Sec. 6) or after
-//    max_refine corrections.
+//    too inaccurate for the refinement to contract: Performance Results,
+//    Accuracy Validation, Fig. illcond) or after max_refine corrections.
 // The normwise backward error max_c |r_c| / (|C| |x_c| + |b_c|) of the last
 // residual is reported alongside.
 template <typename T>
@@ -328,7 +329,7 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
     return HP_OK;
   }
   const double corr_tol = (tol > 0.0) ? tol : kRefineTol;
-  const double stagnation_ok = 1e-6;
+  const double stall_ok = std::max(corr_tol, kStallTol);
   hipLaunchKernelGGL(zero_u64_kernel, dim3(nblk(3 * nc + 2)), dim3(256), 0, st, smax, 3 * nc + 2);
   HP_CHECK_LAUNCH();
   hipLaunchKernelGGL(cnorm_kernel, dim3(nblk(n)), dim3(256), 0, st, nc, nr, sys->hbar2_2mu, E, sys->tl, sys->r,
@@ -368,7 +369,7 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
         return HP_OK;
       }
       if (corr > 0.5 * corr_prev) {  // stopped shrinking
-        if (corr_prev <= stagnation_ok) {
+        if (corr <= stall_ok) {
           if (info) info->converged = 1;
           return HP_OK;
         }

@@ -1,5 +1,5 @@
 // Per-stage device timers (the paper profiles its GPU solve with per-stage
-// device timers, Sec. 6 "GPU Kernel Profiling", Table profile).
+// device timers, Sec. 5.4 "GPU Kernel Profiling", Table profile).
 //
 // When tracing is on, every launch site brackets its kernel with a pair of
 // HIP events on the launch stream and records the algorithmic flops and

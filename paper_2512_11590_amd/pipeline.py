@@ -10,8 +10,8 @@ runs the entry points in order:
     hp_build_matrix -> hp_factor -> hp_solve -> hp_rmatrix -> hp_smatrix
 
 In FP32 mode a refinement that does not converge (or a zero FP32 pivot) is
-followed by the FP64 path on the same system (the paper's fallback, Sec. 5.3),
-and the result says so.  All arithmetic runs in the HIP library.
+followed by the FP64 path on the same system (the paper's fallback mechanism,
+Sec. 5.5, Accuracy Validation), and the result says so.  All arithmetic runs in the HIP library.
 """
 from __future__ import annotations
 

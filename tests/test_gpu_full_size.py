@@ -5,7 +5,7 @@ tests/golden/make_golden.py, which calls only oracle/ and workload/.
 
 Tolerances (normwise relative):
   * S: 1e-10 after refinement (FP32 LU + FP64 refinement, and FP64 LU);
-  * R: max(1e-10, 10 x the FP64 floor).  These systems are ill-conditioned
+  * R: max(1e-10, 3 x the FP64 floor).  These systems are ill-conditioned
     (R-matrix poles crowd the real axis), so FP64 arithmetic itself fixes R
     only to a measured floor: the oracle's own result for the same system with
     its channels numbered in reverse order differs from the first by
@@ -85,12 +85,13 @@ def test_full_size_against_oracle(mods, config, prec):
         er, es = relerr(R, g[f"R_{e}"]), relerr(S, g[f"S_{e}"])
         rfloor = float(g[f"Rfloor_{e}"]) if f"Rfloor_{e}" in g.files else float("nan")
         sfloor = float(g[f"Sfloor_{e}"]) if f"Sfloor_{e}" in g.files else float("nan")
-        tol_r = max(1e-10, 10 * rfloor) if rfloor == rfloor else 1e-10
+        tol_r = max(1e-10, 3 * rfloor) if rfloor == rfloor else 1e-10
         print(f"   R err {er:.2e} (FP64 floor {rfloor:.1e}, tol {tol_r:.1e})  S err {es:.2e} "
               f"(floor {sfloor:.1e})  refinement {res.iterations} backward error {res.backward_error:.1e} "
               f"fallback {res.fallback}", flush=True)
         assert es < 1e-10
         assert er < tol_r
+        assert not res.fallback  # an FP32 result must come from the FP32 factors
         assert np.max(np.abs(S - S.T)) < 1e-9
         if contracting:
             assert np.linalg.norm(S, 2) <= 1.0 + 1e-9

@@ -132,6 +132,16 @@ def test_lu_fp32_backward_error(H, n):
     bound = nu / (1 - nu) * (np.abs(L) @ np.abs(U))
     assert np.all(np.abs(L @ U - A32[p]) <= bound)
     assert relerr(L @ U, A[p]) < 1e-4
+    # partial pivoting (largest |Re| + |Im| in the column, reading of Sec. 3.1):
+    # l_ij u_jj is the entry of column j at step j before the division, so
+    # no entry below the pivot may exceed the pivot in |Re| + |Im| (the
+    # product recovers that entry to a few FP32 roundings)
+    def cabs1(z):
+        return np.abs(z.real) + np.abs(z.imag)
+    d = np.diag(U)
+    below = np.tril(cabs1(np.tril(LU, -1) * d[None, :]), -1)
+    assert np.all(below <= cabs1(d)[None, :] * (1 + 1e-5))
+    assert np.max(np.abs(np.tril(LU, -1))) <= np.sqrt(2.0) * (1 + 1e-6)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -211,6 +221,7 @@ def compare_energy(P, H, sp, idx, prec, tol_r, tol_s, dsys=None, solver=None):
         es = relerr(res.S.cpu().numpy(), o["S"])
         print(f"   R err {er:.2e}  S err {es:.2e}  it {res.iterations} fb {res.fallback}", flush=True)
         assert er < tol_r and es < tol_s
+        assert not res.fallback  # an FP32 result must come from the FP32 factors
         assert res.nopen == sp.nc
     return d, s
 
