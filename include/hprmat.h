@@ -177,6 +177,23 @@ int hp_rmatrix(const hp_system *sys, const double *X, double *R, void *stream);
 int hp_smatrix(const hp_system *sys, double E, const double *R, double *S, int *nopen,
                void *work, size_t work_bytes, void *stream);
 
+/* hp_smatrix for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation with the same kernels and the same result, but its
+ * workspace is a fixed 4 MiB array of device memory inside the library (one
+ * copy per GPU, looked up once per device on first use and held until the
+ * process ends) instead of a caller's buffer.  At most 256 channels
+ * (HP_ERR_UNSUPPORTED beyond).  The call allocates nothing (no hipMalloc,
+ * no stream or event creation; with hp_trace enabled the timers still
+ * create their events).  Every call on one GPU uses that GPU's array, and
+ * everything in it that must start cleared is cleared by the call itself:
+ * calls that overlap on one GPU (from several host threads or streams) race
+ * for the array and must be serialized by the caller.  Synchronizes the
+ * stream, like hp_smatrix.  Errors: as hp_smatrix, plus HP_ERR_UNSUPPORTED
+ * for nc > 256. */
+int hp_smatrix_noalloc(const hp_system *sys, double E, const double *R, double *S, int *nopen,
+                       void *stream);
+
 /* ---- helpers ------------------------------------------------------------ */
 
 /* Coulomb functions F_l, F_l', G_l, G_l' (d/drho) at (eta, rho), computed on

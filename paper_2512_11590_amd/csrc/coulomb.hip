@@ -27,6 +27,7 @@
 #include "common.h"
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 namespace hp {
@@ -230,15 +231,13 @@ extern "C" int hp_coulomb_device(int nch, const int *l, const double *eta, const
   return HP_OK;
 }
 
-extern "C" int hp_smatrix(const hp_system *sys, double E, const double *R, double *S, int *nopen, void *work,
-                          size_t work_bytes, void *stream) {
-  if (!sys || sys->nc < 1 || !(sys->a > 0) || !(sys->hbar2_2mu > 0) || !sys->l || !sys->eps || !R || !S || !work)
-    return HP_ERR_ARG;
+namespace hp {
+
+// The collision matrix from R (see hp_smatrix), on workspace w laid out by ws;
+// hstat: host array of nc ints.
+static int smatrix_impl(const hp_system *sys, double E, const double *R, double *S, int *nopen, char *w,
+                        const Workspace &ws, int *hstat, hipStream_t st) {
   const int nc = sys->nc;
-  Workspace ws = plan_workspace(nc, nc, HP_C128);
-  if (work_bytes < ws.total) return HP_ERR_WORKSPACE;
-  hipStream_t st = (hipStream_t)stream;
-  char *w = (char *)work;
   cplx<double> *ZO = (cplx<double> *)(w + ws.aux_off);
   cplx<double> *tmp = (cplx<double> *)(w + ws.rhs_off);
   double *fg = (double *)(w + ws.red_off);
@@ -259,9 +258,8 @@ extern "C" int hp_smatrix(const hp_system *sys, double E, const double *R, doubl
   if ((rc = lu_factor<double>(nc, ZO, nc, ipiv, perm, finfo, w, ws, st))) return rc;
   if ((rc = lu_solve<double>(nc, nc, ZO, nc, perm, (cplx<double> *)S, nc, tmp, nullptr, st))) return rc;
   int hinfo = 0;
-  std::vector<int> hstat(nc);
   HP_CHECK_HIP(hipMemcpyAsync(&hinfo, finfo, sizeof(int), hipMemcpyDeviceToHost, st));
-  HP_CHECK_HIP(hipMemcpyAsync(hstat.data(), stat, sizeof(int) * nc, hipMemcpyDeviceToHost, st));
+  HP_CHECK_HIP(hipMemcpyAsync(hstat, stat, sizeof(int) * nc, hipMemcpyDeviceToHost, st));
   HP_CHECK_HIP(hipStreamSynchronize(st));
   int open = 0, bad = 0;
   for (int c = 0; c < nc; ++c) {
@@ -275,3 +273,63 @@ extern "C" int hp_smatrix(const hp_system *sys, double E, const double *R, doubl
   if (hinfo > 0) return HP_ERR_SINGULAR;
   return HP_OK;
 }
+
+// Scratch of hp_smatrix_noalloc: file-scope device memory, one copy per GPU,
+// held until the process ends.  In host code the array's name is not a
+// device address: kernels get the address hipGetSymbolAddress returns for
+// the current device, looked up once per device.
+constexpr int kSmatNoallocMaxChannels = 256;
+constexpr size_t kSmatScratchBytes = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kSmatScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[kMaxDevices] = {};
+}  // namespace
+
+static int scratch_for_device(char **out) {
+  int dev = 0;
+  HP_CHECK_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return HP_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    HP_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return HP_ERR_HIP;
+    g_scratch[dev] = (char *)p;
+  }
+  *out = g_scratch[dev];
+  return HP_OK;
+}
+
+static bool smatrix_args_ok(const hp_system *sys, const double *R, const double *S) {
+  return sys && sys->nc >= 1 && sys->a > 0 && sys->hbar2_2mu > 0 && sys->l && sys->eps && R && S;
+}
+
+}  // namespace hp
+
+extern "C" int hp_smatrix(const hp_system *sys, double E, const double *R, double *S, int *nopen, void *work,
+                          size_t work_bytes, void *stream) {
+  if (!smatrix_args_ok(sys, R, S) || !work) return HP_ERR_ARG;
+  const int nc = sys->nc;
+  Workspace ws = plan_workspace(nc, nc, HP_C128);
+  if (work_bytes < ws.total) return HP_ERR_WORKSPACE;
+  std::vector<int> hstat(nc);
+  return smatrix_impl(sys, E, R, S, nopen, (char *)work, ws, hstat.data(), (hipStream_t)stream);
+}
+
+extern "C" int hp_smatrix_noalloc(const hp_system *sys, double E, const double *R, double *S, int *nopen,
+                                  void *stream) {
+  if (!smatrix_args_ok(sys, R, S)) return HP_ERR_ARG;
+  const int nc = sys->nc;
+  if (nc > kSmatNoallocMaxChannels) return HP_ERR_UNSUPPORTED;
+  Workspace ws = plan_workspace(nc, nc, HP_C128);
+  if (ws.total > kSmatScratchBytes) return HP_ERR_UNSUPPORTED;
+  char *w = nullptr;
+  int rc = scratch_for_device(&w);
+  if (rc) return rc;
+  int hstat[kSmatNoallocMaxChannels];
+  return smatrix_impl(sys, E, R, S, nopen, w, ws, hstat, (hipStream_t)stream);
+}
+

@@ -57,7 +57,7 @@ class HpSolveInfo(ctypes.Structure):
 
 
 EXPORTS = ["hp_mesh", "hp_workspace_bytes", "hp_build_matrix", "hp_factor", "hp_solve",
-           "hp_lu_solve", "hp_rmatrix", "hp_smatrix", "hp_coulomb", "hp_coulomb_device",
+           "hp_lu_solve", "hp_rmatrix", "hp_smatrix", "hp_smatrix_noalloc", "hp_coulomb", "hp_coulomb_device",
            "hp_build_info", "hp_strerror", "hp_trace_enable", "hp_trace_read", "hp_last_error",
            "hp_gemm_sub", "hp_set_concurrency", "hp_set_solve_graphs", "hp_batch_workspace_bytes", "hp_batch_build",
            "hp_batch_factor", "hp_batch_factor_stepped", "hp_batch_solve_init", "hp_batch_refine_step", "hp_batch_active",
@@ -110,6 +110,8 @@ def lib() -> ctypes.CDLL:
     L.hp_smatrix.argtypes = [P(HpSystem), c_double, c_void_p, c_void_p, P(c_int), c_void_p,
                              c_size_t, c_void_p]
     L.hp_smatrix.restype = c_int
+    L.hp_smatrix_noalloc.argtypes = [P(HpSystem), c_double, c_void_p, c_void_p, P(c_int), c_void_p]
+    L.hp_smatrix_noalloc.restype = c_int
     L.hp_coulomb.argtypes = [c_int, c_double, c_double, c_void_p]
     L.hp_coulomb.restype = c_int
     L.hp_coulomb_device.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
@@ -248,6 +250,13 @@ def hp_smatrix(sys: HpSystem, E: float, R, S, work, stream=None) -> int:
     _check(lib().hp_smatrix(ctypes.byref(sys), float(E), _ptr(R), _ptr(S), ctypes.byref(nopen),
                             _ptr(work), work.numel() * work.element_size(), _stream(stream)),
            "hp_smatrix")
+    return int(nopen.value)
+
+
+def hp_smatrix_noalloc(sys: HpSystem, E: float, R, S, stream=None) -> int:
+    nopen = c_int(0)
+    _check(lib().hp_smatrix_noalloc(ctypes.byref(sys), float(E), _ptr(R), _ptr(S), ctypes.byref(nopen),
+                                    _stream(stream)), "hp_smatrix_noalloc")
     return int(nopen.value)
 
 
