@@ -243,17 +243,23 @@ int hp_batch_build(int count, const hp_batch_item *items, int prec, void *A, voi
 int hp_batch_factor(int count, const hp_batch_item *items, int prec, void *A, int *ipiv, int *perm,
                     int *info, int panel, int groups, void *work, size_t work_bytes, void *stream);
 
-/* The same factorization in steps, for batches of larger systems: per panel
- * step one launch for the column steps of every system still factoring and
- * one launch of all their trailing-update tiles, so the device is filled by
- * tiles rather than by systems.  n_host: HOST array of the systems' n, which
- * must be listed largest first (HP_ERR_ARG otherwise).  work: at least 256 +
- * 4 * ceil(nmax / panel) * (count + 1) bytes (the batch workspace of
- * hp_batch_workspace_bytes is enough).  Errors: HP_ERR_ARG,
+/* The same factorization in steps, for batches of larger systems, blocked
+ * in two levels: outer blocks of `block` columns (a multiple of `panel`, at
+ * most 64), each factored as panels of `panel` (1..32) columns whose updates
+ * stay inside the block, then the block's row U12 = L11^-1 A12 and one
+ * trailing update with K = block (Sec. 3.1's blocked LU with the update
+ * deferred to the end of each outer block).  Each step is one launch over
+ * every system still factoring: the panels' column steps one workgroup per
+ * system, the block rows and the updates as tiles of all systems, so the
+ * device is filled by tiles rather than by systems.  block == panel is the
+ * one-level form.  n_host: HOST array of the systems' n, which must be
+ * listed largest first (HP_ERR_ARG otherwise).  work: at least 256 + 4 *
+ * (ceil(nmax / panel) + 2 ceil(nmax / block)) * (count + 1) bytes (the batch
+ * workspace of hp_batch_workspace_bytes is enough).  Errors: HP_ERR_ARG,
  * HP_ERR_WORKSPACE, HP_ERR_HIP. */
 int hp_batch_factor_stepped(int count, const hp_batch_item *items, const int *n_host, int prec, void *A,
-                            int *ipiv, int *perm, int *info, int panel, void *work, size_t work_bytes,
-                            void *stream);
+                            int *ipiv, int *perm, int *info, int panel, int block, void *work,
+                            size_t work_bytes, void *stream);
 
 /* Solves every system for its nc surface right-hand sides with the factors:
  * X (FP64, per system at x_off) = C^-1 B.  With refine != 0 (FP32 factors
@@ -288,6 +294,20 @@ int hp_batch_active(const void *work, unsigned *active, void *stream);
  * refinement), 2 not converged, 3 zero pivot, 0 still refining; iters =
  * corrections applied (may be NULL).  Synchronizes the stream. */
 int hp_batch_status(int count, const void *work, int *status, int *iters, void *stream);
+
+/* Collision matrix of every system from its R (R and S: device, nc x nc
+ * complex128 blocks at r_off), by the matching of hp_smatrix, one workgroup
+ * per system: channel functions, Z = [O - Rt O' | I - Rt I'], Gaussian
+ * elimination with partial pivoting (largest |Re| + |Im|) and back
+ * substitution, all in FP64.  status: device int[count], per system 0 ok,
+ * 1 a closed channel (E <= eps_c), 2 a Coulomb continued fraction did not
+ * converge, 3 an exactly zero pivot, 4 more than 512 channels; S of a system
+ * with status != 0 is not written.  sum_nc2 = sum of nc^2 over the systems
+ * (host), nc_max = the largest nc (host, at most 512, else
+ * HP_ERR_UNSUPPORTED).  work: device, at least 32 * sum_nc2 bytes.
+ * Asynchronous, no host synchronisation (may be captured in a graph). */
+int hp_batch_smatrix(int count, const hp_batch_item *items, const double *R, double *S, int *status,
+                     long sum_nc2, int nc_max, void *work, size_t work_bytes, void *stream);
 
 /* R of every system (Sec. 3.1 step 4), FP64 complex at r_off of R. */
 int hp_batch_rmatrix(int count, const hp_batch_item *items, const double *X, double *R, void *stream);

@@ -2,21 +2,26 @@
 
 Many independent systems (one per (J^pi, energy) label, N = nc*nr from a
 few hundred to a few thousand) are laid out in shared device buffers and
-solved by the batched entry points of the C ABI, one workgroup per system:
+solved by the batched entry points of the C ABI:
 
-    hp_batch_build -> hp_batch_factor -> hp_batch_solve_init
+    hp_batch_build -> hp_batch_factor[_stepped] -> hp_batch_solve_init
         -> [hp_batch_refine_step]* (FP32 factors) -> hp_batch_rmatrix
+        -> hp_batch_smatrix
 
 Systems are split into size buckets; each bucket is one persistent
-batched-LU launch (systems largest first, one workgroup per system) or, for
-buckets of larger systems, the stepped form (per panel step one launch of
-every system's column steps and one of all their trailing-update tiles).
-The form, panel width and grid size of each bucket are picked by
-`autotune` (timed on the bucket or its largest systems, cached per bucket
-and precision).  The refinement step is captured once in a HIP graph and
-replayed until no system of the bucket is still refining.  The collision
-matrix S of each system follows from its R through hp_smatrix.  All
-arithmetic runs in the HIP library; this module lays out memory and
+batched-LU launch (systems largest first, one workgroup per system) or the
+stepped form (per step one launch over every system of the bucket: panel
+column steps, block rows, and trailing updates with K up to 64 as tiles of
+all systems).  The form, panel width, outer block and grid size of each
+bucket are picked by `autotune` (timed on the bucket or its largest systems,
+cached per bucket and precision).  After a first eager run, which also
+counts the refinement steps the bucket needs, the whole bucket -- build,
+factorization, solves, that many refinement steps, R and S -- is captured in
+one HIP graph and replayed; a bucket that needs more steps than captured
+continues eagerly.  Systems whose FP32 refinement does not converge, or
+whose FP32 factor has an exactly zero pivot, are solved again in FP64
+through the single-system path (the paper's fallback mechanism, Sec. 5.5).
+All arithmetic runs in the HIP library; this module lays out memory and
 sequences the calls.
 """
 from __future__ import annotations
@@ -33,6 +38,7 @@ E2 = 1.44  # e^2 in MeV fm
 BUCKET_EDGES = (1000, 2000)  # N boundaries of the size buckets
 PANELS = (8, 16, 32)
 GROUPS_PER_CU = (2, 3)
+BLOCKS = (32, 64)  # outer blocks tried for the stepped form
 
 
 @dataclass
@@ -40,6 +46,7 @@ class BucketTuning:
     panel: int
     groups: int  # workgroups of the persistent grid; 0: the stepped form
     ms: float
+    block: int = 64  # outer block of the stepped form (a multiple of panel, <= 64)
 
 
 _TUNED: dict = {}
@@ -108,9 +115,14 @@ class Bucket:
         self.R = torch.empty(int((nc * nc).sum()), dtype=torch.complex128, device=dev)
         self.work = torch.empty(H.hp_batch_workspace_bytes(self.count, self.sum_nc, self.sum_xn, int(n.max()),
                                                            prec), dtype=torch.uint8, device=dev)
+        self.S = torch.empty_like(self.R)
+        self.sstat = torch.zeros(self.count, dtype=torch.int32, device=dev)
+        self.sum_nc2 = int((nc * nc).sum())
+        self.zwork = torch.empty(32 * self.sum_nc2, dtype=torch.uint8, device=dev)
         self.shape = np.stack([n, nc], axis=1).astype(np.int32)  # (n, nc), largest n first
         self.stepped = False  # solves in the stepped form (set with the factorization form)
-        self.graph = None
+        self.graph = None  # captured refinement step
+        self.whole = None  # captured bucket: (graph, key)
         self._steps = 0
         self.flops = float((8.0 / 3.0) * (n.astype(np.float64) ** 3).sum())
 
@@ -118,17 +130,19 @@ class Bucket:
     def key(self):
         return (int(self.n.max()), int(self.n.min()), self.count, self.prec)
 
-    def factor(self, panel: int, groups: int) -> None:
+    def factor(self, panel: int, groups: int, block: int = 64) -> None:
         """Build and factor; groups > 0: persistent grid of that many
-        workgroups, groups == 0: the stepped form."""
+        workgroups, groups == 0: the stepped form with outer blocks of
+        `block` columns (rounded down to a multiple of panel)."""
         H.hp_batch_build(self.count, self.items, self.prec, self.A)
         self.stepped = groups == 0
         if groups > 0:
             H.hp_batch_factor(self.count, self.items, self.prec, self.A, self.ipiv, self.perm, self.info, panel,
                               groups, self.work)
         else:
+            block = max(panel, block // panel * panel)
             H.hp_batch_factor_stepped(self.count, self.items, self.n, self.prec, self.A, self.ipiv, self.perm,
-                                      self.info, panel, self.work)
+                                      self.info, panel, block, self.work)
 
     def solve_init(self, max_refine: int = 30) -> bool:
         """Initial solve; True if FP32 refinement follows."""
@@ -172,6 +186,36 @@ class Bucket:
     def rmatrix(self) -> None:
         H.hp_batch_rmatrix(self.count, self.items, self.X, self.R)
 
+    def smatrix(self) -> None:
+        H.hp_batch_smatrix(self.count, self.items, self.R, self.S, self.sstat, self.sum_nc2, int(self.nc.max()),
+                           self.zwork)
+
+    def enqueue(self, t: BucketTuning, max_refine: int, tol: float, steps: int) -> None:
+        """The whole bucket with a fixed number of refinement steps and no
+        host synchronisation (capturable): build, factor, solve, `steps`
+        refinement steps (systems that have stopped are skipped by the
+        kernels), R, S."""
+        self.factor(t.panel, t.groups, t.block)
+        refine = self.solve_init(max_refine)
+        args = (self.count, self.items, self.shape if self.stepped else None, self.A, self.perm, self.X, max_refine,
+                tol, self.sum_nc, self.sum_xn, self.work)
+        for _ in range(steps if refine else 0):
+            H.hp_batch_refine_step(*args)
+            self._steps += 1
+        self.rmatrix()
+        self.smatrix()
+
+    def capture(self, t: BucketTuning, max_refine: int, tol: float, steps: int) -> None:
+        """Capture enqueue(...) in a graph (after an eager run has set every
+        kernel's launch attributes)."""
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=side):
+            self.enqueue(t, max_refine, tol, steps)
+        torch.cuda.current_stream().wait_stream(side)
+        self.whole = (g, (t.panel, t.groups, t.block, max_refine, tol, steps))
+
     def status(self):
         return H.hp_batch_status(self.count, self.work)
 
@@ -181,22 +225,19 @@ class Bucket:
         o = int(self.r_off[k])
         return self.R[o:o + c * c].view(c, c).cpu().numpy()
 
-    def S_of(self, k: int, swork=None) -> np.ndarray:
+    def S_of(self, k: int) -> np.ndarray:
+        """S of the k-th system of this bucket (host copy; from hp_batch_smatrix)."""
         c = int(self.nc[k])
         o = int(self.r_off[k])
-        S = torch.empty((c, c), dtype=torch.complex128, device=self.device)
-        if swork is None:
-            swork = torch.empty(H.hp_workspace_bytes(c, c, H.HP_C128), dtype=torch.uint8, device=self.device)
-        Rk = self.R[o:o + c * c]
-        H.hp_smatrix(self.sys[k], self.energies[k], Rk, S, swork)
-        return S.cpu().numpy()
+        return self.S[o:o + c * c].view(c, c).cpu().numpy()
 
 
 def autotune(bucket: Bucket, cus: int, reps: int = 1, sample: int | None = None, panels=PANELS,
-             groups_per_cu=GROUPS_PER_CU) -> BucketTuning:
-    """Time the factorization for each panel width and grid size, on the
-    bucket itself or on a bucket of its `sample` largest systems; keep the
-    fastest (cached per bucket shape and precision)."""
+             groups_per_cu=GROUPS_PER_CU, blocks=BLOCKS) -> BucketTuning:
+    """Time the factorization for each panel width and form (persistent
+    grid sizes; stepped with each outer block), on the bucket itself or on a
+    bucket of its `sample` largest systems; keep the fastest (cached per
+    bucket shape and precision)."""
     if bucket.key in _TUNED:
         return _TUNED[bucket.key]
     probe = bucket
@@ -205,17 +246,17 @@ def autotune(bucket: Bucket, cus: int, reps: int = 1, sample: int | None = None,
                        bucket.device)
     best = None
     for panel in panels:
-        for gpc in tuple(groups_per_cu) + (0,):
-            groups = gpc * cus
-            probe.factor(panel, groups)  # warm
+        shapes = [(gpc * cus, panel) for gpc in groups_per_cu] + [(0, b) for b in blocks if b % panel == 0]
+        for groups, block in shapes:
+            probe.factor(panel, groups, block)  # warm
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(reps):
-                probe.factor(panel, groups)
+                probe.factor(panel, groups, block)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) / reps * 1e3
             if best is None or ms < best.ms:
-                best = BucketTuning(panel, groups, ms)
+                best = BucketTuning(panel, groups, ms, block)
     _TUNED[bucket.key] = best
     return best
 
@@ -245,44 +286,94 @@ class Batch:
         return {f"N {int(b.n.min())}-{int(b.n.max())} ({b.count})": vars(self.tuning[b.key]) for b in self.buckets}
 
     def run(self, max_refine: int = 30, tol: float = 0.0, use_graph: bool = True) -> dict:
-        """Build, factor, solve (and refine), R for every system.  Each bucket
-        has its own stream: all factorizations are enqueued first, then the
-        refinement steps of the buckets still refining are interleaved."""
+        """Build, factor, solve (and refine), R and S for every system.  Each
+        bucket has its own stream.  Eager form (the first run, or
+        use_graph=False): all factorizations are enqueued first, then the
+        refinement steps of the buckets still refining are interleaved, each
+        step (after the first) replayed from a captured step.  With a captured
+        bucket (use_graph, after an eager run), one graph replay per bucket;
+        a bucket with systems still refining afterwards continues eagerly."""
         streams = [torch.cuda.Stream() for _ in self.buckets]
         cur = torch.cuda.current_stream()
+        tun = {b.key: self.tuning.get(b.key) or BucketTuning(16, 2 * self.cus, 0.0) for b in self.buckets}
         refining = []
         for b, s in zip(self.buckets, streams):
             s.wait_stream(cur)
-            t = self.tuning.get(b.key) or BucketTuning(16, 2 * self.cus, 0.0)
+            t = tun[b.key]
             with torch.cuda.stream(s):
-                b.factor(t.panel, t.groups)
+                key = (t.panel, t.groups, t.block, max_refine, tol)
+                if use_graph and b.whole is not None and b.whole[1][:5] == key:
+                    b.whole[0].replay()
+                    b._steps = b.whole[1][5]
+                    if self.prec == H.HP_C64:
+                        refining.append((b, s))
+                    continue
+                b.factor(t.panel, t.groups, t.block)
                 if b.solve_init(max_refine):
+                    b.refine_step(max_refine, tol, use_graph)  # sets the count of systems still refining
                     refining.append((b, s))
+        done_eager = set()
         while refining:
-            for b, s in refining:
-                with torch.cuda.stream(s):
-                    b.refine_step(max_refine, tol, use_graph)
             still = []
             for b, s in refining:
                 with torch.cuda.stream(s):
                     if H.hp_batch_active(b.work) > 0 and b._steps < max_refine:
                         still.append((b, s))
+            for b, s in still:
+                with torch.cuda.stream(s):
+                    b.refine_step(max_refine, tol, use_graph)
+                    done_eager.add(id(b))
             refining = still
         for b, s in zip(self.buckets, streams):
+            t = tun[b.key]
             with torch.cuda.stream(s):
-                b.rmatrix()
+                replayed = use_graph and b.whole is not None and b.whole[1][:5] == (t.panel, t.groups, t.block,
+                                                                                    max_refine, tol)
+                if not replayed or id(b) in done_eager:  # X changed after the graph's R and S
+                    b.rmatrix()
+                    b.smatrix()
             cur.wait_stream(s)
+        if use_graph:
+            for b in self.buckets:
+                t = tun[b.key]
+                key = (t.panel, t.groups, t.block, max_refine, tol)
+                if b.whole is None or b.whole[1][:5] != key or b.whole[1][5] < b._steps:
+                    torch.cuda.synchronize()
+                    b.capture(t, max_refine, tol, b._steps)
         return {f"N {int(b.n.min())}-{int(b.n.max())}": b._steps for b in self.buckets}
 
-    def results(self):
-        """[(R, S)] in the original order of the systems."""
+    def results(self, fallback: bool = True):
+        """[(R, S)] in the original order of the systems (host arrays).  A
+        system whose FP32 refinement did not converge (status 2) or whose FP32
+        factor met an exactly zero pivot (status 3) is solved again in FP64
+        through the single-system path when `fallback` is set (its index is
+        then listed in self.fallbacks), else HprmatError is raised."""
+        from . import pipeline as P
         out = [None] * self.count
-        cmax = max(int(b.nc.max()) for b in self.buckets)
-        swork = torch.empty(H.hp_workspace_bytes(cmax, cmax, H.HP_C128), dtype=torch.uint8)
-        swork = swork.to(self.buckets[0].device)
+        st, _ = self.status()
+        self.fallbacks = []
         for b in self.buckets:
+            sst = b.sstat.cpu().numpy()
+            R_all = b.R.cpu().numpy()
+            S_all = b.S.cpu().numpy()
             for k in range(b.count):
-                out[b.index[k]] = (b.R_of(k), b.S_of(k, swork))
+                g = b.index[k]
+                if st[g] in (2, 3):
+                    if not fallback:
+                        raise H.HprmatError(H.HP_ERR_NOCONV if st[g] == 2 else H.HP_ERR_SINGULAR,
+                                            f"batched system {g}")
+                    res = P.Solver(P.DeviceSystem(b.systems[k], device=str(b.device)), H.HP_C128).run(
+                        b.energies[k])
+                    out[g] = (res.R.cpu().numpy(), res.S.cpu().numpy())
+                    self.fallbacks.append(g)
+                    continue
+                if sst[k] != 0:
+                    code = H.HP_ERR_UNSUPPORTED if sst[k] in (1, 4) else (
+                        H.HP_ERR_NOCONV if sst[k] == 2 else H.HP_ERR_SINGULAR)
+                    raise H.HprmatError(code, f"hp_batch_smatrix, system {g}")
+                c = int(b.nc[k])
+                o = int(b.r_off[k])
+                out[g] = (R_all[o:o + c * c].reshape(c, c), S_all[o:o + c * c].reshape(c, c))
         return out
 
     def status(self):

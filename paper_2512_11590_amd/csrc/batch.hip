@@ -60,76 +60,84 @@ constexpr size_t tile_lds_bytes() {
   return (size_t)2 * kBK * kBLd * sizeof(cplx<T>);
 }
 
-// One 64 x 64 output tile (m0, n0) of C[M x N] -= A[M x K] B[K x N]
-// (K <= kBK) by one workgroup: A and B staged k-major in LDS, four
-// wavefronts of 32 x 32 outputs, MFMA 16x16x4.  FP32: three real products
-// per complex product (3M), FP64: four (4M).  A, B and C must not overlap.
-// Ends with a barrier.
+// One 64 x 64 output tile (m0, n0) of C[M x N] -= A[M x K] B[K x N] by one
+// workgroup: K in chunks of kBK, each chunk's A and B staged k-major in LDS
+// (the next chunk's loads are in flight while the current one is
+// multiplied), four wavefronts of 32 x 32 outputs, MFMA 16x16x4.  FP32:
+// three real products per complex product (3M), FP64: four (4M).  A, B and
+// C must not overlap.  The LDS tiles are free again when it returns (its last
+// barrier follows the last product).
 template <typename T>
 __device__ __forceinline__ void tile_gemm_sub(int m0, int n0, int M, int N, int K, const cplx<T> *__restrict__ A, long lda,
                               const cplx<T> *__restrict__ B, long ldb, cplx<T> *__restrict__ C, long ldc,
                               cplx<T> *As, cplx<T> *Bs) {
   typedef typename BMfma<T>::v4 v4;
   constexpr bool M3 = sizeof(T) == 4;
+  constexpr int NS = 64 * kBK / 256;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int fr = lane & 15, fk = lane >> 4;
-  const int Kp = (K + 3) & ~3;
   const cplx<T> zero{T(0), T(0)};
-  {
-    // all of a thread's loads first (clamped addresses: in bounds, no branch
-    // to wait on), then the stores with out-of-range values masked to zero
-    constexpr int NS = 64 * kBK / 256;
-    cplx<T> ra[NS], rb[NS];
+  cplx<T> ra[NS], rb[NS];
+  // a chunk's loads at clamped addresses (in bounds, no branch to wait on);
+  // out-of-range values are masked to zero when stored
+  auto load = [&](int kc) {
+    const int kb = min(kBK, K - kc), Kp = (kb + 3) & ~3;
 #pragma unroll
     for (int u = 0; u < NS; ++u) {
       const int e = tid + 256 * u;
       const int r = e / Kp, k = e - r * Kp;
-      ra[u] = A[(long)min(m0 + r, M - 1) * lda + min(k, K - 1)];
-      const int kb = e >> 6, c = e & 63;
-      rb[u] = B[(long)min(kb, K - 1) * ldb + min(n0 + c, N - 1)];
+      ra[u] = A[(long)min(m0 + r, M - 1) * lda + kc + min(k, kb - 1)];
+      const int kr = e >> 6, c = e & 63;
+      rb[u] = B[(long)(kc + min(kr, kb - 1)) * ldb + min(n0 + c, N - 1)];
     }
-#pragma unroll
-    for (int u = 0; u < NS; ++u) {
-      const int e = tid + 256 * u;
-      if (e < 64 * Kp) {
-        const int r = e / Kp, k = e - r * Kp;
-        As[k * kBLd + r] = (m0 + r < M && k < K) ? ra[u] : zero;
-        const int kb = e >> 6, c = e & 63;
-        Bs[kb * kBLd + c] = (kb < K && n0 + c < N) ? rb[u] : zero;
-      }
-    }
-  }
-  __syncthreads();
+  };
   v4 p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) p1[i][j] = p2[i][j] = p3[i][j] = v4{0, 0, 0, 0};
-  for (int ks = 0; ks < Kp; ks += 4) {
-    const int kk = ks + fk;
-    cplx<T> af[2], bf[2];
+  load(0);
+  for (int kc = 0; kc < K; kc += kBK) {
+    const int kb = min(kBK, K - kc), Kp = (kb + 3) & ~3;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) af[i] = As[kk * kBLd + wm + i * 16 + fr];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) bf[j] = Bs[kk * kBLd + wn + j * 16 + fr];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        if constexpr (M3) {
-          // p1 = Ar Br, p2 = Ai Bi, p3 = (Ar + Ai)(Br + Bi)
-          p1[i][j] = BMfma<T>::mac(af[i].re, bf[j].re, p1[i][j]);
-          p2[i][j] = BMfma<T>::mac(af[i].im, bf[j].im, p2[i][j]);
-          p3[i][j] = BMfma<T>::mac(af[i].re + af[i].im, bf[j].re + bf[j].im, p3[i][j]);
-        } else {
-          // p1 = Ar Br - Ai Bi, p3 = Ar Bi + Ai Br
-          p1[i][j] = BMfma<T>::mac(af[i].re, bf[j].re, p1[i][j]);
-          p1[i][j] = BMfma<T>::mac(-af[i].im, bf[j].im, p1[i][j]);
-          p3[i][j] = BMfma<T>::mac(af[i].re, bf[j].im, p3[i][j]);
-          p3[i][j] = BMfma<T>::mac(af[i].im, bf[j].re, p3[i][j]);
-        }
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + 256 * u;
+      if (e < 64 * Kp) {
+        const int r = e / Kp, k = e - r * Kp;
+        As[k * kBLd + r] = (m0 + r < M && k < kb) ? ra[u] : zero;
+        const int kr = e >> 6, c = e & 63;
+        Bs[kr * kBLd + c] = (kr < kb && n0 + c < N) ? rb[u] : zero;
       }
+    }
+    __syncthreads();
+    if (kc + kBK < K) load(kc + kBK);
+    for (int ks = 0; ks < Kp; ks += 4) {
+      const int kk = ks + fk;
+      cplx<T> af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) af[i] = As[kk * kBLd + wm + i * 16 + fr];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = Bs[kk * kBLd + wn + j * 16 + fr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if constexpr (M3) {
+            // p1 = Ar Br, p2 = Ai Bi, p3 = (Ar + Ai)(Br + Bi)
+            p1[i][j] = BMfma<T>::mac(af[i].re, bf[j].re, p1[i][j]);
+            p2[i][j] = BMfma<T>::mac(af[i].im, bf[j].im, p2[i][j]);
+            p3[i][j] = BMfma<T>::mac(af[i].re + af[i].im, bf[j].re + bf[j].im, p3[i][j]);
+          } else {
+            // p1 = Ar Br - Ai Bi, p3 = Ar Bi + Ai Br
+            p1[i][j] = BMfma<T>::mac(af[i].re, bf[j].re, p1[i][j]);
+            p1[i][j] = BMfma<T>::mac(-af[i].im, bf[j].im, p1[i][j]);
+            p3[i][j] = BMfma<T>::mac(af[i].re, bf[j].im, p3[i][j]);
+            p3[i][j] = BMfma<T>::mac(af[i].im, bf[j].re, p3[i][j]);
+          }
+        }
+    }
+    __syncthreads();
   }
   // C: all eight loads of the thread in flight at once (clamped addresses),
   // then the updates, stored where in range
@@ -161,7 +169,6 @@ __device__ __forceinline__ void tile_gemm_sub(int m0, int n0, int M, int N, int 
         if (gr < M && gc < N) C[(long)gr * ldc + gc] = c;
       }
     }
-  __syncthreads();
 }
 
 // All of C[M x N] -= A[M x K] B[K x N] by one workgroup, tile after tile.
@@ -262,14 +269,15 @@ __global__ __launch_bounds__(256) void batch_build_kernel(int count, const hp_ba
 // Substitution on one diagonal block [b0, b0 + bs) of an LU factor for the
 // right-hand column c of y (leading dimension nc): unit lower (forward) or
 // upper (backward, dividing by the diagonal).  D: the block in LDS at
-// stride kBK + 1, zero past bs.  Rows are taken 8 at a time in registers;
-// the rows solved before such a group (above it forward, below it backward)
-// are read back from y.  Both solve forms of the batch use this routine, so
-// their results agree bit for bit.
-template <typename T>
+// stride LP (kBK + 1 by default), zero past bs.  Rows are taken 8 at a time
+// in registers; the rows solved before such a group (above it forward, below
+// it backward) are read back from y.  Both solve forms of the batch, and the
+// block rows of both factorization forms, use this routine, so their results
+// agree bit for bit.
+template <typename T, int LP = kBK + 1>
 __device__ __forceinline__ void diag_block_solve(const cplx<T> *D, cplx<T> *__restrict__ y, int nc, int b0, int bs,
                                                  int c, bool upper) {
-  constexpr int RB = 8, LP = kBK + 1;
+  constexpr int RB = 8;
   const cplx<T> zero{T(0), T(0)};
   const int nb = (bs + RB - 1) / RB;
 #pragma unroll 1
@@ -317,12 +325,13 @@ __device__ __forceinline__ void stage_diag_block(cplx<T> *D, const cplx<T> *__re
   }
 }
 
-// Column steps and block row of the panel [j0, j0 + w) of one n x n system,
-// by one workgroup.  Records the pivots, and the first exactly zero pivot
-// column (1-based) in *first_zero if it is still 0.
+// Column steps of the panel [j0, j0 + w) of one n x n system and its block
+// row over the columns [j0 + w, cend), by one workgroup.  Records the
+// pivots, and the first exactly zero pivot column (1-based) in *first_zero if
+// it is still 0.
 template <typename T>
-__device__ void panel_steps(cplx<T> *a, int n, int j0, int w, int *piv, int *first_zero, cplx<T> *urow, T *sv,
-                            int *sr, cplx<T> *D) {
+__device__ void panel_steps(cplx<T> *a, int n, int j0, int w, int cend, int *piv, int *first_zero, cplx<T> *urow,
+                            T *sv, int *sr, cplx<T> *D) {
   const int tid = threadIdx.x;
   for (int jj = 0; jj < w; ++jj) {
     const int j = j0 + jj;
@@ -367,7 +376,7 @@ __device__ void panel_steps(cplx<T> *a, int n, int j0, int w, int *piv, int *fir
   // substitution)
   stage_diag_block<T>(D, a, n, j0, w);
   __syncthreads();
-  for (int c = j0 + w + tid; c < n; c += 256) diag_block_solve<T>(D, a + (long)j0 * n, n, 0, w, c, false);
+  for (int c = j0 + w + tid; c < cend; c += 256) diag_block_solve<T>(D, a + (long)j0 * n, n, 0, w, c, false);
   __syncthreads();
 }
 
@@ -408,7 +417,7 @@ __global__ __launch_bounds__(256) void batch_lu_kernel(int count, const hp_batch
     __syncthreads();
     for (int j0 = 0; j0 < n; j0 += W) {
       const int w = min(W, n - j0);
-      panel_steps<T>(a, n, j0, w, piv, &s_zero, urow, sv, sr, As);  // As is free until the product
+      panel_steps<T>(a, n, j0, w, n, piv, &s_zero, urow, sv, sr, As);  // As is free until the product
       const int rest = n - j0 - w;
       if (rest > 0)
         wg_gemm_sub<T>(rest, rest, w, a + (long)(j0 + w) * n + j0, n, a + (long)j0 * n + j0 + w, n,
@@ -422,15 +431,22 @@ __global__ __launch_bounds__(256) void batch_lu_kernel(int count, const hp_batch
   }
 }
 
-// Stepped form, for buckets of larger systems: one launch per panel step for
-// the column steps of every system still factoring (systems listed largest
-// first, so they are items [0, active)), then one launch of all their
-// trailing-update tiles.
+// Stepped form, for buckets of larger systems, blocked in two levels: outer
+// blocks of NB columns (a multiple of the panel width W, at most kBlockMax),
+// each factored as NB / W panels whose updates stay inside the block, then
+// the block's row U12 = L11^-1 A12 over all columns right of it and one
+// trailing update A22 -= L21 U12 with K = NB.  Every step is one launch over
+// the systems still factoring (listed largest first, so they are items
+// [0, active)): the panels' column steps one workgroup per system, the
+// updates and the block row as tiles of all systems.  With NB = W this is
+// the one-level blocked LU.
+constexpr int kBlockMax = 64;
+
 template <typename T>
 __global__ __launch_bounds__(256) void batch_panel_kernel(const hp_batch_item *__restrict__ items,
                                                           cplx<T> *__restrict__ A, int *__restrict__ ipiv,
                                                           int *__restrict__ perm, int *__restrict__ info, int j0,
-                                                          int W) {
+                                                          int W, int NB) {
   __shared__ cplx<T> urow[kBK];
   __shared__ cplx<T> D[kBK * (kBK + 1)];
   __shared__ T sv[4];
@@ -441,46 +457,79 @@ __global__ __launch_bounds__(256) void batch_panel_kernel(const hp_batch_item *_
   const int n = item_n(it);
   if (j0 >= n) return;
   const int w = min(W, n - j0);
+  const int cend = min((j0 / NB + 1) * NB, n);  // end of the outer block
   int *piv = ipiv + it.p_off;
   if (threadIdx.x == 0) s_zero = info[s];
   __syncthreads();
-  panel_steps<T>(A + it.a_off, n, j0, w, piv, &s_zero, urow, sv, sr, D);
+  panel_steps<T>(A + it.a_off, n, j0, w, cend, piv, &s_zero, urow, sv, sr, D);
   if (threadIdx.x == 0) {
     info[s] = s_zero;
     if (j0 + w == n) compose_perm(piv, perm + it.p_off, n);
   }
 }
 
-// Tile offsets of every panel step: offs[t * (count + 1) + s] = number of
-// trailing-update tiles of systems [0, s) at step t (exclusive prefix sum).
-__global__ void batch_tiles_kernel(int count, const hp_batch_item *__restrict__ items, int W, int *offs) {
-  const int t = blockIdx.x;
+// Shapes of the tiled steps of one system (n) at one step:
+//   kind 0, inner update after the panel at j0: rows [j0 + w, n) x columns
+//     [j0 + w, end of the outer block), K = w;
+//   kind 1, outer update of the block at J: rows and columns [J + NB, n), K = NB;
+//   kind 2, block row of the block at J: columns [J + NB, n) in chunks of 256.
+struct StepShape {
+  int r0, rows, c0, cols, k0, K;
+};
+__device__ __host__ inline StepShape step_shape(int kind, int n, int j, int W, int NB) {
+  StepShape sh{0, 0, 0, 0, 0, 0};
+  if (j >= n) return sh;
+  if (kind == 0) {
+    const int w = min(W, n - j);
+    const int cend = min((j / NB + 1) * NB, n);
+    sh.r0 = sh.c0 = j + w;
+    sh.rows = n - sh.r0;
+    sh.cols = cend - sh.c0;
+    sh.k0 = j;
+    sh.K = w;
+  } else {
+    const int nb = min(NB, n - j);
+    sh.r0 = sh.c0 = j + nb;
+    sh.rows = sh.cols = n - sh.r0;
+    sh.k0 = j;
+    sh.K = nb;
+  }
+  return sh;
+}
+__device__ __host__ inline int step_units(int kind, int n, int j, int W, int NB) {
+  const StepShape sh = step_shape(kind, n, j, W, NB);
+  if (sh.rows <= 0 || sh.cols <= 0) return 0;
+  if (kind == 2) return (sh.cols + 255) / 256;
+  return ((sh.rows + 63) / 64) * ((sh.cols + 63) / 64);
+}
+
+// Work-unit offsets of every tiled step: offs[q * (count + 1) + s] = units of
+// systems [0, s) at step q (exclusive prefix sum).  Steps q < P are the inner
+// updates after the panels at j = q W; then, per outer block b (J = b NB),
+// the block row (P + 2b) and the outer update (P + 2b + 1).
+__global__ void batch_tables_kernel(int count, const hp_batch_item *__restrict__ items, int W, int NB, int P,
+                                    int *offs) {
+  const int q = blockIdx.x;
   if (threadIdx.x != 0) return;
-  const int j0 = t * W;
+  int kind, j;
+  if (q < P) {
+    kind = 0;
+    j = q * W;
+  } else {
+    kind = ((q - P) & 1) ? 1 : 2;
+    j = ((q - P) >> 1) * NB;
+  }
   int acc = 0;
-  int *o = offs + (long)t * (count + 1);
+  int *o = offs + (long)q * (count + 1);
   for (int s = 0; s < count; ++s) {
     o[s] = acc;
-    const int n = item_n(items[s]);
-    if (j0 < n) {
-      const int rest = n - j0 - min(W, n - j0);
-      const int tt = (rest + 63) / 64;
-      acc += tt * tt;
-    }
+    acc += step_units(kind, item_n(items[s]), j, W, NB);
   }
   o[count] = acc;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void batch_trail_kernel(int count, const hp_batch_item *__restrict__ items,
-                                                          cplx<T> *__restrict__ A, const int *__restrict__ offs,
-                                                          int j0, int W) {
-  extern __shared__ __align__(16) char smem_raw[];
-  cplx<T> *As = reinterpret_cast<cplx<T> *>(smem_raw);
-  cplx<T> *Bs = As + kBK * kBLd;
-  const int g = blockIdx.x;
-  if (g >= offs[count]) return;
-  // the system owning tile g: offs[s] <= g < offs[s + 1]
+// The system owning unit g of a step: offs[s] <= g < offs[s + 1].
+__device__ __forceinline__ int unit_owner(const int *offs, int count, int g) {
   int lo = 0, hi = count;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
@@ -489,15 +538,57 @@ __global__ __launch_bounds__(256) void batch_trail_kernel(int count, const hp_ba
     else
       hi = mid;
   }
-  const hp_batch_item it = items[lo];
+  return lo;
+}
+
+// The update tiles of one step (kind 0 or 1) of every system.
+template <typename T>
+__global__ __launch_bounds__(256) void batch_trail_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                          cplx<T> *__restrict__ A, const int *__restrict__ offs,
+                                                          int kind, int j, int W, int NB) {
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T> *As = reinterpret_cast<cplx<T> *>(smem_raw);
+  cplx<T> *Bs = As + kBK * kBLd;
+  const int g = blockIdx.x;
+  if (g >= offs[count]) return;
+  const int s = unit_owner(offs, count, g);
+  const hp_batch_item it = items[s];
   const int n = item_n(it);
-  const int w = min(W, n - j0);
-  const int rest = n - j0 - w;
-  const int tn = (rest + 63) / 64;
-  const int l = g - offs[lo];
+  const StepShape sh = step_shape(kind, n, j, W, NB);
+  const int tn = (sh.cols + 63) / 64;
+  const int l = g - offs[s];
   cplx<T> *a = A + it.a_off;
-  tile_gemm_sub<T>((l / tn) * 64, (l % tn) * 64, rest, rest, w, a + (long)(j0 + w) * n + j0, n,
-                   a + (long)j0 * n + j0 + w, n, a + (long)(j0 + w) * n + j0 + w, n, As, Bs);
+  tile_gemm_sub<T>((l / tn) * 64, (l % tn) * 64, sh.rows, sh.cols, sh.K, a + (long)sh.r0 * n + sh.k0, n,
+                   a + (long)sh.k0 * n + sh.c0, n, a + (long)sh.r0 * n + sh.c0, n, As, Bs);
+}
+
+// Block row of the outer block at J of every system: U12 = L11^-1 A12 over
+// the columns [J + nb, n), 256 columns per workgroup, one per thread; L11
+// (unit lower, nb x nb) staged in LDS (zero past nb), the substitution by
+// diag_block_solve.
+template <typename T>
+__global__ __launch_bounds__(256) void batch_brow_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                         cplx<T> *__restrict__ A, const int *__restrict__ offs,
+                                                         int J, int NB) {
+  // every lane reads the same element of D (a broadcast), so no padding
+  constexpr int LP = kBlockMax;
+  __shared__ cplx<T> D[kBlockMax * LP];
+  const int g = blockIdx.x;
+  if (g >= offs[count]) return;
+  const int s = unit_owner(offs, count, g);
+  const hp_batch_item it = items[s];
+  const int n = item_n(it);
+  const int nb = min(NB, n - J);
+  cplx<T> *a = A + it.a_off;
+  const int nbp = (nb + 7) & ~7;  // rows of the last 8-row group
+  for (int e = threadIdx.x; e < nbp * nb; e += 256) {
+    const int r = e / nb, k = e - r * nb;
+    D[r * LP + k] = r < nb ? a[(long)(J + r) * n + J + k] : cplx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  const int c = J + nb + (g - offs[s]) * 256 + (int)threadIdx.x;
+  if (c >= n) return;
+  diag_block_solve<T, LP>(D, a + (long)J * n, n, 0, nb, c, false);
 }
 
 // ------------------------------------------------------------------- solves --
@@ -933,7 +1024,8 @@ size_t batch_bytes(int count, long sum_nc, long sum_xn, int nmax, int prec) {
   const size_t elt = prec == HP_C64 ? sizeof(cplx<float>) : sizeof(cplx<double>);
   return 256 + align_up(sizeof(BatchState) * (size_t)count, 256) + align_up(sizeof(double) * (size_t)sum_nc, 256) +
          align_up(sizeof(cplx<double>) * (size_t)sum_xn, 256) + align_up(elt * (size_t)sum_xn, 256) +
-         align_up(sizeof(int) * 2 * (size_t)solve_steps(std::max(nmax, 1)) * (count + 1), 256);
+         align_up(sizeof(int) * 2 * (size_t)solve_steps(std::max(nmax, 1)) * (count + 1), 256) +
+         align_up(sizeof(int) * 3 * (size_t)std::max(nmax, 1) * (count + 1), 256);  // stepped factor tables
 }
 
 // shape_host: HOST (n, nc) pairs of the systems, largest n first.
@@ -1042,54 +1134,86 @@ extern "C" int hp_batch_factor(int count, const hp_batch_item *items, int prec, 
 }
 
 extern "C" int hp_batch_factor_stepped(int count, const hp_batch_item *items, const int *n_host, int prec,
-                                       void *A, int *ipiv, int *perm, int *info, int panel, void *work,
+                                       void *A, int *ipiv, int *perm, int *info, int panel, int block, void *work,
                                        size_t work_bytes, void *stream) {
   if (count < 1 || !items || !n_host || !A || !ipiv || !perm || !info || !work) return HP_ERR_ARG;
   if (panel < 1 || panel > kBK || (prec != HP_C64 && prec != HP_C128)) return HP_ERR_ARG;
+  if (block < panel || block > kBlockMax || block % panel != 0) return HP_ERR_ARG;
   int nmax = 0;
   for (int s = 0; s < count; ++s) {
     if (n_host[s] < 1 || (s > 0 && n_host[s] > n_host[s - 1])) return HP_ERR_ARG;  // largest first
     nmax = std::max(nmax, n_host[s]);
   }
-  const int steps = (nmax + panel - 1) / panel;
-  const size_t tbl = 256 + sizeof(int) * (size_t)steps * (count + 1);
+  const int P = (nmax + panel - 1) / panel;     // panel steps
+  const int NBk = (nmax + block - 1) / block;  // outer blocks
+  const int Q = P + 2 * NBk;
+  const size_t tbl = 256 + sizeof(int) * (size_t)Q * (count + 1);
   if (work_bytes < tbl) return HP_ERR_WORKSPACE;
   int *offs = (int *)((char *)work + 256);
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(batch_zero_kernel, dim3((count + 255) / 256), dim3(256), 0, st, (unsigned *)info, count);
   HP_CHECK_LAUNCH();
-  hipLaunchKernelGGL(batch_tiles_kernel, dim3(steps), dim3(64), 0, st, count, items, panel, offs);
+  hipLaunchKernelGGL(batch_tables_kernel, dim3(Q), dim3(64), 0, st, count, items, panel, block, P, offs);
   HP_CHECK_LAUNCH();
   const size_t shm = prec == HP_C64 ? tile_lds_bytes<float>() : tile_lds_bytes<double>();
   int rc = prec == HP_C64 ? ensure_dynamic_lds((const void *)batch_trail_kernel<float>, shm)
                           : ensure_dynamic_lds((const void *)batch_trail_kernel<double>, shm);
   if (rc) return rc;
-  TraceScope ts(TR_PANEL, st, 0.0, 0.0);
-  for (int t = 0; t < steps; ++t) {
-    const int j0 = t * panel;
-    int active = 0;
-    long tiles = 0;
-    for (int s = 0; s < count && n_host[s] > j0; ++s) {
-      ++active;
-      const long rest = n_host[s] - j0 - std::min(panel, n_host[s] - j0);
-      const long tt = (rest + 63) / 64;
-      tiles += tt * tt;
+  // units of one tiled step over the systems still factoring (host count,
+  // the same formula as the device tables)
+  auto units = [&](int kind, int j, int *active) {
+    long u = 0;
+    int a = 0;
+    for (int s = 0; s < count && n_host[s] > j; ++s) {
+      ++a;
+      u += step_units(kind, n_host[s], j, panel, block);
     }
-    if (prec == HP_C64)
-      hipLaunchKernelGGL(batch_panel_kernel<float>, dim3(active), dim3(256), 0, st, items, (cplx<float> *)A, ipiv,
-                         perm, info, j0, panel);
-    else
-      hipLaunchKernelGGL(batch_panel_kernel<double>, dim3(active), dim3(256), 0, st, items, (cplx<double> *)A,
-                         ipiv, perm, info, j0, panel);
-    HP_CHECK_LAUNCH();
-    if (tiles == 0) continue;
+    *active = a;
+    return u;
+  };
+  TraceScope ts(TR_PANEL, st, 0.0, 0.0);
+  for (int J = 0; J < nmax; J += block) {
+    for (int j0 = J; j0 < std::min(J + block, nmax); j0 += panel) {
+      int active = 0;
+      const long tiles = units(0, j0, &active);
+      if (prec == HP_C64)
+        hipLaunchKernelGGL(batch_panel_kernel<float>, dim3(active), dim3(256), 0, st, items, (cplx<float> *)A, ipiv,
+                           perm, info, j0, panel, block);
+      else
+        hipLaunchKernelGGL(batch_panel_kernel<double>, dim3(active), dim3(256), 0, st, items, (cplx<double> *)A,
+                           ipiv, perm, info, j0, panel, block);
+      HP_CHECK_LAUNCH();
+      if (tiles == 0) continue;
+      if (tiles > (1L << 30)) return HP_ERR_UNSUPPORTED;
+      const int *o = offs + (long)(j0 / panel) * (count + 1);
+      if (prec == HP_C64)
+        hipLaunchKernelGGL(batch_trail_kernel<float>, dim3((unsigned)tiles), dim3(256), shm, st, active, items,
+                           (cplx<float> *)A, o, 0, j0, panel, block);
+      else
+        hipLaunchKernelGGL(batch_trail_kernel<double>, dim3((unsigned)tiles), dim3(256), shm, st, active, items,
+                           (cplx<double> *)A, o, 0, j0, panel, block);
+      HP_CHECK_LAUNCH();
+    }
+    int active = 0;
+    const long chunks = units(2, J, &active);
+    if (chunks == 0) continue;
+    const long tiles = units(1, J, &active);
     if (tiles > (1L << 30)) return HP_ERR_UNSUPPORTED;
-    if (prec == HP_C64)
+    const int qb = P + 2 * (J / block);
+    const int *ob = offs + (long)qb * (count + 1), *ou = offs + (long)(qb + 1) * (count + 1);
+    if (prec == HP_C64) {
+      hipLaunchKernelGGL(batch_brow_kernel<float>, dim3((unsigned)chunks), dim3(256), 0, st, active, items,
+                         (cplx<float> *)A, ob, J, block);
+      HP_CHECK_LAUNCH();
       hipLaunchKernelGGL(batch_trail_kernel<float>, dim3((unsigned)tiles), dim3(256), shm, st, active, items,
-                         (cplx<float> *)A, offs + (long)t * (count + 1), j0, panel);
-    else
+                         (cplx<float> *)A, ou, 1, J, panel, block);
+    } else {
+      hipLaunchKernelGGL(batch_brow_kernel<double>, dim3((unsigned)chunks), dim3(256), 0, st, active, items,
+                         (cplx<double> *)A, ob, J, block);
+      HP_CHECK_LAUNCH();
       hipLaunchKernelGGL(batch_trail_kernel<double>, dim3((unsigned)tiles), dim3(256), shm, st, active, items,
-                         (cplx<double> *)A, offs + (long)t * (count + 1), j0, panel);
+                         (cplx<double> *)A, ou, 1, J, panel, block);
+    }
     HP_CHECK_LAUNCH();
   }
   return HP_OK;

@@ -26,6 +26,7 @@
 // U O_c)):  U = (O - Rt O')^-1 (I - Rt I'),  Rt = rho^1/2 R rho^1/2.
 #include "common.h"
 
+#include <climits>
 #include <cmath>
 #include <mutex>
 #include <vector>
@@ -233,6 +234,150 @@ extern "C" int hp_coulomb_device(int nch, const int *l, const double *eta, const
 
 namespace hp {
 
+// Collision matrices of a batch of systems (see hp_batch_smatrix), one
+// workgroup per system: the channel functions into LDS, then
+// Z = [ZO | ZI] (nc x 2nc, in the workspace at 2 r_off) as zmat_kernel builds
+// them, Gaussian elimination with partial pivoting (largest |Re| + |Im|,
+// smallest row on ties) on Z, and back substitution of the right half into
+// S (at r_off).  status[s]: 0 ok, 1 a closed channel, 2 a continued fraction
+// did not converge, 3 an exactly zero pivot, 4 more than 512 channels.
+constexpr int kBatchSmatMaxChannels = 512;
+
+__global__ __launch_bounds__(256) void batch_smatrix_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                            const cplx<double> *__restrict__ R,
+                                                            cplx<double> *__restrict__ S, cplx<double> *__restrict__ Z,
+                                                            int *__restrict__ status) {
+  __shared__ double fg[4 * kBatchSmatMaxChannels];
+  __shared__ double sqrho[kBatchSmatMaxChannels];
+  __shared__ double sv[4];
+  __shared__ int sr[4];
+  __shared__ int s_bad;
+  const int sidx = blockIdx.x;
+  if (sidx >= count) return;
+  const hp_batch_item it = items[sidx];
+  const hp_system &sys = it.sys;
+  const int nc = sys.nc, tid = threadIdx.x;
+  if (nc > kBatchSmatMaxChannels) {  // the channel table would not fit
+    if (tid == 0) status[sidx] = 4;
+    return;
+  }
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int c = tid; c < nc; c += 256) {
+    const double ec = it.E - sys.eps[c];
+    if (!(ec > 0.0)) {
+      atomicMax(&s_bad, 1);
+      fg[4 * c] = fg[4 * c + 1] = fg[4 * c + 2] = fg[4 * c + 3] = 0.0;
+      sqrho[c] = 0.0;
+      continue;
+    }
+    const double k = sqrt(ec / sys.hbar2_2mu);
+    const double eta = sys.z1z2e2 / (2.0 * sys.hbar2_2mu * k);
+    const double rho = k * sys.a;
+    const CoulombOut o = coulomb_fg(sys.l[c], eta, rho);
+    fg[4 * c + 0] = o.F;
+    fg[4 * c + 1] = o.Fp;
+    fg[4 * c + 2] = o.G;
+    fg[4 * c + 3] = o.Gp;
+    sqrho[c] = sqrt(rho);
+    if (o.status) atomicMax(&s_bad, 2);
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) status[sidx] = s_bad;
+    return;
+  }
+  const cplx<double> *Rs = R + it.r_off;
+  cplx<double> *z = Z + 2 * it.r_off;  // nc x 2nc, row-major
+  const int w2 = 2 * nc;
+  for (int e = tid; e < nc * nc; e += 256) {
+    const int c = e / nc, cp = e - c * nc;
+    const double sc = sqrho[c] * sqrho[cp];
+    const cplx<double> rt{sc * Rs[e].re, sc * Rs[e].im};
+    const double F = fg[4 * cp], Fp = fg[4 * cp + 1], G = fg[4 * cp + 2], Gp = fg[4 * cp + 3];
+    cplx<double> zo = cmul(rt, cplx<double>{Gp, Fp});
+    cplx<double> zi = cmul(rt, cplx<double>{Gp, -Fp});
+    zo = cplx<double>{-zo.re, -zo.im};
+    zi = cplx<double>{-zi.re, -zi.im};
+    if (c == cp) {
+      zo.re += G;
+      zo.im += F;
+      zi.re += G;
+      zi.im -= F;
+    }
+    z[(long)c * w2 + cp] = zo;
+    z[(long)c * w2 + nc + cp] = zi;
+  }
+  __syncthreads();
+  int zero = 0;
+  for (int k = 0; k < nc; ++k) {
+    double best = -1.0;
+    int brow = INT_MAX;
+    for (int r = k + tid; r < nc; r += 256) {
+      const double v = cabs1(z[(long)r * w2 + k]);
+      if (v > best || (v == best && r < brow)) {
+        best = v;
+        brow = r;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off);
+      const int orow = __shfl_xor(brow, off);
+      if (ov > best || (ov == best && orow < brow)) {
+        best = ov;
+        brow = orow;
+      }
+    }
+    if ((tid & 63) == 0) {
+      sv[tid >> 6] = best;
+      sr[tid >> 6] = brow;
+    }
+    __syncthreads();
+    best = sv[0];
+    brow = sr[0];
+    for (int q = 1; q < 4; ++q)
+      if (sv[q] > best || (sv[q] == best && sr[q] < brow)) {
+        best = sv[q];
+        brow = sr[q];
+      }
+    __syncthreads();
+    if (!(best > 0.0)) {
+      zero = 1;
+      break;
+    }
+    if (brow != k)
+      for (int j = k + tid; j < w2; j += 256) {
+        const cplx<double> x = z[(long)k * w2 + j];
+        z[(long)k * w2 + j] = z[(long)brow * w2 + j];
+        z[(long)brow * w2 + j] = x;
+      }
+    __syncthreads();
+    const cplx<double> inv = crcp(z[(long)k * w2 + k]);
+    // rows below k: l = z_ik / z_kk, z_ij -= l z_kj (j > k); one thread per (i, j)
+    const int rows = nc - k - 1, cols = w2 - k - 1;
+    for (int e = tid; e < rows * cols; e += 256) {
+      const int i = k + 1 + e / cols, j = k + 1 + e % cols;
+      const cplx<double> l = cmul(z[(long)i * w2 + k], inv);
+      z[(long)i * w2 + j] = cfms(z[(long)i * w2 + j], l, z[(long)k * w2 + j]);
+    }
+    __syncthreads();
+  }
+  if (zero) {
+    if (tid == 0) status[sidx] = 3;
+    return;
+  }
+  // back substitution: S = U^-1 (right half), one right-hand column per thread
+  cplx<double> *Ss = S + it.r_off;
+  for (int cp = tid; cp < nc; cp += 256) {
+    for (int i = nc - 1; i >= 0; --i) {
+      cplx<double> acc = z[(long)i * w2 + nc + cp];
+      for (int j = i + 1; j < nc; ++j) acc = cfms(acc, z[(long)i * w2 + j], Ss[(long)j * nc + cp]);
+      Ss[(long)i * nc + cp] = cdiv(acc, z[(long)i * w2 + i]);
+    }
+  }
+  if (tid == 0) status[sidx] = 0;
+}
+
 // The collision matrix from R (see hp_smatrix), on workspace w laid out by ws;
 // hstat: host array of nc ints.
 static int smatrix_impl(const hp_system *sys, double E, const double *R, double *S, int *nopen, char *w,
@@ -333,3 +478,15 @@ extern "C" int hp_smatrix_noalloc(const hp_system *sys, double E, const double *
   return smatrix_impl(sys, E, R, S, nopen, w, ws, hstat, (hipStream_t)stream);
 }
 
+extern "C" int hp_batch_smatrix(int count, const hp_batch_item *items, const double *R, double *S, int *status,
+                                long sum_nc2, int nc_max, void *work, size_t work_bytes, void *stream) {
+  if (count < 1 || !items || !R || !S || !status || !work || sum_nc2 < 1 || nc_max < 1) return HP_ERR_ARG;
+  if (nc_max > kBatchSmatMaxChannels) return HP_ERR_UNSUPPORTED;
+  if (work_bytes < 2 * sizeof(cplx<double>) * (size_t)sum_nc2) return HP_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  TraceScope ts(TR_SMATRIX, st, 0.0, 0.0);
+  hipLaunchKernelGGL(batch_smatrix_kernel, dim3(count), dim3(256), 0, st, count, items, (const cplx<double> *)R,
+                     (cplx<double> *)S, (cplx<double> *)work, status);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}

@@ -61,7 +61,7 @@ EXPORTS = ["hp_mesh", "hp_workspace_bytes", "hp_build_matrix", "hp_factor", "hp_
            "hp_build_info", "hp_strerror", "hp_trace_enable", "hp_trace_read", "hp_last_error",
            "hp_gemm_sub", "hp_set_concurrency", "hp_set_solve_graphs", "hp_batch_workspace_bytes", "hp_batch_build",
            "hp_batch_factor", "hp_batch_factor_stepped", "hp_batch_solve_init", "hp_batch_refine_step", "hp_batch_active",
-           "hp_batch_status", "hp_batch_rmatrix"]
+           "hp_batch_status", "hp_batch_rmatrix", "hp_batch_smatrix"]
 
 _lib = None
 
@@ -124,7 +124,7 @@ def lib() -> ctypes.CDLL:
                                   c_void_p, c_size_t, c_void_p]
     L.hp_batch_factor.restype = c_int
     L.hp_batch_factor_stepped.argtypes = [c_int, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p,
-                                          c_void_p, c_int, c_void_p, c_size_t, c_void_p]
+                                          c_void_p, c_int, c_int, c_void_p, c_size_t, c_void_p]
     L.hp_batch_factor_stepped.restype = c_int
     L.hp_batch_solve_init.argtypes = [c_int, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                       c_int, c_long, c_long, c_void_p, c_size_t, c_void_p]
@@ -132,6 +132,9 @@ def lib() -> ctypes.CDLL:
     L.hp_batch_refine_step.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_double,
                                        c_long, c_long, c_void_p, c_size_t, c_void_p]
     L.hp_batch_refine_step.restype = c_int
+    L.hp_batch_smatrix.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_long, c_int, c_void_p,
+                                   c_size_t, c_void_p]
+    L.hp_batch_smatrix.restype = c_int
     L.hp_batch_active.argtypes = [c_void_p, P(ctypes.c_uint), c_void_p]
     L.hp_batch_active.restype = c_int
     L.hp_batch_status.argtypes = [c_int, c_void_p, c_void_p, c_void_p, c_void_p]
@@ -280,10 +283,11 @@ def hp_batch_factor(count, items, prec, A, ipiv, perm, info, panel, groups, work
                                  groups, _ptr(work), work.numel(), _stream(stream)), "hp_batch_factor")
 
 
-def hp_batch_factor_stepped(count, items, n_host, prec, A, ipiv, perm, info, panel, work, stream=None) -> None:
+def hp_batch_factor_stepped(count, items, n_host, prec, A, ipiv, perm, info, panel, block, work,
+                            stream=None) -> None:
     n = np.ascontiguousarray(n_host, dtype=np.int32)
     _check(lib().hp_batch_factor_stepped(count, _ptr(items), n.ctypes.data, prec, _ptr(A), _ptr(ipiv), _ptr(perm),
-                                         _ptr(info), panel, _ptr(work), work.numel(), _stream(stream)),
+                                         _ptr(info), panel, block, _ptr(work), work.numel(), _stream(stream)),
            "hp_batch_factor_stepped")
 
 
@@ -323,6 +327,12 @@ def hp_batch_status(count, work, stream=None):
 
 def hp_batch_rmatrix(count, items, X, R, stream=None) -> None:
     _check(lib().hp_batch_rmatrix(count, _ptr(items), _ptr(X), _ptr(R), _stream(stream)), "hp_batch_rmatrix")
+
+
+def hp_batch_smatrix(count, items, R, S, status, sum_nc2, nc_max, work, stream=None) -> None:
+    _check(lib().hp_batch_smatrix(count, _ptr(items), _ptr(R), _ptr(S), _ptr(status), int(sum_nc2), int(nc_max),
+                                  _ptr(work), work.numel() * work.element_size(), _stream(stream)),
+           "hp_batch_smatrix")
 
 
 def hp_set_concurrency(factorizations: int) -> int:

@@ -1,13 +1,16 @@
 """Batched uneven systems on the GPU (one workgroup per system).
 
 * small systems of the batch family (N <= 600) against the oracle: R and S
-  within 1e-10, FP64 and FP32 + refinement, for every panel width, in the
-  persistent and the stepped form of the factorization;
+  (batched collision-matrix kernel) within 1e-10, FP64 and FP32 +
+  refinement, for every panel width, in the persistent form and the stepped
+  form in one and two levels (outer blocks of 64 columns) of blocking;
 * larger systems (N up to ~2500) against the single-system path of the
   library: S within 1e-10;
 * refinement steps replayed from a captured graph give bit-identical X to
-  the same steps launched one by one;
-* every system reports convergence.
+  the same steps launched one by one; whole buckets replayed from a graph
+  give bit-identical R and S to the eager run, replay after replay;
+* every system reports convergence; forced non-convergence sends every
+  system to the FP64 single-system path, whose R and S match the oracle.
 """
 from __future__ import annotations
 
@@ -51,16 +54,19 @@ def small():
     return sps, refs
 
 
-@pytest.mark.parametrize("form", ["persistent", "stepped"])
+@pytest.mark.parametrize("form", ["persistent", "stepped", "stepped-blocked"])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("panel", [8, 16, 32])
 def test_small_batch_against_oracle(mods, small, prec, panel, form):
+    """Persistent form; stepped form in one level (outer block = panel) and
+    in two levels (outer blocks of 64 columns, ragged last block)."""
     H, B, P = mods
     sps, refs = small
     say("batch vs oracle", "prec", prec, "panel", panel, form, [sp.nc * sp.nr for sp in sps])
     bt = B.Batch(sps, [sp.energies[0] for sp in sps], prec)
     for b in bt.buckets:
-        bt.tuning[b.key] = B.BucketTuning(panel, 2 * bt.cus if form == "persistent" else 0, 0.0)
+        bt.tuning[b.key] = B.BucketTuning(panel, 2 * bt.cus if form == "persistent" else 0, 0.0,
+                                          64 if form == "stepped-blocked" else panel)
     bt.run()
     st, it = bt.status()
     assert np.all(st == 1), (st, it)
@@ -86,15 +92,67 @@ def test_larger_systems_match_single_path(mods):
 
 
 def test_graph_replay_matches_eager(mods):
+    """Refinement steps replayed from a captured step give bit for bit the X
+    of the same steps launched one by one (same factors, same solve form);
+    the persistent and the stepped factorization forms agree to rounding."""
     H, B, P = mods
     sps = family(64, 1159203, 1500)[:6]
     say("graph vs eager", [sp.nc * sp.nr for sp in sps])
     xs = []
-    for use_graph in (False, True, True):
+    for groups, use_graph in ((0, False), (0, True), (0, True), (512, False)):
         bk = B.Bucket(sps, [sp.energies[0] for sp in sps], list(range(len(sps))), H.HP_C64)
-        bk.factor(16, 0 if use_graph else 512)
+        bk.factor(16, groups, 16)
         steps = bk.solve(max_refine=30, use_graph=use_graph)
         torch.cuda.synchronize()
         xs.append((steps, bk.X.cpu().numpy().copy()))
     assert xs[0][0] == xs[1][0] == xs[2][0] and xs[0][0] >= 2
     assert np.array_equal(xs[0][1], xs[1][1]) and np.array_equal(xs[0][1], xs[2][1])
+    assert relerr(xs[3][1], xs[0][1]) < 1e-12
+
+
+def test_whole_bucket_graph_matches_eager(mods):
+    """A bucket replayed from its captured graph (build, factor, solves,
+    refinement steps, R, S) gives bit for bit the eager run's R and S, on
+    several replays with eager work and synchronisations between them."""
+    H, B, P = mods
+    sps = family(64, 1159204, 2600)[:6]
+    say("whole-bucket graph vs eager", [sp.nc * sp.nr for sp in sps])
+    for prec in (H.HP_C64, H.HP_C128):
+        bt = B.Batch(sps, [sp.energies[0] for sp in sps], prec, edges=())
+        for b in bt.buckets:
+            bt.tuning[b.key] = B.BucketTuning(16, 0, 0.0, 64)
+        bt.run(use_graph=False)
+        ref = [(R.copy(), S.copy()) for R, S in bt.results()]
+        bt.run(use_graph=True)  # eager, then captured
+        assert all(b.whole is not None for b in bt.buckets)
+        for rep in range(3):
+            bt.run(use_graph=True)  # replay
+            torch.cuda.synchronize()
+            got = bt.results()
+            for (R0, S0), (R1, S1) in zip(ref, got):
+                assert np.array_equal(R0, R1) and np.array_equal(S0, S1), (prec, rep)
+            x = torch.randn(1000, device="cuda").sum().item()  # eager work between replays
+            assert x == x
+
+
+def test_batched_fallback_to_fp64(mods, small):
+    """Forced non-convergence (one refinement step, unreachable tolerance):
+    every system reports status 2 and is solved again in FP64; R and S match
+    the oracle.  With fallback disabled, results() raises."""
+    H, B, P = mods
+    sps, refs = small
+    sps, refs = sps[:3], refs[:3]
+    say("batched fallback", [sp.nc * sp.nr for sp in sps])
+    bt = B.Batch(sps, [sp.energies[0] for sp in sps], H.HP_C64)
+    for b in bt.buckets:
+        bt.tuning[b.key] = B.BucketTuning(16, 0, 0.0, 64)
+    bt.run(max_refine=1, tol=1e-300, use_graph=False)
+    st, _ = bt.status()
+    assert np.all(st == 2), st
+    with pytest.raises(H.HprmatError):
+        bt.results(fallback=False)
+    out = bt.results()
+    assert sorted(bt.fallbacks) == list(range(len(sps)))
+    for (R, S), o in zip(out, refs):
+        assert relerr(R, o["R"]) < 1e-10
+        assert relerr(S, o["S"]) < 1e-10
