@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "N=25600 complex solve s & TF/s, FP32-LU+IR vs FP64 LU; served solves/s, p99"
 PEAK_FP32_MFMA = 157.3  # TF/s, MI355X dense FP32 matrix
 PEAK_FP64_MFMA = 78.6   # TF/s, MI355X dense FP64 matrix
+PEAK_FP16_MFMA = 2500.0  # TF/s, MI355X dense FP16 matrix
 # HBM bytes per launch of the FP32 GEMM on this command, over the launches
 # the roofline timers see (each step's factorization and first solve), from
 # FETCH_SIZE and WRITE_SIZE counter runs scaled by a 1 GiB copy
@@ -47,6 +48,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="large")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-update variant")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-refine", type=int, default=30)
     ap.add_argument("--tol", type=float, default=0.0)
@@ -239,6 +241,32 @@ def main():
     last_e = float(sp.energies[(args.steps - 1) % len(sp.energies)])
     del s32
     torch.cuda.empty_cache()
+
+    if not args.no_fp16:
+        # the FP16 variant: FP32 factors whose trailing updates run on the
+        # FP16 matrix cores (split operands under row/column scaling), the
+        # same FP64 refinement; same energies, same step count
+        s16 = P.Solver(d, H.HP_C64H)
+        print(f"[bench] fp16x3-update LU+IR N={n}", file=sys.stderr, flush=True)
+        t16, info16, g16, st16 = timed_steps(s16, sp.energies, args.steps, args.warmup, H, torch, "gemm_f16x3",
+                                             max_refine=args.max_refine, tol=args.tol)
+        ach16 = g16["flops"] / (g16["ms"] * 1e-3) / 1e12 if g16["ms"] > 0 else 0.0
+        import numpy as np
+        S16 = s16.S.cpu().numpy()
+        out["fp16x3_lu_ir"] = {
+            "ms_per_step": t16 * 1e3, "tflops": flops / t16 / 1e12,
+            "refinement_steps": [it for it, _, _ in info16],
+            "fp64_fallbacks": int(sum(1 for _, _, fb in info16 if fb)),
+            "S_relerr_vs_fp32ir_at_E": [last_e, float(np.max(np.abs(S16 - S32)) / np.max(np.abs(S32)))],
+            "stages_ms_one_step": {k: round(v["ms"], 3) for k, v in st16.items() if v["launches"]},
+            "roofline_update": {"bound": "mfma", "kernel": "split-FP16 complex GEMM (gemm_h3_kernel; achieved "
+                                                            "counts the 24MNK FP16 matrix-core flops per launch)",
+                                "achieved": ach16, "peak": PEAK_FP16_MFMA, "unit": "TF/s",
+                                "frac": ach16 / PEAK_FP16_MFMA,
+                                "launches_per_step": g16["launches"] / args.steps,
+                                "avg_launch_us": g16["ms"] * 1e3 / max(1, g16["launches"])}}
+        del s16
+        torch.cuda.empty_cache()
 
     if not args.no_fp64:
         s64 = P.Solver(d, H.HP_C128)

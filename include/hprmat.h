@@ -47,6 +47,12 @@ extern "C" {
 /* Working precision of the matrix and its LU factors. */
 #define HP_C128 0 /* complex FP64 */
 #define HP_C64 1  /* complex FP32 (factor); refinement residual stays FP64 */
+/* complex FP32 factor whose trailing updates run on the FP16 matrix cores
+ * under row and column scaling (split FP16 operands, FP32 accumulation;
+ * Sec. 3.2 / 3.4 mixed precision, the optional FP16 variant); the matrix and
+ * the factors are stored as with HP_C64, and every entry point that takes
+ * HP_C64 takes HP_C64H (only hp_factor computes differently) */
+#define HP_C64H 2
 
 /* Description of one coupled-channel system.  Scalars by value; arrays in
  * device memory, owned by the caller, read-only for the library. */
@@ -344,12 +350,12 @@ int hp_set_solve_graphs(int on);
  * bracketing the kernel launches of the selected stages with HIP events on
  * their stream: mask < 0 selects every stage, otherwise bit s selects stage s
  * (the order of the names below: assemble, panel, laswp, trsm, gemm_c128,
- * gemm_c64, residual, refine, rmatrix, smatrix); hp_trace_enable(0) stops.  hp_trace_read() waits for the recorded events,
+ * gemm_c64, residual, refine, rmatrix, smatrix, gemm_f16x3); hp_trace_enable(0) stops.  hp_trace_read() waits for the recorded events,
  * fills out[0 .. HP_TRACE_STAGES-1] (host array) with, per stage, the launch
  * count, summed kernel time (ms) and summed algorithmic flops and bytes of
  * those launches, clears the record and returns HP_TRACE_STAGES.
  * Errors: HP_ERR_ARG if max_stats < HP_TRACE_STAGES, HP_ERR_HIP. */
-#define HP_TRACE_STAGES 10
+#define HP_TRACE_STAGES 11
 typedef struct hp_trace_stat {
   const char *name; /* stage name, owned by the library */
   long launches;

@@ -13,8 +13,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhprmat.so")
 
-HIP_SOURCES = ["assemble.hip", "lu.hip", "gemm.hip", "solve.hip", "wsolve.hip", "coulomb.hip", "abi.hip", "trace.hip",
-               "batch.hip"]
+HIP_SOURCES = ["assemble.hip", "lu.hip", "gemm.hip", "gemm_h3.hip", "solve.hip", "wsolve.hip", "coulomb.hip", "abi.hip",
+               "trace.hip", "batch.hip"]
 CXX_SOURCES = ["mesh.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,

@@ -35,7 +35,7 @@ int ensure_dynamic_lds(const void *func, size_t bytes) {
 Workspace plan_workspace(int n, int nrhs, int prec) {
   Workspace w{};
   const size_t A = 256;
-  const size_t elt = (prec == HP_C64) ? sizeof(cplx<float>) : sizeof(cplx<double>);
+  const size_t elt = is_c64(prec) ? sizeof(cplx<float>) : sizeof(cplx<double>);
   size_t off = 0;
   w.sync_off = off;
   w.sync_bytes = align_up(factor_sync_bytes(std::max(n, 1)), A);
@@ -60,12 +60,12 @@ Workspace plan_workspace(int n, int nrhs, int prec) {
   w.inv_off = off;
   w.inv_bytes = align_up(inverse_bytes(n, prec), A);
   off += w.inv_bytes;
-  if (prec == HP_C64) {
+  if (is_c64(prec)) {
     w.u12_off = off;
     w.u12_bytes = align_up((size_t)kInvBlock * n * sizeof(cplx<float>), A);
     off += w.u12_bytes;
   }
-  if (prec == HP_C64 && nrhs > 0) {
+  if (is_c64(prec) && nrhs > 0) {
     w.wv_off = off;
     w.wv_bytes = align_up(wform_bytes(n), A);
     off += w.wv_bytes;
@@ -79,6 +79,14 @@ Workspace plan_workspace(int n, int nrhs, int prec) {
     w.wtmp_bytes = align_up(wform_tmp_bytes(n), A);
     off += w.wtmp_bytes;
   }
+  w.h3 = prec == HP_C64H;
+  if (w.h3) {  // the trailing update's operands: at most n rows of L21 and n columns of U12, K = kOuterBlock
+    w.h3_bytes = h3_operand_bytes(n, kOuterBlock);
+    w.h3a_off = off;
+    off += w.h3_bytes;
+    w.h3b_off = off;
+    off += w.h3_bytes;
+  }
   w.total = off;
   return w;
 }
@@ -88,14 +96,14 @@ Workspace plan_workspace(int n, int nrhs, int prec) {
 using namespace hp;
 
 extern "C" size_t hp_workspace_bytes(int n, int nrhs, int prec) {
-  if (n < 1 || nrhs < 0 || (prec != HP_C128 && prec != HP_C64)) return 0;
+  if (n < 1 || nrhs < 0 || !prec_ok(prec)) return 0;
   return plan_workspace(n, nrhs, prec).total;
 }
 
 extern "C" int hp_factor(int n, int prec, void *A, long lda, int *ipiv, int *perm, int *info, void *work,
                          size_t work_bytes, void *stream) {
   if (n < 1 || !A || !ipiv || !perm || !info || !work || lda < n) return HP_ERR_ARG;
-  if (prec != HP_C128 && prec != HP_C64) return HP_ERR_ARG;
+  if (!prec_ok(prec)) return HP_ERR_ARG;
   Workspace ws = plan_workspace(n, 0, prec);
   if (work_bytes < ws.total) return HP_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
@@ -107,7 +115,7 @@ extern "C" int hp_factor(int n, int prec, void *A, long lda, int *ipiv, int *per
 extern "C" int hp_lu_solve(int n, int nrhs, int prec, const void *LU, long lda, const int *perm, void *X, long ldx,
                            void *work, size_t work_bytes, void *stream) {
   if (n < 1 || nrhs < 1 || !LU || !perm || !X || !work || lda < n || ldx < nrhs) return HP_ERR_ARG;
-  if (prec != HP_C128 && prec != HP_C64) return HP_ERR_ARG;
+  if (!prec_ok(prec)) return HP_ERR_ARG;
   Workspace ws = plan_workspace(n, nrhs, prec);
   if (work_bytes < ws.total) return HP_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;

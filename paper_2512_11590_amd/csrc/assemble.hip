@@ -61,12 +61,12 @@ extern "C" int hp_build_matrix(const hp_system *sys, double E, int prec, void *C
   if (ldc < n) return HP_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
   dim3 grid((unsigned)n), block(256);
-  const double elt = (prec == HP_C64) ? 8.0 : 16.0;
+  const double elt = is_c64(prec) ? 8.0 : 16.0;
   TraceScope ts(TR_ASSEMBLE, st, 0.0, elt * (double)n * (double)n);
   if (prec == HP_C128) {
     hipLaunchKernelGGL(assemble_kernel<double>, grid, block, 0, st, sys->nc, sys->nr, sys->hbar2_2mu,
                        E, sys->tl, sys->r, sys->l, sys->eps, sys->v, (cplx<double> *)C, ldc);
-  } else if (prec == HP_C64) {
+  } else if (is_c64(prec)) {
     hipLaunchKernelGGL(assemble_kernel<float>, grid, block, 0, st, sys->nc, sys->nr, sys->hbar2_2mu,
                        E, sys->tl, sys->r, sys->l, sys->eps, sys->v, (cplx<float> *)C, ldc);
   } else {

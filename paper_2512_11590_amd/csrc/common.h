@@ -52,7 +52,7 @@ __host__ __device__ __forceinline__ cplx<T> cdiv(cplx<T> a, cplx<T> b) { return 
 // --------------------------------------------------------------- tracing --
 enum TraceCat {
   TR_ASSEMBLE = 0, TR_PANEL, TR_LASWP, TR_TRSM, TR_GEMM64, TR_GEMM32, TR_RESIDUAL, TR_REFINE, TR_RMATRIX,
-  TR_SMATRIX, TR_COUNT
+  TR_SMATRIX, TR_GEMM16, TR_COUNT
 };
 static_assert(TR_COUNT == HP_TRACE_STAGES, "trace stage count");
 bool trace_on();
@@ -112,8 +112,15 @@ struct Workspace {
   size_t wv_off, wv_bytes, inv2_off, inv2_bytes, z_off, z_bytes, wtmp_off, wtmp_bytes;
   // FP32 factorizations: one 128-row half of the U12 block row (128 x n)
   size_t u12_off, u12_bytes;
+  // HP_C64H factorizations: the split-FP16 operands of the trailing update
+  // (L21 rows and U12 columns with their scales)
+  bool h3;
+  size_t h3a_off, h3b_off, h3_bytes;
   size_t total;
 };
+// Storage precision of the factors: HP_C64H factors are complex FP32 like HP_C64.
+inline bool is_c64(int prec) { return prec == HP_C64 || prec == HP_C64H; }
+inline bool prec_ok(int prec) { return prec == HP_C128 || prec == HP_C64 || prec == HP_C64H; }
 Workspace plan_workspace(int n, int nrhs, int prec);
 
 // Internal launchers (defined in lu.hip).
@@ -148,6 +155,12 @@ template <typename T>
 int gemm_set_batched(int M, int N, int K, T alpha, const cplx<T> *A, long lda, long sa, const cplx<T> *B, long ldb,
                      long sb, cplx<T> *C, long ldc, long sc, int batch, hipStream_t st);
 size_t factor_sync_bytes(int n);
+// Split-FP16 trailing update (gemm_h3.hip): operand conversion and product.
+size_t h3_operand_bytes(int rows, int K);
+int h3_convert_rows(int M, int K, const cplx<float> *L, long lda, void *buf, hipStream_t st);
+int h3_convert_cols(int N, int K, const cplx<float> *U, long ldb, void *buf, hipStream_t st);
+int gemm_h3_sub(int M, int N, int K, const void *abuf, int Mtot, int r0, const void *bbuf, int Ntot, int c0,
+                cplx<float> *C, long ldc, hipStream_t st);
 size_t factor_slot_bytes();
 // Transformed form of an FP32 factor for repeated solves (wsolve.hip)
 size_t wform_bytes(int n);

@@ -22,6 +22,7 @@
 // XCD gets a contiguous range of tiles.
 #include "common.h"
 
+#include <cstdlib>
 #include <type_traits>
 
 namespace hp {
@@ -316,21 +317,24 @@ __device__ __forceinline__ void lds_direct_load16(unsigned lds_byte_addr, const 
                : "memory", "m0");
 }
 
-template <bool SET>
-__global__ __launch_bounds__(256, 4) void gemm_direct_kernel(int M, int N, int K, const cplx<float> *__restrict__ A,
-                                                             long lda, long sa, const cplx<float> *__restrict__ B,
-                                                             long ldb, long sb, cplx<float> *__restrict__ C, long ldc,
-                                                             long sc, int tm, int tn, int total, int per_xcd,
-                                                             float alpha) {
+// MW = 1: 64 x 64 tiles, each wavefront 32 x 32 outputs, held to three
+// wavefronts per SIMD (registers claimed up to v135), 32 KB of LDS: three
+// workgroups per CU leave room (LDS and registers) for a panel workgroup
+// beside them -- the panel runs next to the trailing update and its grid
+// only proceeds once all of its workgroups are resident.
+// MW = 2: 128 x 64 tiles, each wavefront 64 x 32 outputs (twice the matrix-
+// core work per operand read and per barrier), 48 KB of LDS, two workgroups
+// per CU (two wavefronts per SIMD), again with room for a panel workgroup.
+template <bool SET, int MW, bool CAP2 = false>
+__global__ __launch_bounds__(256, (MW == 1 ? 4 : 2)) void gemm_direct_kernel(
+    int M, int N, int K, const cplx<float> *__restrict__ A, long lda, long sa, const cplx<float> *__restrict__ B,
+    long ldb, long sb, cplx<float> *__restrict__ C, long ldc, long sc, int tm, int tn, int total, int per_xcd,
+    float alpha) {
   typedef typename Mfma<float>::v4 v4;
-  // Occupancy cap: claiming registers up to v135 holds the kernel to three
-  // wavefronts per SIMD, so at most three workgroups per CU (96 KB of LDS),
-  // which leaves room (LDS and registers) for a panel workgroup beside them:
-  // the panel runs next to the trailing update and its grid only proceeds
-  // once all of its workgroups are resident.  Three per CU run within 1 % of
-  // five on a large update.
-  asm volatile("" ::: "v135");
-  constexpr int BM = 64, BN = 64, BK = kDirectBK;
+  if constexpr (MW == 1) asm volatile("" ::: "v135");
+  if constexpr (CAP2) asm volatile("" ::: "v183");
+  constexpr int BM = 64 * MW, BN = 64, BK = kDirectBK;
+  constexpr int TI = 2 * MW;                 // 16-row MFMA tiles per wavefront
   constexpr int ACH = BK / 2;                // 16-byte chunks per A row
   constexpr int APW = BM * ACH / 64 / 4;     // A wave-loads per wavefront per stage
   constexpr int BPW = BK * (BN / 2) / 64 / 4;  // B wave-loads per wavefront per stage
@@ -355,7 +359,7 @@ __global__ __launch_bounds__(256, 4) void gemm_direct_kernel(int M, int N, int K
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * (16 * TI), wn = (wave & 1) * 32;
 
   // this lane's source chunks (k0 = 0) and its wavefront's LDS slots
   const cplx<float> *asrc[APW];
@@ -385,9 +389,9 @@ __global__ __launch_bounds__(256, 4) void gemm_direct_kernel(int M, int N, int K
           bsrc[i] + (long)k0 * ldb);
   };
 
-  v4 acc_re[2][2], acc_im[2][2], acc_p2[2][2];  // 3M: P1, P3, P2
+  v4 acc_re[TI][2], acc_im[TI][2], acc_p2[TI][2];  // 3M: P1, P3, P2
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       acc_re[i][j] = v4{0, 0, 0, 0};
@@ -408,9 +412,9 @@ __global__ __launch_bounds__(256, 4) void gemm_direct_kernel(int M, int N, int K
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kk = ks + fk;
-      cplx<float> af[2], bf[2];
+      cplx<float> af[TI], bf[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < TI; ++i) {
         const int row = wm + i * 16 + fr;
         af[i] = as[row * BK + 2 * ((kk >> 1) ^ ((row >> 1) & (ACH - 1))) + (kk & 1)];
       }
@@ -420,7 +424,7 @@ __global__ __launch_bounds__(256, 4) void gemm_direct_kernel(int M, int N, int K
 #pragma unroll
       for (int j = 0; j < 2; ++j) bsum[j] = bf[j].re + bf[j].im;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < TI; ++i) {
         const float asum = af[i].re + af[i].im;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -431,9 +435,9 @@ __global__ __launch_bounds__(256, 4) void gemm_direct_kernel(int M, int N, int K
       }
     }
   }
-  // epilogue as in gemm_sub_kernel
+  // epilogue as in gemm_sub_kernel, one 16-row tile at a time
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < TI; ++i) {
     cplx<float> cv[4][2];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -463,6 +467,18 @@ __global__ __launch_bounds__(256, 4) void gemm_direct_kernel(int M, int N, int K
   }
 }
 
+// Form of the direct-staged FP32 kernel (HP_GEMM_TILE): 64 (64-row tiles),
+// 128 (128-row tiles, occupancy as registers and LDS allow), 1282 (128-row
+// tiles held to two wavefronts per SIMD).
+static int direct_form() {
+  static const int form = [] {
+    const char *e = getenv("HP_GEMM_TILE");
+    const int v = e ? atoi(e) : 64;
+    return (v == 128 || v == 1282) ? v : 64;
+  }();
+  return form;
+}
+
 template <typename T, int WTM, int WTN, bool SET>
 static int launch_gemm(int M, int N, int K, const cplx<T> *A, long lda, long sa, const cplx<T> *B, long ldb,
                        long sb, cplx<T> *C, long ldc, long sc, int batch, T alpha, hipStream_t st) {
@@ -481,9 +497,21 @@ static int launch_gemm(int M, int N, int K, const cplx<T> *A, long lda, long sa,
   dim3 grid((unsigned)(8 * per_xcd));
   if constexpr (sizeof(T) == 4 && WTM == 2 && WTN == 2) {
     if (vec && K % kDirectBK == 0 && N % 2 == 0 && ldc > 0) {
-      const size_t dshm = (size_t)2 * 2 * 64 * kDirectBK * sizeof(cplx<float>);
-      hipLaunchKernelGGL((gemm_direct_kernel<SET>), grid, dim3(256), dshm, st, M, N, K, A, lda, sa, B, ldb, sb, C,
-                         ldc, sc, tm, tn, total, per_xcd, alpha);
+      const int form = direct_form();
+      const int rows = form == 64 ? 64 : 128;
+      const int dtm = (M + rows - 1) / rows;
+      const long dtotal_l = (long)dtm * tn * batch;
+      const int dtotal = (int)dtotal_l, dper = (dtotal + 7) / 8;
+      const size_t dshm = (size_t)2 * (rows + 64) * kDirectBK * sizeof(cplx<float>);
+      if (form == 128)
+        hipLaunchKernelGGL((gemm_direct_kernel<SET, 2>), dim3((unsigned)(8 * dper)), dim3(256), dshm, st, M, N, K,
+                           A, lda, sa, B, ldb, sb, C, ldc, sc, dtm, tn, dtotal, dper, alpha);
+      else if (form == 1282)
+        hipLaunchKernelGGL((gemm_direct_kernel<SET, 2, true>), dim3((unsigned)(8 * dper)), dim3(256), dshm, st, M, N,
+                           K, A, lda, sa, B, ldb, sb, C, ldc, sc, dtm, tn, dtotal, dper, alpha);
+      else
+        hipLaunchKernelGGL((gemm_direct_kernel<SET, 1>), grid, dim3(256), dshm, st, M, N, K, A, lda, sa, B, ldb, sb,
+                           C, ldc, sc, tm, tn, total, per_xcd, alpha);
       HP_CHECK_LAUNCH();
       return HP_OK;
     }

@@ -1099,7 +1099,7 @@ static int tri_inverse(int n, const cplx<T> *LU, long lda, cplx<T> *inv, int blk
 }
 
 size_t inverse_bytes(int n, int prec) {
-  if (prec != HP_C64) return 0;
+  if (!is_c64(prec)) return 0;
   const size_t nb = (size_t)(n + kInvBlock - 1) / kInvBlock;
   return 2 * nb * kInvBlock * kInvBlock * sizeof(cplx<float>);
 }
@@ -1394,14 +1394,33 @@ static int lu_factor_on(int n, cplx<T> *A, long lda, int *ipiv, int *perm, int *
     // workgroups to drain (10x slower there than here)
     if ((rc = invert_block<T>(n, k, A, lda, work, ws, st))) return rc;
     if ((rc = block_row_solve<T>(n, k, kb, rest, A, lda, work, ws, st))) return rc;
+    // trailing update A22 -= L21 U12 (the columns [c0, c0 + nc) of it): FP32
+    // or FP64 matrix cores, or with HP_C64H the split-FP16 operands made
+    // once per block from L21 and U12
+    bool h3 = false;
+    if constexpr (std::is_same<T, float>::value) h3 = ws.h3 && kb == kOuterBlock;
+    auto update = [&](int c0, int ncols) -> int {
+      if constexpr (std::is_same<T, float>::value) {
+        if (h3)
+          return gemm_h3_sub(rest, ncols, kb, work + ws.h3a_off, rest, 0, work + ws.h3b_off, rest, c0, A22 + c0, lda,
+                             st);
+      }
+      return gemm_sub<T>(rest, ncols, kb, L21, lda, U12 + c0, lda, A22 + c0, lda, st);
+    };
+    if constexpr (std::is_same<T, float>::value) {
+      if (h3) {
+        if ((rc = h3_convert_rows(rest, kb, L21, lda, work + ws.h3a_off, st))) return rc;
+        if ((rc = h3_convert_cols(rest, kb, U12, lda, work + ws.h3b_off, st))) return rc;
+      }
+    }
     // the next block's columns first
-    if ((rc = gemm_sub<T>(rest, kb2, kb, L21, lda, U12, lda, A22, lda, st))) return rc;
+    if ((rc = update(0, kb2))) return rc;
     if (rest > kb2) {  // here n > 2 kOuterBlock, so la is set
       HP_CHECK_HIP(hipEventRecord(la->ready, st));
       HP_CHECK_HIP(hipStreamWaitEvent(la->panel, la->ready, 0));
       if ((rc = factor_block<T>(n, k2, kb2, A, lda, ipiv, info, bars, slots, la->panel))) return rc;
       HP_CHECK_HIP(hipEventRecord(la->done, la->panel));
-      if ((rc = gemm_sub<T>(rest, rest - kb2, kb, L21, lda, U12 + kb2, lda, A22 + kb2, lda, st))) return rc;
+      if ((rc = update(kb2, rest - kb2))) return rc;
       HP_CHECK_HIP(hipStreamWaitEvent(st, la->done, 0));
     } else {
       if ((rc = factor_block<T>(n, k2, kb2, A, lda, ipiv, info, bars, slots, st))) return rc;

@@ -423,7 +423,7 @@ extern "C" int hp_solve(const hp_system *sys, double E, int prec, const void *LU
                         size_t work_bytes, hp_solve_info *info, void *stream) {
   if (!sys_ok(sys) || !LU || !perm || !X || !work) return HP_ERR_ARG;
   const long n = (long)sys->nc * sys->nr;
-  if (lda < n || (prec != HP_C128 && prec != HP_C64) || max_refine < 0) return HP_ERR_ARG;
+  if (lda < n || !prec_ok(prec) || max_refine < 0) return HP_ERR_ARG;
   Workspace ws = plan_workspace((int)n, sys->nc, prec);
   if (work_bytes < ws.total) return HP_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;

@@ -37,8 +37,8 @@ hipEvent_t get_event() {
 }
 }  // namespace
 
-const char *const kTraceNames[TR_COUNT] = {"assemble", "panel",    "laswp",   "trsm",    "gemm_c128",
-                                           "gemm_c64", "residual", "refine",  "rmatrix", "smatrix"};
+const char *const kTraceNames[TR_COUNT] = {"assemble", "panel",    "laswp",   "trsm",    "gemm_c128",  "gemm_c64",
+                                           "residual", "refine",   "rmatrix", "smatrix", "gemm_f16x3"};
 
 bool trace_on() { return g_on; }
 

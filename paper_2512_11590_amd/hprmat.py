@@ -27,6 +27,7 @@ HP_ERR_SYNC = -7
 
 HP_C128 = 0
 HP_C64 = 1
+HP_C64H = 2  # complex FP32 factors, split-FP16 trailing updates under row/column scaling
 
 c_int, c_long, c_double, c_void_p, c_size_t = (ctypes.c_int, ctypes.c_long, ctypes.c_double,
                                                ctypes.c_void_p, ctypes.c_size_t)
@@ -48,7 +49,7 @@ class HpTraceStat(ctypes.Structure):
                 ("bytes", c_double)]
 
 
-HP_TRACE_STAGES = 10
+HP_TRACE_STAGES = 11
 
 
 class HpSolveInfo(ctypes.Structure):

@@ -61,7 +61,9 @@ class EnergyResult:
 
 
 class Solver:
-    """Buffers for one system in one working precision (HP_C64 or HP_C128)."""
+    """Buffers for one system in one working precision: HP_C128, HP_C64, or
+    HP_C64H (FP32 factors whose trailing updates run on the FP16 matrix cores
+    under row and column scaling)."""
 
     def __init__(self, dsys: DeviceSystem, prec: int = H.HP_C64, ld: int | None = None,
                  fallback: bool = True):
@@ -71,7 +73,7 @@ class Solver:
         n, nc = dsys.n, dsys.nc
         self.ld = ld or n
         dev = dsys.device
-        ctype = torch.complex64 if prec == H.HP_C64 else torch.complex128
+        ctype = torch.complex128 if prec == H.HP_C128 else torch.complex64
         self.A = torch.empty((n, self.ld), dtype=ctype, device=dev)
         self.ipiv = torch.empty(n, dtype=torch.int32, device=dev)
         self.perm = torch.empty(n, dtype=torch.int32, device=dev)
@@ -93,11 +95,11 @@ class Solver:
 
     def run(self, E: float, max_refine: int = 30, tol: float = 0.0, smatrix: bool = True) -> EnergyResult:
         self.factor(E)
-        code, info = self.solve(E, max_refine if self.prec == H.HP_C64 else 0, tol)
+        code, info = self.solve(E, max_refine if self.prec != H.HP_C128 else 0, tol)
         iterations, backward = info.iterations, info.residual
         used_fallback = False
         if code != H.HP_OK:
-            if not (self.fallback and self.prec == H.HP_C64 and code in (H.HP_ERR_NOCONV, H.HP_ERR_SINGULAR)):
+            if not (self.fallback and self.prec != H.HP_C128 and code in (H.HP_ERR_NOCONV, H.HP_ERR_SINGULAR)):
                 raise H.HprmatError(code, "hp_solve")
             if self._fp64 is None:
                 self._fp64 = Solver(self.d, H.HP_C128, fallback=False)
