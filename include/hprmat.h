@@ -256,11 +256,13 @@ int hp_batch_factor(int count, const hp_batch_item *items, int prec, void *A, in
  * trailing update with K = block (Sec. 3.1's blocked LU with the update
  * deferred to the end of each outer block).  Each step is one launch over
  * every system still factoring: the panels' column steps one workgroup per
- * system, the block rows and the updates as tiles of all systems, so the
- * device is filled by tiles rather than by systems.  block == panel is the
- * one-level form.  n_host: HOST array of the systems' n, which must be
- * listed largest first (HP_ERR_ARG otherwise).  work: at least 256 + 4 *
- * (ceil(nmax / panel) + 2 ceil(nmax / block)) * (count + 1) bytes (the batch
+ * system (interchanges inside the panel), then each panel's interchanges on
+ * the other columns with its block row, the outer block rows and the
+ * updates as column chunks and tiles of all systems, so the device is
+ * filled by tiles rather than by systems.  block == panel is the one-level
+ * form.  n_host: HOST array of the systems' n, which must be listed largest
+ * first (HP_ERR_ARG otherwise).  work: at least 256 + 4 * (2 ceil(nmax /
+ * panel) + 2 ceil(nmax / block)) * (count + 1) bytes (the batch
  * workspace of hp_batch_workspace_bytes is enough).  Errors: HP_ERR_ARG,
  * HP_ERR_WORKSPACE, HP_ERR_HIP. */
 int hp_batch_factor_stepped(int count, const hp_batch_item *items, const int *n_host, int prec, void *A,
@@ -273,7 +275,7 @@ int hp_batch_factor_stepped(int count, const hp_batch_item *items, const int *n_
  * systems with a zero pivot (info_factor) are marked and left alone.
  * shape_host: NULL (one workgroup solves each system) or the HOST (n, nc)
  * pairs of the systems, largest n first, for the stepped form (per block of
- * 32 rows one launch of every system's diagonal block and one of all update
+ * 64 rows one launch of every system's diagonal block and one of all update
  * tiles).  No host synchronisation.  work: hp_batch_workspace_bytes(...). */
 int hp_batch_solve_init(int count, const hp_batch_item *items, const int *shape_host, int prec, const void *LU,
                         const int *perm, const int *info_factor, double *X, int refine, long sum_nc,
@@ -325,15 +327,16 @@ int hp_batch_rmatrix(int count, const hp_batch_item *items, const double *X, dou
  * workgroups wait for each other at every column, so they must be resident
  * together.  With 1, each factorization runs on its caller's stream (plus the
  * look-ahead stream) with panel workgroups of up to ~150 KB of LDS.  With
- * k > 1, factorizations of n > 256 are serialized on one device-wide stream (the
- * caller's stream hands over and waits by events; its other work still
+ * k > 1, factorizations of n > 256 are serialized on one device-wide stream
+ * (the caller's stream hands over and waits by events; its other work still
  * overlaps with other streams), and panel workgroups hold 64 KB of rows, or
  * the ceil(n / 128) rows that a grid of 128 workgroups needs when that is
- * more, so that they find room beside other streams' kernels (the same
- * limit as with 1 applies: about 150 KB of rows per workgroup, beyond which
- * hp_factor fails with HP_ERR_UNSUPPORTED).  Returns the previous setting, or HP_ERR_ARG
- * if k is outside [1, 256].  Host-side setting; takes effect for
- * factorizations enqueued afterwards. */
+ * more, so that they find room beside other streams' kernels (up to ~150 KB
+ * of rows per workgroup, beyond which hp_factor fails with
+ * HP_ERR_UNSUPPORTED).  Factorizations that must overlap each other use the
+ * batched entry points, which have no grid-wide waits.  Returns the previous
+ * setting, or HP_ERR_ARG if k is outside [1, 256].  Host-side setting; takes
+ * effect for factorizations enqueued afterwards. */
 int hp_set_concurrency(int k);
 
 /* Whether hp_solve replays the refinement solves of FP32 factors from a HIP

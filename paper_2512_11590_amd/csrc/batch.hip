@@ -62,7 +62,7 @@ constexpr size_t tile_lds_bytes() {
 
 // One 64 x 64 output tile (m0, n0) of C[M x N] -= A[M x K] B[K x N] by one
 // workgroup: K in chunks of kBK, each chunk's A and B staged k-major in LDS
-// (the next chunk's loads are in flight while the current one is
+// (in FP32 the next chunk's loads are in flight while the current one is
 // multiplied), four wavefronts of 32 x 32 outputs, MFMA 16x16x4.  FP32:
 // three real products per complex product (3M), FP64: four (4M).  A, B and
 // C must not overlap.  The LDS tiles are free again when it returns (its last
@@ -81,7 +81,7 @@ __device__ __forceinline__ void tile_gemm_sub(int m0, int n0, int M, int N, int 
   cplx<T> ra[NS], rb[NS];
   // a chunk's loads at clamped addresses (in bounds, no branch to wait on);
   // out-of-range values are masked to zero when stored
-  auto load = [&](int kc) {
+  auto load = [&](int kc) __attribute__((always_inline)) {
     const int kb = min(kBK, K - kc), Kp = (kb + 3) & ~3;
 #pragma unroll
     for (int u = 0; u < NS; ++u) {
@@ -97,9 +97,14 @@ __device__ __forceinline__ void tile_gemm_sub(int m0, int n0, int M, int N, int 
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) p1[i][j] = p2[i][j] = p3[i][j] = v4{0, 0, 0, 0};
+  // FP32: the next chunk's loads are issued before the current chunk's
+  // products; FP64 loads each chunk at its start (its registers would not
+  // fit beside the accumulators of the 4M product)
+  constexpr bool kPrefetch = sizeof(T) == 4;
   load(0);
   for (int kc = 0; kc < K; kc += kBK) {
     const int kb = min(kBK, K - kc), Kp = (kb + 3) & ~3;
+    if (!kPrefetch && kc > 0) load(kc);
 #pragma unroll
     for (int u = 0; u < NS; ++u) {
       const int e = tid + 256 * u;
@@ -111,7 +116,7 @@ __device__ __forceinline__ void tile_gemm_sub(int m0, int n0, int M, int N, int 
       }
     }
     __syncthreads();
-    if (kc + kBK < K) load(kc + kBK);
+    if (kPrefetch && kc + kBK < K) load(kc + kBK);
     for (int ks = 0; ks < Kp; ks += 4) {
       const int kk = ks + fk;
       cplx<T> af[2], bf[2];
@@ -139,26 +144,24 @@ __device__ __forceinline__ void tile_gemm_sub(int m0, int n0, int M, int N, int 
     }
     __syncthreads();
   }
-  // C: all eight loads of the thread in flight at once (clamped addresses),
-  // then the updates, stored where in range
-  cplx<T> cv[2][4][2];
+  // C, one 16-row tile at a time: its eight loads in flight at once
+  // (clamped addresses), then the updates, stored where in range
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2; ++i) {
+    cplx<T> cv[4][2];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gr = min(m0 + wm + i * 16 + BMfma<T>::d_row(lane, r), M - 1);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) cv[i][r][j] = C[(long)gr * ldc + min(n0 + wn + j * 16 + fr, N - 1)];
+      for (int j = 0; j < 2; ++j) cv[r][j] = C[(long)gr * ldc + min(n0 + wn + j * 16 + fr, N - 1)];
     }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gr = m0 + wm + i * 16 + BMfma<T>::d_row(lane, r);
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int gc = n0 + wn + j * 16 + fr;
-        cplx<T> c = cv[i][r][j];
+        cplx<T> c = cv[r][j];
         if constexpr (M3) {
           c.re -= p1[i][j][r] - p2[i][j][r];
           c.im -= p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
@@ -169,6 +172,7 @@ __device__ __forceinline__ void tile_gemm_sub(int m0, int n0, int M, int N, int 
         if (gr < M && gc < N) C[(long)gr * ldc + gc] = c;
       }
     }
+  }
 }
 
 // All of C[M x N] -= A[M x K] B[K x N] by one workgroup, tile after tile.
@@ -271,9 +275,8 @@ __global__ __launch_bounds__(256) void batch_build_kernel(int count, const hp_ba
 // upper (backward, dividing by the diagonal).  D: the block in LDS at
 // stride LP (kBK + 1 by default), zero past bs.  Rows are taken 8 at a time
 // in registers; the rows solved before such a group (above it forward, below
-// it backward) are read back from y.  Both solve forms of the batch, and the
-// block rows of both factorization forms, use this routine, so their results
-// agree bit for bit.
+// it backward) are read back from y.  Both solve forms of the batch and the
+// block rows of both factorization forms use this routine.
 template <typename T, int LP = kBK + 1>
 __device__ __forceinline__ void diag_block_solve(const cplx<T> *D, cplx<T> *__restrict__ y, int nc, int b0, int bs,
                                                  int c, bool upper) {
@@ -325,25 +328,30 @@ __device__ __forceinline__ void stage_diag_block(cplx<T> *D, const cplx<T> *__re
   }
 }
 
-// Column steps of the panel [j0, j0 + w) of one n x n system and its block
-// row over the columns [j0 + w, cend), by one workgroup.  Records the
-// pivots, and the first exactly zero pivot column (1-based) in *first_zero if
-// it is still 0.
+// Column steps of the panel [j0, j0 + w) of one n x n system, by one
+// workgroup.  Records the pivots, and the first exactly zero pivot column
+// (1-based) in *first_zero if it is still 0.  The candidate of column j + 1
+// is found while column j's update writes it (one pass over the panel rows
+// per column).  full_rows: every interchange is applied to the whole row at
+// once and the block row U12 = L11^-1 A12 over [j0 + w, n) follows (the
+// persistent form); otherwise the interchanges touch the panel's columns
+// only, and batch_swap_brow_kernel applies them to the other columns and
+// forms the block row afterwards (the stepped form).
 template <typename T>
-__device__ void panel_steps(cplx<T> *a, int n, int j0, int w, int cend, int *piv, int *first_zero, cplx<T> *urow,
-                            T *sv, int *sr, cplx<T> *D) {
+__device__ void panel_steps(cplx<T> *a, int n, int j0, int w, bool full_rows, int *piv, int *first_zero,
+                            cplx<T> *urow, T *sv, int *sr, cplx<T> *D) {
   const int tid = threadIdx.x;
+  T best = T(-1);
+  int brow = INT_MAX;
+  for (int r = j0 + tid; r < n; r += 256) {
+    const T v = cabs1(a[(long)r * n + j0]);
+    if (v > best || (v == best && r < brow)) {
+      best = v;
+      brow = r;
+    }
+  }
   for (int jj = 0; jj < w; ++jj) {
     const int j = j0 + jj;
-    T best = T(-1);
-    int brow = INT_MAX;
-    for (int r = j + tid; r < n; r += 256) {
-      const T v = cabs1(a[(long)r * n + j]);
-      if (v > best || (v == best && r < brow)) {
-        best = v;
-        brow = r;
-      }
-    }
     wg_argmax(best, brow, sv, sr);
     const int p = (brow >= j && brow < n) ? brow : j;
     const bool nz = best > T(0);
@@ -351,32 +359,45 @@ __device__ void panel_steps(cplx<T> *a, int n, int j0, int w, int cend, int *piv
       piv[j] = p;
       if (!nz && *first_zero == 0) *first_zero = j + 1;
     }
-    if (p != j)
-      for (int c = tid; c < n; c += 256) {
+    if (p != j) {
+      const int c0 = full_rows ? 0 : j0, c1 = full_rows ? n : j0 + w;
+      for (int c = c0 + tid; c < c1; c += 256) {
         const cplx<T> x = a[(long)j * n + c];
         a[(long)j * n + c] = a[(long)p * n + c];
         a[(long)p * n + c] = x;
       }
+    }
     __syncthreads();
     if (tid < w) urow[tid] = a[(long)j * n + j0 + tid];
     __syncthreads();
-    if (nz) {
-      const cplx<T> inv = crcp(urow[jj]);
-      for (int r = j + 1 + tid; r < n; r += 256) {
-        cplx<T> *row = a + (long)r * n + j0;
+    best = T(-1);
+    brow = INT_MAX;
+    const bool next = jj + 1 < w;
+    const cplx<T> inv = nz ? crcp(urow[jj]) : cplx<T>{T(0), T(0)};
+    for (int r = j + 1 + tid; r < n; r += 256) {
+      cplx<T> *row = a + (long)r * n + j0;
+      if (nz) {
         const cplx<T> l = cmul(row[jj], inv);
         row[jj] = l;
         for (int c = jj + 1; c < w; ++c) row[c] = cfms(row[c], l, urow[c]);
       }
+      if (next) {
+        const T v = cabs1(row[jj + 1]);
+        if (v > best || (v == best && r < brow)) {
+          best = v;
+          brow = r;
+        }
+      }
     }
     __syncthreads();
   }
+  if (!full_rows) return;
   // U12 = L11^-1 A12: L11 staged in LDS (D: kBK x (kBK + 1)), each column
   // of A12 by diag_block_solve (the terms in the same order as a plain
   // substitution)
   stage_diag_block<T>(D, a, n, j0, w);
   __syncthreads();
-  for (int c = j0 + w + tid; c < cend; c += 256) diag_block_solve<T>(D, a + (long)j0 * n, n, 0, w, c, false);
+  for (int c = j0 + w + tid; c < n; c += 256) diag_block_solve<T>(D, a + (long)j0 * n, n, 0, w, c, false);
   __syncthreads();
 }
 
@@ -417,7 +438,7 @@ __global__ __launch_bounds__(256) void batch_lu_kernel(int count, const hp_batch
     __syncthreads();
     for (int j0 = 0; j0 < n; j0 += W) {
       const int w = min(W, n - j0);
-      panel_steps<T>(a, n, j0, w, n, piv, &s_zero, urow, sv, sr, As);  // As is free until the product
+      panel_steps<T>(a, n, j0, w, true, piv, &s_zero, urow, sv, sr, As);  // As is free until the product
       const int rest = n - j0 - w;
       if (rest > 0)
         wg_gemm_sub<T>(rest, rest, w, a + (long)(j0 + w) * n + j0, n, a + (long)j0 * n + j0 + w, n,
@@ -457,11 +478,11 @@ __global__ __launch_bounds__(256) void batch_panel_kernel(const hp_batch_item *_
   const int n = item_n(it);
   if (j0 >= n) return;
   const int w = min(W, n - j0);
-  const int cend = min((j0 / NB + 1) * NB, n);  // end of the outer block
+  (void)NB;
   int *piv = ipiv + it.p_off;
   if (threadIdx.x == 0) s_zero = info[s];
   __syncthreads();
-  panel_steps<T>(A + it.a_off, n, j0, w, cend, piv, &s_zero, urow, sv, sr, D);
+  panel_steps<T>(A + it.a_off, n, j0, w, false, piv, &s_zero, urow, sv, sr, D);
   if (threadIdx.x == 0) {
     info[s] = s_zero;
     if (j0 + w == n) compose_perm(piv, perm + it.p_off, n);
@@ -472,7 +493,10 @@ __global__ __launch_bounds__(256) void batch_panel_kernel(const hp_batch_item *_
 //   kind 0, inner update after the panel at j0: rows [j0 + w, n) x columns
 //     [j0 + w, end of the outer block), K = w;
 //   kind 1, outer update of the block at J: rows and columns [J + NB, n), K = NB;
-//   kind 2, block row of the block at J: columns [J + NB, n) in chunks of 256.
+//   kind 2, block row of the block at J: columns [J + NB, n) in chunks of 256;
+//   kind 3, after the panel at j0: its interchanges on every column outside
+//     the panel, and the panel's block row over [j0 + w, end of the outer
+//     block), columns in chunks of 256.
 struct StepShape {
   int r0, rows, c0, cols, k0, K;
 };
@@ -497,6 +521,7 @@ __device__ __host__ inline StepShape step_shape(int kind, int n, int j, int W, i
   return sh;
 }
 __device__ __host__ inline int step_units(int kind, int n, int j, int W, int NB) {
+  if (kind == 3) return j < n ? (n - min(W, n - j) + 255) / 256 : 0;
   const StepShape sh = step_shape(kind, n, j, W, NB);
   if (sh.rows <= 0 || sh.cols <= 0) return 0;
   if (kind == 2) return (sh.cols + 255) / 256;
@@ -505,8 +530,9 @@ __device__ __host__ inline int step_units(int kind, int n, int j, int W, int NB)
 
 // Work-unit offsets of every tiled step: offs[q * (count + 1) + s] = units of
 // systems [0, s) at step q (exclusive prefix sum).  Steps q < P are the inner
-// updates after the panels at j = q W; then, per outer block b (J = b NB),
-// the block row (P + 2b) and the outer update (P + 2b + 1).
+// updates after the panels at j = q W, steps P <= q < 2P their interchange
+// and block-row steps; then, per outer block b (J = b NB), the block row
+// (2P + 2b) and the outer update (2P + 2b + 1).
 __global__ void batch_tables_kernel(int count, const hp_batch_item *__restrict__ items, int W, int NB, int P,
                                     int *offs) {
   const int q = blockIdx.x;
@@ -515,9 +541,12 @@ __global__ void batch_tables_kernel(int count, const hp_batch_item *__restrict__
   if (q < P) {
     kind = 0;
     j = q * W;
+  } else if (q < 2 * P) {
+    kind = 3;
+    j = (q - P) * W;
   } else {
-    kind = ((q - P) & 1) ? 1 : 2;
-    j = ((q - P) >> 1) * NB;
+    kind = ((q - 2 * P) & 1) ? 1 : 2;
+    j = ((q - 2 * P) >> 1) * NB;
   }
   int acc = 0;
   int *o = offs + (long)q * (count + 1);
@@ -560,6 +589,43 @@ __global__ __launch_bounds__(256) void batch_trail_kernel(int count, const hp_ba
   cplx<T> *a = A + it.a_off;
   tile_gemm_sub<T>((l / tn) * 64, (l % tn) * 64, sh.rows, sh.cols, sh.K, a + (long)sh.r0 * n + sh.k0, n,
                    a + (long)sh.k0 * n + sh.c0, n, a + (long)sh.r0 * n + sh.c0, n, As, Bs);
+}
+
+// After the panel at j of every system (kind 3 units): the panel's
+// interchanges on every column outside it, 256 columns per workgroup, one per
+// thread, in the order they were chosen; for the columns [j + w, end of the
+// outer block) then the panel's block row by diag_block_solve with the
+// panel's L11 staged in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void batch_swap_brow_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                              cplx<T> *__restrict__ A, const int *__restrict__ ipiv,
+                                                              const int *__restrict__ offs, int j, int W, int NB) {
+  __shared__ cplx<T> D[kBK * (kBK + 1)];
+  __shared__ int sp[kBK];
+  const int g = blockIdx.x;
+  if (g >= offs[count]) return;
+  const int s = unit_owner(offs, count, g);
+  const hp_batch_item it = items[s];
+  const int n = item_n(it);
+  const int w = min(W, n - j);
+  const int cend = min((j / NB + 1) * NB, n);
+  cplx<T> *a = A + it.a_off;
+  const int *piv = ipiv + it.p_off;
+  if (threadIdx.x < w) sp[threadIdx.x] = piv[j + threadIdx.x];
+  stage_diag_block<T>(D, a, n, j, w);
+  __syncthreads();
+  const int x = (g - offs[s]) * 256 + (int)threadIdx.x;
+  if (x >= n - w) return;
+  const int c = x < j ? x : x + w;
+  for (int k = 0; k < w; ++k) {
+    const int p = sp[k];
+    if (p != j + k) {
+      const cplx<T> v = a[(long)(j + k) * n + c];
+      a[(long)(j + k) * n + c] = a[(long)p * n + c];
+      a[(long)p * n + c] = v;
+    }
+  }
+  if (c >= j + w && c < cend) diag_block_solve<T>(D, a + (long)j * n, n, 0, w, c, false);
 }
 
 // Block row of the outer block at J of every system: U12 = L11^-1 A12 over
@@ -867,9 +933,10 @@ __global__ void batch_rmatrix_kernel(int count, const hp_batch_item *__restrict_
 }
 
 // ------------------------------------------------------- stepped solves --
-// The solves of a bucket of larger systems, in steps of kBK rows: per step
+// The solves of a bucket of larger systems, in steps of kSB rows: per step
 // one launch of every system's diagonal block (one thread per right-hand
-// column) and one launch of all update tiles of the rows beyond it.
+// column) and one launch of all update tiles of the rows beyond it (K = kSB).
+constexpr int kSB = 64;
 
 // P B (mode 0) or P R / s (mode 1, systems still refining) into Y.
 template <typename T>
@@ -917,7 +984,7 @@ __global__ __launch_bounds__(256) void batch_widen_kernel(int count, const hp_ba
 __global__ void batch_solve_tiles_kernel(int count, const hp_batch_item *__restrict__ items, int *fwd, int *bwd) {
   const int t = blockIdx.x;
   if (threadIdx.x != 0) return;
-  const int b0 = t * kBK;
+  const int b0 = t * kSB;
   int af = 0, ab = 0;
   int *of = fwd + (long)t * (count + 1), *ob = bwd + (long)t * (count + 1);
   for (int s = 0; s < count; ++s) {
@@ -925,7 +992,7 @@ __global__ void batch_solve_tiles_kernel(int count, const hp_batch_item *__restr
     ob[s] = ab;
     const int nc = items[s].sys.nc, n = item_n(items[s]);
     if (b0 < n) {
-      const int below = n - b0 - min(kBK, n - b0);
+      const int below = n - b0 - min(kSB, n - b0);
       const int tn = (nc + 63) / 64;
       af += ((below + 63) / 64) * tn;
       ab += ((b0 + 63) / 64) * tn;
@@ -942,17 +1009,22 @@ template <typename T>
 __global__ __launch_bounds__(256) void batch_sdiag_kernel(const hp_batch_item *__restrict__ items,
                                                           const cplx<T> *__restrict__ LU, cplx<T> *__restrict__ Y,
                                                           int b0, int upper, const BatchState *state) {
-  __shared__ cplx<T> D[kBK * (kBK + 1)];
+  // every lane reads the same element of D (a broadcast), so no padding
+  __shared__ cplx<T> D[kSB * kSB];
   const int s = blockIdx.x;
   if (state && state[s].status != 0) return;
   const hp_batch_item it = items[s];
   const int nc = it.sys.nc, n = item_n(it);
   if (b0 >= n) return;
-  const int bs = min(kBK, n - b0);
-  stage_diag_block<T>(D, LU + it.a_off, n, b0, bs);
+  const int bs = min(kSB, n - b0);
+  const cplx<T> *lu = LU + it.a_off;
+  for (int e = threadIdx.x; e < kSB * kSB; e += blockDim.x) {
+    const int r = e / kSB, k = e - r * kSB;
+    D[e] = (r < bs && k < bs) ? lu[(long)(b0 + r) * n + b0 + k] : cplx<T>{T(0), T(0)};
+  }
   __syncthreads();
   cplx<T> *y = Y + it.x_off;
-  for (int c = threadIdx.x; c < nc; c += 256) diag_block_solve<T>(D, y, nc, b0, bs, c, upper != 0);
+  for (int c = threadIdx.x; c < nc; c += 256) diag_block_solve<T, kSB>(D, y, nc, b0, bs, c, upper != 0);
 }
 
 // Update tiles of a solve step: forward Y[b0+bs:n] -= L[b0+bs:n, b0:b0+bs] Y[b0:b0+bs],
@@ -978,7 +1050,7 @@ __global__ __launch_bounds__(256) void batch_strail_kernel(int count, const hp_b
   if (state && state[lo].status != 0) return;
   const hp_batch_item it = items[lo];
   const int nc = it.sys.nc, n = item_n(it);
-  const int bs = min(kBK, n - b0);
+  const int bs = min(kSB, n - b0);
   const int tn = (nc + 63) / 64;
   const int l = g - offs[lo];
   const cplx<T> *lu = LU + it.a_off;
@@ -999,7 +1071,7 @@ struct BatchWork {
   int *fwd, *bwd;     // [steps][count + 1] tile offsets of the stepped solves
 };
 
-int solve_steps(int nmax) { return (nmax + kBK - 1) / kBK; }
+int solve_steps(int nmax) { return (nmax + kSB - 1) / kSB; }
 
 BatchWork carve(char *w, int count, long sum_nc, long sum_xn, int prec) {
   const size_t elt = prec == HP_C64 ? sizeof(cplx<float>) : sizeof(cplx<double>);
@@ -1025,7 +1097,7 @@ size_t batch_bytes(int count, long sum_nc, long sum_xn, int nmax, int prec) {
   return 256 + align_up(sizeof(BatchState) * (size_t)count, 256) + align_up(sizeof(double) * (size_t)sum_nc, 256) +
          align_up(sizeof(cplx<double>) * (size_t)sum_xn, 256) + align_up(elt * (size_t)sum_xn, 256) +
          align_up(sizeof(int) * 2 * (size_t)solve_steps(std::max(nmax, 1)) * (count + 1), 256) +
-         align_up(sizeof(int) * 3 * (size_t)std::max(nmax, 1) * (count + 1), 256);  // stepped factor tables
+         align_up(sizeof(int) * 4 * (size_t)std::max(nmax, 1) * (count + 1), 256);  // stepped factor tables
 }
 
 // shape_host: HOST (n, nc) pairs of the systems, largest n first.
@@ -1057,13 +1129,13 @@ int stepped_solve(int count, const hp_batch_item *items, const int *shape_host, 
     const int upper = pass;
     for (int q = 0; q < steps; ++q) {
       const int t = upper ? steps - 1 - q : q;
-      const int b0 = t * kBK;
+      const int b0 = t * kSB;
       int active = 0;
       long tiles = 0;
       for (int s = 0; s < count && shape_host[2 * s] > b0; ++s) {
         ++active;
         const int n = shape_host[2 * s], nc = shape_host[2 * s + 1];
-        const long rows = upper ? b0 : n - b0 - std::min(kBK, n - b0);
+        const long rows = upper ? b0 : n - b0 - std::min(kSB, n - b0);
         tiles += ((rows + 63) / 64) * ((nc + 63) / 64);
       }
       hipLaunchKernelGGL(batch_sdiag_kernel<T>, dim3(active), dim3(256), 0, st, items, LU, Y, b0, upper, state);
@@ -1146,7 +1218,7 @@ extern "C" int hp_batch_factor_stepped(int count, const hp_batch_item *items, co
   }
   const int P = (nmax + panel - 1) / panel;     // panel steps
   const int NBk = (nmax + block - 1) / block;  // outer blocks
-  const int Q = P + 2 * NBk;
+  const int Q = 2 * P + 2 * NBk;
   const size_t tbl = 256 + sizeof(int) * (size_t)Q * (count + 1);
   if (work_bytes < tbl) return HP_ERR_WORKSPACE;
   int *offs = (int *)((char *)work + 256);
@@ -1183,6 +1255,20 @@ extern "C" int hp_batch_factor_stepped(int count, const hp_batch_item *items, co
         hipLaunchKernelGGL(batch_panel_kernel<double>, dim3(active), dim3(256), 0, st, items, (cplx<double> *)A,
                            ipiv, perm, info, j0, panel, block);
       HP_CHECK_LAUNCH();
+      {
+        int act3 = 0;
+        const long chunks = units(3, j0, &act3);
+        const int *o3 = offs + (long)(P + j0 / panel) * (count + 1);
+        if (chunks > 0) {
+          if (prec == HP_C64)
+            hipLaunchKernelGGL(batch_swap_brow_kernel<float>, dim3((unsigned)chunks), dim3(256), 0, st, act3, items,
+                               (cplx<float> *)A, ipiv, o3, j0, panel, block);
+          else
+            hipLaunchKernelGGL(batch_swap_brow_kernel<double>, dim3((unsigned)chunks), dim3(256), 0, st, act3, items,
+                               (cplx<double> *)A, ipiv, o3, j0, panel, block);
+          HP_CHECK_LAUNCH();
+        }
+      }
       if (tiles == 0) continue;
       if (tiles > (1L << 30)) return HP_ERR_UNSUPPORTED;
       const int *o = offs + (long)(j0 / panel) * (count + 1);
@@ -1199,7 +1285,7 @@ extern "C" int hp_batch_factor_stepped(int count, const hp_batch_item *items, co
     if (chunks == 0) continue;
     const long tiles = units(1, J, &active);
     if (tiles > (1L << 30)) return HP_ERR_UNSUPPORTED;
-    const int qb = P + 2 * (J / block);
+    const int qb = 2 * P + 2 * (J / block);
     const int *ob = offs + (long)qb * (count + 1), *ou = offs + (long)(qb + 1) * (count + 1);
     if (prec == HP_C64) {
       hipLaunchKernelGGL(batch_brow_kernel<float>, dim3((unsigned)chunks), dim3(256), 0, st, active, items,

@@ -1148,6 +1148,7 @@ static size_t slot_key_words() { return 2 * 2 * kMaxPanelGroups; }  // 32-bit wo
 // (hp_set_concurrency).
 std::atomic<int> g_concurrency{1};
 
+
 template <typename T>
 static int panel_grid(int m, int lds_cap, int &G, int &rpw) {
   // at least 64 rows per workgroup, at most kMaxPanelGroups workgroups (one

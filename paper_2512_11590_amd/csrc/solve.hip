@@ -15,6 +15,8 @@
 // point (batched MFMA gemm_sub).
 #include "common.h"
 
+#include <mutex>
+
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -218,18 +220,58 @@ static double u64_as_double(unsigned long long u) {
 // Whether hp_solve replays its FP32 refinement solves from a captured graph.
 std::atomic<int> g_solve_graphs{1};
 
-// A captured solve: capture stream, graph and executable, released on scope exit.
-struct SolveGraph {
-  hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
+// Captured refinement solves, kept across hp_solve calls.  A capture records
+// kernel launches whose arguments are the factor, workspace and right-hand
+// side addresses and the sizes; a later call with the same (device, n, nc,
+// factor address and leading dimension, workspace address) replays the same
+// launches on the memory it names, so it reuses the executable.  The first
+// kSolveGraphCache keys are kept for the life of the process (never
+// destroyed, so no executable is released while another thread may launch
+// it, and none while the runtime shuts down at exit); a call with a key
+// beyond them captures a graph of its own and releases it on return.
+struct SolveGraphKey {
+  int dev, n, nc;
+  const void *lu;
+  long lda;
+  const void *work;
+  bool operator==(const SolveGraphKey &o) const {
+    return dev == o.dev && n == o.n && nc == o.nc && lu == o.lu && lda == o.lda && work == o.work;
+  }
+};
+struct SolveGraphEntry {
+  SolveGraphKey key;
+  hipGraphExec_t exec;
+};
+constexpr int kSolveGraphCache = 64;
+namespace {
+std::mutex g_sg_mu;
+SolveGraphEntry g_sg[kSolveGraphCache];
+int g_sg_count = 0;
+}  // namespace
+
+static hipGraphExec_t solve_graph_find(const SolveGraphKey &key) {
+  std::lock_guard<std::mutex> lk(g_sg_mu);
+  for (int i = 0; i < g_sg_count; ++i)
+    if (g_sg[i].key == key) return g_sg[i].exec;
+  return nullptr;
+}
+
+// Keeps x for key if there is room (returns true), else the caller owns it.
+static bool solve_graph_keep(const SolveGraphKey &key, hipGraphExec_t x) {
+  std::lock_guard<std::mutex> lk(g_sg_mu);
+  if (g_sg_count >= kSolveGraphCache) return false;
+  g_sg[g_sg_count++] = SolveGraphEntry{key, x};
+  return true;
+}
+
+// An executable owned by one hp_solve call (released on scope exit).
+struct OwnedGraph {
   hipGraphExec_t exec = nullptr;
-  SolveGraph() = default;
-  SolveGraph(const SolveGraph &) = delete;
-  SolveGraph &operator=(const SolveGraph &) = delete;
-  ~SolveGraph() {
+  OwnedGraph() = default;
+  OwnedGraph(const OwnedGraph &) = delete;
+  OwnedGraph &operator=(const OwnedGraph &) = delete;
+  ~OwnedGraph() {
     if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (cap) (void)hipStreamDestroy(cap);
   }
 };
 
@@ -280,11 +322,13 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
     Ysol = (cplx<float> *)(work + ws.z_off);
   }
   // The refinement solves are the same ~300 launches on the same buffers each
-  // time: with FP32 factors they are captured once (at the first refinement
-  // solve, after the initial solve has run eagerly) into a HIP graph that is
-  // replayed on the caller's stream, which removes the per-launch gaps.
-  SolveGraph sg;
+  // time: with FP32 factors they are captured (at the first refinement solve
+  // of the first call on these buffers, after the initial solve has run
+  // eagerly) into a HIP graph that is replayed on the caller's stream, which
+  // removes the per-launch gaps; the executable is kept for later calls.
   const bool graphs = g_solve_graphs.load(std::memory_order_relaxed) != 0;
+  hipGraphExec_t sg_exec = nullptr;
+  OwnedGraph owned;
   auto solve_y = [&](bool eager) -> int {
     if constexpr (sizeof(T) == sizeof(float)) {
       auto run = [&](hipStream_t s) {
@@ -293,18 +337,31 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
                            Ysol, nc, s);
       };
       if (eager || !graphs) return run(st);
-      if (!sg.exec) {
-        HP_CHECK_HIP(hipStreamCreateWithFlags(&sg.cap, hipStreamNonBlocking));
-        HP_CHECK_HIP(hipStreamBeginCapture(sg.cap, hipStreamCaptureModeThreadLocal));
-        const int rc1 = run(sg.cap);
-        hipGraph_t g = nullptr;
-        const hipError_t e = hipStreamEndCapture(sg.cap, &g);
-        sg.graph = g;
-        if (rc1) return rc1;
-        HP_CHECK_HIP(e);
-        HP_CHECK_HIP(hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0));
+      if (!sg_exec) {
+        int dev = 0;
+        HP_CHECK_HIP(hipGetDevice(&dev));
+        const SolveGraphKey key{dev, (int)n, nc, (const void *)LU, lda, (const void *)work};
+        sg_exec = solve_graph_find(key);
+        if (!sg_exec) {
+          hipStream_t cap = nullptr;
+          HP_CHECK_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+          HP_CHECK_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+          const int rc1 = run(cap);
+          hipGraph_t g = nullptr;
+          const hipError_t e = hipStreamEndCapture(cap, &g);
+          (void)hipStreamDestroy(cap);
+          hipGraphExec_t x = nullptr;
+          hipError_t ei = hipSuccess;
+          if (!rc1 && e == hipSuccess) ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+          if (g) (void)hipGraphDestroy(g);  // the executable does not need it
+          if (rc1) return rc1;
+          HP_CHECK_HIP(e);
+          HP_CHECK_HIP(ei);
+          if (!solve_graph_keep(key, x)) owned.exec = x;
+          sg_exec = x;
+        }
       }
-      HP_CHECK_HIP(hipGraphLaunch(sg.exec, st));
+      HP_CHECK_HIP(hipGraphLaunch(sg_exec, st));
       return HP_OK;
     } else {
       (void)eager;

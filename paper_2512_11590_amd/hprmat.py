@@ -354,7 +354,7 @@ def hp_set_solve_graphs(on: bool) -> bool:
 
 
 TRACE_STAGES = ("assemble", "panel", "laswp", "trsm", "gemm_c128", "gemm_c64", "residual", "refine",
-                "rmatrix", "smatrix")
+                "rmatrix", "smatrix", "gemm_f16x3")
 
 
 def hp_trace_enable(on: bool = True, stages=None) -> None:

@@ -12,10 +12,15 @@ once and runs, per energy, the five entry points of the C ABI
 FP32 + FP64 refinement or in FP64.  Factors are not shared between requests:
 C(E) differs for every (system, energy).
 
-Panel grids must be resident as a whole, so the server declares its number
-of slots to the library (hp_set_concurrency), which then serializes the
-factorizations of all slots on one device-wide stream and keeps panel
-workgroups small; everything else of the slots overlaps.
+The single-system factorization's panel grid must be resident as a whole,
+so the server declares its number of slots to the library
+(hp_set_concurrency), which then serializes those factorizations on one
+device-wide stream and keeps panel workgroups small.  Requests of up to
+`batched_max_n` unknowns take the batched path instead: all energies of the
+request as one bucket of the stepped batched LU (hp_batch_*, no grid-wide
+waits), with its solves, refinement, R and S, on the slot's own stream -- so
+their factorizations overlap each other and the serialized large ones.
+Everything else of the slots overlaps in either case.
 
 Latency of a request = completion time - arrival time (host clock, the
 request's S matrices copied back).  The summary reports p50 / p99 latency and
@@ -39,11 +44,24 @@ from . import pipeline as P
 
 def request_bytes(nc: int, nr: int, prec: int) -> int:
     """Device bytes one request holds while admitted (matrix, workspace, solution,
-    potential values, small buffers)."""
+    potential values, small buffers); with FP32 factors also the FP64 matrix
+    and workspace that a fallback to the FP64 solve allocates."""
     n = nc * nr
-    elt = 8 if prec == H.HP_C64 else 16
-    return (n * n * elt + H.hp_workspace_bytes(n, nc, prec) + H.hp_workspace_bytes(nc, nc, H.HP_C128)
+    elt = 16 if prec == H.HP_C128 else 8
+    need = (n * n * elt + H.hp_workspace_bytes(n, nc, prec) + H.hp_workspace_bytes(nc, nc, H.HP_C128)
             + n * nc * 16 + 3 * nc * nc * 16 + nr * nc * nc * 16 + 64 * n)
+    if prec != H.HP_C128:
+        need += n * n * 16 + H.hp_workspace_bytes(n, nc, H.HP_C128) + n * nc * 16 + 3 * nc * nc * 16 + 64 * n
+    return need
+
+
+def served_bytes(params, prec: int, batched_max_n: int) -> int:
+    """Device bytes a request holds while admitted: one system's buffers, or,
+    on the batched path, one per energy (a bound: the bucket holds each
+    energy's matrix, solution and potential values)."""
+    nc, nr = int(params.nc), int(params.nr)
+    ne = len(params.energies) if nc * nr <= batched_max_n else 1
+    return ne * request_bytes(nc, nr, prec)
 
 
 @dataclass
@@ -69,7 +87,7 @@ class Served:
 class Server:
     def __init__(self, slots: int = 4, prec: int = H.HP_C64, hbm_budget: int | None = None,
                  max_refine: int = 30, tol: float = 0.0, device: str = "cuda", executor=None,
-                 bytes_of=None):
+                 bytes_of=None, batched_max_n: int = 4000):
         """executor(req, params) runs one admitted request (default: the HIP
         pipeline on the slot's stream); bytes_of(params) its device bytes
         (default: request_bytes).  Both are replaceable so the scheduling can be
@@ -78,10 +96,11 @@ class Server:
             raise ValueError("slots >= 1")
         self.slots = slots
         self.prec = prec
+        self.batched_max_n = batched_max_n
         self.max_refine = max_refine
         self.tol = tol
         self._execute = executor or self._run_request
-        self._bytes_of = bytes_of or (lambda sp: request_bytes(int(sp.nc), int(sp.nr), self.prec))
+        self._bytes_of = bytes_of or (lambda sp: served_bytes(sp, self.prec, self.batched_max_n))
         dev = torch.device(device)
         self.gpu = dev.type == "cuda"
         if self.gpu:
@@ -127,6 +146,8 @@ class Server:
 
     # -- one slot --------------------------------------------------------------
     def _run_request(self, req: Served, params) -> None:
+        if req.n <= self.batched_max_n:
+            return self._run_request_batched(req, params)
         d = P.DeviceSystem(params, device=str(self.device))
         s = P.Solver(d, self.prec)
         for E in req.energies:
@@ -135,6 +156,39 @@ class Server:
             req.S.append(r.S.cpu().numpy().copy())
             req.iterations.append(r.iterations)
             req.fallback.append(r.fallback)
+
+    def _run_request_batched(self, req: Served, params) -> None:
+        """All energies of the request as one bucket of the batched path."""
+        from . import batch as B
+        ne = len(req.energies)
+        bk = B.Bucket([params] * ne, [float(E) for E in req.energies], list(range(ne)), self.prec,
+                      device=str(self.device))
+        bk.factor(16, 0, 64)
+        bk.solve(max_refine=self.max_refine, tol=self.tol, use_graph=False)
+        bk.rmatrix()
+        bk.smatrix()
+        st, it = bk.status()
+        sst = bk.sstat.cpu().numpy()
+        R_all = bk.R.cpu().numpy()
+        S_all = bk.S.cpu().numpy()
+        out = [None] * ne
+        for k in range(ne):
+            if st[k] in (2, 3):  # FP32 refinement did not converge / zero pivot: FP64 single-system solve
+                r = P.Solver(P.DeviceSystem(params, device=str(self.device)), H.HP_C128).run(bk.energies[k])
+                out[bk.index[k]] = (r.R.cpu().numpy().copy(), r.S.cpu().numpy().copy(), int(it[k]), True)
+                continue
+            if sst[k] != 0:
+                raise H.HprmatError(H.HP_ERR_UNSUPPORTED if sst[k] in (1, 4) else H.HP_ERR_SINGULAR,
+                                    f"hp_batch_smatrix (request {req.rid})")
+            c = int(bk.nc[k])
+            o = int(bk.r_off[k])
+            out[bk.index[k]] = (R_all[o:o + c * c].reshape(c, c).copy(), S_all[o:o + c * c].reshape(c, c).copy(),
+                                int(it[k]), False)
+        for R, S, its, fb in out:
+            req.R.append(R)
+            req.S.append(S)
+            req.iterations.append(its)
+            req.fallback.append(fb)
 
     def _slot(self, k: int, stream) -> None:
         if self.gpu:

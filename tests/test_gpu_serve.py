@@ -1,7 +1,9 @@
 """Served stream (continuous batching) on the GPU.
 
 * every request's S in the mix equals its S when it runs alone, within the
-  S tolerance 1e-10 (the kernels are deterministic, so in practice bit for bit);
+  S tolerance 1e-10 (the kernels are deterministic, so in practice bit for
+  bit); the mix holds requests of both paths (the batched path up to 4000
+  unknowns, the single-system path above);
 * FP32 + refinement and FP64 agree on S within 1e-10 per request;
 * a small request (N = 160, the small workload) served in the mix matches the
   oracle within 1e-10;
@@ -54,6 +56,10 @@ def test_same_alone_and_in_mix(mods):
     small = make_system("small")
     small.energies = small.energies[:2]
     reqs.insert(3, (reqs[3][0], small))
+    # one request above the batched-path size, so both paths run in the mix
+    big = make_system("small", nc=48, nr=100, lmax=12)
+    big.energies = big.energies[:2]
+    reqs.insert(1, (reqs[1][0], big))
     say("mix", [sp.nc * sp.nr for _, sp in reqs])
     mix = S.Server(slots=3, prec=H.HP_C64).run(reqs)
     assert all(r.error is None for r in mix), [r.error for r in mix]
@@ -65,7 +71,7 @@ def test_same_alone_and_in_mix(mods):
     md = osys.MeshData(small.nr, small.a)
     for e, E in enumerate(small.energies):
         o = opipe.solve_energy(small, float(E), md)
-        assert relerr(mix[3].S[e], o["S"]) < 1e-10
+        assert relerr(mix[4].S[e], o["S"]) < 1e-10
     st = S.summary(mix)
     say("summary", st)
     assert st["failed"] == 0 and st["latency_p99_s"] >= st["latency_p50_s"] > 0
@@ -86,7 +92,7 @@ def test_admission_by_memory(mods):
     H, S = mods
     t0, sp = small_stream(count=1, seed=1159107)[0]
     reqs = [(t0 + 0.001 * k, sp) for k in range(4)]  # four requests of one size
-    need = S.request_bytes(sp.nc, sp.nr, H.HP_C64)
+    need = S.served_bytes(sp, H.HP_C64, 4000)
     res = S.Server(slots=3, prec=H.HP_C64, hbm_budget=need).run(reqs)
     assert all(r.error is None for r in res)
     spans = sorted((r.admitted, r.done) for r in res)
