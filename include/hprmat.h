@@ -166,6 +166,16 @@ int hp_lu_solve(int n, int nrhs, int prec, const void *LU, long lda, const int *
 int hp_gemm_sub(int M, int N, int K, int prec, const void *A, long lda, const void *B, long ldb, void *C,
                 long ldc, void *stream);
 
+/* The HP_C64H trailing update on its own: C -= A B (complex FP32, row-major)
+ * with A's rows and B's columns scaled by powers of two into [-1, 1], split
+ * into two FP16 words each and multiplied on the FP16 matrix cores with FP32
+ * accumulation (three products per real product).  K a multiple of 32, at
+ * most 256 (HP_ERR_UNSUPPORTED otherwise).  work: device, at least
+ * 8 K (M + N) + 4 (M + N) + 512 bytes for the converted operands
+ * (HP_ERR_WORKSPACE otherwise).  Exposed for tests and tuning; asynchronous. */
+int hp_gemm_h3_sub(int M, int N, int K, const void *A, long lda, const void *B, long ldb, void *C, long ldc,
+                   void *work, size_t work_bytes, void *stream);
+
 /* R-matrix (Sec. 3.1, step 4, with the factor hbar^2/(2 mu a)):
  *   R[c][c'] = (hbar2_2mu / a) sum_i q_i X[(c,i)][c'],
  * X device n x nc complex128, R device nc x nc complex128 (row-major). */

@@ -227,33 +227,41 @@ __global__ __launch_bounds__(256, 1) void gemm_h3_kernel(int M, int N, int K, co
     if (kt + 1 < nk) issue((kt + 1) & 1, (kt + 1) * (kH3BK / 8));
     const h8 *as = As + (kt & 1) * ASZ;
     const h8 *bs = Bs + (kt & 1) * BSZ;
-    // all fragments of the stage first, then the products grouped by operand
-    // pair, so that consecutive MFMAs update different accumulators
-    h8 a[2][4], b[4][4];
+    h8 a[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int row = wm + i * 16 + fr;
 #pragma unroll
       for (int p = 0; p < 4; ++p) a[i][p] = as[row * U + ((g * 4 + p) ^ (row & 15))];
     }
+    // per tile, the three products of each real product in turn (hi hi,
+    // hi lo, lo hi) into one accumulator: measured on the N = 25600 system,
+    // this order refines like the FP32 product (contraction 0.03 per step);
+    // the same sums issued product by product across the tiles, or with the
+    // hi lo and lo hi terms in accumulators of their own, contracted 0.25
+    // and 0.1 per step (the matrix cores' FP32 accumulation is not
+    // order-independent at this level)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int col = wn + j * 16 + fr;
+      h8 b[4];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) b[j][p] = bs[col * U + ((g * 4 + p) ^ (col & 15))];
-    }
-    // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo; (A plane, B plane, accumulator)
-    constexpr int kProd[12][3] = {{0, 0, 0}, {2, 2, 1}, {0, 2, 2}, {2, 0, 2}, {0, 1, 0}, {2, 3, 1},
-                                  {0, 3, 2}, {2, 1, 2}, {1, 0, 0}, {3, 2, 1}, {1, 2, 2}, {3, 0, 2}};
+      for (int p = 0; p < 4; ++p) b[p] = bs[col * U + ((g * 4 + p) ^ (col & 15))];
 #pragma unroll
-    for (int q = 0; q < 12; ++q) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          f4v &acc = kProd[q][2] == 0 ? acc_rr[i][j] : (kProd[q][2] == 1 ? acc_ii[i][j] : acc_im[i][j]);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][kProd[q][0]], b[j][kProd[q][1]], acc, 0, 0, 0);
-        }
+      for (int i = 0; i < 2; ++i) {
+        acc_rr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][0], b[0], acc_rr[i][j], 0, 0, 0);
+        acc_rr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][0], b[1], acc_rr[i][j], 0, 0, 0);
+        acc_rr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][1], b[0], acc_rr[i][j], 0, 0, 0);
+        acc_ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][2], b[2], acc_ii[i][j], 0, 0, 0);
+        acc_ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][2], b[3], acc_ii[i][j], 0, 0, 0);
+        acc_ii[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][3], b[2], acc_ii[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][0], b[2], acc_im[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][0], b[3], acc_im[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][1], b[2], acc_im[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][2], b[0], acc_im[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][2], b[1], acc_im[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[i][3], b[0], acc_im[i][j], 0, 0, 0);
+      }
     }
   }
   // epilogue: C -= r_m c_n (P_rr - P_ii, P_im), one 16-row tile at a time
@@ -337,3 +345,21 @@ int gemm_h3_sub(int M, int N, int K, const void *abuf, int Mtot, int r0, const v
 }
 
 }  // namespace hp
+
+using namespace hp;
+
+extern "C" int hp_gemm_h3_sub(int M, int N, int K, const void *A, long lda, const void *B, long ldb, void *C, long ldc,
+                              void *work, size_t work_bytes, void *stream) {
+  if (M < 0 || N < 0 || K < 0) return HP_ERR_ARG;
+  if (M == 0 || N == 0 || K == 0) return HP_OK;
+  if (!A || !B || !C || !work || lda < K || ldb < N || ldc < N) return HP_ERR_ARG;
+  if (K % kH3BK != 0 || K > 256) return HP_ERR_UNSUPPORTED;
+  const size_t ab = h3_operand_bytes(M, K), bb = h3_operand_bytes(N, K);
+  if (work_bytes < ab + bb) return HP_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)work;
+  int rc;
+  if ((rc = h3_convert_rows(M, K, (const cplx<float> *)A, lda, w, st))) return rc;
+  if ((rc = h3_convert_cols(N, K, (const cplx<float> *)B, ldb, w + ab, st))) return rc;
+  return gemm_h3_sub(M, N, K, w, M, 0, w + ab, N, 0, (cplx<float> *)C, ldc, st);
+}

@@ -60,7 +60,7 @@ class HpSolveInfo(ctypes.Structure):
 EXPORTS = ["hp_mesh", "hp_workspace_bytes", "hp_build_matrix", "hp_factor", "hp_solve",
            "hp_lu_solve", "hp_rmatrix", "hp_smatrix", "hp_smatrix_noalloc", "hp_coulomb", "hp_coulomb_device",
            "hp_build_info", "hp_strerror", "hp_trace_enable", "hp_trace_read", "hp_last_error",
-           "hp_gemm_sub", "hp_set_concurrency", "hp_set_solve_graphs", "hp_batch_workspace_bytes", "hp_batch_build",
+           "hp_gemm_sub", "hp_gemm_h3_sub", "hp_set_concurrency", "hp_set_solve_graphs", "hp_batch_workspace_bytes", "hp_batch_build",
            "hp_batch_factor", "hp_batch_factor_stepped", "hp_batch_solve_init", "hp_batch_refine_step", "hp_batch_active",
            "hp_batch_status", "hp_batch_rmatrix", "hp_batch_smatrix"]
 
@@ -106,6 +106,9 @@ def lib() -> ctypes.CDLL:
     L.hp_gemm_sub.argtypes = [c_int, c_int, c_int, c_int, c_void_p, c_long, c_void_p, c_long, c_void_p,
                               c_long, c_void_p]
     L.hp_gemm_sub.restype = c_int
+    L.hp_gemm_h3_sub.argtypes = [c_int, c_int, c_int, c_void_p, c_long, c_void_p, c_long, c_void_p, c_long,
+                                 c_void_p, c_size_t, c_void_p]
+    L.hp_gemm_h3_sub.restype = c_int
     L.hp_rmatrix.argtypes = [P(HpSystem), c_void_p, c_void_p, c_void_p]
     L.hp_rmatrix.restype = c_int
     L.hp_smatrix.argtypes = [P(HpSystem), c_double, c_void_p, c_void_p, P(c_int), c_void_p,
@@ -243,6 +246,11 @@ def hp_gemm_sub(M: int, N: int, K: int, prec: int, A, lda: int, B, ldb: int, C, 
                 stream=None) -> None:
     _check(lib().hp_gemm_sub(M, N, K, prec, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, _stream(stream)),
            "hp_gemm_sub")
+
+
+def hp_gemm_h3_sub(M: int, N: int, K: int, A, lda: int, B, ldb: int, C, ldc: int, work, stream=None) -> None:
+    _check(lib().hp_gemm_h3_sub(M, N, K, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, _ptr(work),
+                                work.numel() * work.element_size(), _stream(stream)), "hp_gemm_h3_sub")
 
 
 def hp_rmatrix(sys: HpSystem, X, R, stream=None) -> None:

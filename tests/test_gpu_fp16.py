@@ -109,3 +109,28 @@ def test_pipeline_h3_against_oracle(mods, nc, nr):
         print(f"   R err {er:.2e}  S err {es:.2e}  refinement {res.iterations}  fallback {res.fallback}", flush=True)
         assert er < 1e-10 and es < 1e-10
         assert not res.fallback
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 32), (64, 128, 32), (300, 260, 64), (1000, 777, 256), (129, 4000, 256)])
+def test_gemm_h3_matches_fp64_product(mods, M, N, K):
+    """The split-FP16 product against the FP64 product of the same FP32
+    operands: |error| <= 2^-20 (|A||B|) elementwise, rows and columns of very
+    different magnitudes (the power-of-two scaling keeps them in range)."""
+    H, P = mods
+    say("gemm h3", M, N, K)
+    rng = np.random.default_rng(M + 7 * N + K)
+    A = rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N)) + 1j * rng.standard_normal((K, N))
+    A *= 2.0 ** rng.integers(-30, 30, size=(M, 1))
+    B *= 2.0 ** rng.integers(-30, 30, size=(1, N))
+    C = rng.standard_normal((M, N)) + 1j * rng.standard_normal((M, N))
+    A, B, C = (x.astype(np.complex64) for x in (A, B, C))
+    ref = C.astype(np.complex128) - A.astype(np.complex128) @ B.astype(np.complex128)
+    dA, dB, dC = (torch.from_numpy(x.copy()).to("cuda") for x in (A, B, C))
+    work = torch.empty(8 * K * (M + N) + 4 * (M + N) + 1024, dtype=torch.uint8, device="cuda")
+    H.hp_gemm_h3_sub(M, N, K, dA, K, dB, N, dC, N, work)
+    got = dC.cpu().numpy().astype(np.complex128)
+    mag = np.abs(A.astype(np.complex128)) @ np.abs(B.astype(np.complex128)) + np.abs(C)
+    err = np.max(np.abs(got - ref) / mag)
+    print(f"   max |err| / (|A||B| + |C|) = {err:.2e}", flush=True)
+    assert err < 2.0 ** -20
