@@ -114,7 +114,7 @@ def batched(args, H, torch):
     for name, prec in (("fp32_ir", H.HP_C64), ("fp64", H.HP_C128)):
         print(f"[bench] batched {name}: {len(sps)} systems", file=sys.stderr, flush=True)
         bt = B.Batch(sps, [s.energies[0] for s in sps], prec)
-        tuned = bt.tune(sample=8, panels=(16, 32))
+        tuned = bt.tune(sample=16, panels=(8, 16, 32), groups_per_cu=(2,))
         bt.run()  # warm (captures the refinement graphs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

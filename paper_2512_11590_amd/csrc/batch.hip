@@ -101,18 +101,33 @@ __device__ __forceinline__ void tile_gemm_sub(int m0, int n0, int M, int N, int 
   // products; FP64 loads each chunk at its start (its registers would not
   // fit beside the accumulators of the 4M product)
   constexpr bool kPrefetch = sizeof(T) == 4;
-  load(0);
+  if constexpr (kPrefetch) load(0);
   for (int kc = 0; kc < K; kc += kBK) {
     const int kb = min(kBK, K - kc), Kp = (kb + 3) & ~3;
-    if (!kPrefetch && kc > 0) load(kc);
+    if constexpr (kPrefetch) {
 #pragma unroll
-    for (int u = 0; u < NS; ++u) {
-      const int e = tid + 256 * u;
-      if (e < 64 * Kp) {
-        const int r = e / Kp, k = e - r * Kp;
-        As[k * kBLd + r] = (m0 + r < M && k < kb) ? ra[u] : zero;
-        const int kr = e >> 6, c = e & 63;
-        Bs[kr * kBLd + c] = (kr < kb && n0 + c < N) ? rb[u] : zero;
+      for (int u = 0; u < NS; ++u) {
+        const int e = tid + 256 * u;
+        if (e < 64 * Kp) {
+          const int r = e / Kp, k = e - r * Kp;
+          As[k * kBLd + r] = (m0 + r < M && k < kb) ? ra[u] : zero;
+          const int kr = e >> 6, c = e & 63;
+          Bs[kr * kBLd + c] = (kr < kb && n0 + c < N) ? rb[u] : zero;
+        }
+      }
+    } else {
+      // each value stored as it arrives (no staging registers)
+#pragma unroll
+      for (int u = 0; u < NS; ++u) {
+        const int e = tid + 256 * u;
+        if (e < 64 * Kp) {
+          const int r = e / Kp, k = e - r * Kp;
+          const cplx<T> va = A[(long)min(m0 + r, M - 1) * lda + kc + min(k, kb - 1)];
+          const int kr = e >> 6, c = e & 63;
+          const cplx<T> vb = B[(long)(kc + min(kr, kb - 1)) * ldb + min(n0 + c, N - 1)];
+          As[k * kBLd + r] = (m0 + r < M && k < kb) ? va : zero;
+          Bs[kr * kBLd + c] = (kr < kb && n0 + c < N) ? vb : zero;
+        }
       }
     }
     __syncthreads();
@@ -741,29 +756,33 @@ __global__ __launch_bounds__(256) void batch_solve_kernel(int count, const hp_ba
 }
 
 // R = B - C X in FP64 from the block structure, and per column s = max |R|
-// (|Re|+|Im|; 1 for an exactly zero column), for systems still refining.
-__global__ __launch_bounds__(256) void batch_residual_kernel(int count, const hp_batch_item *__restrict__ items,
-                                                             const cplx<double> *__restrict__ X,
-                                                             cplx<double> *__restrict__ Rr, double *cscale,
-                                                             const BatchState *state) {
-  const int s = blockIdx.x;
+// (|Re|+|Im|; 1 for an exactly zero column), for systems still refining,
+// spread over kResChunks workgroups per system (grid kResChunks x count):
+// R = h (T + L) X + diagonal term (pass 1, RB1 mesh rows of one channel per
+// item), then R = B - (R + V_i X_i) (pass 2, RB2 channels at one mesh point
+// per item) with the column maxima gathered by atomics into cscale (as the
+// bits of non-negative doubles), then the maxima turned into scales.  Every
+// output element keeps the summation order of the definition (kinetic terms
+// over j, the diagonal term, coupling terms over c').
+constexpr int kResChunks = 64;
+
+__global__ __launch_bounds__(256) void batch_res_kinetic_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                                const cplx<double> *__restrict__ X,
+                                                                cplx<double> *__restrict__ Rr, double *cscale,
+                                                                const BatchState *state) {
+  constexpr int RB1 = 8;
+  const int s = blockIdx.y;
   if (s >= count || state[s].status != 0) return;
   const hp_batch_item it = items[s];
-  const int nc = it.sys.nc, nr = it.sys.nr, n = nc * nr;
+  const int nc = it.sys.nc, nr = it.sys.nr;
   const double h = it.sys.hbar2_2mu, E = it.E;
   const cplx<double> *x = X + it.x_off;
   cplx<double> *rr = Rr + it.x_off;
-  // Each X element loaded feeds RB1 (RB2) outputs held in registers; every
-  // output element keeps the summation order of the definition (kinetic
-  // terms over j, the diagonal term, coupling terms over c').
-  constexpr int RB1 = 8, RB2 = 4, kMaxCols = 256;
-  __shared__ unsigned long long smax[kMaxCols];  // column maxima as the bits of non-negative doubles
-  smax[threadIdx.x] = 0ull;
-  // pass 1: h (T + L) X + diagonal, RB1 mesh rows of one channel per item,
-  // partial sums into R
+  if (blockIdx.x == 0)
+    for (int c = threadIdx.x; c < nc; c += 256) cscale[it.c_off + c] = 0.0;  // pass 2 gathers maxima here
   const int nrb = (nr + RB1 - 1) / RB1;
   const long n1 = (long)nc * nrb * nc;
-  for (long e = threadIdx.x; e < n1; e += 256) {
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n1; e += (long)kResChunks * 256) {
     const int cc = (int)(e % nc);
     const long t = e / nc;
     const int ib = (int)(t % nrb), c = (int)(t / nrb);
@@ -794,11 +813,23 @@ __global__ __launch_bounds__(256) void batch_residual_kernel(int count, const hp
       }
     }
   }
-  __syncthreads();
-  // pass 2: + V_i X_i, RB2 channels at one mesh point per item; R = B - sum
+}
+
+__global__ __launch_bounds__(256) void batch_res_coupling_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                                 const cplx<double> *__restrict__ X,
+                                                                 cplx<double> *__restrict__ Rr, double *cscale,
+                                                                 const BatchState *state) {
+  constexpr int RB2 = 4;
+  const int s = blockIdx.y;
+  if (s >= count || state[s].status != 0) return;
+  const hp_batch_item it = items[s];
+  const int nc = it.sys.nc, nr = it.sys.nr;
+  const cplx<double> *x = X + it.x_off;
+  cplx<double> *rr = Rr + it.x_off;
+  unsigned long long *cmax = reinterpret_cast<unsigned long long *>(cscale + it.c_off);
   const int ncb = (nc + RB2 - 1) / RB2;
   const long n2 = (long)nr * ncb * nc;
-  for (long e = threadIdx.x; e < n2; e += 256) {
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n2; e += (long)kResChunks * 256) {
     const int cc = (int)(e % nc);
     const long t = e / nc;
     const int cb = (int)(t % ncb), i = (int)(t / ncb);
@@ -822,6 +853,7 @@ __global__ __launch_bounds__(256) void batch_residual_kernel(int count, const hp
         si[u] += vr * xv.im + vim * xv.re;
       }
     }
+    double m = 0.0;
 #pragma unroll
     for (int u = 0; u < RB2; ++u) {
       const int c = c0 + u;
@@ -829,19 +861,21 @@ __global__ __launch_bounds__(256) void batch_residual_kernel(int count, const hp
         const double b = (c == cc) ? it.sys.q[i] : 0.0;
         const cplx<double> out{b - sr[u], -si[u]};
         rr[((long)c * nr + i) * nc + cc] = out;
-        if (cc < kMaxCols) atomicMax(&smax[cc], (unsigned long long)__double_as_longlong(cabs1(out)));
+        m = fmax(m, cabs1(out));
       }
     }
+    atomicMax(&cmax[cc], (unsigned long long)__double_as_longlong(m));
   }
-  __syncthreads();
-  // column maxima (1 for an exactly zero column); columns past kMaxCols scan R
-  for (int cc = threadIdx.x; cc < nc; cc += 256) {
-    double m = 0.0;
-    if (cc < kMaxCols)
-      m = __longlong_as_double((long long)smax[cc]);
-    else
-      for (int row = 0; row < n; ++row) m = fmax(m, cabs1(rr[(long)row * nc + cc]));
-    cscale[it.c_off + cc] = (m > 0.0) ? m : 1.0;
+}
+
+__global__ void batch_res_scale_kernel(int count, const hp_batch_item *__restrict__ items, double *cscale,
+                                       const BatchState *state) {
+  const int s = blockIdx.x;
+  if (s >= count || state[s].status != 0) return;
+  const hp_batch_item it = items[s];
+  for (int c = threadIdx.x; c < it.sys.nc; c += blockDim.x) {
+    const double m = cscale[it.c_off + c];  // the maximum's bits, read as the double they encode
+    cscale[it.c_off + c] = (m > 0.0) ? m : 1.0;
   }
 }
 
@@ -1360,8 +1394,13 @@ extern "C" int hp_batch_refine_step(int count, const hp_batch_item *items, const
   HP_CHECK_LAUNCH();
   {
     TraceScope ts(TR_RESIDUAL, st, 0.0, 0.0);
-    hipLaunchKernelGGL(batch_residual_kernel, dim3(count), dim3(256), 0, st, count, items, (const cplx<double> *)X,
-                       w.res, w.cscale, w.state);
+    hipLaunchKernelGGL(batch_res_kinetic_kernel, dim3(kResChunks, count), dim3(256), 0, st, count, items,
+                       (const cplx<double> *)X, w.res, w.cscale, w.state);
+    HP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(batch_res_coupling_kernel, dim3(kResChunks, count), dim3(256), 0, st, count, items,
+                       (const cplx<double> *)X, w.res, w.cscale, w.state);
+    HP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(batch_res_scale_kernel, dim3(count), dim3(64), 0, st, count, items, w.cscale, w.state);
     HP_CHECK_LAUNCH();
   }
   {
