@@ -145,5 +145,6 @@ extern "C" const char *hp_last_error(void) { return g_last_error; }
 
 extern "C" const char *hp_build_info(void) {
   return "hprmat gfx950: blocked right-looking complex LU (co-resident panel grid, MFMA trailing update: "
-         "4M in FP64, 3M in FP32), FP64/FP32 factors, device FP64 refinement";
+         "4M in FP64, 3M in FP32, split-FP16 4M x 3 in the FP16 variant), FP64/FP32 factors, device FP64 "
+         "refinement; batched stepped LU for many small systems (no grid-wide waits)";
 }
