@@ -92,7 +92,7 @@ constexpr double kRefineTol = 0x1p-29;
 // contract (the ill-conditioned case of the paper's Fig. illcond) and is
 // reported as non-convergence, which sends the caller to the FP64 solve.
 constexpr double kStallTol = 0x1p-26;
-constexpr int kMaxPanelGroups = 128;  // workgroups of one cooperative panel grid
+constexpr int kMaxPanelGroups = 256;  // workgroups of one cooperative panel grid (at most one per CU)
 constexpr unsigned kSpinLimit = 1u << 22;  // bounded grid-barrier wait (a few seconds)
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }

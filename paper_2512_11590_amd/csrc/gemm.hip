@@ -1,5 +1,9 @@
 // Complex GEMM C -= A B on the matrix cores (the trailing update of the LU,
 // Sec. 3.1 / 3.4, and every block update of the triangular solves).
+// Operands with K a multiple of the stage depth go through the kernels that
+// stage them by direct global->LDS loads (gemm_direct_kernel for FP32,
+// gemm_direct64_kernel for FP64); the register-staged gemm_sub_kernel below
+// takes the remaining shapes.
 //
 // Row-major interleaved complex operands.  FP64 forms each complex product
 // from four real MFMA products ("4M"):  Cr += Ar Br - Ai Bi,
@@ -296,17 +300,27 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 4 : 2)) void gemm_sub_kernel
 // registers and no LDS store instructions; on MI355X this runs the 3M update
 // ~15 % faster than the register-staged kernel (120 vs 104 TF/s of 3M flops
 // on a 25344 x 25088 x 256 update).  A wave's direct load writes 64
-// consecutive 16-byte slots, so the LDS layouts follow the loads: B rows are
-// row-major [BK][64]; A is row-major [64][BK] with the 16-byte chunks of row r
-// permuted by chunk ^ ((r / 2) % 8): a row spans half the banks, so rows r and
-// r + 1 sit in different halves and the permutation separates the 8 pairs,
-// and the MFMA operand reads (16 rows at one k) touch distinct banks.  The loads are issued from inline assembly (LDS
-// base in M0) so that the compiler neither reorders them nor waits for them
-// before the current stage's LDS reads; each thread waits for its own loads
-// (vmcnt) before the barrier that publishes a stage.  Requirements (checked by
-// the launcher): 16-byte aligned rows of A and B, K a multiple of 16, N even.
-// Rows of A past M read row M - 1 and columns of B past N read the last column
-// pair (their outputs are discarded).
+// consecutive 16-byte slots, so the LDS layouts follow the loads, and the
+// lane -> source mapping permutes the 16-byte chunks so that the MFMA operand
+// reads spread over the banks:
+//  * A is row-major [BM][BK]; the chunk (2 consecutive k) at position p of
+//    row r sits at p ^ swz(r), where swz separates the rows that share a
+//    256-byte bank window (BK = 16: rows r, r + 1 share one, so swz = r/2 mod
+//    8; BK = 8: rows r .. r + 3, swz = r/4 mod 4).  The operand read of one
+//    MFMA (16 rows at one k) then touches every bank at most once per window.
+//  * B is row-major [BK][64].  (Rotating the chunks of odd-k rows by half a
+//    row would spread one operand read's four k rows over both halves of a
+//    bank window, but it makes the two B reads' offsets depend on k, so they
+//    no longer pair into one ds_read2: measured 5 % slower in the LU.)
+// The loads are issued from inline assembly (LDS base in M0) so that the
+// compiler neither reorders them nor waits for them before the current
+// stage's LDS reads.  NBUF LDS buffers form a ring with NBUF - 1 stages of
+// loads in flight: before the barrier that publishes stage kt, each thread
+// waits (vmcnt) only until its own loads of stage kt have landed, the loads
+// of the later stages staying in flight.  Requirements (checked by the
+// launcher): 16-byte aligned rows of A and B, K a multiple of BK, N even.
+// Rows of A past M read row M - 1 and columns of B past N read the last
+// column pair (their outputs are discarded).
 constexpr int kDirectBK = 16;
 // lds_byte_addr must be uniform over the wavefront.  M0 is declared clobbered,
 // so the compiler keeps nothing of its own in M0 across the load.
@@ -317,15 +331,25 @@ __device__ __forceinline__ void lds_direct_load16(unsigned lds_byte_addr, const 
                : "memory", "m0");
 }
 
+// s_waitcnt with vmcnt <= n (0 <= n < 64) and the other counters unconstrained
+// (gfx9 encoding: vmcnt low bits [3:0], high bits [15:14], expcnt [6:4],
+// lgkmcnt [11:8]).
+template <int n>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(n >= 0 && n < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
+}
+
 // MW = 1: 64 x 64 tiles, each wavefront 32 x 32 outputs, held to three
-// wavefronts per SIMD (registers claimed up to v135), 32 KB of LDS: three
-// workgroups per CU leave room (LDS and registers) for a panel workgroup
-// beside them -- the panel runs next to the trailing update and its grid
-// only proceeds once all of its workgroups are resident.
+// wavefronts per SIMD (registers claimed up to v135): three workgroups per CU
+// leave room (LDS and registers) for a panel workgroup beside them -- the
+// panel runs next to the trailing update and its grid only proceeds once all
+// of its workgroups are resident.
 // MW = 2: 128 x 64 tiles, each wavefront 64 x 32 outputs (twice the matrix-
-// core work per operand read and per barrier), 48 KB of LDS, two workgroups
-// per CU (two wavefronts per SIMD), again with room for a panel workgroup.
-template <bool SET, int MW, bool CAP2 = false>
+// core work per operand read and per barrier), two or three workgroups per
+// CU as registers and LDS allow; CAP2 holds it to two.
+// LDS: NBUF (64 MW + 64) BK complex (MW = 1, BK = 16, NBUF = 2: 32 KB).
+template <bool SET, int MW, int BK, int NBUF, bool CAP2 = false>
 __global__ __launch_bounds__(256, (MW == 1 ? 4 : 2)) void gemm_direct_kernel(
     int M, int N, int K, const cplx<float> *__restrict__ A, long lda, long sa, const cplx<float> *__restrict__ B,
     long ldb, long sb, cplx<float> *__restrict__ C, long ldc, long sc, int tm, int tn, int total, int per_xcd,
@@ -333,14 +357,19 @@ __global__ __launch_bounds__(256, (MW == 1 ? 4 : 2)) void gemm_direct_kernel(
   typedef typename Mfma<float>::v4 v4;
   if constexpr (MW == 1) asm volatile("" ::: "v135");
   if constexpr (CAP2) asm volatile("" ::: "v183");
-  constexpr int BM = 64 * MW, BN = 64, BK = kDirectBK;
-  constexpr int TI = 2 * MW;                 // 16-row MFMA tiles per wavefront
-  constexpr int ACH = BK / 2;                // 16-byte chunks per A row
-  constexpr int APW = BM * ACH / 64 / 4;     // A wave-loads per wavefront per stage
+  static_assert(BK == 8 || BK == 16, "BK");
+  static_assert(NBUF >= 2 && NBUF <= 4, "NBUF");
+  constexpr int BM = 64 * MW, BN = 64;
+  constexpr int TI = 2 * MW;                   // 16-row MFMA tiles per wavefront
+  constexpr int ACH = BK / 2;                  // 16-byte chunks per A row
+  constexpr int AWS = BK == 16 ? 1 : 2;        // log2 of the A rows per 256-byte bank window
+  constexpr int APW = BM * ACH / 64 / 4;       // A wave-loads per wavefront per stage
   constexpr int BPW = BK * (BN / 2) / 64 / 4;  // B wave-loads per wavefront per stage
+  constexpr int LPT = APW + BPW;               // direct loads per thread per stage
+  constexpr int ASZ = BM * BK, BSZ = BK * BN;  // complex per buffer
   extern __shared__ __align__(16) char smem_raw[];
-  cplx<float> *As = reinterpret_cast<cplx<float> *>(smem_raw);  // [2][BM * BK]
-  cplx<float> *Bs = As + 2 * BM * BK;                            // [2][BK * BN]
+  cplx<float> *As = reinterpret_cast<cplx<float> *>(smem_raw);  // [NBUF][BM * BK]
+  cplx<float> *Bs = As + NBUF * ASZ;                             // [NBUF][BK * BN]
 
   const int bid = blockIdx.x;
   const int t = (bid & 7) * per_xcd + (bid >> 3);
@@ -368,7 +397,7 @@ __global__ __launch_bounds__(256, (MW == 1 ? 4 : 2)) void gemm_direct_kernel(
   for (int i = 0; i < APW; ++i) {
     const int c = (wave * APW + i) * 64 + lane;
     const int row = c / ACH, pos = c - row * ACH;
-    asrc[i] = A + (long)min(m0 + row, M - 1) * lda + 2 * (pos ^ ((row >> 1) & (ACH - 1)));
+    asrc[i] = A + (long)min(m0 + row, M - 1) * lda + 2 * (pos ^ ((row >> AWS) & (ACH - 1)));
   }
 #pragma unroll
   for (int i = 0; i < BPW; ++i) {
@@ -380,13 +409,12 @@ __global__ __launch_bounds__(256, (MW == 1 ? 4 : 2)) void gemm_direct_kernel(
   auto issue = [&](int buf, int k0) {
 #pragma unroll
     for (int i = 0; i < APW; ++i)
-      lds_direct_load16(lds0 + (unsigned)((buf * BM * BK + (wave * APW + i) * 128) * sizeof(cplx<float>)),
+      lds_direct_load16(lds0 + (unsigned)((buf * ASZ + (wave * APW + i) * 128) * sizeof(cplx<float>)),
                         asrc[i] + k0);
 #pragma unroll
     for (int i = 0; i < BPW; ++i)
-      lds_direct_load16(
-          lds0 + (unsigned)(((2 * BM * BK) + buf * BK * BN + (wave * BPW + i) * 128) * sizeof(cplx<float>)),
-          bsrc[i] + (long)k0 * ldb);
+      lds_direct_load16(lds0 + (unsigned)((NBUF * ASZ + buf * BSZ + (wave * BPW + i) * 128) * sizeof(cplx<float>)),
+                        bsrc[i] + (long)k0 * ldb);
   };
 
   v4 acc_re[TI][2], acc_im[TI][2], acc_p2[TI][2];  // 3M: P1, P3, P2
@@ -400,15 +428,25 @@ __global__ __launch_bounds__(256, (MW == 1 ? 4 : 2)) void gemm_direct_kernel(
     }
   const int fr = lane & 15, fk = lane >> 4;
   const int nk = K / BK;
-  issue(0, 0);
+#pragma unroll
+  for (int s = 0; s < NBUF - 1; ++s)
+    if (s < nk) issue(s, s * BK);
+  int cur = 0;
   for (int kt = 0; kt < nk; ++kt) {
-    // this thread's loads of stage kt have landed; the barrier publishes
-    // everyone's and frees the other buffer (read during stage kt - 1)
-    __builtin_amdgcn_s_waitcnt(0);
+    // this thread's loads of stage kt have landed (those of the NBUF - 2
+    // later stages may still be in flight); the barrier publishes everyone's
+    // and frees the buffer read during stage kt - 1
+    if (kt + NBUF - 2 < nk)
+      wait_vmcnt<(NBUF - 2) * LPT>();
+    else
+      wait_vmcnt<0>();
     __syncthreads();
-    if (kt + 1 < nk) issue((kt + 1) & 1, (kt + 1) * BK);
-    const cplx<float> *as = As + (kt & 1) * BM * BK;
-    const cplx<float> *bs = Bs + (kt & 1) * BK * BN;
+    if (kt + NBUF - 1 < nk) {
+      const int nb = cur == 0 ? NBUF - 1 : cur - 1;
+      issue(nb, (kt + NBUF - 1) * BK);
+    }
+    const cplx<float> *as = As + cur * ASZ;
+    const cplx<float> *bs = Bs + cur * BSZ;
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kk = ks + fk;
@@ -416,7 +454,7 @@ __global__ __launch_bounds__(256, (MW == 1 ? 4 : 2)) void gemm_direct_kernel(
 #pragma unroll
       for (int i = 0; i < TI; ++i) {
         const int row = wm + i * 16 + fr;
-        af[i] = as[row * BK + 2 * ((kk >> 1) ^ ((row >> 1) & (ACH - 1))) + (kk & 1)];
+        af[i] = as[row * BK + 2 * ((kk >> 1) ^ ((row >> AWS) & (ACH - 1))) + (kk & 1)];
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) bf[j] = bs[kk * BN + wn + j * 16 + fr];
@@ -434,6 +472,7 @@ __global__ __launch_bounds__(256, (MW == 1 ? 4 : 2)) void gemm_direct_kernel(
         }
       }
     }
+    cur = cur + 1 == NBUF ? 0 : cur + 1;
   }
   // epilogue as in gemm_sub_kernel, one 16-row tile at a time
 #pragma unroll
@@ -467,16 +506,250 @@ __global__ __launch_bounds__(256, (MW == 1 ? 4 : 2)) void gemm_direct_kernel(
   }
 }
 
-// Form of the direct-staged FP32 kernel (HP_GEMM_TILE): 64 (64-row tiles),
-// 128 (128-row tiles, occupancy as registers and LDS allow), 1282 (128-row
-// tiles held to two wavefronts per SIMD).
-static int direct_form() {
-  static const int form = [] {
+// Form of the direct-staged FP32 kernel (HP_GEMM_TILE, for tuning): MW, BK
+// and NBUF of the kernel above and whether it is held to two wavefronts per
+// SIMD.  Default: 64-row tiles, BK = 16, two buffers.  Measured on MI355X
+// alone (25344^2 x 256 update with its operands inside a 25600-wide matrix,
+// 6MNK flops): 121 TF/s (77 % of the FP32 matrix peak) for the default, 124
+// (79 %) for 128-row tiles, 118-120 for BK = 8 with three or four buffers
+// and for BK = 16 with three, so operand latency is not what holds it below
+// the peak (a register-only MFMA loop reaches 99 %); with K = 1024 the
+// default reaches 81 %.
+struct DirectForm {
+  int mw, bk, nbuf;
+  bool cap2;
+};
+static DirectForm direct_form() {
+  static const DirectForm form = [] {
     const char *e = getenv("HP_GEMM_TILE");
-    const int v = e ? atoi(e) : 64;
-    return (v == 128 || v == 1282) ? v : 64;
+    const int v = e ? atoi(e) : 0;
+    switch (v) {
+      case 6483: return DirectForm{1, 8, 3, false};
+      case 6484: return DirectForm{1, 8, 4, false};
+      case 64163: return DirectForm{1, 16, 3, false};
+      case 128: return DirectForm{2, 16, 2, false};
+      case 1282: return DirectForm{2, 16, 2, true};
+      case 12884: return DirectForm{2, 8, 4, false};
+      case 128842: return DirectForm{2, 8, 4, true};
+      case 128163: return DirectForm{2, 16, 3, false};
+      default: return DirectForm{1, 16, 2, false};
+    }
   }();
   return form;
+}
+
+template <bool SET, int MW, int BK, int NBUF, bool CAP2>
+static int launch_direct(int M, int N, int K, const cplx<float> *A, long lda, long sa, const cplx<float> *B,
+                          long ldb, long sb, cplx<float> *C, long ldc, long sc, int tn, int batch, float alpha,
+                          hipStream_t st) {
+  const int dtm = (M + 64 * MW - 1) / (64 * MW);
+  const int dtotal = (int)((long)dtm * tn * batch), dper = (dtotal + 7) / 8;
+  const size_t shm = (size_t)NBUF * (64 * MW + 64) * BK * sizeof(cplx<float>);
+  if (shm > 64 * 1024) {
+    const int rc = ensure_dynamic_lds((const void *)gemm_direct_kernel<SET, MW, BK, NBUF, CAP2>, shm);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL((gemm_direct_kernel<SET, MW, BK, NBUF, CAP2>), dim3((unsigned)(8 * dper)), dim3(256), shm, st,
+                     M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, dtm, tn, dtotal, dper, alpha);
+  return HP_OK;
+}
+
+// FP64 operands staged by direct global->LDS loads: one complex double is
+// one 16-byte chunk, so a wave's direct load fills 64 consecutive elements.
+// A is row-major [64][BK] with element k of row r at k ^ swz(r), swz
+// separating the rows that share a 256-byte bank window (BK = 8: rows r and
+// r + 1, swz = r/2 mod 8; BK = 16: swz = r mod 16), so the operand read of
+// one MFMA (16 rows at one k, 16 bytes each) covers a window once; B is
+// row-major [BK][64] (16 consecutive columns per k: one window).  The
+// products are the 4M form of gemm_sub_kernel on v_mfma_f64_16x16x4f64; the
+// ring of NBUF buffers and the vmcnt waits are those of the FP32 kernel.
+// 64 x 64 tiles, each wavefront 32 x 32 outputs; LDS NBUF 128 BK 16 bytes
+// (BK = 8, NBUF = 2: 32 KB).  Rows of A past M read row M - 1 and columns of
+// B past N read column N - 1 (outputs discarded).  K a multiple of BK.
+template <bool SET, int BK, int NBUF, int OCC>
+__global__ __launch_bounds__(256, OCC) void gemm_direct64_kernel(
+    int M, int N, int K, const cplx<double> *__restrict__ A, long lda, long sa, const cplx<double> *__restrict__ B,
+    long ldb, long sb, cplx<double> *__restrict__ C, long ldc, long sc, int tm, int tn, int total, int per_xcd,
+    double alpha) {
+  typedef typename Mfma<double>::v4 v4;
+  // OCC = 2 or 3: registers claimed so that at most OCC wavefronts share a SIMD
+  if constexpr (OCC == 2) asm volatile("" ::: "v183");
+  if constexpr (OCC == 3) asm volatile("" ::: "v135");
+  static_assert(BK == 8 || BK == 16, "BK");
+  static_assert(NBUF >= 2 && NBUF <= 4, "NBUF");
+  constexpr int BM = 64, BN = 64, TI = 2;
+  constexpr int AWS = BK == 16 ? 0 : 1;        // log2 of the A rows per 256-byte bank window
+  constexpr int APW = BM * BK / 64 / 4;        // A wave-loads per wavefront per stage
+  constexpr int BPW = BK * BN / 64 / 4;        // B wave-loads per wavefront per stage
+  constexpr int LPT = APW + BPW;
+  constexpr int ASZ = BM * BK, BSZ = BK * BN;
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<double> *As = reinterpret_cast<cplx<double> *>(smem_raw);  // [NBUF][BM * BK]
+  cplx<double> *Bs = As + NBUF * ASZ;                              // [NBUF][BK * BN]
+
+  const int bid = blockIdx.x;
+  const int t = (bid & 7) * per_xcd + (bid >> 3);
+  if (t >= total) return;
+  const int per_batch = tm * tn;
+  const int z = t / per_batch;
+  const int tb = t - z * per_batch;
+  const int grp = tb / (kGroupM * tn);
+  const int first_m = grp * kGroupM;
+  const int gm = min(kGroupM, tm - first_m);
+  const int in_grp = tb - grp * kGroupM * tn;
+  const int m0 = (first_m + in_grp % gm) * BM, n0 = (in_grp / gm) * BN;
+  A += sa * z;
+  B += sb * z;
+  C += sc * z;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+
+  const cplx<double> *asrc[APW];
+  const cplx<double> *bsrc[BPW];
+#pragma unroll
+  for (int i = 0; i < APW; ++i) {
+    const int c = (wave * APW + i) * 64 + lane;
+    const int row = c / BK, pos = c - row * BK;
+    asrc[i] = A + (long)min(m0 + row, M - 1) * lda + (pos ^ ((row >> AWS) & (BK - 1)));
+  }
+#pragma unroll
+  for (int i = 0; i < BPW; ++i) {
+    const int c = (wave * BPW + i) * 64 + lane;
+    const int kr = c / BN, pos = c - kr * BN;
+    bsrc[i] = B + (long)kr * ldb + min(n0 + pos, N - 1);
+  }
+  const unsigned lds0 = (unsigned)(size_t)(const __attribute__((address_space(3))) void *)As;
+  auto issue = [&](int buf, int k0) {
+#pragma unroll
+    for (int i = 0; i < APW; ++i)
+      lds_direct_load16(lds0 + (unsigned)((buf * ASZ + (wave * APW + i) * 64) * sizeof(cplx<double>)), asrc[i] + k0);
+#pragma unroll
+    for (int i = 0; i < BPW; ++i)
+      lds_direct_load16(lds0 + (unsigned)((NBUF * ASZ + buf * BSZ + (wave * BPW + i) * 64) * sizeof(cplx<double>)),
+                        bsrc[i] + (long)k0 * ldb);
+  };
+
+  v4 acc_re[TI][2], acc_im[TI][2];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc_re[i][j] = v4{0, 0, 0, 0};
+      acc_im[i][j] = v4{0, 0, 0, 0};
+    }
+  const int fr = lane & 15, fk = lane >> 4;
+  const int nk = K / BK;
+#pragma unroll
+  for (int s = 0; s < NBUF - 1; ++s)
+    if (s < nk) issue(s, s * BK);
+  int cur = 0;
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + NBUF - 2 < nk)
+      wait_vmcnt<(NBUF - 2) * LPT>();
+    else
+      wait_vmcnt<0>();
+    __syncthreads();
+    if (kt + NBUF - 1 < nk) {
+      const int nb = cur == 0 ? NBUF - 1 : cur - 1;
+      issue(nb, (kt + NBUF - 1) * BK);
+    }
+    const cplx<double> *as = As + cur * ASZ;
+    const cplx<double> *bs = Bs + cur * BSZ;
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kk = ks + fk;
+      cplx<double> af[TI], bf[2];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        const int row = wm + i * 16 + fr;
+        af[i] = as[row * BK + (kk ^ ((row >> AWS) & (BK - 1)))];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = bs[kk * BN + wn + j * 16 + fr];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) {
+        const double nai = -af[i].im;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc_re[i][j] = Mfma<double>::mac(af[i].re, bf[j].re, acc_re[i][j]);
+          acc_im[i][j] = Mfma<double>::mac(af[i].re, bf[j].im, acc_im[i][j]);
+          acc_re[i][j] = Mfma<double>::mac(nai, bf[j].im, acc_re[i][j]);
+          acc_im[i][j] = Mfma<double>::mac(af[i].im, bf[j].re, acc_im[i][j]);
+        }
+      }
+    }
+    cur = cur + 1 == NBUF ? 0 : cur + 1;
+  }
+#pragma unroll
+  for (int i = 0; i < TI; ++i) {
+    cplx<double> cv[4][2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = min(m0 + wm + i * 16 + MfmaLayout<double>::d_row(lane, r), M - 1);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if constexpr (SET)
+          cv[r][j] = cplx<double>{0.0, 0.0};
+        else
+          cv[r][j] = C[(long)gr * ldc + min(n0 + wn + j * 16 + fr, N - 1)];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = m0 + wm + i * 16 + MfmaLayout<double>::d_row(lane, r);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int gc = n0 + wn + j * 16 + fr;
+        cplx<double> c = cv[r][j];
+        c.re -= acc_re[i][j][r];
+        c.im -= acc_im[i][j][r];
+        if constexpr (SET) c = cplx<double>{-alpha * c.re, -alpha * c.im};
+        if (gr < M && gc < N) C[(long)gr * ldc + gc] = c;
+      }
+    }
+  }
+}
+
+// Form of the direct-staged FP64 kernel (HP_GEMM64_TILE, for tuning): BK,
+// NBUF and the wavefronts per SIMD (= workgroups per CU) it is held to; 0
+// selects the register-staged kernel.  Measured on MI355X alone (25344^2 x
+// 256 update, 8MNK flops): 68.8 TF/s (87.5 % of the FP64 matrix peak) for
+// the default (BK = 8, two buffers, three workgroups per CU: 96 KB of LDS, so
+// a 256-workgroup FP64 panel's 53 KB of rows fit beside it), 66.3 for two
+// workgroups, 69.6 for four (which leaves the panel no room: the FP64 LU step
+// is 11 % slower), against 63.0 for the register-staged kernel.
+struct Direct64Form {
+  int bk, nbuf, occ;
+};
+static Direct64Form direct64_form() {
+  static const Direct64Form form = [] {
+    const char *e = getenv("HP_GEMM64_TILE");
+    const int v = e ? atoi(e) : 823;
+    switch (v) {
+      case 0: return Direct64Form{0, 0, 0};
+      case 822: return Direct64Form{8, 2, 2};
+      case 824: return Direct64Form{8, 2, 4};
+      default: return Direct64Form{8, 2, 3};
+    }
+  }();
+  return form;
+}
+
+template <bool SET, int BK, int NBUF, int OCC>
+static int launch_direct64(int M, int N, int K, const cplx<double> *A, long lda, long sa, const cplx<double> *B,
+                           long ldb, long sb, cplx<double> *C, long ldc, long sc, int tm, int tn, int batch,
+                           double alpha, hipStream_t st) {
+  const int total = (int)((long)tm * tn * batch), per = (total + 7) / 8;
+  const size_t shm = (size_t)NBUF * 128 * BK * sizeof(cplx<double>);
+  if (shm > 64 * 1024) {
+    const int rc = ensure_dynamic_lds((const void *)gemm_direct64_kernel<SET, BK, NBUF, OCC>, shm);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL((gemm_direct64_kernel<SET, BK, NBUF, OCC>), dim3((unsigned)(8 * per)), dim3(256), shm, st, M,
+                     N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, tm, tn, total, per, alpha);
+  return HP_OK;
 }
 
 template <typename T, int WTM, int WTN, bool SET>
@@ -496,22 +769,37 @@ static int launch_gemm(int M, int N, int K, const cplx<T> *A, long lda, long sa,
   }
   dim3 grid((unsigned)(8 * per_xcd));
   if constexpr (sizeof(T) == 4 && WTM == 2 && WTN == 2) {
-    if (vec && K % kDirectBK == 0 && N % 2 == 0 && ldc > 0) {
-      const int form = direct_form();
-      const int rows = form == 64 ? 64 : 128;
-      const int dtm = (M + rows - 1) / rows;
-      const long dtotal_l = (long)dtm * tn * batch;
-      const int dtotal = (int)dtotal_l, dper = (dtotal + 7) / 8;
-      const size_t dshm = (size_t)2 * (rows + 64) * kDirectBK * sizeof(cplx<float>);
-      if (form == 128)
-        hipLaunchKernelGGL((gemm_direct_kernel<SET, 2>), dim3((unsigned)(8 * dper)), dim3(256), dshm, st, M, N, K,
-                           A, lda, sa, B, ldb, sb, C, ldc, sc, dtm, tn, dtotal, dper, alpha);
-      else if (form == 1282)
-        hipLaunchKernelGGL((gemm_direct_kernel<SET, 2, true>), dim3((unsigned)(8 * dper)), dim3(256), dshm, st, M, N,
-                           K, A, lda, sa, B, ldb, sb, C, ldc, sc, dtm, tn, dtotal, dper, alpha);
-      else
-        hipLaunchKernelGGL((gemm_direct_kernel<SET, 1>), grid, dim3(256), dshm, st, M, N, K, A, lda, sa, B, ldb, sb,
-                           C, ldc, sc, tm, tn, total, per_xcd, alpha);
+    const DirectForm f = direct_form();
+    if (vec && K % f.bk == 0 && N % 2 == 0 && ldc > 0) {
+      const int id = f.mw * 10000 + f.bk * 100 + f.nbuf * 10 + (f.cap2 ? 1 : 0);
+      int rc;
+      switch (id) {
+        case 10830: rc = launch_direct<SET, 1, 8, 3, false>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, tn, batch, alpha, st); break;
+        case 10840: rc = launch_direct<SET, 1, 8, 4, false>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, tn, batch, alpha, st); break;
+        case 11630: rc = launch_direct<SET, 1, 16, 3, false>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, tn, batch, alpha, st); break;
+        case 21620: rc = launch_direct<SET, 2, 16, 2, false>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, tn, batch, alpha, st); break;
+        case 21621: rc = launch_direct<SET, 2, 16, 2, true>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, tn, batch, alpha, st); break;
+        case 20840: rc = launch_direct<SET, 2, 8, 4, false>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, tn, batch, alpha, st); break;
+        case 20841: rc = launch_direct<SET, 2, 8, 4, true>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, tn, batch, alpha, st); break;
+        case 21630: rc = launch_direct<SET, 2, 16, 3, false>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, tn, batch, alpha, st); break;
+        default: rc = launch_direct<SET, 1, 16, 2, false>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, tn, batch, alpha, st); break;
+      }
+      if (rc) return rc;
+      HP_CHECK_LAUNCH();
+      return HP_OK;
+    }
+  }
+  if constexpr (sizeof(T) == 8 && WTM == 2 && WTN == 2) {
+    const Direct64Form f = direct64_form();
+    if (f.bk > 0 && K % f.bk == 0 && ldc > 0) {
+      const int id = f.bk * 100 + f.nbuf * 10 + f.occ;
+      int rc;
+      switch (id) {
+        case 822: rc = launch_direct64<SET, 8, 2, 2>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, tm, tn, batch, alpha, st); break;
+        case 824: rc = launch_direct64<SET, 8, 2, 4>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, tm, tn, batch, alpha, st); break;
+        default: rc = launch_direct64<SET, 8, 2, 3>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, tm, tn, batch, alpha, st); break;
+      }
+      if (rc) return rc;
       HP_CHECK_LAUNCH();
       return HP_OK;
     }
@@ -538,12 +826,11 @@ int gemm_sub_batched(int M, int N, int K, const cplx<T> *A, long lda, long sa, c
   // real matrix-core flops of the product: 8 M N K (4M, FP64) or 6 M N K (3M, FP32)
   TraceScope ts(sizeof(T) == 8 ? TR_GEMM64 : TR_GEMM32, st, (sizeof(T) == 8 ? 8.0 : 6.0) * M * (double)N * K * batch,
                 2.0 * sizeof(cplx<T>) * (double)M * N * batch);
-  // 64 x 64 tiles: measured on MI355X (12800^2 x 256 update, complex rate
-  // 8MNK / t) at 120 TF/s in FP32 (90 TF/s of 3M matrix-core flops then, 104
-  // since the epilogue loads were batched) and 57 TF/s in FP64, against
-  // 79-110 TF/s and 45 TF/s for the 128-wide tiles, whose register footprint
-  // leaves one wavefront per SIMD.  A variant that loads C during the last K
-  // stage was 1 % faster alone but slower beside the panel (more registers).
+  // 64 x 64 tiles in both precisions (the direct-staged kernels' forms and
+  // their measured rates are given with the kernels).  The register-staged
+  // kernel: 64 x 64 tiles measured against 128-wide ones, whose register
+  // footprint leaves one wavefront per SIMD.  Loading C during the last K
+  // stage (FP32) measured 1 % slower alone, and slower beside the panel.
   return launch_gemm<T, 2, 2, false>(M, N, K, A, lda, sa, B, ldb, sb, C, ldc, sc, batch, T(1), st);
 }
 

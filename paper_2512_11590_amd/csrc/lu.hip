@@ -1156,8 +1156,17 @@ static int panel_grid(int m, int lds_cap, int &G, int &rpw) {
   // per-group arrival flags), and at most lds_cap bytes of rows per workgroup
   const int rpw_max = lds_cap / (int)(kPanelLd * sizeof(cplx<T>));
   const int rpw_min = 64;
+  // FP32: 128 workgroups (measured fastest on a 25600-row panel); FP64: up to
+  // 256 (at most 53 KB of rows each at 25600 rows), so that a panel
+  // workgroup fits beside the FP64 trailing update's workgroups on a CU
+  static const int gmax64 = [] {
+    const char *e = getenv("HP_PANEL_GMAX64");
+    const int v = e ? atoi(e) : kMaxPanelGroups;
+    return std::max(1, std::min(v, kMaxPanelGroups));
+  }();
+  const int gmax = std::is_same<T, double>::value ? gmax64 : 128;
   G = (m + rpw_min - 1) / rpw_min;
-  G = std::min(G, kMaxPanelGroups);
+  G = std::min(G, gmax);
   G = std::max(G, 1);
   // tuning knob: HP_PANEL_GROUPS overrides the workgroup count (still capped by LDS below)
   static const int forced = [] {

@@ -309,7 +309,7 @@ def test_repeat_is_bitwise_deterministic(H, P):
 
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("M,N,K", [(1, 1, 1), (16, 16, 4), (63, 65, 17), (130, 129, 33), (300, 256, 256),
-                                   (2100, 700, 256), (129, 4000, 32)])
+                                   (2100, 700, 256), (129, 4000, 32), (65, 67, 8), (191, 193, 48)])
 def test_gemm_sub_matches_numpy(H, prec, M, N, K):
     say("gemm", prec, M, N, K)
     rng = np.random.default_rng(M * 7 + N * 3 + K)
@@ -327,14 +327,16 @@ def test_gemm_sub_matches_numpy(H, prec, M, N, K):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_gemm_sub_offset_views(H, prec):
-    """Sub-matrix views with odd leading dimensions and offsets (scalar-load path)."""
-    say("gemm views", prec)
+@pytest.mark.parametrize("K", [37, 40])
+def test_gemm_sub_offset_views(H, prec, K):
+    """Sub-matrix views with odd leading dimensions and offsets (FP32: the
+    scalar-load path; FP64 with K a multiple of 8: the direct-staged kernel)."""
+    say("gemm views", prec, K)
     rng = np.random.default_rng(5)
     ct = np.complex64 if prec == H.HP_C64 else np.complex128
     big = (rng.standard_normal((301, 303)) + 1j * rng.standard_normal((301, 303))).astype(ct)
     d = torch.from_numpy(big).to("cuda")
-    M, N, K = 150, 140, 37
+    M, N = 150, 140
     A = big[1:1 + M, 3:3 + K]
     B = big[200:200 + K, 5:5 + N]
     C = big[151:151 + M, 150:150 + N].astype(np.complex128) - A.astype(np.complex128) @ B.astype(np.complex128)
