@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 #include <vector>
 
 namespace hp {
@@ -189,6 +190,112 @@ __device__ __forceinline__ void tile_gemm_sub(int m0, int n0, int M, int N, int 
     }
   }
 }
+
+// FP64 form of tile_gemm_sub with the operands staged by direct
+// global->LDS loads in stages of 8 (two buffers, 32 KB of LDS): the next
+// stage's loads are in flight during the current stage's products, with no
+// register staging and no LDS store instructions.  A is row-major [64][8] in
+// LDS with element k of row r at k ^ (r/2 mod 8) (the 16 rows of one MFMA
+// operand read cover a 256-byte bank window once), B row-major [8][64].
+// Loads past M, N or K read clamped, in-bounds addresses; A values past K are
+// zeroed before their products, the other clamped values only reach outputs
+// that are not stored.
+__device__ __forceinline__ void tile_gemm_sub_direct64(int m0, int n0, int M, int N, int K,
+                                                       const cplx<double> *__restrict__ A, long lda,
+                                                       const cplx<double> *__restrict__ B, long ldb,
+                                                       cplx<double> *__restrict__ C, long ldc, cplx<double> *smem) {
+  typedef BMfma<double>::v4 v4;
+  constexpr int BK = 8, NBUF = 2, ASZ = 64 * BK, BSZ = BK * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int fr = lane & 15, fk = lane >> 4;
+  // this lane's two A chunks and two B chunks of a stage
+  const cplx<double> *arow[2], *bcol[2];
+  int ak[2], bk[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int c = (wave * 2 + i) * 64 + lane;
+    const int row = c >> 3, pos = c & 7;
+    arow[i] = A + (long)min(m0 + row, M - 1) * lda;
+    ak[i] = pos ^ ((row >> 1) & 7);
+    const int kr = c >> 6, col = c & 63;
+    bcol[i] = B + min(n0 + col, N - 1);
+    bk[i] = kr;
+  }
+  const unsigned lds0 = (unsigned)(size_t)(const __attribute__((address_space(3))) void *)smem;
+  auto issue = [&](int buf, int k0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      lds_direct_load16(lds0 + (unsigned)((buf * ASZ + (wave * 2 + i) * 64) * sizeof(cplx<double>)),
+                        arow[i] + min(k0 + ak[i], K - 1));
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      lds_direct_load16(lds0 + (unsigned)((NBUF * ASZ + buf * BSZ + (wave * 2 + i) * 64) * sizeof(cplx<double>)),
+                        bcol[i] + (long)min(k0 + bk[i], K - 1) * ldb);
+  };
+  v4 p1[2][2], p3[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) p1[i][j] = p3[i][j] = v4{0, 0, 0, 0};
+  const int nk = (K + BK - 1) / BK;
+  if (nk > 0) issue(0, 0);
+  for (int kt = 0; kt < nk; ++kt) {
+    wait_vmcnt<0>();
+    __syncthreads();
+    if (kt + 1 < nk) issue((kt + 1) & 1, (kt + 1) * BK);
+    const cplx<double> *as = smem + (kt & 1) * ASZ;
+    const cplx<double> *bs = smem + NBUF * ASZ + (kt & 1) * BSZ;
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kk = ks + fk;
+      const bool live = kt * BK + kk < K;
+      cplx<double> af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm + i * 16 + fr;
+        af[i] = as[row * BK + (kk ^ ((row >> 1) & 7))];
+        if (!live) af[i] = cplx<double>{0.0, 0.0};
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = bs[kk * 64 + wn + j * 16 + fr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          p1[i][j] = BMfma<double>::mac(af[i].re, bf[j].re, p1[i][j]);
+          p1[i][j] = BMfma<double>::mac(-af[i].im, bf[j].im, p1[i][j]);
+          p3[i][j] = BMfma<double>::mac(af[i].re, bf[j].im, p3[i][j]);
+          p3[i][j] = BMfma<double>::mac(af[i].im, bf[j].re, p3[i][j]);
+        }
+    }
+  }
+  // the LDS buffers are free again once every wavefront has read the last stage
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    cplx<double> cv[4][2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = min(m0 + wm + i * 16 + BMfma<double>::d_row(lane, r), M - 1);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) cv[r][j] = C[(long)gr * ldc + min(n0 + wn + j * 16 + fr, N - 1)];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = m0 + wm + i * 16 + BMfma<double>::d_row(lane, r);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int gc = n0 + wn + j * 16 + fr;
+        cplx<double> c = cv[r][j];
+        c.re -= p1[i][j][r];
+        c.im -= p3[i][j][r];
+        if (gr < M && gc < N) C[(long)gr * ldc + gc] = c;
+      }
+    }
+  }
+}
+constexpr size_t kDirect64TileLds = (size_t)2 * 2 * 64 * 8 * sizeof(cplx<double>);  // 32 KB
 
 // All of C[M x N] -= A[M x K] B[K x N] by one workgroup, tile after tile.
 template <typename T>
@@ -602,8 +709,12 @@ __global__ __launch_bounds__(256) void batch_trail_kernel(int count, const hp_ba
   const int tn = (sh.cols + 63) / 64;
   const int l = g - offs[s];
   cplx<T> *a = A + it.a_off;
-  tile_gemm_sub<T>((l / tn) * 64, (l % tn) * 64, sh.rows, sh.cols, sh.K, a + (long)sh.r0 * n + sh.k0, n,
-                   a + (long)sh.k0 * n + sh.c0, n, a + (long)sh.r0 * n + sh.c0, n, As, Bs);
+  if constexpr (std::is_same<T, double>::value)
+    tile_gemm_sub_direct64((l / tn) * 64, (l % tn) * 64, sh.rows, sh.cols, sh.K, a + (long)sh.r0 * n + sh.k0, n,
+                           a + (long)sh.k0 * n + sh.c0, n, a + (long)sh.r0 * n + sh.c0, n, As);
+  else
+    tile_gemm_sub<T>((l / tn) * 64, (l % tn) * 64, sh.rows, sh.cols, sh.K, a + (long)sh.r0 * n + sh.k0, n,
+                     a + (long)sh.k0 * n + sh.c0, n, a + (long)sh.r0 * n + sh.c0, n, As, Bs);
 }
 
 // After the panel at j of every system (kind 3 units): the panel's
@@ -1261,7 +1372,8 @@ extern "C" int hp_batch_factor_stepped(int count, const hp_batch_item *items, co
   HP_CHECK_LAUNCH();
   hipLaunchKernelGGL(batch_tables_kernel, dim3(Q), dim3(64), 0, st, count, items, panel, block, P, offs);
   HP_CHECK_LAUNCH();
-  const size_t shm = prec == HP_C64 ? tile_lds_bytes<float>() : tile_lds_bytes<double>();
+  // FP64 trailing tiles: the direct-staged tile product (32 KB of LDS)
+  const size_t shm = prec == HP_C64 ? tile_lds_bytes<float>() : kDirect64TileLds;
   int rc = prec == HP_C64 ? ensure_dynamic_lds((const void *)batch_trail_kernel<float>, shm)
                           : ensure_dynamic_lds((const void *)batch_trail_kernel<double>, shm);
   if (rc) return rc;

@@ -171,6 +171,31 @@ int wform_build(int n, const cplx<float> *LU, long lda, const cplx<float> *inv, 
 int wform_solve(int n, int nrhs, const cplx<float> *LU, long lda, const cplx<float> *inv, const cplx<float> *W,
                 const cplx<float> *inv2, cplx<float> *Y, long ldy, cplx<float> *Z, long ldz, hipStream_t st);
 
+
+// Direct global -> LDS load (global_load_lds_dwordx4) of one 16-byte chunk per
+// lane: a wavefront's 64 chunks land in 64 consecutive 16-byte LDS slots from
+// lds_byte_addr (uniform over the wavefront; passed in M0, which is declared
+// clobbered, so the compiler keeps nothing of its own there).  Issued from
+// inline assembly so the compiler neither reorders it nor waits for it; a
+// thread waits for its own loads with wait_vmcnt before the barrier that
+// publishes them.
+__device__ __forceinline__ void lds_direct_load16(unsigned lds_byte_addr, const void *src) {
+  const unsigned m0v = __builtin_amdgcn_readfirstlane(lds_byte_addr);
+  // one wait state between the M0 write and the LDS-DMA load that reads it
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(m0v), "v"(src)
+               : "memory", "m0");
+}
+
+// s_waitcnt with vmcnt <= n (0 <= n < 64) and the other counters unconstrained
+// (gfx9 encoding: vmcnt low bits [3:0], high bits [15:14], expcnt [6:4],
+// lgkmcnt [11:8]).  Vector memory operations complete in issue order, so this
+// waits for all but the n most recent.
+template <int n>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(n >= 0 && n < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
+}
+
 }  // namespace hp
 
 namespace hp {

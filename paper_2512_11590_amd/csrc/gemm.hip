@@ -321,25 +321,6 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 4 : 2)) void gemm_sub_kernel
 // launcher): 16-byte aligned rows of A and B, K a multiple of BK, N even.
 // Rows of A past M read row M - 1 and columns of B past N read the last
 // column pair (their outputs are discarded).
-constexpr int kDirectBK = 16;
-// lds_byte_addr must be uniform over the wavefront.  M0 is declared clobbered,
-// so the compiler keeps nothing of its own in M0 across the load.
-__device__ __forceinline__ void lds_direct_load16(unsigned lds_byte_addr, const void *src) {
-  const unsigned m0v = __builtin_amdgcn_readfirstlane(lds_byte_addr);
-  // one wait state between the M0 write and the LDS-DMA load that reads it
-  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(m0v), "v"(src)
-               : "memory", "m0");
-}
-
-// s_waitcnt with vmcnt <= n (0 <= n < 64) and the other counters unconstrained
-// (gfx9 encoding: vmcnt low bits [3:0], high bits [15:14], expcnt [6:4],
-// lgkmcnt [11:8]).
-template <int n>
-__device__ __forceinline__ void wait_vmcnt() {
-  static_assert(n >= 0 && n < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
-}
-
 // MW = 1: 64 x 64 tiles, each wavefront 32 x 32 outputs, held to three
 // wavefronts per SIMD (registers claimed up to v135): three workgroups per CU
 // leave room (LDS and registers) for a panel workgroup beside them -- the

@@ -146,14 +146,6 @@ __global__ __launch_bounds__(256) void h3_cols_kernel(int N, int K, const cplx<f
   }
 }
 
-// Direct global -> LDS load of one 16-byte unit per lane (the LDS base of the
-// wavefront's 64 units in M0, uniform; M0 declared clobbered).
-__device__ __forceinline__ void h3_direct_load16(unsigned lds_byte_addr, const void *src) {
-  const unsigned m0v = __builtin_amdgcn_readfirstlane(lds_byte_addr);
-  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(m0v), "v"(src)
-               : "memory", "m0");
-}
-
 // C (M x N complex FP32, ldc) -= diag(rs) (Ah Bh^T) diag(cs) with the split
 // FP16 products.  Workgroup tile 64 x 128, four wavefronts of 32 x 64 (2 x 4
 // MFMA tiles), K in stages of 32 through double-buffered LDS (48 KB a
@@ -207,10 +199,10 @@ __global__ __launch_bounds__(256, 1) void gemm_h3_kernel(int M, int N, int K, co
   auto issue = [&](int buf, int kc) {  // kc: first chunk of the stage
 #pragma unroll
     for (int i = 0; i < APW; ++i)
-      h3_direct_load16(lds0 + (unsigned)((buf * ASZ + (wave * APW + i) * 64) * 16), asrc[i] + (long)kc * 4);
+      lds_direct_load16(lds0 + (unsigned)((buf * ASZ + (wave * APW + i) * 64) * 16), asrc[i] + (long)kc * 4);
 #pragma unroll
     for (int i = 0; i < BPW; ++i)
-      h3_direct_load16(lds0 + (unsigned)((2 * ASZ + buf * BSZ + (wave * BPW + i) * 64) * 16), bsrc[i] + (long)kc * 4);
+      lds_direct_load16(lds0 + (unsigned)((2 * ASZ + buf * BSZ + (wave * BPW + i) * 64) * 16), bsrc[i] + (long)kc * 4);
   };
 
   f4v acc_rr[2][4], acc_ii[2][4], acc_im[2][4];
