@@ -57,6 +57,20 @@ def parse():
     ap.add_argument("--batched-systems", type=int, default=512)
     ap.add_argument("--served-requests", type=int, default=24)
     ap.add_argument("--served-rate", type=float, default=4.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--served-rate-sustained", type=float, default=2.0,
+                    help="a second, lower arrival rate for the same requests (0: skip)")
+    ap.add_argument("--only", choices=("batched", "served"), default=None,
+                    help="run only this block (for profiling) and print it as the JSON line")
+    ap.add_argument("--counter-summary", metavar="CSV", default=None,
+                    help="read a rocprofv3 --pmc counter CSV (no GPU) and print per-kernel counter sums, "
+                         "then exit")
+    ap.add_argument("--kernel", default="", help="with --counter-summary: only kernels whose name contains this")
+    ap.add_argument("--window", nargs=2, metavar=("FIRST", "LAST"), default=None,
+                    help="with --counter-summary: only dispatches from each dispatch of a kernel named FIRST "
+                         "up to the next one named LAST")
+    ap.add_argument("--trace-overlap", metavar="CSV", default=None,
+                    help="read a rocprofv3 kernel-trace CSV (no GPU) and print how long factorization "
+                         "kernels of different hardware queues ran at the same time, then exit")
     ap.add_argument("--served-slots", type=int, default=4)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (a plain copy of known size, "
@@ -130,7 +144,7 @@ def batched(args, H, torch):
     return res
 
 
-def served_stream(args, H, torch):
+def served_stream(args, H, torch, rate=None):
     """The served stream: Poisson arrivals, N log-uniform in [500, 16000],
     1-8 energies each, continuous batching over a few slots; FP32 + IR, then
     FP64 on the same arrivals.  Reports solves/s, p50/p99 latency and the
@@ -138,13 +152,14 @@ def served_stream(args, H, torch):
     import numpy as np
     from paper_2512_11590_amd import serve
     from workload import served_requests
-    reqs = served_requests(args.served_requests, args.served_rate)
-    res = {"requests": len(reqs), "rate_hz": args.served_rate, "slots": args.served_slots,
+    rate = args.served_rate if rate is None else rate
+    reqs = served_requests(args.served_requests, rate)
+    res = {"requests": len(reqs), "rate_hz": rate, "slots": args.served_slots,
            "N_range": [min(sp.nc * sp.nr for _, sp in reqs), max(sp.nc * sp.nr for _, sp in reqs)],
            "energies": int(sum(len(sp.energies) for _, sp in reqs))}
     runs = {}
     for name, prec in (("fp32_ir", H.HP_C64), ("fp64", H.HP_C128)):
-        print(f"[bench] served stream {name}: {len(reqs)} requests at {args.served_rate}/s", file=sys.stderr,
+        print(f"[bench] served stream {name}: {len(reqs)} requests at {rate}/s", file=sys.stderr,
               flush=True)
         t0 = time.perf_counter()
         done = []
@@ -163,6 +178,86 @@ def served_stream(args, H, torch):
              for a, b in zip(ra.S, rb.S)]
     res["S_relerr_fp32ir_vs_fp64_max"] = max(diffs) if diffs else None
     return res
+
+
+def counter_summary(path: str, kernel: str = "", window=None) -> dict:
+    """Per-kernel sums of rocprofv3 --pmc counters (one row per dispatch and
+    counter), over the dispatches whose name contains `kernel`; with window =
+    (FIRST, LAST), only dispatches from a FIRST dispatch up to the next LAST
+    one (by dispatch id), e.g. one LU step's factorization and first solve."""
+    import csv
+    from collections import defaultdict
+    disp = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            d = int(r["Dispatch_Id"])
+            e = disp.setdefault(d, {"name": r["Kernel_Name"], "counters": {}})
+            e["counters"][r["Counter_Name"]] = e["counters"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    keep = set(disp)
+    if window:
+        keep, inside = set(), False
+        for d in sorted(disp):
+            nm = disp[d]["name"]
+            if window[0] in nm:
+                inside = True
+            if inside:
+                keep.add(d)
+            if inside and window[1] in nm:
+                inside = False
+    out = defaultdict(lambda: {"dispatches": 0, "counters": defaultdict(float)})
+    for d in sorted(keep):
+        nm = disp[d]["name"]
+        if kernel and kernel not in nm:
+            continue
+        key = nm.split("(")[0] if "(anonymous" not in nm else nm.replace("(anonymous namespace)::", "").split("(")[0]
+        out[key]["dispatches"] += 1
+        for c, v in disp[d]["counters"].items():
+            out[key]["counters"][c] += v
+    return {k: {"dispatches": v["dispatches"], "counters": dict(v["counters"])} for k, v in out.items()}
+
+
+def trace_overlap(path: str) -> dict:
+    """Factorization kernels in a rocprofv3 kernel trace (single-system panel
+    grids and panel finishes; batched panel, interchange/block-row and
+    trailing-update steps): total time with at least one of them running,
+    time with kernels of two or more hardware queues running at once, and
+    time with a batched and a single-system factorization running at once."""
+    import csv
+    from collections import Counter
+    single = ("panel_kernel", "panel_finish_kernel")
+    batched_k = ("batch_panel_kernel", "batch_trail_kernel", "batch_lu_kernel", "batch_swap_brow_kernel",
+                 "batch_brow_kernel")
+    edges = []
+    kinds = Counter()
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            name = r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0].split("::")[-1]
+            base = name.split("<")[0]
+            kind = "single" if base in single else "batched" if base in batched_k else None
+            if kind is None:
+                continue
+            q = r["Queue_Id"]
+            kinds[(kind, q)] += 1
+            edges.append((int(r["Start_Timestamp"]), 1, q, kind))
+            edges.append((int(r["End_Timestamp"]), -1, q, kind))
+    edges.sort()
+    live = Counter()
+    t_any = t_multi = t_mixed = 0
+    last = edges[0][0] if edges else 0
+    for t, d, q, kind in edges:
+        on = [k for k, v in live.items() if v > 0]
+        dt = t - last
+        if on:
+            t_any += dt
+        if len({k[0] for k in on}) >= 2:
+            t_multi += dt
+        if {"single", "batched"} <= {k[1] for k in on}:
+            t_mixed += dt
+        live[(q, kind)] += d
+        last = t
+    return {"factorization_kernels": {f"{k} queue {q}": v for (k, q), v in sorted(kinds.items())},
+            "ms_any_running": t_any / 1e6, "ms_two_or_more_queues": t_multi / 1e6,
+            "ms_batched_and_single_system": t_mixed / 1e6}
 
 
 def cpu_baseline(n_full: int):
@@ -189,6 +284,12 @@ def cpu_baseline(n_full: int):
 
 def main():
     args = parse()
+    if args.trace_overlap:
+        print(json.dumps(trace_overlap(args.trace_overlap)), flush=True)
+        return
+    if args.counter_summary:
+        print(json.dumps(counter_summary(args.counter_summary, args.kernel, args.window)), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -208,6 +309,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes}))
+        return
+    if args.only:
+        blk = batched(args, H, torch) if args.only == "batched" else served_stream(args, H, torch)
+        print(json.dumps({"only": args.only, args.only: blk}), flush=True)
         return
     sp = make_system(args.config)
     n = sp.n
@@ -287,6 +392,8 @@ def main():
         out["batched"] = batched(args, H, torch)
     if not args.no_served:
         out["served"] = served_stream(args, H, torch)
+        if args.served_rate_sustained > 0:
+            out["served_sustained"] = served_stream(args, H, torch, rate=args.served_rate_sustained)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(n)

@@ -68,7 +68,11 @@ class Bucket:
         nr = np.array([s.nr for s in self.systems], dtype=np.int64)
         n = nc * nr
         self.n, self.nc, self.nr = n, nc, nr
-        self.a_off = np.concatenate([[0], np.cumsum(n * n)[:-1]])
+        # each matrix starts on a 256-byte boundary (a multiple of 32 elements),
+        # so the rows of every system with even n are 16-byte aligned (the
+        # batched FP32 tile product then stages them by direct loads)
+        slot = (n * n + 31) // 32 * 32
+        self.a_off = np.concatenate([[0], np.cumsum(slot)[:-1]])
         self.x_off = np.concatenate([[0], np.cumsum(n * nc)[:-1]])
         self.p_off = np.concatenate([[0], np.cumsum(n)[:-1]])
         self.r_off = np.concatenate([[0], np.cumsum(nc * nc)[:-1]])
@@ -107,7 +111,7 @@ class Bucket:
         raw = np.frombuffer(bytes(items), dtype=np.uint8).copy()
         self.items = torch.from_numpy(raw).to(dev)
         ctype = torch.complex64 if prec == H.HP_C64 else torch.complex128
-        self.A = torch.empty(int((n * n).sum()), dtype=ctype, device=dev)
+        self.A = torch.empty(int(slot.sum()), dtype=ctype, device=dev)
         self.ipiv = torch.empty(int(n.sum()), dtype=torch.int32, device=dev)
         self.perm = torch.empty(int(n.sum()), dtype=torch.int32, device=dev)
         self.info = torch.zeros(self.count, dtype=torch.int32, device=dev)

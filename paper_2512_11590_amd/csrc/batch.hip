@@ -297,6 +297,106 @@ __device__ __forceinline__ void tile_gemm_sub_direct64(int m0, int n0, int M, in
 }
 constexpr size_t kDirect64TileLds = (size_t)2 * 2 * 64 * 8 * sizeof(cplx<double>);  // 32 KB
 
+// FP32 form for operands whose rows are 16-byte aligned (even leading
+// dimension and block offsets, K and N even): 16-byte chunks of two complex
+// staged by direct global->LDS loads in stages of 16, two buffers (32 KB).
+// A is row-major [64][16] with the chunk at position p of row r stored at
+// p ^ (r/2 mod 8), B row-major [16][64]; 3M products as in tile_gemm_sub.
+// Chunks past K or N read clamped in-bounds chunks; A values past K are
+// zeroed before their products.
+__device__ __forceinline__ void tile_gemm_sub_direct32(int m0, int n0, int M, int N, int K,
+                                                       const cplx<float> *__restrict__ A, long lda,
+                                                       const cplx<float> *__restrict__ B, long ldb,
+                                                       cplx<float> *__restrict__ C, long ldc, cplx<float> *smem) {
+  typedef BMfma<float>::v4 v4;
+  constexpr int BK = 16, NBUF = 2, ASZ = 64 * BK, BSZ = BK * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int fr = lane & 15, fk = lane >> 4;
+  const cplx<float> *arow[2], *bcol[2];
+  int ak[2], bk[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int c = (wave * 2 + i) * 64 + lane;
+    const int row = c >> 3, pos = c & 7;
+    arow[i] = A + (long)min(m0 + row, M - 1) * lda;
+    ak[i] = 2 * (pos ^ ((row >> 1) & 7));
+    const int kr = c >> 5, cp = c & 31;
+    bcol[i] = B + min(n0 + 2 * cp, N - 2);
+    bk[i] = kr;
+  }
+  const unsigned lds0 = (unsigned)(size_t)(const __attribute__((address_space(3))) void *)smem;
+  auto issue = [&](int buf, int k0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      lds_direct_load16(lds0 + (unsigned)((buf * ASZ + (wave * 2 + i) * 128) * sizeof(cplx<float>)),
+                        arow[i] + min(k0 + ak[i], K - 2));
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      lds_direct_load16(lds0 + (unsigned)((NBUF * ASZ + buf * BSZ + (wave * 2 + i) * 128) * sizeof(cplx<float>)),
+                        bcol[i] + (long)min(k0 + bk[i], K - 1) * ldb);
+  };
+  v4 p1[2][2], p2[2][2], p3[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) p1[i][j] = p2[i][j] = p3[i][j] = v4{0, 0, 0, 0};
+  const int nk = (K + BK - 1) / BK;
+  if (nk > 0) issue(0, 0);
+  for (int kt = 0; kt < nk; ++kt) {
+    wait_vmcnt<0>();
+    __syncthreads();
+    if (kt + 1 < nk) issue((kt + 1) & 1, (kt + 1) * BK);
+    const cplx<float> *as = smem + (kt & 1) * ASZ;
+    const cplx<float> *bs = smem + NBUF * ASZ + (kt & 1) * BSZ;
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kk = ks + fk;
+      const bool live = kt * BK + kk < K;
+      cplx<float> af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm + i * 16 + fr;
+        af[i] = as[row * BK + 2 * ((kk >> 1) ^ ((row >> 1) & 7)) + (kk & 1)];
+        if (!live) af[i] = cplx<float>{0.f, 0.f};
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = bs[kk * 64 + wn + j * 16 + fr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          p1[i][j] = BMfma<float>::mac(af[i].re, bf[j].re, p1[i][j]);
+          p2[i][j] = BMfma<float>::mac(af[i].im, bf[j].im, p2[i][j]);
+          p3[i][j] = BMfma<float>::mac(af[i].re + af[i].im, bf[j].re + bf[j].im, p3[i][j]);
+        }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    cplx<float> cv[4][2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = min(m0 + wm + i * 16 + BMfma<float>::d_row(lane, r), M - 1);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) cv[r][j] = C[(long)gr * ldc + min(n0 + wn + j * 16 + fr, N - 1)];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gr = m0 + wm + i * 16 + BMfma<float>::d_row(lane, r);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int gc = n0 + wn + j * 16 + fr;
+        cplx<float> c = cv[r][j];
+        c.re -= p1[i][j][r] - p2[i][j][r];
+        c.im -= p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
+        if (gr < M && gc < N) C[(long)gr * ldc + gc] = c;
+      }
+    }
+  }
+}
+
 // All of C[M x N] -= A[M x K] B[K x N] by one workgroup, tile after tile.
 template <typename T>
 __device__ void wg_gemm_sub(int M, int N, int K, const cplx<T> *__restrict__ A, long lda,
@@ -709,12 +809,20 @@ __global__ __launch_bounds__(256) void batch_trail_kernel(int count, const hp_ba
   const int tn = (sh.cols + 63) / 64;
   const int l = g - offs[s];
   cplx<T> *a = A + it.a_off;
-  if constexpr (std::is_same<T, double>::value)
-    tile_gemm_sub_direct64((l / tn) * 64, (l % tn) * 64, sh.rows, sh.cols, sh.K, a + (long)sh.r0 * n + sh.k0, n,
-                           a + (long)sh.k0 * n + sh.c0, n, a + (long)sh.r0 * n + sh.c0, n, As);
-  else
-    tile_gemm_sub<T>((l / tn) * 64, (l % tn) * 64, sh.rows, sh.cols, sh.K, a + (long)sh.r0 * n + sh.k0, n,
-                     a + (long)sh.k0 * n + sh.c0, n, a + (long)sh.r0 * n + sh.c0, n, As, Bs);
+  const cplx<T> *pa = a + (long)sh.r0 * n + sh.k0, *pb = a + (long)sh.k0 * n + sh.c0;
+  cplx<T> *pc = a + (long)sh.r0 * n + sh.c0;
+  if constexpr (std::is_same<T, double>::value) {
+    tile_gemm_sub_direct64((l / tn) * 64, (l % tn) * 64, sh.rows, sh.cols, sh.K, pa, n, pb, n, pc, n, As);
+  } else {
+    // direct staging needs 16-byte aligned rows and chunks that never
+    // straddle the end of K or of a row (uniform over the workgroup)
+    const bool aligned = (n % 2 == 0) && (sh.K % 2 == 0) && (sh.cols % 2 == 0) &&
+                         ((((uintptr_t)pa) | ((uintptr_t)pb)) & 15) == 0;
+    if (aligned)
+      tile_gemm_sub_direct32((l / tn) * 64, (l % tn) * 64, sh.rows, sh.cols, sh.K, pa, n, pb, n, pc, n, As);
+    else
+      tile_gemm_sub<T>((l / tn) * 64, (l % tn) * 64, sh.rows, sh.cols, sh.K, pa, n, pb, n, pc, n, As, Bs);
+  }
 }
 
 // After the panel at j of every system (kind 3 units): the panel's
