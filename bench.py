@@ -37,8 +37,8 @@ PEAK_FP16_MFMA = 2500.0  # TF/s, MI355X dense FP16 matrix
 # FETCH_SIZE and WRITE_SIZE counter runs scaled by a 1 GiB copy
 # (profiles/gemm_direct_kernel_fp32_large_N25600_traffic.md); valid only for
 # the GEMM source it was measured on.
-GEMM_TRAFFIC = {"bytes_per_launch": 3.3396e+08,
-                "gemm_source_sha256": "a59b431c811e42fafe6a67ae1e94aa145b0e9314941c434d7c22160023424ee2"}
+GEMM_TRAFFIC = {"bytes_per_launch": 3.3425e+08,
+                "gemm_source_sha256": "eb8322e4a8d94eff31b1c7563e7a8fc9c34ed4338b59a1b362586c2fa9ee4a44"}
 
 
 def parse():
@@ -62,8 +62,8 @@ def parse():
     ap.add_argument("--only", choices=("batched", "served"), default=None,
                     help="run only this block (for profiling) and print it as the JSON line")
     ap.add_argument("--counter-summary", metavar="CSV", default=None,
-                    help="read a rocprofv3 --pmc counter CSV (no GPU) and print per-kernel counter sums, "
-                         "then exit")
+                    help="read a rocprofv3 --pmc counter CSV or --kernel-trace CSV (no GPU) and print "
+                         "per-kernel counter (or duration) sums, then exit")
     ap.add_argument("--kernel", default="", help="with --counter-summary: only kernels whose name contains this")
     ap.add_argument("--window", nargs=2, metavar=("FIRST", "LAST"), default=None,
                     help="with --counter-summary: only dispatches from each dispatch of a kernel named FIRST "
@@ -182,7 +182,8 @@ def served_stream(args, H, torch, rate=None):
 
 def counter_summary(path: str, kernel: str = "", window=None) -> dict:
     """Per-kernel sums of rocprofv3 --pmc counters (one row per dispatch and
-    counter), over the dispatches whose name contains `kernel`; with window =
+    counter; from a --kernel-trace CSV, the dispatch durations as the counter
+    DurationNs), over the dispatches whose name contains `kernel`; with window =
     (FIRST, LAST), only dispatches from a FIRST dispatch up to the next LAST
     one (by dispatch id), e.g. one LU step's factorization and first solve."""
     import csv
@@ -192,7 +193,11 @@ def counter_summary(path: str, kernel: str = "", window=None) -> dict:
         for r in csv.DictReader(f):
             d = int(r["Dispatch_Id"])
             e = disp.setdefault(d, {"name": r["Kernel_Name"], "counters": {}})
-            e["counters"][r["Counter_Name"]] = e["counters"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            if "Counter_Name" in r:
+                c, v = r["Counter_Name"], float(r["Counter_Value"])
+            else:  # a --kernel-trace CSV: the dispatch's duration
+                c, v = "DurationNs", float(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+            e["counters"][c] = e["counters"].get(c, 0.0) + v
     keep = set(disp)
     if window:
         keep, inside = set(), False
