@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--config", default="large")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-update variant")
+    ap.add_argument("--scan-slots", type=int, default=3,
+                    help="solvers in flight in the FP32+IR energy-scan block (0: skip the block)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-refine", type=int, default=30)
     ap.add_argument("--tol", type=float, default=0.0)
@@ -347,10 +349,38 @@ def main():
                        "achieved": ach, "peak": PEAK_FP32_MFMA, "unit": "TF/s", "frac": ach / PEAK_FP32_MFMA,
                        "traffic": gemm_traffic(), "launches_per_step": g["launches"] / args.steps,
                        "avg_launch_us": g["ms"] * 1e3 / max(1, g["launches"])}
+    # S of the breakdown step that timed_steps runs after the timed ones
     S32 = s32.S.cpu().numpy().copy()
-    last_e = float(sp.energies[(args.steps - 1) % len(sp.energies)])
+    last_e = float(sp.energies[args.steps % len(sp.energies)])
     del s32
     torch.cuda.empty_cache()
+
+    if args.scan_slots > 0:
+        # the same FP32+IR solves as an energy scan with several solvers in
+        # flight: one energy's solves, refinement, R and S run beside the
+        # next one's assembly and factorization (factorizations serialized)
+        import numpy as np
+        scan = P.EnergyScan(d, H.HP_C64, slots=args.scan_slots)
+        ne = len(sp.energies)
+        es = [float(sp.energies[s % ne]) for s in range(max(args.steps + 1, 3 * args.scan_slots))]
+        print(f"[bench] fp32-LU+IR energy scan, {args.scan_slots} solvers in flight, {len(es)} energies",
+              file=sys.stderr, flush=True)
+        scan.run(es[:args.scan_slots], max_refine=args.max_refine, tol=args.tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = scan.run(es, max_refine=args.max_refine, tol=args.tol)
+        torch.cuda.synchronize()
+        tsc = (time.perf_counter() - t0) / len(es)
+        k_last = args.steps % ne
+        same = [float(np.max(np.abs(r.S.numpy() - S32)) / np.max(np.abs(S32)))
+                for i, r in enumerate(res) if i % ne == k_last]
+        out["fp32_ir_scan"] = {"solvers_in_flight": args.scan_slots, "energies": len(es),
+                               "ms_per_energy": tsc * 1e3, "tflops": flops / tsc / 1e12,
+                               "refinement_steps": [r.iterations for r in res],
+                               "fp64_fallbacks": int(sum(r.fallback for r in res)),
+                               "S_relerr_vs_single_solver_at_E": [last_e, max(same) if same else None]}
+        del scan
+        torch.cuda.empty_cache()
 
     if not args.no_fp16:
         # the FP16 variant: FP32 factors whose trailing updates run on the

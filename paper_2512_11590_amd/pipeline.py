@@ -118,3 +118,70 @@ class Solver:
         return EnergyResult(E=E, prec=self.prec, R=self.R, S=S, iterations=iterations,
                             correction=info.correction, fallback=used_fallback, nopen=nopen,
                             backward_error=backward)
+
+
+class EnergyScan:
+    """An energy scan of one system with `slots` solvers in flight (the
+    paper's steady-state energy scan, Sec. 5.3, with persistent buffers per
+    slot): each slot owns a Solver (matrix, factors, workspace) and a stream,
+    and takes the next energy as soon as its previous one is done.  The
+    library serializes the slots' factorizations on one device-wide stream
+    (hp_set_concurrency), so one slot's triangular solves, refinement, R and S
+    run beside the next slot's assembly and factorization.  Results are
+    returned in energy order (R and S copied to the host)."""
+
+    def __init__(self, dsys: DeviceSystem, prec: int = H.HP_C64, slots: int = 2, fallback: bool = True):
+        if slots < 1:
+            raise ValueError("slots >= 1")
+        self.d = dsys
+        self.prec = prec
+        self.slots = [Solver(dsys, prec, fallback=fallback) for _ in range(slots)]
+        self.streams = [torch.cuda.Stream(device=dsys.device) for _ in range(slots)]
+
+    def run(self, energies, max_refine: int = 30, tol: float = 0.0) -> list[EnergyResult]:
+        import threading
+        energies = [float(E) for E in energies]
+        out: list[EnergyResult | None] = [None] * len(energies)
+        errors: list[BaseException] = []
+        lock = threading.Lock()
+        nxt = [0]
+        dev = self.d.device
+        index = dev.index if dev.index is not None else torch.cuda.current_device()
+        cur = torch.cuda.current_stream(index)
+
+        def slot(k: int) -> None:
+            try:
+                torch.cuda.set_device(index)
+                st = self.streams[k]
+                st.wait_stream(cur)
+                with torch.cuda.stream(st):
+                    while True:
+                        with lock:
+                            i = nxt[0]
+                            if i >= len(energies) or errors:
+                                return
+                            nxt[0] = i + 1
+                        r = self.slots[k].run(energies[i], max_refine=max_refine, tol=tol)
+                        out[i] = EnergyResult(E=r.E, prec=r.prec, R=r.R.cpu().clone(),
+                                              S=None if r.S is None else r.S.cpu().clone(),
+                                              iterations=r.iterations, correction=r.correction,
+                                              fallback=r.fallback, nopen=r.nopen,
+                                              backward_error=r.backward_error)
+            except BaseException as exc:  # stop the scan, re-raised below
+                with lock:
+                    errors.append(exc)
+
+        prev = H.hp_set_concurrency(len(self.slots))
+        try:
+            threads = [threading.Thread(target=slot, args=(k,), daemon=True) for k in range(len(self.slots))]
+            for t in threads:
+                t.start()
+            for t in threads:
+                t.join()
+        finally:
+            H.hp_set_concurrency(prev)
+        for st in self.streams:
+            cur.wait_stream(st)
+        if errors:
+            raise errors[0]
+        return out
