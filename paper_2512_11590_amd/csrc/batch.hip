@@ -452,16 +452,22 @@ __global__ void batch_zero_kernel(unsigned *p, int n) {
 }
 
 // ---------------------------------------------------------------- assembly --
+// Assembly of every system's C(E) (as hp_build_matrix, Eq. block_structure):
+// rows spread over kBuildGroups workgroups per system so that a bucket's
+// matrices are written by thousands of workgroups at once.
+constexpr int kBuildGroups = 64;
 template <typename T>
 __global__ __launch_bounds__(256) void batch_build_kernel(int count, const hp_batch_item *__restrict__ items,
                                                           cplx<T> *__restrict__ A) {
-  const int s = blockIdx.x;
+  // kBuildGroups workgroups per system (blockIdx.y), each taking every
+  // kBuildGroups-th row
+  const int s = blockIdx.y;
   if (s >= count) return;
   const hp_batch_item it = items[s];
   const int nc = it.sys.nc, nr = it.sys.nr, n = nc * nr;
   const double h = it.sys.hbar2_2mu, E = it.E;
   cplx<T> *a = A + it.a_off;
-  for (int row = 0; row < n; ++row) {
+  for (int row = blockIdx.x; row < n; row += gridDim.x) {
     const int c = row / nr, i = row - c * nr;
     const int lc = it.sys.l[c];
     const double ri = it.sys.r[i];
@@ -1421,10 +1427,13 @@ extern "C" int hp_batch_build(int count, const hp_batch_item *items, int prec, v
   if (count < 1 || !items || !A) return HP_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
   TraceScope ts(TR_ASSEMBLE, st, 0.0, 0.0);
+  if (count > 65535) return HP_ERR_UNSUPPORTED;  // grid y limit
   if (prec == HP_C64)
-    hipLaunchKernelGGL(batch_build_kernel<float>, dim3(count), dim3(256), 0, st, count, items, (cplx<float> *)A);
+    hipLaunchKernelGGL(batch_build_kernel<float>, dim3(kBuildGroups, count), dim3(256), 0, st, count, items,
+                       (cplx<float> *)A);
   else if (prec == HP_C128)
-    hipLaunchKernelGGL(batch_build_kernel<double>, dim3(count), dim3(256), 0, st, count, items, (cplx<double> *)A);
+    hipLaunchKernelGGL(batch_build_kernel<double>, dim3(kBuildGroups, count), dim3(256), 0, st, count, items,
+                       (cplx<double> *)A);
   else
     return HP_ERR_ARG;
   HP_CHECK_LAUNCH();
