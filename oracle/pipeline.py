@@ -19,8 +19,16 @@ def solve_energy(params, E: float, md: system.MeshData | None = None,
     R = rmatrix.rmatrix(X, md.q, params.nc, params.nr, params.hbar2_2mu, params.a)
     out = {"E": E, "X": X, "R": R, "ipiv": ipiv}
     if with_smatrix:
-        k, eta = rmatrix.wave_numbers(E, params.eps, params.hbar2_2mu, params.z1z2)
-        fg = rmatrix.coulomb_table(params.l, eta, k * params.a)
-        U = rmatrix.smatrix(R, k, params.a, fg)
-        out.update(k=k, eta=eta, fg=fg, S=U, sigma=rmatrix.cross_sections(U, k))
+        if np.all(E > np.asarray(params.eps, dtype=np.float64)):
+            k, eta = rmatrix.wave_numbers(E, params.eps, params.hbar2_2mu, params.z1z2)
+            fg = rmatrix.coulomb_table(params.l, eta, k * params.a)
+            U = rmatrix.smatrix(R, k, params.a, fg)
+            out.update(k=k, eta=eta, fg=fg, S=U, sigma=rmatrix.cross_sections(U, k),
+                       open=np.arange(params.nc))
+        else:
+            # closed channels eliminated; S over the open channels only
+            U, o, _ = rmatrix.smatrix_closed(R, E, np.asarray(params.eps), np.asarray(params.l),
+                                             params.hbar2_2mu, params.z1z2, params.a)
+            _, _, kk, eta = rmatrix.channels(E, params.eps, params.hbar2_2mu, params.z1z2)
+            out.update(k=kk[o], eta=eta[o], S=U, sigma=rmatrix.cross_sections(U, kk[o]), open=o)
     return out

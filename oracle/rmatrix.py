@@ -18,6 +18,20 @@ where O, O', I, I' are diagonal and ' is d/drho.
 Coulomb functions come from mpmath (arbitrary precision); derivatives use
 Abramowitz & Stegun 14.2.2,
     (l+1) u_l' = ((l+1)^2/rho + eta) u_l - sqrt((l+1)^2 + eta^2) u_{l+1}.
+
+Closed channels (E < eps_c; the Whittaker functions of the paper's special-
+function set, Sec. 4.1): the external solution decays,
+u_c(r) = C_c W_{-eta_c, l_c + 1/2}(2 kappa_c r) with kappa_c = sqrt((eps_c - E)/h)
+and eta_c = Z1Z2 e^2 / (2 h kappa_c), so a u_c'(a) = L_c u_c(a) with
+L_c = x W'(x) / W(x) at x = kappa_c a (W as a function of x).  Splitting
+u(a) = R a u'(a) into open (o) and closed (c) channels and eliminating the
+closed ones gives the open channels' effective R-matrix
+
+    R_eff = R_oo + R_oc L (I - R_cc L)^-1 R_co,   L = diag(L_c),
+
+from which U (open channels only) follows as above (reading R12).
+Whittaker values come from mpmath; the derivative by mpmath's numerical
+differentiation at the working precision.
 """
 from __future__ import annotations
 
@@ -85,6 +99,48 @@ def smatrix(R: np.ndarray, k: np.ndarray, a: float, fg: np.ndarray) -> np.ndarra
     ZO = np.diag(O) - Rt * Op[None, :]
     ZI = np.diag(I) - Rt * Ip[None, :]
     return np.linalg.solve(ZO, ZI)
+
+
+def closed_logderiv(l: int, eta: float, x: float, dps: int = 30) -> float:
+    """x W'(x) / W(x) for W(x) = W_{-eta, l + 1/2}(2 x): the decaying solution of
+    u'' = (1 + l(l+1)/x^2 + 2 eta/x) u, x = kappa r."""
+    with mpmath.workdps(dps):
+        kap = -mpmath.mpf(eta)
+        mu = mpmath.mpf(l) + mpmath.mpf(1) / 2
+
+        def w(xx):
+            return mpmath.whitw(kap, mu, 2 * xx)
+
+        X = mpmath.mpf(x)
+        return float(X * mpmath.diff(w, X) / w(X))
+
+
+def channels(E: float, eps: np.ndarray, hbar2_2mu: float, z1z2: int):
+    """Open and closed channel indices, and per channel the wave number k
+    (open) or decay constant kappa (closed) and its Sommerfeld parameter."""
+    ec = E - np.asarray(eps, dtype=np.float64)
+    if np.any(ec == 0.0):
+        raise ValueError("energy at a threshold")
+    kk = np.sqrt(np.abs(ec) / hbar2_2mu)
+    eta = z1z2 * E2 / (2.0 * hbar2_2mu * kk)
+    return np.where(ec > 0)[0], np.where(ec < 0)[0], kk, eta
+
+
+def smatrix_closed(R: np.ndarray, E: float, eps: np.ndarray, l: np.ndarray, hbar2_2mu: float, z1z2: int,
+                   a: float):
+    """Collision matrix of the open channels with the closed ones eliminated
+    through R_eff.  Returns (U, open indices, R_eff)."""
+    o, c, kk, eta = channels(E, eps, hbar2_2mu, z1z2)
+    if len(o) == 0:
+        raise ValueError("no open channel")
+    Reff = R[np.ix_(o, o)]
+    if len(c):
+        Lc = np.array([closed_logderiv(int(l[ci]), float(eta[ci]), float(kk[ci] * a)) for ci in c])
+        Lm = np.diag(Lc)
+        Y = np.linalg.solve(np.eye(len(c)) - R[np.ix_(c, c)] @ Lm, R[np.ix_(c, o)])
+        Reff = Reff + R[np.ix_(o, c)] @ Lm @ Y
+    fg = coulomb_table(np.asarray(l)[o], eta[o], kk[o] * a)
+    return smatrix(Reff, kk[o], a, fg), o, Reff
 
 
 def cross_sections(U: np.ndarray, k: np.ndarray) -> np.ndarray:

@@ -320,3 +320,111 @@ def test_solution_satisfies_system_structured_residual():
     M, B = system.assemble(sp, E, md)
     res = B - system.apply(sp, E, out["X"], md)
     assert np.max(np.abs(res)) / (np.abs(M).sum(axis=1).max() * np.max(np.abs(out["X"]))) < 1e-14
+
+
+# ---------------------------------------------------------- closed channels --
+
+@pytest.mark.parametrize("l,x", [(0, 0.3), (0, 4.0), (1, 0.5), (1, 2.0), (2, 0.7), (2, 5.0)])
+def test_closed_logderiv_bessel_closed_forms(l, x):
+    """eta = 0: W_{0, l+1/2}(2x) is e^-x times 1, 1 + 1/x, 1 + 3/x + 3/x^2
+    (modified spherical Bessel), so x W'/W = -x, -x - 1/(x+1),
+    -x - (3x + 6)/(x^2 + 3x + 3)."""
+    ref = {0: -x, 1: -x - 1.0 / (x + 1.0), 2: -x - (3 * x + 6.0) / (x * x + 3 * x + 3.0)}[l]
+    assert abs(rmatrix.closed_logderiv(l, 0.0, x) - ref) < 1e-13 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("l,eta,x", [(0, 0.8, 1.5), (3, 2.5, 2.0), (6, 0.3, 4.0)])
+def test_closed_logderiv_solves_the_equation_and_decays(l, eta, x):
+    """With Coulomb (eta != 0), without trusting the library's Whittaker
+    routine: y = W'/W satisfies the Riccati form y' = f - y^2 of
+    u'' = (1 + l(l+1)/x^2 + 2 eta/x) u, and far out y -> -1 - eta/x (the
+    decaying solution, W ~ e^-x (2x)^-eta), not +1 (the growing one)."""
+    f = 1.0 + l * (l + 1) / x ** 2 + 2.0 * eta / x
+    h = 1e-4
+    y = lambda t: rmatrix.closed_logderiv(l, eta, t) / t  # noqa: E731
+    dy = (y(x + h) - y(x - h)) / (2 * h)
+    assert abs(dy - (f - y(x) ** 2)) < 1e-6
+    X = 60.0 + l
+    assert abs(y(X) - (-1.0 - eta / X)) < 2.0 * (l * (l + 1) + eta * eta + 1.0) / X ** 2
+
+
+def _well_with_closed_channel():
+    a, h, E = 7.0, 2.0, 4.0
+    W = np.array([[-25.0, 4.0, -2.5], [4.0, -18.0, 3.0], [-2.5, 3.0, -31.0]])
+    eps = np.array([0.0, 1.0, 6.0])  # channel 2 closed at E = 4
+    nc = 3
+    sp = CustomSystem(nc=nc, nr=45, a=a, l=np.zeros(nc, int), eps=eps, hbar2_2mu=h,
+                      pot=lambda r: np.broadcast_to(W.astype(complex), (len(r), nc, nc)).copy())
+    return sp, W, E
+
+
+def test_square_well_with_closed_channel_direct_matching():
+    """Constant real coupling W for r < a, l = 0, no Coulomb, one closed
+    channel: inside u = P diag(s_n(r)) A with M = (W + eps - E)/h = P m P^T
+    (s = sinh or sin of sqrt|m| r); outside e^-ikr - U e^ikr in the open
+    channels and C e^-kappa r in the closed one.  Matching u and u' at r = a
+    directly (2 nc equations per entrance channel) must give the oracle's
+    U over the open channels."""
+    sp, W, E = _well_with_closed_channel()
+    out = pipeline.solve_energy(sp, E)
+    o = list(out["open"])
+    assert o == [0, 1]
+    a, h, eps = sp.a, sp.hbar2_2mu, sp.eps
+    m, P = np.linalg.eigh((W + np.diag(eps) - E * np.eye(3)) / h)
+    q = np.sqrt(np.abs(m))
+    s = np.where(m > 0, np.sinh(q * a), np.sin(q * a))
+    sp_ = np.where(m > 0, q * np.cosh(q * a), q * np.cos(q * a))
+    k = np.sqrt((E - eps[:2]) / h)
+    kap = np.sqrt((eps[2] - E) / h)
+    U = np.zeros((2, 2), dtype=complex)
+    for c0 in range(2):
+        Mx = np.zeros((6, 6), dtype=complex)
+        rhs = np.zeros(6, dtype=complex)
+        for c in range(3):
+            Mx[c, :3] = P[c] * s
+            Mx[3 + c, :3] = P[c] * sp_
+            if c < 2:
+                Mx[c, 3 + c] = np.exp(1j * k[c] * a) / np.sqrt(k[c])
+                Mx[3 + c, 3 + c] = 1j * k[c] * np.exp(1j * k[c] * a) / np.sqrt(k[c])
+                if c == c0:
+                    rhs[c] = np.exp(-1j * k[c] * a) / np.sqrt(k[c])
+                    rhs[3 + c] = -1j * k[c] * np.exp(-1j * k[c] * a) / np.sqrt(k[c])
+            else:
+                Mx[c, 5] = -np.exp(-kap * a)
+                Mx[3 + c, 5] = kap * np.exp(-kap * a)
+        x = np.linalg.solve(Mx, rhs)
+        U[:, c0] = x[3:5]
+    assert relerr(out["S"], U) < 1e-10
+
+
+def test_uncoupled_closed_channel_drops_out():
+    """A closed channel with no coupling to the others (Coulomb in every
+    channel, l > 0 in the closed one) leaves the open channels' U equal to
+    that of the system without it."""
+    nc, nr, a, h, E = 3, 50, 12.0, 2.0, 6.0
+    Wt = np.array([[-30.0, 5.0, 0.0], [5.0, -22.0, 0.0], [0.0, 0.0, -27.0]])
+
+    def pot(r):
+        f = 1.0 / (1.0 + np.exp((r - 5.0) / 0.6))
+        return (Wt[None, :, :] * f[:, None, None]).astype(complex)
+
+    sp = CustomSystem(nc=nc, nr=nr, a=a, l=np.array([0, 2, 3]), eps=np.array([0.0, 2.0, 9.0]), hbar2_2mu=h,
+                      pot=pot, z1z2=6)
+    sub = CustomSystem(nc=2, nr=nr, a=a, l=np.array([0, 2]), eps=np.array([0.0, 2.0]), hbar2_2mu=h,
+                       pot=lambda r: pot(r)[:, :2, :2].copy(), z1z2=6)
+    full = pipeline.solve_energy(sp, E)
+    ref = pipeline.solve_energy(sub, E)
+    assert list(full["open"]) == [0, 1]
+    assert relerr(full["S"], ref["S"]) < 1e-12
+
+
+def test_real_potential_with_closed_channels_unitary_and_symmetric():
+    """Real coupled potential with two closed channels: flux stays in the
+    open ones (U unitary there) and U is symmetric."""
+    sp = _real_family(nc=6, nr=70, a=15.0)
+    E = 0.5 * (np.sort(sp.eps)[3] + np.sort(sp.eps)[4])  # four open, two closed
+    out = pipeline.solve_energy(sp, E)
+    S = out["S"]
+    assert len(out["open"]) == 4
+    assert np.max(np.abs(S.conj().T @ S - np.eye(4))) < 1e-10
+    assert np.max(np.abs(S - S.T)) < 1e-10
