@@ -186,10 +186,17 @@ int hp_rmatrix(const hp_system *sys, const double *X, double *R, void *stream);
  * Coulomb routine, Sec. 4.1): with rho_c = k_c a, k_c = sqrt((E - eps_c)/h),
  * eta_c = z1z2e2 / (2 h k_c), O = G + iF, I = G - iF,
  *   U = (O - Rt O')^-1 (I - Rt I'),   Rt = rho^1/2 R rho^1/2.
- * R, S: device nc x nc complex128.  nopen (host, may be NULL) receives the
- * number of open channels.  All channels must be open (E > eps_c), else
- * HP_ERR_UNSUPPORTED.  Uses work (hp_workspace_bytes(nc, nc, HP_C128)).
- * Synchronizes the stream. */
+ * Closed channels (E < eps_c) end in decaying Whittaker functions
+ * W_{-eta_c, l_c + 1/2}(2 kappa_c r), kappa_c = sqrt((eps_c - E)/h),
+ * eta_c = z1z2e2 / (2 h kappa_c) (the special functions of Sec. 4.1): with
+ * L_c = a u_c'(a)/u_c(a) they are eliminated through the open channels'
+ * effective R-matrix R_eff = R_oo + R_oc L (I - R_cc L)^-1 R_co, from which U
+ * follows over the open channels as above.
+ * R, S: device nc x nc complex128; S receives U on the open-open entries and
+ * zeros in the closed channels' rows and columns.  nopen (host, may be NULL)
+ * receives the number of open channels.  HP_ERR_UNSUPPORTED if no channel is
+ * open or E equals a threshold.  Uses work (hp_workspace_bytes(nc, nc,
+ * HP_C128)).  Synchronizes the stream. */
 int hp_smatrix(const hp_system *sys, double E, const double *R, double *S, int *nopen,
                void *work, size_t work_bytes, void *stream);
 

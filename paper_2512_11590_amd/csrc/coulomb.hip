@@ -95,15 +95,19 @@ __host__ __device__ static void steed(int L, double eta, double rho, CoulombOut 
   o.Gp = (p * g - q) * F;
 }
 
-// one Taylor step of u'' = (L(L+1)/x^2 + 2 eta/x - 1) u from x0 to x0 + h
-__host__ __device__ static void taylor_step(double LL, double eta, double x0, double h, double &u, double &up) {
+// one Taylor step of u'' = (L(L+1)/x^2 + 2 eta/x + sigma) u from x0 to x0 + h
+// (sigma = -1: the Coulomb equation of an open channel, x = rho; sigma = +1:
+// a closed channel, x = kappa r).  With u = sum c_n t^n, t = x - x0, the
+// equation times x^2 gives the three-term recurrence below.
+__host__ __device__ static void taylor_step(double LL, double eta, double x0, double h, double &u, double &up,
+                                            double sigma = -1.0) {
   double cm2 = 0.0, cm1 = 0.0, c0 = u, c1 = up;
   double s = u + up * h, sp = up;
   double hp = h;  // h^(n+1)
-  const double A = LL + 2.0 * eta * x0 - x0 * x0;
-  const double B = 2.0 * eta - 2.0 * x0;
+  const double A = LL + 2.0 * eta * x0 + sigma * x0 * x0;
+  const double B = 2.0 * eta + 2.0 * sigma * x0;
   for (int n = 0; n < 300; ++n) {
-    const double c2 = (A * c0 + B * cm1 - cm2 - 2.0 * x0 * (n + 1) * n * c1 - (double)n * (n - 1) * c0) /
+    const double c2 = (A * c0 + B * cm1 + sigma * cm2 - 2.0 * x0 * (n + 1) * n * c1 - (double)n * (n - 1) * c0) /
                       (x0 * x0 * (n + 2.0) * (n + 1.0));
     const double dterm = (n + 2.0) * c2 * hp;  // (n+2) c_{n+2} h^(n+1)
     hp *= h;
@@ -146,6 +150,32 @@ __host__ __device__ static CoulombOut coulomb_fg(int L, double eta, double rho) 
   return o;
 }
 
+// Closed channel: x W'(x) / W(x) at x = kappa a for the solution of
+// u'' = (1 + L(L+1)/x^2 + 2 eta/x) u that decays outward (the Whittaker
+// function W_{-eta, L+1/2}(2x)).  For eta >= 0 the coefficient is >= 1
+// everywhere, so integrated inward that solution dominates the growing one
+// by at least e^(2 dx): started kClosedSpan units further out with the local
+// log-derivative -sqrt(coefficient) and carried inward by Taylor steps (the
+// pair (u, u') renormalized after each step), the start's error is damped by
+// e^(-2 kClosedSpan) at x.  Status 1 if the input is out of range.
+constexpr double kClosedSpan = 40.0;
+__host__ __device__ static double closed_logderiv(int L, double eta, double x, int *status) {
+  *status = (x > 0.0 && eta >= 0.0) ? 0 : 1;
+  if (*status) return 0.0;
+  const double LL = (double)L * (L + 1);
+  double xc = x + kClosedSpan;
+  double u = 1.0, up = -sqrt(1.0 + LL / (xc * xc) + 2.0 * eta / xc);
+  while (xc > x) {
+    const double h = -fmin(1.0, fmin(0.25 * xc, xc - x));
+    taylor_step(LL, eta, xc, h, u, up, 1.0);
+    xc += h;
+    const double m = fabs(u);
+    u /= m;
+    up /= m;
+  }
+  return x * up / u;
+}
+
 __global__ void coulomb_kernel(int nch, const int *__restrict__ l, const double *__restrict__ eta,
                                const double *__restrict__ rho, double *__restrict__ out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -158,7 +188,9 @@ __global__ void coulomb_kernel(int nch, const int *__restrict__ l, const double 
 }
 
 // Per channel: k, eta, rho, then (F, F', G, G'); status per channel in st[c]
-// (0 ok, 1 closed channel, 2 continued fraction did not converge).
+// (0 ok, 2 continued fraction did not converge, 3 closed channel with its
+// log-derivative L_c = a u'(a)/u(a) in fg[4c], 4 at a threshold or out of
+// range).
 __global__ void channel_kernel(int nc, double E, double h, double z1z2e2, double a, const int *__restrict__ l,
                                const double *__restrict__ eps, double *__restrict__ fg, double *__restrict__ sqrho,
                                int *__restrict__ stat) {
@@ -166,9 +198,17 @@ __global__ void channel_kernel(int nc, double E, double h, double z1z2e2, double
   if (c >= nc) return;
   const double ec = E - eps[c];
   if (!(ec > 0.0)) {
-    stat[c] = 1;
     fg[4 * c] = fg[4 * c + 1] = fg[4 * c + 2] = fg[4 * c + 3] = 0.0;
     sqrho[c] = 0.0;
+    if (!(ec < 0.0)) {
+      stat[c] = 4;
+      return;
+    }
+    const double kappa = sqrt(-ec / h);
+    const double eta = z1z2e2 / (2.0 * h * kappa);
+    int bad = 0;
+    fg[4 * c] = closed_logderiv(l[c], eta, kappa * a, &bad);
+    stat[c] = bad ? 4 : 3;
     return;
   }
   const double k = sqrt(ec / h);
@@ -206,6 +246,91 @@ __global__ void zmat_kernel(int nc, const cplx<double> *__restrict__ R, const do
   }
   ZO[e] = zo;
   ZI[e] = zi;
+}
+
+// Closed channels (E < eps_c) are eliminated from u(a) = R a u'(a) through
+// the open channels' effective R-matrix
+//   R_eff = R_oo + R_oc L (I - R_cc L)^-1 R_co,   L = diag(a u_c'(a) / u_c(a)),
+// the log-derivatives of the decaying external solutions (channel_kernel);
+// U then follows over the open channels as above.  oidx / cidx list the open
+// and closed channels; matrices packed row-major.
+// Mcc = I - R_cc L (ncl x ncl) and Y = R_co (ncl x no).
+__global__ void closed_mats_kernel(int nc, int ncl, int no, const cplx<double> *__restrict__ R,
+                                   const double *__restrict__ fg, const int *__restrict__ cidx,
+                                   const int *__restrict__ oidx, cplx<double> *__restrict__ Mcc,
+                                   cplx<double> *__restrict__ Y) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nm = (long)ncl * ncl, ny = (long)ncl * no;
+  if (e < nm) {
+    const int i = (int)(e / ncl), j = (int)(e - (long)i * ncl);
+    const double Lj = fg[4 * cidx[j]];
+    const cplx<double> r = R[(long)cidx[i] * nc + cidx[j]];
+    cplx<double> m{-r.re * Lj, -r.im * Lj};
+    if (i == j) m.re += 1.0;
+    Mcc[e] = m;
+  } else if (e < nm + ny) {
+    const long f = e - nm;
+    const int i = (int)(f / no), j = (int)(f - (long)i * no);
+    Y[f] = R[(long)cidx[i] * nc + oidx[j]];
+  }
+}
+
+// R_eff = R_oo + R_oc L Y (no x no), Y = (I - R_cc L)^-1 R_co.
+__global__ void reff_kernel(int nc, int ncl, int no, const cplx<double> *__restrict__ R,
+                            const double *__restrict__ fg, const int *__restrict__ cidx,
+                            const int *__restrict__ oidx, const cplx<double> *__restrict__ Y,
+                            cplx<double> *__restrict__ Reff) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)no * no) return;
+  const int i = (int)(e / no), j = (int)(e - (long)i * no);
+  cplx<double> acc = R[(long)oidx[i] * nc + oidx[j]];
+  for (int k = 0; k < ncl; ++k) {
+    const double Lk = fg[4 * cidx[k]];
+    const cplx<double> r = R[(long)oidx[i] * nc + cidx[k]];
+    const cplx<double> y = Y[(long)k * no + j];
+    acc.re += Lk * (r.re * y.re - r.im * y.im);
+    acc.im += Lk * (r.re * y.im + r.im * y.re);
+  }
+  Reff[e] = acc;
+}
+
+// zmat_kernel over the open channels, from R_eff.
+__global__ void zmat_open_kernel(int no, const cplx<double> *__restrict__ Reff, const double *__restrict__ fg,
+                                 const double *__restrict__ sqrho, const int *__restrict__ oidx,
+                                 cplx<double> *__restrict__ ZO, cplx<double> *__restrict__ ZI) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)no * no) return;
+  const int i = (int)(e / no), j = (int)(e - (long)i * no);
+  const int c = oidx[i], cp = oidx[j];
+  const double s = sqrho[c] * sqrho[cp];
+  const cplx<double> rt{s * Reff[e].re, s * Reff[e].im};
+  const double F = fg[4 * cp], Fp = fg[4 * cp + 1], G = fg[4 * cp + 2], Gp = fg[4 * cp + 3];
+  cplx<double> zo = cmul(rt, cplx<double>{Gp, Fp});
+  cplx<double> zi = cmul(rt, cplx<double>{Gp, -Fp});
+  zo = cplx<double>{-zo.re, -zo.im};
+  zi = cplx<double>{-zi.re, -zi.im};
+  if (i == j) {
+    zo.re += G;
+    zo.im += F;
+    zi.re += G;
+    zi.im -= F;
+  }
+  ZO[e] = zo;
+  ZI[e] = zi;
+}
+
+__global__ void zero_c128_kernel(long n, cplx<double> *__restrict__ p) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = cplx<double>{0.0, 0.0};
+}
+
+// S[oidx[i]][oidx[j]] = U[i][j] (the rest of S was cleared).
+__global__ void scatter_open_kernel(int nc, int no, const int *__restrict__ oidx, const cplx<double> *__restrict__ U,
+                                    cplx<double> *__restrict__ S) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)no * no) return;
+  const int i = (int)(e / no), j = (int)(e - (long)i * no);
+  S[(long)oidx[i] * nc + oidx[j]] = U[e];
 }
 
 }  // namespace hp
@@ -379,9 +504,9 @@ __global__ __launch_bounds__(256) void batch_smatrix_kernel(int count, const hp_
 }
 
 // The collision matrix from R (see hp_smatrix), on workspace w laid out by ws;
-// hstat: host array of nc ints.
+// hstat, hidx: host arrays of nc ints.
 static int smatrix_impl(const hp_system *sys, double E, const double *R, double *S, int *nopen, char *w,
-                        const Workspace &ws, int *hstat, hipStream_t st) {
+                        const Workspace &ws, int *hstat, int *hidx, hipStream_t st) {
   const int nc = sys->nc;
   cplx<double> *ZO = (cplx<double> *)(w + ws.aux_off);
   cplx<double> *tmp = (cplx<double> *)(w + ws.rhs_off);
@@ -406,16 +531,71 @@ static int smatrix_impl(const hp_system *sys, double E, const double *R, double 
   HP_CHECK_HIP(hipMemcpyAsync(&hinfo, finfo, sizeof(int), hipMemcpyDeviceToHost, st));
   HP_CHECK_HIP(hipMemcpyAsync(hstat, stat, sizeof(int) * nc, hipMemcpyDeviceToHost, st));
   HP_CHECK_HIP(hipStreamSynchronize(st));
-  int open = 0, bad = 0;
+  int open = 0, closed = 0, bad = 0, edge = 0;
   for (int c = 0; c < nc; ++c) {
-    if (hstat[c] == 0) ++open;
-    if (hstat[c] == 2) bad = 1;
+    if (hstat[c] == 0)
+      ++open;
+    else if (hstat[c] == 3)
+      ++closed;
+    else if (hstat[c] == 2)
+      bad = 1;
+    else
+      edge = 1;
   }
   if (nopen) *nopen = open;
-  if (open < nc) return HP_ERR_UNSUPPORTED;
   if (bad) return HP_ERR_NOCONV;
-  if (hinfo == -1) return HP_ERR_SYNC;
-  if (hinfo > 0) return HP_ERR_SINGULAR;
+  if (edge || open == 0) return HP_ERR_UNSUPPORTED;  // at a threshold, or no open channel
+  if (closed == 0) {
+    if (hinfo == -1) return HP_ERR_SYNC;
+    if (hinfo > 0) return HP_ERR_SINGULAR;
+    return HP_OK;
+  }
+  // closed channels: the pass above is discarded; eliminate them through
+  // R_eff and match over the open channels
+  const int no = open, ncl = closed;
+  for (int c = 0, io = 0, ic = 0; c < nc; ++c) {
+    if (hstat[c] == 0)
+      hidx[io++] = c;
+    else
+      hidx[no + ic++] = c;
+  }
+  int *oidx = perm + nc, *cidx = oidx + no;
+  cplx<double> *Y = (cplx<double> *)S;                 // ncl x no, then the open channels' ZI and U
+  cplx<double> *Reff = (cplx<double> *)(w + ws.res_off);  // no x no
+  HP_CHECK_HIP(hipMemcpyAsync(oidx, hidx, sizeof(int) * (size_t)nc, hipMemcpyHostToDevice, st));
+  {
+    const long cnt2 = (long)ncl * ncl + (long)ncl * no;
+    hipLaunchKernelGGL(closed_mats_kernel, dim3((unsigned)((cnt2 + 255) / 256)), dim3(256), 0, st, nc, ncl, no,
+                       (const cplx<double> *)R, fg, cidx, oidx, ZO, Y);
+    HP_CHECK_LAUNCH();
+  }
+  if ((rc = lu_factor<double>(ncl, ZO, ncl, ipiv, perm, finfo + 1, w, ws, st))) return rc;
+  if ((rc = lu_solve<double>(ncl, no, ZO, ncl, perm, Y, no, tmp, nullptr, st))) return rc;
+  const long cnt_o = (long)no * no;
+  hipLaunchKernelGGL(reff_kernel, dim3((unsigned)((cnt_o + 255) / 256)), dim3(256), 0, st, nc, ncl, no,
+                     (const cplx<double> *)R, fg, cidx, oidx, Y, Reff);
+  HP_CHECK_LAUNCH();
+  hipLaunchKernelGGL(zmat_open_kernel, dim3((unsigned)((cnt_o + 255) / 256)), dim3(256), 0, st, no, Reff, fg,
+                     sqrho, oidx, ZO, (cplx<double> *)S);
+  HP_CHECK_LAUNCH();
+  if ((rc = lu_factor<double>(no, ZO, no, ipiv, perm, finfo, w, ws, st))) return rc;
+  if ((rc = lu_solve<double>(no, no, ZO, no, perm, (cplx<double> *)S, no, tmp, nullptr, st))) return rc;
+  // U (no x no, packed at the start of S) to its place in S, zeros elsewhere
+  HP_CHECK_HIP(hipMemcpyAsync(Reff, S, sizeof(cplx<double>) * (size_t)cnt_o, hipMemcpyDeviceToDevice, st));
+  {
+    const long cnt_s = (long)nc * nc;
+    hipLaunchKernelGGL(zero_c128_kernel, dim3((unsigned)((cnt_s + 255) / 256)), dim3(256), 0, st, cnt_s,
+                       (cplx<double> *)S);
+    HP_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(scatter_open_kernel, dim3((unsigned)((cnt_o + 255) / 256)), dim3(256), 0, st, nc, no, oidx,
+                     Reff, (cplx<double> *)S);
+  HP_CHECK_LAUNCH();
+  int hinfo2[2] = {0, 0};
+  HP_CHECK_HIP(hipMemcpyAsync(hinfo2, finfo, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HP_CHECK_HIP(hipStreamSynchronize(st));
+  if (hinfo2[0] == -1 || hinfo2[1] == -1) return HP_ERR_SYNC;
+  if (hinfo2[0] > 0 || hinfo2[1] > 0) return HP_ERR_SINGULAR;
   return HP_OK;
 }
 
@@ -460,8 +640,8 @@ extern "C" int hp_smatrix(const hp_system *sys, double E, const double *R, doubl
   const int nc = sys->nc;
   Workspace ws = plan_workspace(nc, nc, HP_C128);
   if (work_bytes < ws.total) return HP_ERR_WORKSPACE;
-  std::vector<int> hstat(nc);
-  return smatrix_impl(sys, E, R, S, nopen, (char *)work, ws, hstat.data(), (hipStream_t)stream);
+  std::vector<int> hstat(nc), hidx(nc);
+  return smatrix_impl(sys, E, R, S, nopen, (char *)work, ws, hstat.data(), hidx.data(), (hipStream_t)stream);
 }
 
 extern "C" int hp_smatrix_noalloc(const hp_system *sys, double E, const double *R, double *S, int *nopen,
@@ -474,8 +654,8 @@ extern "C" int hp_smatrix_noalloc(const hp_system *sys, double E, const double *
   char *w = nullptr;
   int rc = scratch_for_device(&w);
   if (rc) return rc;
-  int hstat[kSmatNoallocMaxChannels];
-  return smatrix_impl(sys, E, R, S, nopen, w, ws, hstat, (hipStream_t)stream);
+  int hstat[kSmatNoallocMaxChannels], hidx[kSmatNoallocMaxChannels];
+  return smatrix_impl(sys, E, R, S, nopen, w, ws, hstat, hidx, (hipStream_t)stream);
 }
 
 extern "C" int hp_batch_smatrix(int count, const hp_batch_item *items, const double *R, double *S, int *status,

@@ -1,0 +1,139 @@
+"""GPU parity of the collision matrix with closed channels (E below some
+thresholds): the device log-derivatives of the decaying external solutions
+(inward Taylor integration of the closed-channel equation) and the
+elimination through the open channels' effective R-matrix, against the
+oracle (whose Whittaker values come from mpmath and whose matching is pinned
+to a directly matched coupled well on the CPU).  S over the open channels is
+compared normwise; its closed rows and columns must be exactly zero."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import pipeline as opipe  # noqa: E402
+from tests.helpers import CustomSystem, relerr  # noqa: E402
+from workload import make_system  # noqa: E402
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2512_11590_amd import hprmat, pipeline
+    hprmat.lib()
+    return hprmat, pipeline
+
+
+def _check_S(S: np.ndarray, o: dict, tol: float) -> None:
+    op = np.asarray(o["open"])
+    closed = np.setdiff1d(np.arange(S.shape[0]), op)
+    assert relerr(S[np.ix_(op, op)], o["S"]) < tol
+    assert not np.any(S[closed, :]) and not np.any(S[:, closed])
+
+
+# Thresholds and energies with every channel at least 0.5 MeV from threshold:
+# open channels right above threshold under a Coulomb barrier have
+# sub-barrier Coulomb functions beyond double range (F ~ exp(-pi eta)), which
+# no unscaled matching survives, open or closed.
+CASES = [(np.array([0.0, 0.5, 1.0, 6.0, 7.0, 8.0]), 3.0, 3),
+         (np.array([0.0, 3.0, 5.0, 5.5, 6.0, 9.0]), 4.0, 2),
+         (np.array([0.0, 6.0, 6.5, 7.0, 8.0, 9.0]), 2.0, 1)]
+
+
+def _small(eps):
+    sp = make_system("small", nc=6, nr=50)
+    sp.eps = eps.copy()
+    return sp
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_smatrix_closed_from_oracle_R(mods, case):
+    """hp_smatrix alone on the oracle's R: 6 channels with Coulomb and l up to
+    4, some of them closed."""
+    H, P = mods
+    eps, E, k = CASES[case]
+    sp = _small(eps)
+    o = opipe.solve_energy(sp, E)
+    assert len(o["open"]) == k
+    d = P.DeviceSystem(sp)
+    R = torch.from_numpy(o["R"]).to("cuda")
+    S = torch.empty_like(R)
+    work = torch.empty(H.hp_workspace_bytes(sp.nc, sp.nc, H.HP_C128), dtype=torch.uint8, device="cuda")
+    say("smatrix closed, open", k)
+    nopen = H.hp_smatrix(d.sys, E, R, S, work)
+    assert nopen == k
+    _check_S(S.cpu().numpy(), o, 1e-12)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_well_with_closed_channel(mods, prec):
+    """The three-channel constant-coupling well with one closed channel (the
+    oracle's U there equals the direct matching at r = a)."""
+    H, P = mods
+    a, h, E = 7.0, 2.0, 4.0
+    W = np.array([[-25.0, 4.0, -2.5], [4.0, -18.0, 3.0], [-2.5, 3.0, -31.0]])
+    sp = CustomSystem(nc=3, nr=45, a=a, l=np.zeros(3, int), eps=np.array([0.0, 1.0, 6.0]), hbar2_2mu=h,
+                      pot=lambda r: np.broadcast_to(W.astype(complex), (len(r), 3, 3)).copy())
+    o = opipe.solve_energy(sp, E)
+    say("well with a closed channel, prec", prec)
+    res = P.Solver(P.DeviceSystem(sp), prec).run(E)
+    assert res.nopen == 2
+    _check_S(res.S.cpu().numpy(), o, 1e-10)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_closed_channels_end_to_end(mods, prec):
+    """N = 2400 (40 channels, Coulomb, l up to 20) at 4 MeV with 12 channels
+    closed (thresholds 6-11 MeV) and 28 open (thresholds 0-2 MeV): FP64 LU
+    and FP32 LU + FP64 refinement."""
+    H, P = mods
+    sp = make_system("mid", nc=40)
+    e = np.asarray(sp.eps, dtype=np.float64)
+    sp.eps = np.where(np.arange(40) < 28, 0.4 * e, 6.0 + e)
+    E = 4.0
+    o = opipe.solve_energy(sp, E)
+    assert len(o["open"]) == 28
+    say("end to end N", sp.n, "open", len(o["open"]), "prec", prec)
+    res = P.Solver(P.DeviceSystem(sp), prec).run(E)
+    assert res.nopen == 28 and not res.fallback
+    _check_S(res.S.cpu().numpy(), o, 1e-10)
+
+
+def test_noalloc_form_with_closed_channels(mods):
+    """hp_smatrix_noalloc takes the same path: same S as hp_smatrix."""
+    H, P = mods
+    eps, E, k = CASES[0]
+    sp = _small(eps)
+    o = opipe.solve_energy(sp, E)
+    d = P.DeviceSystem(sp)
+    R = torch.from_numpy(o["R"]).to("cuda")
+    S1 = torch.empty_like(R)
+    S2 = torch.empty_like(R)
+    work = torch.empty(H.hp_workspace_bytes(sp.nc, sp.nc, H.HP_C128), dtype=torch.uint8, device="cuda")
+    say("noalloc closed")
+    n1 = H.hp_smatrix(d.sys, E, R, S1, work)
+    n2 = H.hp_smatrix_noalloc(d.sys, E, R, S2)
+    assert n1 == n2 == k
+    assert torch.equal(S1, S2)
+
+
+def test_threshold_and_no_open_channel_are_reported(mods):
+    """An energy exactly at a threshold, or below every threshold, has no
+    collision matrix: HP_ERR_UNSUPPORTED."""
+    H, P = mods
+    sp = make_system("small")
+    d = P.DeviceSystem(sp)
+    s = P.Solver(d, H.HP_C128)
+    for E in (float(np.sort(sp.eps)[1]), float(np.min(sp.eps)) - 0.5):
+        say("unsupported E", E)
+        with pytest.raises(H.HprmatError) as ei:
+            s.run(E)
+        assert ei.value.code == H.HP_ERR_UNSUPPORTED

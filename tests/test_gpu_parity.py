@@ -283,17 +283,6 @@ def test_coulomb_device_matches_host(H):
         assert np.max(np.abs(got[k] - ref) / np.abs(ref)) < 1e-12
 
 
-def test_closed_channel_is_reported(H, P):
-    sp = make_system("small")
-    d = P.DeviceSystem(sp)
-    s = P.Solver(d, H.HP_C128)
-    E = float(np.max(sp.eps)) - 0.01
-    say("closed channel")
-    with pytest.raises(H.HprmatError) as ei:
-        s.run(E)
-    assert ei.value.code == H.HP_ERR_UNSUPPORTED
-
-
 def test_repeat_is_bitwise_deterministic(H, P):
     sp = make_system("small", nc=8, nr=45)
     d = P.DeviceSystem(sp)
