@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--max-refine", type=int, default=30)
     ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-closed", action="store_true", help="skip the closed-channel matching block")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-systems", type=int, default=512)
     ap.add_argument("--served-requests", type=int, default=24)
@@ -142,6 +143,38 @@ def batched(args, H, torch):
                      "buckets": tuned, "refinement_steps": steps,
                      "converged": int(np.sum(st == 1)), "mean_corrections": float(it.mean())}
         del bt
+        torch.cuda.empty_cache()
+    return res
+
+
+def closed_channels(sp, H, P, torch):
+    """The matching step with closed channels at full size: the same system
+    with the thresholds of every eighth channel raised above the energy
+    (32 of 256 closed), one FP32+IR solve there, then hp_smatrix timed on its
+    R against the all-open matching of the original system's R."""
+    import copy
+    import numpy as np
+    E = 16.25
+    spc = copy.deepcopy(sp)
+    e = np.asarray(sp.eps, dtype=np.float64)
+    spc.eps = np.where(np.arange(sp.nc) % 8 != 7, e, 22.0 + e)
+    res = {"energy": E, "closed": int(np.sum(spc.eps > E)), "open": int(np.sum(spc.eps < E))}
+    for name, params in (("all_open", sp), ("closed", spc)):
+        d = P.DeviceSystem(params)
+        s = P.Solver(d, H.HP_C64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.run(E)
+        torch.cuda.synchronize()
+        t_step = time.perf_counter() - t0
+        reps = 10
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            nopen = H.hp_smatrix(d.sys, E, s.R, s.S, s.swork)
+        torch.cuda.synchronize()
+        res[name] = {"step_ms": t_step * 1e3, "smatrix_ms": (time.perf_counter() - t0) / reps * 1e3,
+                     "nopen": nopen, "refinement_steps": r.iterations}
+        del s, d
         torch.cuda.empty_cache()
     return res
 
@@ -423,6 +456,8 @@ def main():
                           "S_relerr_fp32ir_vs_fp64_at_E": [last_e, err]}
         del s64
         torch.cuda.empty_cache()
+    if not args.no_closed:
+        out["closed_channels"] = closed_channels(sp, H, P, torch)
     if not args.no_batched:
         out["batched"] = batched(args, H, torch)
     if not args.no_served:

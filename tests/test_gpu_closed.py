@@ -137,3 +137,23 @@ def test_threshold_and_no_open_channel_are_reported(mods):
         with pytest.raises(H.HprmatError) as ei:
             s.run(E)
         assert ei.value.code == H.HP_ERR_UNSUPPORTED
+
+
+def test_full_size_with_closed_channels(mods):
+    """N = 25600 (256 channels) at 16.25 MeV with the thresholds of every
+    eighth channel raised to 22-27 MeV (32 closed): FP32 LU + FP64
+    refinement end to end; the matching step at full size against the
+    oracle's on the same R (its elimination and its Coulomb and Whittaker
+    values for all 256 channels)."""
+    H, P = mods
+    from oracle import rmatrix as ormat
+    sp = make_system("large")
+    e = np.asarray(sp.eps, dtype=np.float64)
+    sp.eps = np.where(np.arange(sp.nc) % 8 != 7, e, 22.0 + e)
+    E = 16.25
+    say("full size closed N", sp.n)
+    res = P.Solver(P.DeviceSystem(sp), H.HP_C64).run(E)
+    assert res.nopen == sp.nc - sp.nc // 8 and not res.fallback
+    R = res.R.cpu().numpy()
+    U, op, _ = ormat.smatrix_closed(R, E, sp.eps, np.asarray(sp.l), sp.hbar2_2mu, sp.z1z2, sp.a)
+    _check_S(res.S.cpu().numpy(), {"open": op, "S": U}, 1e-12)
