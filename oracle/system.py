@@ -14,6 +14,18 @@ Gauss approximation for the local terms (Lagrange property):
                                                     + eps_c - E ) ]
                     + delta_ij V_cc'(r_i),           h = hbar^2 / 2 mu.
 
+Non-local potentials (Sec. 2: the coupling blocks D become full matrices).
+A system may carry a non-local kernel W_cc'(r, r') besides the local V.  Its
+Lagrange-mesh matrix element, with the same Gauss quadrature as the local
+terms and f_i(r_k) = delta_ik / sqrt(w_i), is
+
+  <f_i | W_cc' | f_j> = sqrt(w_i w_j) W_cc'(r_i, r_j),      w_i = a lambda_i,
+
+added to every element of block (c, c').  The system supplies the kernel at
+the mesh-point pairs through ``nonlocal_potential(r)`` (shape
+(nc, nr, nc, nr): W[c, i, c', j] = W_cc'(r_i, r_j), MeV/fm); a system
+without that method, or returning None, is local.
+
 B (Sec. 3.1, step 2) is N x n_ch; column c holds q_i = f_i(a) in block c.
 """
 from __future__ import annotations
@@ -32,6 +44,19 @@ class MeshData:
         self.r, self.w = mesh.mesh(nr, a)
         self.tl = mesh.kinetic_bloch(nr, a)
         self.q = mesh.surface_values(nr, a)
+
+
+def nonlocal_elements(params, md: MeshData) -> np.ndarray | None:
+    """The N x N non-local matrix elements sqrt(w_i w_j) W_cc'(r_i, r_j) in
+    channel-major order, or None for a local system."""
+    fn = getattr(params, "nonlocal_potential", None)
+    W = fn(md.r) if fn is not None else None
+    if W is None:
+        return None
+    nc, nr = params.nc, params.nr
+    W = np.asarray(W, dtype=np.complex128).reshape(nc, nr, nc, nr)
+    sw = np.sqrt(md.w)
+    return (sw[None, :, None, None] * W * sw[None, None, None, :]).reshape(nc * nr, nc * nr)
 
 
 def assemble(params, E: float, md: MeshData | None = None) -> tuple[np.ndarray, np.ndarray]:
@@ -53,6 +78,9 @@ def assemble(params, E: float, md: MeshData | None = None) -> tuple[np.ndarray, 
             rows = c * nr + np.arange(nr)
             cols = cp * nr + np.arange(nr)
             M[rows, cols] += v[:, c, cp]
+    Wm = nonlocal_elements(params, md)
+    if Wm is not None:
+        M += Wm
     B = np.zeros((n, nc), dtype=np.complex128)
     for c in range(nc):
         B[c * nr:(c + 1) * nr, c] = md.q
@@ -63,7 +91,8 @@ def apply(params, E: float, X: np.ndarray, md: MeshData | None = None) -> np.nda
     """M @ X using the block structure (no N x N array), X of shape (N, k).
 
     Row (c, i): sum_j h TL_ij X[(c, j)] + (h l_c(l_c+1)/r_i^2 + eps_c - E) X[(c, i)]
-                + sum_c' V_cc'(r_i) X[(c', i)].
+                + sum_c' V_cc'(r_i) X[(c', i)]
+                + sum_c',j sqrt(w_i w_j) W_cc'(r_i, r_j) X[(c', j)]   (non-local systems).
     """
     nc, nr = params.nc, params.nr
     md = md or MeshData(nr, params.a)
@@ -76,4 +105,8 @@ def apply(params, E: float, X: np.ndarray, md: MeshData | None = None) -> np.nda
         out[c] = h * (md.tl @ Xb[c]) + diag[:, None] * Xb[c]
     # sum over c' of V_cc'(r_i) X[(c', i)], for every i
     out += np.einsum("icd,dik->cik", v, Xb)
-    return out.reshape(nc * nr, -1)
+    out = out.reshape(nc * nr, -1)
+    Wm = nonlocal_elements(params, md)
+    if Wm is not None:
+        out += Wm @ X
+    return out

@@ -16,7 +16,8 @@ import scipy.special as sps
 import mpmath
 
 from oracle import ge, mesh, pipeline, rmatrix, system
-from tests.helpers import CustomSystem, diagonal_potential, relerr
+from tests.helpers import (CustomSystem, diagonal_potential, relerr, separable_kmatrix,
+                           separable_nonlocal)
 from workload import make_system
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
@@ -428,3 +429,70 @@ def test_real_potential_with_closed_channels_unitary_and_symmetric():
     assert len(out["open"]) == 4
     assert np.max(np.abs(S.conj().T @ S - np.eye(4))) < 1e-10
     assert np.max(np.abs(S - S.T)) < 1e-10
+
+
+# ---------------------------------------------------------------- non-local --
+# Sec. 2: with a non-local potential the coupling blocks are full matrices.
+# The separable kernel -lam g_c(r) g_c'(r') has a closed-form K matrix
+# (derived in tests/helpers.py), which pins the quadrature factor
+# sqrt(w_i w_j), the (r_i, r_j) orientation inside each block and the
+# channel placement of the blocks.
+
+_NL_H = 20.736  # hbar^2 / 2mu of two nucleons (MeV fm^2)
+
+
+def _zero_local(nc):
+    return lambda r: np.zeros((len(r), nc, nc), dtype=complex)
+
+
+@pytest.mark.parametrize("E", [1.0, 10.0, 50.0])
+def test_separable_single_channel_phase_shift(E):
+    """One s-wave channel, kernel -lam exp(-b r) exp(-b r'): S = exp(2 i delta)
+    with tan(delta) = lam I^2 / (h k - lam J)."""
+    lam, b = 120.0, 1.4
+    sp = CustomSystem(nc=1, nr=60, a=20.0, l=np.array([0]), eps=np.array([0.0]), pot=_zero_local(1),
+                      hbar2_2mu=_NL_H, nlpot=separable_nonlocal(lam, b))
+    S = pipeline.solve_energy(sp, E)["S"][0, 0]
+    K = separable_kmatrix(lam, b, np.sqrt(E / _NL_H), _NL_H)[0, 0]
+    assert abs(S - (1 + 1j * K) / (1 - 1j * K)) < 1e-10
+    assert abs(abs(S) - 1.0) < 1e-12  # a real kernel conserves flux
+
+
+@pytest.mark.parametrize("E", [7.0, 15.0, 40.0])
+def test_separable_coupled_channels_kmatrix(E):
+    """Three s-wave channels with thresholds 0, 2.5, 6 MeV coupled only by a
+    rank-one separable kernel with a different range per channel: the
+    oracle's S equals (1 + iK)(1 - iK)^-1 of the closed-form K."""
+    lam = 60.0
+    beta = np.array([1.4, 0.9, 1.8])
+    eps = np.array([0.0, 2.5, 6.0])
+    sp = CustomSystem(nc=3, nr=80, a=30.0, l=np.zeros(3, dtype=int), eps=eps, pot=_zero_local(3),
+                      hbar2_2mu=_NL_H, nlpot=separable_nonlocal(lam, beta))
+    S = pipeline.solve_energy(sp, E)["S"]
+    K = separable_kmatrix(lam, beta, np.sqrt((E - eps) / _NL_H), _NL_H)
+    Sa = (np.eye(3) + 1j * K) @ np.linalg.inv(np.eye(3) - 1j * K)
+    assert np.max(np.abs(S - Sa)) < 5e-11
+    assert np.max(np.abs(Sa - np.eye(3))) > 0.5  # strong coupling, not a near-identity S
+
+
+def test_nonlocal_assembly_and_apply_agree():
+    """The structured product (apply) equals the assembled matrix times X for
+    a system with local and non-symmetric complex non-local parts, and a zero
+    kernel reproduces the local matrix exactly."""
+    rng = np.random.default_rng(11)
+    nc, nr = 3, 9
+    V = rng.normal(size=(nr, nc, nc)) + 1j * rng.normal(size=(nr, nc, nc))
+    W = rng.normal(size=(nc, nr, nc, nr)) + 1j * rng.normal(size=(nc, nr, nc, nr))
+    kw = dict(nc=nc, nr=nr, a=8.0, l=np.array([0, 1, 3]), eps=np.array([0.0, 1.0, 2.0]),
+              pot=lambda r: V, hbar2_2mu=2.0)
+    sp = CustomSystem(**kw, nlpot=lambda r: W)
+    md = system.MeshData(nr, 8.0)
+    M, _ = system.assemble(sp, 3.0, md)
+    X = rng.normal(size=(nc * nr, 2)) + 1j * rng.normal(size=(nc * nr, 2))
+    assert relerr(system.apply(sp, 3.0, X, md), M @ X) < 1e-13
+    # element (c, i), (c', j) off the local pattern is sqrt(w_i w_j) W
+    c, i, cp, j = 2, 4, 0, 7
+    assert M[c * nr + i, cp * nr + j] == pytest.approx(np.sqrt(md.w[i] * md.w[j]) * W[c, i, cp, j], rel=1e-15)
+    Ml, _ = system.assemble(CustomSystem(**kw), 3.0, md)
+    M0, _ = system.assemble(CustomSystem(**kw, nlpot=lambda r: np.zeros((nc, nr, nc, nr))), 3.0, md)
+    assert np.array_equal(Ml, M0)
