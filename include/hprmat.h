@@ -68,6 +68,16 @@ typedef struct hp_system {
   const int *l;      /* device [nc]: orbital angular momentum per channel */
   const double *eps; /* device [nc]: threshold energy per channel (MeV) */
   const double *v;   /* device [nr*nc*nc] complex128: V[i][c][c'] = V_cc'(r_i) (MeV) */
+  /* Optional non-local potential (Sec. 2: the coupling blocks D become full
+   * matrices).  NULL for a local system.  Otherwise device [n*n] complex128,
+   * n = nc*nr, row-major in the channel-major index:
+   * vnl[(c*nr+i)*n + c'*nr+j] = W_cc'(r_i, r_j) (MeV/fm), the kernel at the
+   * mesh-point pairs.  The library adds the Lagrange-mesh matrix element
+   * sqrt(w_i w_j) W_cc'(r_i, r_j) (Gauss quadrature) to element
+   * ((c,i),(c',j)) of C(E).  The batched entry points report it per system
+   * as unsupported. */
+  const double *w;   /* device [nr]: mesh weights w_i on (0, a); required when vnl != NULL */
+  const double *vnl;
 } hp_system;
 
 /* Outcome of hp_solve (host struct, written by the library). */
@@ -102,8 +112,11 @@ size_t hp_workspace_bytes(int n, int nrhs, int prec);
  * nc*nr, leading dimension ldc >= n, complex128 if prec == HP_C128, complex64
  * if HP_C64, converted from FP64 values), overwriting every element:
  *   C[(c,i),(c',j)] = delta_cc' [ h tl_ij + delta_ij (h l_c(l_c+1)/r_i^2 + eps_c - E) ]
- *                     + delta_ij V_cc'(r_i),   h = hbar2_2mu.
- * Errors: HP_ERR_ARG (null pointer, ldc < n, bad prec), HP_ERR_HIP. */
+ *                     + delta_ij V_cc'(r_i)
+ *                     [ + sqrt(w_i w_j) W_cc'(r_i, r_j)  if sys->vnl != NULL ],
+ * h = hbar2_2mu.
+ * Errors: HP_ERR_ARG (null pointer, vnl without w, ldc < n, bad prec),
+ * HP_ERR_HIP. */
 int hp_build_matrix(const hp_system *sys, double E, int prec, void *C, long ldc, void *stream);
 
 /* LU factorization with partial pivoting in place, P A = L U (Sec. 3.1,
@@ -130,7 +143,9 @@ int hp_factor(int n, int prec, void *A, long lda, int *ipiv, int *perm, int *inf
  * The factors give X0 (prec == HP_C64: FP32 factors, X0 widened to FP64).
  * With max_refine > 0, iterative refinement follows (Sec. 3.2 and Sec. 3.4
  * step 7, here entirely on the device): r = B - C X in FP64 from the block
- * structure of sys (no N x N FP64 matrix), correction from the factors,
+ * structure of sys (no N x N FP64 matrix of the local part; a non-local
+ * system adds one FP64 product with its n x n kernel values, the X rows and
+ * the result scaled by sqrt(w)), correction from the factors,
  * X += d in FP64.  The relative correction max_c |d_c| / |x_c| tracks the
  * forward error: refinement stops converged when it is <= tol (tol <= 0:
  * 2^-29 = u64/u32: the error left after such a correction, about kappa u32
@@ -252,7 +267,10 @@ typedef struct hp_batch_item {
 size_t hp_batch_workspace_bytes(int count, long sum_nc, long sum_xn, int nmax, int prec);
 
 /* C(E) of every system into A (precision prec), as hp_build_matrix does for one
- * (Eq. block_structure).  One workgroup per system. */
+ * (Eq. block_structure).  One workgroup per system.  Local systems only:
+ * the non-local term of an item with sys.vnl != NULL is not assembled, and
+ * such an item is reported per system (hp_batch_status 4,
+ * hp_batch_smatrix 5) instead of solved. */
 int hp_batch_build(int count, const hp_batch_item *items, int prec, void *A, void *stream);
 
 /* LU with partial pivoting of every system (Sec. 3.1), in place, as
@@ -316,7 +334,9 @@ int hp_batch_refine_step(int count, const hp_batch_item *items, const int *shape
 int hp_batch_active(const void *work, unsigned *active, void *stream);
 
 /* Per-system outcome (host arrays of count): status 1 converged (or no
- * refinement), 2 not converged, 3 zero pivot, 0 still refining; iters =
+ * refinement), 2 not converged, 3 zero pivot, 4 non-local system (not
+ * supported by the batched path: its X is not a solution), 0 still
+ * refining; iters =
  * corrections applied (may be NULL).  Synchronizes the stream. */
 int hp_batch_status(int count, const void *work, int *status, int *iters, void *stream);
 
@@ -326,8 +346,8 @@ int hp_batch_status(int count, const void *work, int *status, int *iters, void *
  * elimination with partial pivoting (largest |Re| + |Im|) and back
  * substitution, all in FP64.  status: device int[count], per system 0 ok,
  * 1 a closed channel (E <= eps_c), 2 a Coulomb continued fraction did not
- * converge, 3 an exactly zero pivot, 4 more than 512 channels; S of a system
- * with status != 0 is not written.  sum_nc2 = sum of nc^2 over the systems
+ * converge, 3 an exactly zero pivot, 4 more than 512 channels, 5 a non-local
+ * system (sys.vnl != NULL); S of a system with status != 0 is not written.  sum_nc2 = sum of nc^2 over the systems
  * (host), nc_max = the largest nc (host, at most 512, else
  * HP_ERR_UNSUPPORTED).  work: device, at least 32 * sum_nc2 bytes.
  * Asynchronous, no host synchronisation (may be captured in a graph). */

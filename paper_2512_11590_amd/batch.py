@@ -82,6 +82,9 @@ class Bucket:
         r_h, q_h, tl_h, l_h, eps_h, v_h = [], [], [], [], [], []
         for s in self.systems:
             r, w, q, tl = H.hp_mesh(int(s.nr), float(s.a))
+            fn = getattr(s, "nonlocal_potential", None)
+            if fn is not None and fn(r) is not None:  # the batched kernels handle local systems only
+                raise ValueError("non-local systems are solved one at a time (pipeline.Solver), not batched")
             r_h.append(r)
             q_h.append(q)
             tl_h.append(np.ascontiguousarray(tl).ravel())

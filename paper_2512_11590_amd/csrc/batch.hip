@@ -932,7 +932,7 @@ __device__ void wg_lu_solve(int n, int nc, const cplx<T> *__restrict__ lu, cplx<
 
 // Per-system refinement state.
 struct BatchState {
-  int status;  // 0 running, 1 converged, 2 not converged, 3 zero pivot
+  int status;  // 0 running, 1 converged, 2 not converged, 3 zero pivot, 4 non-local system
   int iters;
   double corr_prev;
   double corr;
@@ -1161,11 +1161,13 @@ __global__ __launch_bounds__(256) void batch_update_kernel(int count, const hp_b
   }
 }
 
-__global__ void batch_state_init_kernel(int count, const int *__restrict__ info, BatchState *state, int refine) {
+__global__ void batch_state_init_kernel(int count, const hp_batch_item *__restrict__ items,
+                                        const int *__restrict__ info, BatchState *state, int refine) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= count) return;
   BatchState st;
-  st.status = (info && info[s] != 0) ? 3 : (refine ? 0 : 1);
+  // the batched kernels assemble and refine local systems only
+  st.status = items[s].sys.vnl ? 4 : (info && info[s] != 0) ? 3 : (refine ? 0 : 1);
   st.iters = 0;
   st.corr_prev = 0.0;
   st.corr = 0.0;
@@ -1578,8 +1580,8 @@ extern "C" int hp_batch_solve_init(int count, const hp_batch_item *items, const 
   if (work_bytes < batch_bytes(count, sum_nc, sum_xn, nmax, prec)) return HP_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   BatchWork w = carve((char *)work, count, sum_nc, sum_xn, prec);
-  hipLaunchKernelGGL(batch_state_init_kernel, dim3((count + 255) / 256), dim3(256), 0, st, count, info_factor,
-                     w.state, refine);
+  hipLaunchKernelGGL(batch_state_init_kernel, dim3((count + 255) / 256), dim3(256), 0, st, count, items,
+                     info_factor, w.state, refine);
   HP_CHECK_LAUNCH();
   TraceScope ts(TR_TRSM, st, 0.0, 0.0);
   if (shape_host) {

@@ -365,7 +365,8 @@ namespace hp {
 // them, Gaussian elimination with partial pivoting (largest |Re| + |Im|,
 // smallest row on ties) on Z, and back substitution of the right half into
 // S (at r_off).  status[s]: 0 ok, 1 a closed channel, 2 a continued fraction
-// did not converge, 3 an exactly zero pivot, 4 more than 512 channels.
+// did not converge, 3 an exactly zero pivot, 4 more than 512 channels,
+// 5 a non-local system (its R did not come from the batched solves).
 constexpr int kBatchSmatMaxChannels = 512;
 
 __global__ __launch_bounds__(256) void batch_smatrix_kernel(int count, const hp_batch_item *__restrict__ items,
@@ -384,6 +385,10 @@ __global__ __launch_bounds__(256) void batch_smatrix_kernel(int count, const hp_
   const int nc = sys.nc, tid = threadIdx.x;
   if (nc > kBatchSmatMaxChannels) {  // the channel table would not fit
     if (tid == 0) status[sidx] = 4;
+    return;
+  }
+  if (sys.vnl) {
+    if (tid == 0) status[sidx] = 5;
     return;
   }
   if (tid == 0) s_bad = 0;

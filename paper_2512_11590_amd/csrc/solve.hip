@@ -12,7 +12,10 @@
 // which costs nc nr^2 + nr nc^2 complex operations per column instead of
 // (nc nr)^2.  The kinetic part is a real x complex product per channel
 // (residual_local_kernel); the coupling part is one complex GEMM per radial
-// point (batched MFMA gemm_sub).
+// point (batched MFMA gemm_sub).  A non-local system (Sec. 2: full coupling
+// blocks sqrt(w_i w_j) W_cc'(r_i, r_j)) adds one FP64 GEMM with its n x n
+// kernel values: T = -W (s X) with s_j = sqrt(w_j) is written into R first,
+// and residual_local_kernel folds s_i T_i into the row it writes.
 #include "common.h"
 
 #include <mutex>
@@ -39,7 +42,9 @@ __global__ void rhs_from_perm_kernel(int nc, int nr, const int *__restrict__ per
   Y[e] = cplx<T>{(T)((c == col) ? q[ii] : 0.0), T(0)};
 }
 
-// r = B - (h TL (x) I_c) X - diag X, for a column tile of 32 and one channel.
+// r = B - (h TL (x) I_c) X - diag X, for a column tile of 32 and one channel;
+// with w (non-local systems) R holds T = -W (s X) on entry and
+// r + sqrt(w_i) T is written.
 constexpr int kResCols = 32;
 __global__ __launch_bounds__(256) void residual_local_kernel(int nc, int nr, double h, double E,
                                                              const double *__restrict__ tl,
@@ -47,6 +52,7 @@ __global__ __launch_bounds__(256) void residual_local_kernel(int nc, int nr, dou
                                                              const int *__restrict__ l,
                                                              const double *__restrict__ eps,
                                                              const double *__restrict__ q,
+                                                             const double *__restrict__ w,
                                                              const cplx<double> *__restrict__ X,
                                                              cplx<double> *__restrict__ R) {
   extern __shared__ __align__(16) char smem_raw[];
@@ -78,8 +84,46 @@ __global__ __launch_bounds__(256) void residual_local_kernel(int nc, int nr, dou
     const cplx<double> x = Xs[i * kResCols + cc];
     const int col = col0 + cc;
     const double b = (col == c) ? q[i] : 0.0;
-    R[((long)c * nr + i) * nc + col] = cplx<double>{b - h * sr - dg * x.re, -h * si - dg * x.im};
+    cplx<double> out{b - h * sr - dg * x.re, -h * si - dg * x.im};
+    const long o = ((long)c * nr + i) * nc + col;
+    if (w) {
+      const double si_w = sqrt(w[i]);
+      const cplx<double> t = R[o];
+      out.re += si_w * t.re;
+      out.im += si_w * t.im;
+    }
+    R[o] = out;
   }
+}
+
+// Xs[(c,j)][col] = sqrt(w_j) X[(c,j)][col] (the right operand of the
+// non-local residual product).
+__global__ void scale_rows_sqrtw_kernel(long n, int nr, int nc, const double *__restrict__ w,
+                                        const cplx<double> *__restrict__ X, cplx<double> *__restrict__ Xs) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nc) return;
+  const long row = e / nc;
+  const double s = sqrt(w[row % nr]);
+  const cplx<double> x = X[e];
+  Xs[e] = cplx<double>{s * x.re, s * x.im};
+}
+
+// out[(c,i)] = sum over (c',j) of sqrt(w_i w_j) (|Re W| + |Im W|): the
+// non-local part of the row sums of |C| (one workgroup per row).
+__global__ __launch_bounds__(256) void nl_rowsum_kernel(long n, int nr, const double *__restrict__ w,
+                                                        const cplx<double> *__restrict__ W, double *__restrict__ out) {
+  __shared__ double part[4];
+  const long row = blockIdx.x;
+  const cplx<double> *wr = W + row * n;
+  double sum = 0.0;
+  for (long col = threadIdx.x; col < n; col += 256) {
+    const cplx<double> v = wr[col];
+    sum += sqrt(w[col % nr]) * (fabs(v.re) + fabs(v.im));
+  }
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) out[row] = sqrt(w[row % nr]) * (part[0] + part[1] + part[2] + part[3]);
 }
 
 // Per-column max of |Re|+|Im| into out[col] (non-negative doubles compare as
@@ -154,7 +198,7 @@ __global__ void update_kernel(long n, int nc, const cplx<T> *__restrict__ D, con
 __global__ void cnorm_kernel(int nc, int nr, double h, double E, const double *__restrict__ tl,
                              const double *__restrict__ r, const int *__restrict__ l, const double *__restrict__ eps,
                              const double *__restrict__ v, const double *__restrict__ q,
-                             unsigned long long *__restrict__ out) {
+                             const double *__restrict__ nlsum, unsigned long long *__restrict__ out) {
   const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double sum = 0.0, qm = 0.0;
   if (row < (long)nc * nr) {
@@ -170,6 +214,7 @@ __global__ void cnorm_kernel(int nc, int nr, double h, double E, const double *_
       if (cp == c) re += dg;
       sum += fabs(re) + fabs(im);
     }
+    if (nlsum) sum += nlsum[row];
     qm = fabs(q[i]);
   }
   for (int off = 32; off > 0; off >>= 1) {
@@ -193,16 +238,29 @@ __global__ void widen_kernel(long count, const cplx<T> *__restrict__ S, cplx<dou
 
 static unsigned nblk(long count) { return (unsigned)((count + 255) / 256); }
 
-static int residual(const hp_system *sys, double E, const cplx<double> *X, cplx<double> *R, hipStream_t st) {
+// `scratch`: n x nc complex128 of free device memory (used by non-local
+// systems for sqrt(w) X).
+static int residual(const hp_system *sys, double E, const cplx<double> *X, cplx<double> *R, cplx<double> *scratch,
+                    hipStream_t st) {
   const int nc = sys->nc, nr = sys->nr;
   const size_t shm = (size_t)nr * kResCols * sizeof(cplx<double>);
   if (shm > 150 * 1024) return HP_ERR_UNSUPPORTED;
   int rc0 = ensure_dynamic_lds((const void *)residual_local_kernel, shm);
   if (rc0) return rc0;
   dim3 grid((nc + kResCols - 1) / kResCols, nc);
+  const long n = (long)nc * nr;
+  if (sys->vnl) {
+    const long cnt = n * nc;
+    hipLaunchKernelGGL(scale_rows_sqrtw_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, n, nr, nc,
+                       sys->w, X, scratch);
+    HP_CHECK_LAUNCH();
+    if ((rc0 = gemm_set_batched<double>((int)n, nc, (int)n, -1.0, (const cplx<double> *)sys->vnl, n, 0, scratch, nc,
+                                        0, R, nc, 0, 1, st)))
+      return rc0;
+  }
   TraceScope ts(TR_RESIDUAL, st, 4.0 * (double)nc * nr * nr * nc, 0.0);
   hipLaunchKernelGGL(residual_local_kernel, grid, dim3(256), shm, st, nc, nr, sys->hbar2_2mu, E, sys->tl, sys->r,
-                     sys->l, sys->eps, sys->q, X, R);
+                     sys->l, sys->eps, sys->q, sys->vnl ? sys->w : nullptr, X, R);
   HP_CHECK_LAUNCH();
   // coupling part: for every radial point i, R_i -= V_i X_i with
   // V_i = V[i] (nc x nc), X_i = rows (c', i) of X (stride nr rows).
@@ -389,14 +447,22 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
   const double stall_ok = std::max(corr_tol, kStallTol);
   hipLaunchKernelGGL(zero_u64_kernel, dim3(nblk(3 * nc + 2)), dim3(256), 0, st, smax, 3 * nc + 2);
   HP_CHECK_LAUNCH();
+  double *nlsum = nullptr;
+  if (sys->vnl) {  // Rr is free until the first residual
+    nlsum = (double *)Rr;
+    hipLaunchKernelGGL(nl_rowsum_kernel, dim3((unsigned)n), dim3(256), 0, st, n, nr, sys->w,
+                       (const cplx<double> *)sys->vnl, nlsum);
+    HP_CHECK_LAUNCH();
+  }
   hipLaunchKernelGGL(cnorm_kernel, dim3(nblk(n)), dim3(256), 0, st, nc, nr, sys->hbar2_2mu, E, sys->tl, sys->r,
-                     sys->l, sys->eps, sys->v, sys->q, norms);
+                     sys->l, sys->eps, sys->v, sys->q, nlsum, norms);
   HP_CHECK_LAUNCH();
   std::vector<unsigned long long> h(3 * (size_t)nc + 2);
   double corr_prev = INFINITY;
   const unsigned cm_blocks = (unsigned)std::min<long>(2048, std::max<long>(1, (n * nc + 255) / 256));
   for (int it = 0;; ++it) {
-    if ((rc = residual(sys, E, X, Rr, st))) return rc;
+    // the working-precision right-hand sides are free until scale_perm_kernel
+    if ((rc = residual(sys, E, X, Rr, (cplx<double> *)(work + ws.rhs_off), st))) return rc;
     {
       TraceScope ts(TR_REFINE, st, 0.0, 32.0 * (double)cnt);
       hipLaunchKernelGGL(zero_u64_kernel, dim3(nblk(2 * nc)), dim3(256), 0, st, smax, 2 * nc);
@@ -472,7 +538,7 @@ using namespace hp;
 
 static bool sys_ok(const hp_system *sys) {
   return sys && sys->nc >= 1 && sys->nr >= 1 && sys->a > 0 && sys->r && sys->q && sys->tl && sys->l && sys->eps &&
-         sys->v;
+         sys->v && (!sys->vnl || sys->w);
 }
 
 extern "C" int hp_solve(const hp_system *sys, double E, int prec, const void *LU, long lda, const int *perm,

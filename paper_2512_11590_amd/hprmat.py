@@ -36,7 +36,7 @@ c_int, c_long, c_double, c_void_p, c_size_t = (ctypes.c_int, ctypes.c_long, ctyp
 class HpSystem(ctypes.Structure):
     _fields_ = [("nc", c_int), ("nr", c_int), ("a", c_double), ("hbar2_2mu", c_double),
                 ("z1z2e2", c_double), ("r", c_void_p), ("q", c_void_p), ("tl", c_void_p),
-                ("l", c_void_p), ("eps", c_void_p), ("v", c_void_p)]
+                ("l", c_void_p), ("eps", c_void_p), ("v", c_void_p), ("w", c_void_p), ("vnl", c_void_p)]
 
 
 class HpBatchItem(ctypes.Structure):

@@ -26,7 +26,12 @@ E2 = 1.44  # e^2 in MeV fm
 
 
 class DeviceSystem:
-    def __init__(self, params, device: str = "cuda"):
+    """`vnl`: optional device complex128 tensor (N, N) of non-local kernel
+    values W_cc'(r_i, r_j) in channel-major order; without it, a
+    ``nonlocal_potential(r)`` method of `params` (shape (nc, nr, nc, nr))
+    supplies them, and a system with neither is local."""
+
+    def __init__(self, params, device: str = "cuda", vnl: torch.Tensor | None = None):
         self.params = params
         self.nc, self.nr = int(params.nc), int(params.nr)
         self.n = self.nc * self.nr
@@ -41,10 +46,23 @@ class DeviceSystem:
         self.l = torch.from_numpy(np.asarray(params.l, dtype=np.int32)).to(dev)
         self.eps = torch.from_numpy(np.asarray(params.eps, dtype=np.float64)).to(dev)
         self.v = torch.from_numpy(v).to(dev)
+        self.w = torch.from_numpy(w).to(dev)
+        if vnl is None:
+            fn = getattr(params, "nonlocal_potential", None)
+            W = fn(r) if fn is not None else None
+            if W is not None:
+                W = np.ascontiguousarray(np.asarray(W, dtype=np.complex128).reshape(self.n, self.n))
+                vnl = torch.from_numpy(W).to(dev)
+        if vnl is not None:
+            if (tuple(vnl.shape) != (self.n, self.n) or vnl.dtype != torch.complex128 or not vnl.is_contiguous()
+                    or vnl.device != self.r.device):
+                raise ValueError("vnl must be a contiguous complex128 (N, N) tensor on the system's device")
+        self.vnl = vnl
         self.sys = H.HpSystem(self.nc, self.nr, float(params.a), float(params.hbar2_2mu),
                               float(params.z1z2) * E2, self.r.data_ptr(), self.q.data_ptr(),
                               self.tl.data_ptr(), self.l.data_ptr(), self.eps.data_ptr(),
-                              self.v.data_ptr())
+                              self.v.data_ptr(), self.w.data_ptr(),
+                              vnl.data_ptr() if vnl is not None else None)
 
 
 @dataclass

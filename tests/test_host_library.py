@@ -112,3 +112,35 @@ def test_concurrency_setter(H):
     assert H.lib().hp_set_concurrency(0) == H.HP_ERR_ARG
     assert H.lib().hp_set_concurrency(257) == H.HP_ERR_ARG
     assert H.hp_set_concurrency(1) == 2
+
+
+def test_system_struct_matches_header(H):
+    """The binding's hp_system fields are the header's, in the header's order
+    (the non-local fields w and vnl last)."""
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct hp_system \{(.*?)\} hp_system;", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"\*?\s*([a-z_0-9]+)\s*;", body)
+    assert names == [f for f, _ in H.HpSystem._fields_]
+    assert names[-2:] == ["w", "vnl"]
+
+
+def test_nonlocal_arguments_checked_without_device(H):
+    """A non-local system needs the mesh weights: vnl without w is an
+    argument error of the assembly and the solve, found before any launch."""
+    L = H.lib()
+    s = H.HpSystem(2, 3, 5.0, 20.0, 0.0, 1, 1, 1, 1, 1, 1, None, 1)
+    assert L.hp_build_matrix(ctypes.byref(s), 1.0, H.HP_C128, 1, 6, None) == H.HP_ERR_ARG
+    assert L.hp_solve(ctypes.byref(s), 1.0, H.HP_C64, 1, 6, 1, None, 1, 0, 0.0, 1, 1 << 30, None,
+                      None) == H.HP_ERR_ARG
+
+
+def test_batch_layer_rejects_nonlocal_systems(H):
+    """Non-local systems go through the single-system solver; the batched
+    layer refuses them before touching a device."""
+    from paper_2512_11590_amd import batch
+    from tests.helpers import CustomSystem, separable_nonlocal
+    sp = CustomSystem(nc=1, nr=10, a=10.0, l=np.array([0]), eps=np.array([0.0]),
+                      pot=lambda r: np.zeros((len(r), 1, 1), dtype=complex), nlpot=separable_nonlocal(1.0, 1.0))
+    with pytest.raises(ValueError, match="non-local"):
+        batch.Bucket([sp], [1.0], [0], H.HP_C128, device="cpu")
