@@ -56,13 +56,14 @@ def parse():
     ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-closed", action="store_true", help="skip the closed-channel matching block")
+    ap.add_argument("--no-nonlocal", action="store_true", help="skip the non-local potential block")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-systems", type=int, default=512)
     ap.add_argument("--served-requests", type=int, default=24)
     ap.add_argument("--served-rate", type=float, default=4.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--served-rate-sustained", type=float, default=2.0,
                     help="a second, lower arrival rate for the same requests (0: skip)")
-    ap.add_argument("--only", choices=("batched", "served"), default=None,
+    ap.add_argument("--only", choices=("batched", "served", "nonlocal"), default=None,
                     help="run only this block (for profiling) and print it as the JSON line")
     ap.add_argument("--counter-summary", metavar="CSV", default=None,
                     help="read a rocprofv3 --pmc counter CSV or --kernel-trace CSV (no GPU) and print "
@@ -176,6 +177,42 @@ def closed_channels(sp, H, P, torch):
                      "nopen": nopen, "refinement_steps": r.iterations}
         del s, d
         torch.cuda.empty_cache()
+    return res
+
+
+def nonlocal_block(sp, H, P, torch, steps=3):
+    """The headline system with a non-local kernel added (Sec. 2: full
+    coupling blocks): a Perey-Buck-form optical kernel coupled across the
+    channels like the local couplings, passed as dense n x n values
+    (10.5 GB at N = 25600), built on the device as kron(B, K).  FP32 LU +
+    FP64 refinement steps timed as in the main line (one warmup), then one
+    FP64-LU solve of the same system for the S difference."""
+    import numpy as np
+    from workload import perey_buck_factors
+    n = sp.nc * sp.nr
+    r = H.hp_mesh(sp.nr, float(sp.a))[0]
+    B, K = perey_buck_factors(sp, r)
+    W = torch.kron(torch.from_numpy(B.astype(np.complex128)).to("cuda"), torch.from_numpy(K).to("cuda"))
+    d = P.DeviceSystem(sp, vnl=W)
+    E = float(sp.energies[steps % len(sp.energies)])
+    res = {"N": n, "kernel": "Perey-Buck form x0.4, width 0.85 fm, channel coupling I + beta",
+           "kernel_bytes": int(W.numel() * W.element_size()), "energy_of_checks": E}
+    print("[bench] non-local block: fp32+ir", file=sys.stderr, flush=True)
+    s = P.Solver(d, H.HP_C64)
+    t, infos, _, stages = timed_steps(s, sp.energies, steps, 1, H, torch, "gemm_c64")
+    S32 = s.S.cpu().numpy()
+    res["fp32_ir"] = {"ms_per_step": t * 1e3, "refinement_steps": [i[0] for i in infos],
+                      "backward_error": [i[1] for i in infos], "fp64_fallbacks": sum(bool(i[2]) for i in infos),
+                      "stages_ms_one_step": {k: round(v["ms"], 3) for k, v in stages.items() if v["launches"]}}
+    del s
+    torch.cuda.empty_cache()
+    print("[bench] non-local block: fp64 check", file=sys.stderr, flush=True)
+    s = P.Solver(d, H.HP_C128)
+    s.run(E)
+    S64 = s.S.cpu().numpy()
+    res["S_relerr_fp32ir_vs_fp64"] = float(np.max(np.abs(S32 - S64)) / np.max(np.abs(S64)))
+    del s, d, W
+    torch.cuda.empty_cache()
     return res
 
 
@@ -351,7 +388,10 @@ def main():
         print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes}))
         return
     if args.only:
-        blk = batched(args, H, torch) if args.only == "batched" else served_stream(args, H, torch)
+        if args.only == "nonlocal":
+            blk = nonlocal_block(make_system(args.config), H, P, torch)
+        else:
+            blk = batched(args, H, torch) if args.only == "batched" else served_stream(args, H, torch)
         print(json.dumps({"only": args.only, args.only: blk}), flush=True)
         return
     sp = make_system(args.config)
@@ -458,6 +498,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_closed:
         out["closed_channels"] = closed_channels(sp, H, P, torch)
+    if not args.no_nonlocal:
+        out["nonlocal"] = nonlocal_block(sp, H, P, torch)
     if not args.no_batched:
         out["batched"] = batched(args, H, torch)
     if not args.no_served:

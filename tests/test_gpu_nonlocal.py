@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 from oracle import pipeline as opipe  # noqa: E402
 from oracle import system as osys  # noqa: E402
 from tests.helpers import CustomSystem, relerr, separable_kmatrix, separable_nonlocal  # noqa: E402
-from workload import make_system  # noqa: E402
+from workload import make_system, with_perey_buck  # noqa: E402
 
 
 def say(*a):
@@ -113,6 +113,24 @@ def test_nonlocal_pipeline_matches_oracle(mods, nc, nr, prec):
         assert not res.fallback
         if prec != H.HP_C128:
             assert res.iterations >= 1 and 0 <= res.backward_error < 1e-14
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_perey_buck_system_matches_oracle(mods, prec):
+    """N = 2400 (40 channels of the mid family, Coulomb, l up to 20) with the
+    Perey-Buck-form kernel coupled across channels: R and S against the
+    oracle.  (The family's all-pairs couplings make the potential neither
+    absorptive nor flux-conserving, so no unitarity bound applies.)"""
+    H, P = mods
+    sp = with_perey_buck(make_system("mid", nc=40))
+    md = osys.MeshData(sp.nr, sp.a)
+    E = float(sp.energies[2 if prec == 0 else 15])
+    say("Perey-Buck N", sp.n, "prec", prec, "E", E)
+    res = P.Solver(P.DeviceSystem(sp), prec).run(E)
+    o = opipe.solve_energy(sp, E, md)
+    S = res.S.cpu().numpy()
+    assert relerr(res.R.cpu().numpy(), o["R"]) < 1e-10 and relerr(S, o["S"]) < 1e-10
+    assert not res.fallback
 
 
 _NL_H = 20.736

@@ -100,6 +100,38 @@ class SystemParams:
         return v.astype(np.complex128)
 
 
+def perey_buck_factors(sp: SystemParams, r: np.ndarray, strength: float = 0.4,
+                       width: float = 0.85) -> tuple[np.ndarray, np.ndarray]:
+    """A non-local optical kernel of Perey-Buck form on the system's channels
+    (an input of the non-local coupled-channel equation, Sec. 2):
+
+        W_cc'(r, r') = B_cc' s U((r + r')/2) exp(-((r - r')/width)^2) / (sqrt(pi) width),
+
+    U the system's complex Woods-Saxon shape, s = `strength`, B = I + beta
+    (the system's coupling strengths off the diagonal).  Returned as the
+    factors (B [nc, nc] float64, K [nr, nr] complex128 at the points r), so
+    that the kernel values in channel-major order are kron(B, K)."""
+    r = np.asarray(r, dtype=np.float64)
+    rbar = 0.5 * (r[:, None] + r[None, :])
+    h = np.exp(-((r[:, None] - r[None, :]) / width) ** 2) / (math.sqrt(math.pi) * width)
+    K = strength * sp.central(rbar.ravel()).reshape(rbar.shape) * h
+    B = np.eye(sp.nc) + np.asarray(sp.beta, dtype=np.float64)
+    return B, K.astype(np.complex128)
+
+
+def with_perey_buck(sp: SystemParams, strength: float = 0.4) -> SystemParams:
+    """The same system with the Perey-Buck kernel added: sets its
+    ``nonlocal_potential(r)`` (shape (nc, nr, nc, nr)); for small systems, as
+    the values are held on the host."""
+    def nonlocal_potential(r):
+        B, K = perey_buck_factors(sp, r, strength)
+        n = len(r)
+        return np.kron(B, K).reshape(sp.nc, n, sp.nc, n)
+    sp.nonlocal_potential = nonlocal_potential
+    sp.label += f" + Perey-Buck non-local x{strength}"
+    return sp
+
+
 def _draw(rng: np.random.Generator, nc: int, nr: int, a: float, lmax: int,
           n_energies: int, label: str) -> SystemParams:
     v0 = float(rng.uniform(40.0, 60.0))
