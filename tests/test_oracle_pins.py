@@ -496,3 +496,52 @@ def test_nonlocal_assembly_and_apply_agree():
     Ml, _ = system.assemble(CustomSystem(**kw), 3.0, md)
     M0, _ = system.assemble(CustomSystem(**kw, nlpot=lambda r: np.zeros((nc, nr, nc, nr))), 3.0, md)
     assert np.array_equal(Ml, M0)
+
+
+# ------------------------------------------------------- Woodbury-kinetic --
+# Sec. 3.3 (Type 3): S = I + K^-1 V in radial-major order.  Its definition is
+# pinned to the (already pinned) assembled M: (K (x) I_nc) S = M with M's
+# unknowns reordered radial-major, and the Schur solution is the direct one.
+
+def _radial_major(nc, nr):
+    """Channel-major index of radial-major position k = i*nc + a."""
+    return np.array([a * nr + i for i in range(nr) for a in range(nc)])
+
+
+@pytest.mark.parametrize("cfg,kw", [("small", {}), ("small", dict(nc=3, nr=17)), ("mid", dict(nc=6))])
+def test_woodbury_schur_matrix_reassembles_M(cfg, kw):
+    from oracle import woodbury
+    sp = make_system(cfg, **kw)
+    md = system.MeshData(sp.nr, sp.a)
+    E = float(sp.energies[3])
+    S, bt = woodbury.schur_system(sp, E, md)
+    M, B = system.assemble(sp, E, md)
+    p = _radial_major(sp.nc, sp.nr)
+    KI = np.kron(sp.hbar2_2mu * md.tl, np.eye(sp.nc))
+    assert relerr(KI @ S, M[np.ix_(p, p)]) < 1e-13
+    assert relerr(KI @ bt, B[p]) < 1e-10
+    # the identity part and the coupling: S - I has the radial-diagonal V in every (i, j) block
+    Ki = woodbury.kinetic_inverse(sp, md)
+    V = woodbury.radial_diagonal(sp, E, md)
+    i, j, a, b = 2, 5, 1, 0
+    assert S[i * sp.nc + a, j * sp.nc + b] == pytest.approx(Ki[i, j] * V[j, a, b], rel=1e-15)
+
+
+@pytest.mark.parametrize("cfg,kw", [("small", {}), ("small", dict(nc=3, nr=17)), ("mid", dict(nc=6))])
+def test_woodbury_solution_equals_direct(cfg, kw):
+    from oracle import woodbury
+    sp = make_system(cfg, **kw)
+    md = system.MeshData(sp.nr, sp.a)
+    for e in (0, 7):
+        E = float(sp.energies[e])
+        w = woodbury.solve(sp, E, md)
+        o = pipeline.solve_energy(sp, E, md, with_smatrix=False)
+        assert relerr(w["X"], o["X"]) < 1e-10 and relerr(w["R"], o["R"]) < 1e-10
+
+
+def test_woodbury_refuses_nonlocal_systems():
+    from oracle import woodbury
+    sp = CustomSystem(nc=1, nr=8, a=10.0, l=np.array([0]), eps=np.array([0.0]), pot=_zero_local(1),
+                      nlpot=separable_nonlocal(1.0, 1.0))
+    with pytest.raises(ValueError, match="local"):
+        woodbury.schur_system(sp, 1.0)
