@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--served-rate", type=float, default=4.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--served-rate-sustained", type=float, default=2.0,
                     help="a second, lower arrival rate for the same requests (0: skip)")
-    ap.add_argument("--only", choices=("batched", "served", "nonlocal"), default=None,
+    ap.add_argument("--only", choices=("batched", "served", "nonlocal", "woodbury"), default=None,
                     help="run only this block (for profiling) and print it as the JSON line")
     ap.add_argument("--counter-summary", metavar="CSV", default=None,
                     help="read a rocprofv3 --pmc counter CSV or --kernel-trace CSV (no GPU) and print "
@@ -213,6 +213,31 @@ def nonlocal_block(sp, H, P, torch, steps=3):
     res["S_relerr_fp32ir_vs_fp64"] = float(np.max(np.abs(S32 - S64)) / np.max(np.abs(S64)))
     del s, d, W
     torch.cuda.empty_cache()
+    return res
+
+
+def woodbury_block(sp, H, P, torch, steps=3):
+    """The Woodbury-kinetic form (the paper's Type 3, Sec. 3.3) on the headline
+    system: FP32 factors of S(E) = I + K_diag^-1 V, FP64 refinement on
+    C(E)'s residual, timed like the main line (one warmup, `steps` energies);
+    then the same energy through the direct form for the S difference and
+    the refinement steps side by side."""
+    import numpy as np
+    d = P.DeviceSystem(sp)
+    res = {}
+    for name, schur in (("schur", True), ("direct", False)):
+        print(f"[bench] woodbury block: {name}", file=sys.stderr, flush=True)
+        s = P.Solver(d, H.HP_C64, schur=schur)
+        t, infos, _, stages = timed_steps(s, sp.energies, steps, 1, H, torch, "gemm_c64")
+        res[name] = {"ms_per_step": t * 1e3, "refinement_steps": [i[0] for i in infos],
+                     "fp64_fallbacks": sum(bool(i[2]) for i in infos),
+                     "stages_ms_one_step": {k: round(v["ms"], 3) for k, v in stages.items() if v["launches"]}}
+        res[name + "_S"] = s.S.cpu().numpy()
+        del s
+        torch.cuda.empty_cache()
+    a, b = res.pop("schur_S"), res.pop("direct_S")
+    res["energy_of_check"] = float(sp.energies[steps % len(sp.energies)])
+    res["S_relerr_schur_vs_direct"] = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
     return res
 
 
@@ -390,6 +415,8 @@ def main():
     if args.only:
         if args.only == "nonlocal":
             blk = nonlocal_block(make_system(args.config), H, P, torch)
+        elif args.only == "woodbury":
+            blk = woodbury_block(make_system(args.config), H, P, torch)
         else:
             blk = batched(args, H, torch) if args.only == "batched" else served_stream(args, H, torch)
         print(json.dumps({"only": args.only, args.only: blk}), flush=True)

@@ -98,6 +98,15 @@ typedef struct hp_solve_info {
  * Errors: HP_ERR_ARG if nr < 1 or a <= 0. */
 int hp_mesh(int nr, double a, double *r, double *w, double *q, double *tl);
 
+/* Inverse of the kinetic + Bloch matrix tl of hp_mesh (the shared kinetic
+ * block K = (hbar^2/2mu) tl of the Woodbury-kinetic form, Sec. 3.3, step 1,
+ * without the factor hbar^2/2mu): kinv[i*nr + j] = (tl^-1)_ij for the rounded
+ * tl that hp_mesh returns, by Gauss-Jordan elimination with partial pivoting
+ * in binary128, rounded once.  Energy-independent: once per mesh.  kinv:
+ * HOST nr*nr doubles.  Errors: HP_ERR_ARG (nr < 1, a <= 0, kinv NULL),
+ * HP_ERR_SINGULAR. */
+int hp_kinetic_inverse(int nr, double a, double *kinv);
+
 /* Device workspace (bytes) that hp_factor, hp_solve and hp_smatrix need for
  * an n x n factorization with nrhs right-hand sides in precision prec.  One
  * workspace may serve all three calls on one stream in sequence.  With
@@ -168,6 +177,41 @@ int hp_factor(int n, int prec, void *A, long lda, int *ipiv, int *perm, int *inf
 int hp_solve(const hp_system *sys, double E, int prec, const void *LU, long lda,
              const int *perm, const int *info_factor, double *X, int max_refine, double tol,
              void *work, size_t work_bytes, hp_solve_info *info, void *stream);
+
+/* ---- Woodbury-kinetic form (Sec. 3.3, Type 3) ---------------------------
+ * M = K_diag (I + K_diag^-1 V) with K = h tl shared by every channel, so
+ * M c = b becomes S c = K_diag^-1 b with S = I + K_diag^-1 V.  The library
+ * keeps the channel-major unknown order of C(E) (the paper lists S in
+ * radial-major order: the same matrix up to one symmetric permutation), so
+ * S[(c,i),(c',j)] = delta_cc' delta_ij + (1/h) kinv_ij Vd_cc'(r_j) with
+ * Vd_cc'(r_j) = V_cc'(r_j) + delta_cc' (h l_c(l_c+1)/r_j^2 + eps_c - E) (every
+ * term of C(E) that is diagonal in the radial index).  S is factored by
+ * hp_factor like C(E) (it is not symmetric; the factorization does not
+ * assume symmetry).  Local systems only (HP_ERR_UNSUPPORTED if sys->vnl). */
+
+/* Workspace of hp_solve_schur: hp_workspace_bytes(n, nrhs, prec) plus room for
+ * the transformed residual (n*nrhs complex128), the complex copy of kinv/h
+ * and K^-1 q; nr = n / nrhs.  0 on bad arguments. */
+size_t hp_schur_workspace_bytes(int n, int nrhs, int prec);
+
+/* Assemble S(E) into device matrix S (n x n, leading dimension lds >= n,
+ * complex128 for HP_C128, complex64 for HP_C64/HP_C64H, from FP64 values).
+ * kinv: device nr*nr doubles from hp_kinetic_inverse.
+ * Errors: HP_ERR_ARG, HP_ERR_UNSUPPORTED (non-local system), HP_ERR_HIP. */
+int hp_build_schur(const hp_system *sys, double E, int prec, const double *kinv, void *S, long lds,
+                   void *stream);
+
+/* Solve C(E) X = B through the factors of S(E) (hp_factor on hp_build_schur's
+ * matrix): X0 from S X0 = K_diag^-1 B; with max_refine > 0 the FP64 residual
+ * r = B - C X of C(E) itself (as in hp_solve) is transformed, S d =
+ * K_diag^-1 r, X += d, with hp_solve's stop rule and reported figures (the
+ * backward error is C(E)'s).  max_refine = 0 with FP32 factors is the paper's
+ * single-precision Type 3 solve.  Arguments, X layout and errors as
+ * hp_solve, plus kinv (device, as for hp_build_schur); work: at least
+ * hp_schur_workspace_bytes(n, nc, prec) bytes. */
+int hp_solve_schur(const hp_system *sys, double E, int prec, const double *kinv, const void *LU, long lda,
+                   const int *perm, const int *info_factor, double *X, int max_refine, double tol, void *work,
+                   size_t work_bytes, hp_solve_info *info, void *stream);
 
 /* General solve with the factors: X (device n x nrhs, leading dimension ldx,
  * precision prec) holds B on entry and X = A^-1 B on return. */

@@ -14,7 +14,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhprmat.so")
 
 HIP_SOURCES = ["assemble.hip", "lu.hip", "gemm.hip", "gemm_h3.hip", "solve.hip", "wsolve.hip", "coulomb.hip", "abi.hip",
-               "trace.hip", "batch.hip"]
+               "trace.hip", "batch.hip", "woodbury.hip"]
 CXX_SOURCES = ["mesh.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,

@@ -347,10 +347,24 @@ struct OwnedGraph {
 //    Accuracy Validation, Fig. illcond) or after max_refine corrections.
 // The normwise backward error max_c |r_c| / (|C| |x_c| + |b_c|) of the last
 // residual is reported alongside.
+//
+// With `sch` (the Woodbury-kinetic form, Sec. 3.3) the factors are those of
+// S = K_diag^-1 C: the right-hand sides are K^-1 q / h in every channel block
+// (qt), and each residual is transformed per channel, rt_c = (kinv/h) r_c (one
+// batched FP64 GEMM over the channels with the complex copy kc of kinv/h),
+// before it is scaled and solved; the residual, its norm and the backward
+// error stay those of C(E).
+struct SchurOps {
+  const cplx<double> *kc;     // nr x nr: kinv / h as complex128
+  const double *qt;           // nr: kinv q / h
+  cplx<double> *rt;           // n x nc: transformed residual
+  unsigned long long *tmax;   // nc: its column maxima
+};
+
 template <typename T>
 static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long lda, const int *perm,
                       const int *finfo, cplx<double> *X, int max_refine, double tol, char *work,
-                      const Workspace &ws, hp_solve_info *info, hipStream_t st) {
+                      const Workspace &ws, hp_solve_info *info, hipStream_t st, const SchurOps *sch = nullptr) {
   const int nc = sys->nc, nr = sys->nr;
   const long n = (long)nc * nr;
   const long cnt = n * nc;
@@ -427,7 +441,8 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
     }
   };
   // initial solve
-  hipLaunchKernelGGL(rhs_from_perm_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, nc, nr, perm, sys->q, Y);
+  hipLaunchKernelGGL(rhs_from_perm_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, nc, nr, perm,
+                     sch ? sch->qt : sys->q, Y);
   HP_CHECK_LAUNCH();
   if ((rc = solve_y(true))) return rc;
   hipLaunchKernelGGL(widen_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, cnt, Ysol, X);
@@ -501,9 +516,25 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
       corr_prev = corr;
     }
     if (it >= max_refine) return HP_ERR_NOCONV;
+    // the right-hand side of the correction solve and its column scales
+    const cplx<double> *rsrc = Rr;
+    const unsigned long long *rscale = smax;
+    if (sch) {
+      if ((rc = gemm_set_batched<double>(nr, nc, nr, 1.0, sch->kc, nr, 0, Rr, nc, (long)nr * nc, sch->rt, nc,
+                                         (long)nr * nc, nc, st)))
+        return rc;
+      TraceScope ts(TR_REFINE, st, 0.0, 16.0 * cnt);
+      hipLaunchKernelGGL(zero_u64_kernel, dim3(nblk(nc)), dim3(256), 0, st, sch->tmax, nc);
+      HP_CHECK_LAUNCH();
+      hipLaunchKernelGGL(colmax_kernel, dim3(cm_blocks), dim3(256), 0, st, n, nc, (const cplx<double> *)sch->rt,
+                         sch->tmax, (const cplx<double> *)nullptr, (unsigned long long *)nullptr);
+      HP_CHECK_LAUNCH();
+      rsrc = sch->rt;
+      rscale = sch->tmax;
+    }
     {
       TraceScope ts(TR_REFINE, st, 0.0, 16.0 * cnt + sizeof(cplx<T>) * (double)cnt);
-      hipLaunchKernelGGL(scale_perm_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, n, nc, perm, Rr, smax, Y);
+      hipLaunchKernelGGL(scale_perm_kernel<T>, dim3(nblk(cnt)), dim3(256), 0, st, n, nc, perm, rsrc, rscale, Y);
       HP_CHECK_LAUNCH();
     }
     if ((rc = solve_y(false))) return rc;
@@ -511,7 +542,7 @@ static int solve_impl(const hp_system *sys, double E, const cplx<T> *LU, long ld
       TraceScope ts(TR_REFINE, st, 0.0, (sizeof(cplx<T>) + 32.0) * (double)cnt);
       hipLaunchKernelGGL(zero_u64_kernel, dim3(nblk(nc)), dim3(256), 0, st, dmax, nc);
       HP_CHECK_LAUNCH();
-      hipLaunchKernelGGL(update_kernel<T>, dim3(cm_blocks), dim3(256), 0, st, n, nc, Ysol, smax, X, dmax);
+      hipLaunchKernelGGL(update_kernel<T>, dim3(cm_blocks), dim3(256), 0, st, n, nc, Ysol, rscale, X, dmax);
       HP_CHECK_LAUNCH();
     }
   }
@@ -555,6 +586,64 @@ extern "C" int hp_solve(const hp_system *sys, double E, int prec, const void *LU
                               max_refine, tol, (char *)work, ws, info, st);
   return solve_impl<float>(sys, E, (const cplx<float> *)LU, lda, perm, info_factor, (cplx<double> *)X,
                            max_refine, tol, (char *)work, ws, info, st);
+}
+
+// Woodbury-kinetic solves: workspace = hp_solve's, then rt, kc, qt, tmax.
+static size_t schur_extra_off(int n, int nrhs, int prec) { return plan_workspace(n, nrhs, prec).total; }
+static size_t schur_bytes(int n, int nrhs, int prec) {
+  const int nr = n / nrhs;
+  return schur_extra_off(n, nrhs, prec) + align_up((size_t)n * nrhs * sizeof(cplx<double>), 256) +
+         align_up((size_t)nr * nr * sizeof(cplx<double>), 256) + align_up((size_t)nr * sizeof(double), 256) +
+         align_up((size_t)nrhs * sizeof(unsigned long long), 256);
+}
+
+extern "C" size_t hp_schur_workspace_bytes(int n, int nrhs, int prec) {
+  if (n < 1 || nrhs < 1 || n % nrhs != 0 || !prec_ok(prec)) return 0;
+  return schur_bytes(n, nrhs, prec);
+}
+
+// kc = kinv / h as complex128, qt = kinv q / h.
+__global__ void schur_setup_kernel(int nr, double inv_h, const double *__restrict__ kinv, const double *__restrict__ q,
+                                   cplx<double> *__restrict__ kc, double *__restrict__ qt) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nr * nr) kc[e] = cplx<double>{kinv[e] * inv_h, 0.0};
+  if (e < nr) {
+    double s = 0.0;
+    for (int j = 0; j < nr; ++j) s += kinv[(long)e * nr + j] * q[j];
+    qt[e] = s * inv_h;
+  }
+}
+
+extern "C" int hp_solve_schur(const hp_system *sys, double E, int prec, const double *kinv, const void *LU, long lda,
+                              const int *perm, const int *info_factor, double *X, int max_refine, double tol,
+                              void *work, size_t work_bytes, hp_solve_info *info, void *stream) {
+  if (!sys_ok(sys) || !kinv || !LU || !perm || !X || !work) return HP_ERR_ARG;
+  if (sys->vnl) return HP_ERR_UNSUPPORTED;
+  const long n = (long)sys->nc * sys->nr;
+  if (lda < n || !prec_ok(prec) || max_refine < 0) return HP_ERR_ARG;
+  if (work_bytes < schur_bytes((int)n, sys->nc, prec)) return HP_ERR_WORKSPACE;
+  Workspace ws = plan_workspace((int)n, sys->nc, prec);
+  hipStream_t st = (hipStream_t)stream;
+  const int nr = sys->nr, nc = sys->nc;
+  char *extra = (char *)work + schur_extra_off((int)n, nc, prec);
+  SchurOps so;
+  so.rt = (cplx<double> *)extra;
+  extra += align_up((size_t)n * nc * sizeof(cplx<double>), 256);
+  cplx<double> *kc = (cplx<double> *)extra;
+  so.kc = kc;
+  extra += align_up((size_t)nr * nr * sizeof(cplx<double>), 256);
+  double *qt = (double *)extra;
+  so.qt = qt;
+  extra += align_up((size_t)nr * sizeof(double), 256);
+  so.tmax = (unsigned long long *)extra;
+  hipLaunchKernelGGL(schur_setup_kernel, dim3(nblk((long)nr * nr)), dim3(256), 0, st, nr, 1.0 / sys->hbar2_2mu, kinv,
+                     sys->q, kc, qt);
+  HP_CHECK_LAUNCH();
+  if (prec == HP_C128)
+    return solve_impl<double>(sys, E, (const cplx<double> *)LU, lda, perm, info_factor, (cplx<double> *)X,
+                              max_refine, tol, (char *)work, ws, info, st, &so);
+  return solve_impl<float>(sys, E, (const cplx<float> *)LU, lda, perm, info_factor, (cplx<double> *)X, max_refine,
+                           tol, (char *)work, ws, info, st, &so);
 }
 
 extern "C" int hp_set_solve_graphs(int on) {

@@ -62,7 +62,8 @@ EXPORTS = ["hp_mesh", "hp_workspace_bytes", "hp_build_matrix", "hp_factor", "hp_
            "hp_build_info", "hp_strerror", "hp_trace_enable", "hp_trace_read", "hp_last_error",
            "hp_gemm_sub", "hp_gemm_h3_sub", "hp_set_concurrency", "hp_set_solve_graphs", "hp_batch_workspace_bytes", "hp_batch_build",
            "hp_batch_factor", "hp_batch_factor_stepped", "hp_batch_solve_init", "hp_batch_refine_step", "hp_batch_active",
-           "hp_batch_status", "hp_batch_rmatrix", "hp_batch_smatrix"]
+           "hp_batch_status", "hp_batch_rmatrix", "hp_batch_smatrix", "hp_kinetic_inverse",
+           "hp_schur_workspace_bytes", "hp_build_schur", "hp_solve_schur"]
 
 _lib = None
 
@@ -100,6 +101,15 @@ def lib() -> ctypes.CDLL:
     L.hp_solve.argtypes = [P(HpSystem), c_double, c_int, c_void_p, c_long, c_void_p, c_void_p,
                            c_void_p, c_int, c_double, c_void_p, c_size_t, P(HpSolveInfo), c_void_p]
     L.hp_solve.restype = c_int
+    L.hp_kinetic_inverse.argtypes = [c_int, c_double, c_void_p]
+    L.hp_kinetic_inverse.restype = c_int
+    L.hp_schur_workspace_bytes.argtypes = [c_int, c_int, c_int]
+    L.hp_schur_workspace_bytes.restype = c_size_t
+    L.hp_build_schur.argtypes = [P(HpSystem), c_double, c_int, c_void_p, c_void_p, c_long, c_void_p]
+    L.hp_build_schur.restype = c_int
+    L.hp_solve_schur.argtypes = [P(HpSystem), c_double, c_int, c_void_p, c_void_p, c_long, c_void_p, c_void_p,
+                                 c_void_p, c_int, c_double, c_void_p, c_size_t, P(HpSolveInfo), c_void_p]
+    L.hp_solve_schur.restype = c_int
     L.hp_lu_solve.argtypes = [c_int, c_int, c_int, c_void_p, c_long, c_void_p, c_void_p, c_long,
                               c_void_p, c_size_t, c_void_p]
     L.hp_lu_solve.restype = c_int
@@ -203,6 +213,17 @@ def hp_workspace_bytes(n: int, nrhs: int, prec: int) -> int:
     return int(lib().hp_workspace_bytes(n, nrhs, prec))
 
 
+def hp_kinetic_inverse(nr: int, a: float) -> np.ndarray:
+    """The inverse of hp_mesh's tl, nr x nr host array (binary128 elimination)."""
+    out = np.zeros((nr, nr))
+    _check(lib().hp_kinetic_inverse(nr, a, out.ctypes.data), "hp_kinetic_inverse")
+    return out
+
+
+def hp_schur_workspace_bytes(n: int, nrhs: int, prec: int) -> int:
+    return int(lib().hp_schur_workspace_bytes(n, nrhs, prec))
+
+
 def hp_coulomb(l: int, eta: float, rho: float) -> np.ndarray:
     out = np.zeros(4)
     _check(lib().hp_coulomb(int(l), float(eta), float(rho), out.ctypes.data), "hp_coulomb")
@@ -234,6 +255,23 @@ def hp_solve(sys: HpSystem, E: float, prec: int, LU, lda: int, perm, info_factor
                           work.numel() * work.element_size(), ctypes.byref(info), _stream(stream))
     if check and code not in (HP_OK, HP_ERR_NOCONV, HP_ERR_SINGULAR):
         raise HprmatError(code, "hp_solve")
+    return code, info
+
+
+def hp_build_schur(sys: HpSystem, E: float, prec: int, kinv, S, lds: int, stream=None) -> None:
+    _check(lib().hp_build_schur(ctypes.byref(sys), float(E), prec, _ptr(kinv), _ptr(S), lds, _stream(stream)),
+           "hp_build_schur")
+
+
+def hp_solve_schur(sys: HpSystem, E: float, prec: int, kinv, LU, lda: int, perm, info_factor, X,
+                   max_refine: int, tol: float, work, stream=None, check: bool = True):
+    """As hp_solve, through the factors of the Woodbury-kinetic matrix."""
+    info = HpSolveInfo()
+    code = lib().hp_solve_schur(ctypes.byref(sys), float(E), prec, _ptr(kinv), _ptr(LU), lda, _ptr(perm),
+                                _ptr(info_factor), _ptr(X), int(max_refine), float(tol), _ptr(work),
+                                work.numel() * work.element_size(), ctypes.byref(info), _stream(stream))
+    if check and code not in (HP_OK, HP_ERR_NOCONV, HP_ERR_SINGULAR):
+        raise HprmatError(code, "hp_solve_schur")
     return code, info
 
 

@@ -58,11 +58,20 @@ class DeviceSystem:
                     or vnl.device != self.r.device):
                 raise ValueError("vnl must be a contiguous complex128 (N, N) tensor on the system's device")
         self.vnl = vnl
+        self._kinv = None
         self.sys = H.HpSystem(self.nc, self.nr, float(params.a), float(params.hbar2_2mu),
                               float(params.z1z2) * E2, self.r.data_ptr(), self.q.data_ptr(),
                               self.tl.data_ptr(), self.l.data_ptr(), self.eps.data_ptr(),
                               self.v.data_ptr(), self.w.data_ptr(),
                               vnl.data_ptr() if vnl is not None else None)
+
+
+    @property
+    def kinv(self) -> torch.Tensor:
+        """The kinetic inverse of the Woodbury-kinetic form (device, made once)."""
+        if self._kinv is None:
+            self._kinv = torch.from_numpy(H.hp_kinetic_inverse(self.nr, float(self.params.a))).to(self.device)
+        return self._kinv
 
 
 @dataclass
@@ -81,13 +90,17 @@ class EnergyResult:
 class Solver:
     """Buffers for one system in one working precision: HP_C128, HP_C64, or
     HP_C64H (FP32 factors whose trailing updates run on the FP16 matrix cores
-    under row and column scaling)."""
+    under row and column scaling).  With schur=True the factored matrix is
+    the Woodbury-kinetic S(E) = I + K_diag^-1 V (the paper's Type 3, Sec. 3.3)
+    instead of C(E); the refinement (both precisions) works on C(E)'s FP64
+    residual, and max_refine=0 gives the paper's unrefined Type 3 solve."""
 
     def __init__(self, dsys: DeviceSystem, prec: int = H.HP_C64, ld: int | None = None,
-                 fallback: bool = True):
+                 fallback: bool = True, schur: bool = False):
         self.d = dsys
         self.prec = prec
         self.fallback = fallback
+        self.schur = schur
         n, nc = dsys.n, dsys.nc
         self.ld = ld or n
         dev = dsys.device
@@ -99,25 +112,36 @@ class Solver:
         self.X = torch.empty((n, nc), dtype=torch.complex128, device=dev)
         self.R = torch.empty((nc, nc), dtype=torch.complex128, device=dev)
         self.S = torch.empty((nc, nc), dtype=torch.complex128, device=dev)
-        self.work = torch.empty(H.hp_workspace_bytes(n, nc, prec), dtype=torch.uint8, device=dev)
+        wb = H.hp_schur_workspace_bytes(n, nc, prec) if schur else H.hp_workspace_bytes(n, nc, prec)
+        self.work = torch.empty(wb, dtype=torch.uint8, device=dev)
         self.swork = torch.empty(H.hp_workspace_bytes(nc, nc, H.HP_C128), dtype=torch.uint8, device=dev)
         self._fp64 = None
 
     def factor(self, E: float) -> None:
-        H.hp_build_matrix(self.d.sys, E, self.prec, self.A, self.ld)
+        if self.schur:
+            H.hp_build_schur(self.d.sys, E, self.prec, self.d.kinv, self.A, self.ld)
+        else:
+            H.hp_build_matrix(self.d.sys, E, self.prec, self.A, self.ld)
         H.hp_factor(self.d.n, self.prec, self.A, self.ld, self.ipiv, self.perm, self.info, self.work)
 
     def solve(self, E: float, max_refine: int, tol: float):
+        if self.schur:
+            return H.hp_solve_schur(self.d.sys, E, self.prec, self.d.kinv, self.A, self.ld, self.perm, self.info,
+                                    self.X, max_refine, tol, self.work)
         return H.hp_solve(self.d.sys, E, self.prec, self.A, self.ld, self.perm, self.info, self.X,
                           max_refine, tol, self.work)
 
     def run(self, E: float, max_refine: int = 30, tol: float = 0.0, smatrix: bool = True) -> EnergyResult:
+        """max_refine applies to FP32 factors and to the Woodbury-kinetic form;
+        a plain FP64 factorization is solved once."""
         self.factor(E)
-        code, info = self.solve(E, max_refine if self.prec != H.HP_C128 else 0, tol)
+        refine = max_refine if (self.prec != H.HP_C128 or self.schur) else 0
+        code, info = self.solve(E, refine, tol)
         iterations, backward = info.iterations, info.residual
         used_fallback = False
         if code != H.HP_OK:
-            if not (self.fallback and self.prec != H.HP_C128 and code in (H.HP_ERR_NOCONV, H.HP_ERR_SINGULAR)):
+            if not (self.fallback and (self.prec != H.HP_C128 or self.schur)
+                    and code in (H.HP_ERR_NOCONV, H.HP_ERR_SINGULAR)):
                 raise H.HprmatError(code, "hp_solve")
             if self._fp64 is None:
                 self._fp64 = Solver(self.d, H.HP_C128, fallback=False)

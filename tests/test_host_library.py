@@ -144,3 +144,35 @@ def test_batch_layer_rejects_nonlocal_systems(H):
                       pot=lambda r: np.zeros((len(r), 1, 1), dtype=complex), nlpot=separable_nonlocal(1.0, 1.0))
     with pytest.raises(ValueError, match="non-local"):
         batch.Bucket([sp], [1.0], [0], H.HP_C128, device="cpu")
+
+
+@pytest.mark.parametrize("nr,a", [(7, 5.0), (60, 20.0)])
+def test_kinetic_inverse_is_the_rounded_exact_inverse(H, nr, a):
+    """hp_kinetic_inverse returns the inverse of hp_mesh's rounded tl to
+    within an ulp or two, against a 40-digit mpmath inverse of the same
+    matrix (double precision would lose about log10(cond) digits)."""
+    import mpmath
+    tl = H.hp_mesh(nr, a)[3]
+    ki = H.hp_kinetic_inverse(nr, a)
+    with mpmath.workdps(40):
+        ref = mpmath.matrix(tl.tolist()) ** -1
+        ref = np.array([[float(ref[i, j]) for j in range(nr)] for i in range(nr)])
+    assert np.max(np.abs(ki - ref)) <= 4e-16 * np.max(np.abs(ref))
+    assert np.linalg.cond(tl) > (1e6 if nr == 60 else 1.0)
+
+
+def test_woodbury_arguments_checked_without_device(H):
+    """The Woodbury-kinetic entry points refuse non-local systems and bad
+    arguments before any launch."""
+    L = H.lib()
+    s = H.HpSystem(2, 3, 5.0, 20.0, 0.0, 1, 1, 1, 1, 1, 1, 1, 1)  # vnl set
+    assert L.hp_build_schur(ctypes.byref(s), 1.0, H.HP_C64, 1, 1, 6, None) == H.HP_ERR_UNSUPPORTED
+    assert L.hp_solve_schur(ctypes.byref(s), 1.0, H.HP_C64, 1, 1, 6, 1, None, 1, 0, 0.0, 1, 1 << 30, None,
+                            None) == H.HP_ERR_UNSUPPORTED
+    s.vnl = None
+    assert L.hp_build_schur(ctypes.byref(s), 1.0, H.HP_C64, None, 1, 6, None) == H.HP_ERR_ARG
+    assert L.hp_build_schur(ctypes.byref(s), 1.0, H.HP_C64, 1, 1, 5, None) == H.HP_ERR_ARG
+    assert H.hp_schur_workspace_bytes(6, 4, H.HP_C64) == 0  # n not a multiple of nrhs
+    assert H.hp_schur_workspace_bytes(6, 2, H.HP_C64) > H.hp_workspace_bytes(6, 2, H.HP_C64)
+    assert L.hp_solve_schur(ctypes.byref(s), 1.0, H.HP_C64, 1, 1, 6, 1, None, 1, 0, 0.0, 1, 16, None,
+                            None) == H.HP_ERR_WORKSPACE
