@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-closed", action="store_true", help="skip the closed-channel matching block")
     ap.add_argument("--no-nonlocal", action="store_true", help="skip the non-local potential block")
+    ap.add_argument("--no-woodbury", action="store_true", help="skip the Woodbury-kinetic (Type 3) block")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-systems", type=int, default=512)
     ap.add_argument("--served-requests", type=int, default=24)
@@ -527,6 +528,8 @@ def main():
         out["closed_channels"] = closed_channels(sp, H, P, torch)
     if not args.no_nonlocal:
         out["nonlocal"] = nonlocal_block(sp, H, P, torch)
+    if not args.no_woodbury:
+        out["woodbury_kinetic"] = woodbury_block(sp, H, P, torch)
     if not args.no_batched:
         out["batched"] = batched(args, H, torch)
     if not args.no_served:
