@@ -386,15 +386,22 @@ int hp_batch_status(int count, const void *work, int *status, int *iters, void *
 
 /* Collision matrix of every system from its R (R and S: device, nc x nc
  * complex128 blocks at r_off), by the matching of hp_smatrix, one workgroup
- * per system: channel functions, Z = [O - Rt O' | I - Rt I'], Gaussian
+ * per system, all in FP64: channel functions (Coulomb functions of the open
+ * channels, decaying-solution log-derivatives L_c of the closed ones, as
+ * hp_smatrix); with closed channels the open channels' effective R-matrix
+ * R_eff = R_oo + R_oc L (I - R_cc L)^-1 R_co by Gaussian elimination with
+ * partial pivoting; then Z = [O - Rt O' | I - Rt I'] over the open channels,
  * elimination with partial pivoting (largest |Re| + |Im|) and back
- * substitution, all in FP64.  status: device int[count], per system 0 ok,
- * 1 a closed channel (E <= eps_c), 2 a Coulomb continued fraction did not
- * converge, 3 an exactly zero pivot, 4 more than 512 channels, 5 a non-local
- * system (sys.vnl != NULL); S of a system with status != 0 is not written.  sum_nc2 = sum of nc^2 over the systems
- * (host), nc_max = the largest nc (host, at most 512, else
- * HP_ERR_UNSUPPORTED).  work: device, at least 32 * sum_nc2 bytes.
- * Asynchronous, no host synchronisation (may be captured in a graph). */
+ * substitution.  S is zero in closed rows and columns.  status: device
+ * int[count], per system 0 ok, 1 no open channel or E exactly at a
+ * threshold, 2 a Coulomb continued fraction (or a closed channel's
+ * integration) did not converge, 3 an exactly zero pivot, 4 more than 512
+ * channels, 5 a non-local system (sys.vnl != NULL); S of a system with status
+ * 1, 2, 4 or 5 is not written, with status 3 it holds no result.
+ * sum_nc2 = sum of nc^2 over the systems (host), nc_max = the largest nc
+ * (host, at most 512, else HP_ERR_UNSUPPORTED).  work: device, at least
+ * 32 * sum_nc2 bytes.  Asynchronous, no host synchronisation (may be
+ * captured in a graph). */
 int hp_batch_smatrix(int count, const hp_batch_item *items, const double *R, double *S, int *status,
                      long sum_nc2, int nc_max, void *work, size_t work_bytes, void *stream);
 

@@ -375,7 +375,7 @@ class Batch:
                     self.fallbacks.append(g)
                     continue
                 if sst[k] != 0:
-                    code = H.HP_ERR_UNSUPPORTED if sst[k] in (1, 4) else (
+                    code = H.HP_ERR_UNSUPPORTED if sst[k] in (1, 4, 5) else (
                         H.HP_ERR_NOCONV if sst[k] == 2 else H.HP_ERR_SINGULAR)
                     raise H.HprmatError(code, f"hp_batch_smatrix, system {g}")
                 c = int(b.nc[k])

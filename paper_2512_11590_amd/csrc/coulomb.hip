@@ -359,92 +359,17 @@ extern "C" int hp_coulomb_device(int nch, const int *l, const double *eta, const
 
 namespace hp {
 
-// Collision matrices of a batch of systems (see hp_batch_smatrix), one
-// workgroup per system: the channel functions into LDS, then
-// Z = [ZO | ZI] (nc x 2nc, in the workspace at 2 r_off) as zmat_kernel builds
-// them, Gaussian elimination with partial pivoting (largest |Re| + |Im|,
-// smallest row on ties) on Z, and back substitution of the right half into
-// S (at r_off).  status[s]: 0 ok, 1 a closed channel, 2 a continued fraction
-// did not converge, 3 an exactly zero pivot, 4 more than 512 channels,
-// 5 a non-local system (its R did not come from the batched solves).
-constexpr int kBatchSmatMaxChannels = 512;
-
-__global__ __launch_bounds__(256) void batch_smatrix_kernel(int count, const hp_batch_item *__restrict__ items,
-                                                            const cplx<double> *__restrict__ R,
-                                                            cplx<double> *__restrict__ S, cplx<double> *__restrict__ Z,
-                                                            int *__restrict__ status) {
-  __shared__ double fg[4 * kBatchSmatMaxChannels];
-  __shared__ double sqrho[kBatchSmatMaxChannels];
-  __shared__ double sv[4];
-  __shared__ int sr[4];
-  __shared__ int s_bad;
-  const int sidx = blockIdx.x;
-  if (sidx >= count) return;
-  const hp_batch_item it = items[sidx];
-  const hp_system &sys = it.sys;
-  const int nc = sys.nc, tid = threadIdx.x;
-  if (nc > kBatchSmatMaxChannels) {  // the channel table would not fit
-    if (tid == 0) status[sidx] = 4;
-    return;
-  }
-  if (sys.vnl) {
-    if (tid == 0) status[sidx] = 5;
-    return;
-  }
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
-  for (int c = tid; c < nc; c += 256) {
-    const double ec = it.E - sys.eps[c];
-    if (!(ec > 0.0)) {
-      atomicMax(&s_bad, 1);
-      fg[4 * c] = fg[4 * c + 1] = fg[4 * c + 2] = fg[4 * c + 3] = 0.0;
-      sqrho[c] = 0.0;
-      continue;
-    }
-    const double k = sqrt(ec / sys.hbar2_2mu);
-    const double eta = sys.z1z2e2 / (2.0 * sys.hbar2_2mu * k);
-    const double rho = k * sys.a;
-    const CoulombOut o = coulomb_fg(sys.l[c], eta, rho);
-    fg[4 * c + 0] = o.F;
-    fg[4 * c + 1] = o.Fp;
-    fg[4 * c + 2] = o.G;
-    fg[4 * c + 3] = o.Gp;
-    sqrho[c] = sqrt(rho);
-    if (o.status) atomicMax(&s_bad, 2);
-  }
-  __syncthreads();
-  if (s_bad) {
-    if (tid == 0) status[sidx] = s_bad;
-    return;
-  }
-  const cplx<double> *Rs = R + it.r_off;
-  cplx<double> *z = Z + 2 * it.r_off;  // nc x 2nc, row-major
-  const int w2 = 2 * nc;
-  for (int e = tid; e < nc * nc; e += 256) {
-    const int c = e / nc, cp = e - c * nc;
-    const double sc = sqrho[c] * sqrho[cp];
-    const cplx<double> rt{sc * Rs[e].re, sc * Rs[e].im};
-    const double F = fg[4 * cp], Fp = fg[4 * cp + 1], G = fg[4 * cp + 2], Gp = fg[4 * cp + 3];
-    cplx<double> zo = cmul(rt, cplx<double>{Gp, Fp});
-    cplx<double> zi = cmul(rt, cplx<double>{Gp, -Fp});
-    zo = cplx<double>{-zo.re, -zo.im};
-    zi = cplx<double>{-zi.re, -zi.im};
-    if (c == cp) {
-      zo.re += G;
-      zo.im += F;
-      zi.re += G;
-      zi.im -= F;
-    }
-    z[(long)c * w2 + cp] = zo;
-    z[(long)c * w2 + nc + cp] = zi;
-  }
-  __syncthreads();
-  int zero = 0;
-  for (int k = 0; k < nc; ++k) {
+// Gaussian elimination with partial pivoting (largest |Re| + |Im|, smallest
+// row on ties) of the first n columns of the row-major n x w matrix z, the
+// other columns carried along; all 256 threads of the workgroup take part.
+// Returns 1 on an exactly zero pivot.
+__device__ static int block_eliminate(cplx<double> *z, int n, int w, double *sv, int *sr) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < n; ++k) {
     double best = -1.0;
     int brow = INT_MAX;
-    for (int r = k + tid; r < nc; r += 256) {
-      const double v = cabs1(z[(long)r * w2 + k]);
+    for (int r = k + tid; r < n; r += 256) {
+      const double v = cabs1(z[(long)r * w + k]);
       if (v > best || (v == best && r < brow)) {
         best = v;
         brow = r;
@@ -471,40 +396,206 @@ __global__ __launch_bounds__(256) void batch_smatrix_kernel(int count, const hp_
         brow = sr[q];
       }
     __syncthreads();
-    if (!(best > 0.0)) {
-      zero = 1;
-      break;
-    }
+    if (!(best > 0.0)) return 1;
     if (brow != k)
-      for (int j = k + tid; j < w2; j += 256) {
-        const cplx<double> x = z[(long)k * w2 + j];
-        z[(long)k * w2 + j] = z[(long)brow * w2 + j];
-        z[(long)brow * w2 + j] = x;
+      for (int j = k + tid; j < w; j += 256) {
+        const cplx<double> x = z[(long)k * w + j];
+        z[(long)k * w + j] = z[(long)brow * w + j];
+        z[(long)brow * w + j] = x;
       }
     __syncthreads();
-    const cplx<double> inv = crcp(z[(long)k * w2 + k]);
+    const cplx<double> inv = crcp(z[(long)k * w + k]);
     // rows below k: l = z_ik / z_kk, z_ij -= l z_kj (j > k); one thread per (i, j)
-    const int rows = nc - k - 1, cols = w2 - k - 1;
+    const int rows = n - k - 1, cols = w - k - 1;
     for (int e = tid; e < rows * cols; e += 256) {
       const int i = k + 1 + e / cols, j = k + 1 + e % cols;
-      const cplx<double> l = cmul(z[(long)i * w2 + k], inv);
-      z[(long)i * w2 + j] = cfms(z[(long)i * w2 + j], l, z[(long)k * w2 + j]);
+      const cplx<double> l = cmul(z[(long)i * w + k], inv);
+      z[(long)i * w + j] = cfms(z[(long)i * w + j], l, z[(long)k * w + j]);
     }
     __syncthreads();
   }
-  if (zero) {
+  return 0;
+}
+
+// Back substitution after block_eliminate: out = U^-1 (right part of z,
+// nrhs columns), one right-hand column per thread; row i / column cp of the
+// result is stored at out[rmap[i] * ldo + cmap[cp]] (maps may be null for
+// the identity).
+__device__ static void block_back_substitute(const cplx<double> *z, int n, int w, int nrhs, cplx<double> *out,
+                                             long ldo, const int *rmap, const int *cmap) {
+  for (int cp = threadIdx.x; cp < nrhs; cp += 256) {
+    const long oc = cmap ? cmap[cp] : cp;
+    for (int i = n - 1; i >= 0; --i) {
+      cplx<double> acc = z[(long)i * w + n + cp];
+      for (int j = i + 1; j < n; ++j) acc = cfms(acc, z[(long)i * w + j], out[(rmap ? rmap[j] : j) * ldo + oc]);
+      out[(rmap ? rmap[i] : i) * ldo + oc] = cdiv(acc, z[(long)i * w + i]);
+    }
+  }
+}
+
+// Collision matrices of a batch of systems (see hp_batch_smatrix), one
+// workgroup per system: the channel functions into LDS (Coulomb functions of
+// the open channels, decaying-solution log-derivatives L_c of the closed
+// ones); with closed channels, Y = (I - R_cc L)^-1 R_co by elimination in the
+// workspace and R_eff = R_oo + R_oc L Y into S's block (compact, no x no);
+// then Z = [ZO | ZI] over the open channels from R (or R_eff) in the
+// workspace at 2 r_off, Gaussian elimination with partial pivoting, and back
+// substitution into S (at r_off), whose closed rows and columns are zero.
+// status[s]: 0 ok, 1 no open channel or E at a threshold, 2 a continued
+// fraction or a closed channel's integration failed, 3 an exactly zero pivot,
+// 4 more than 512 channels, 5 a non-local system (its R did not come from the
+// batched solves).
+constexpr int kBatchSmatMaxChannels = 512;
+
+__global__ __launch_bounds__(256) void batch_smatrix_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                            const cplx<double> *__restrict__ R,
+                                                            cplx<double> *__restrict__ S, cplx<double> *__restrict__ Z,
+                                                            int *__restrict__ status) {
+  __shared__ double fg[4 * kBatchSmatMaxChannels];
+  __shared__ double sqrho[kBatchSmatMaxChannels];
+  __shared__ int oidx[kBatchSmatMaxChannels], cidx[kBatchSmatMaxChannels];
+  __shared__ double sv[4];
+  __shared__ int sr[4];
+  __shared__ int s_bad, s_no, s_ncl;
+  const int sidx = blockIdx.x;
+  if (sidx >= count) return;
+  const hp_batch_item it = items[sidx];
+  const hp_system &sys = it.sys;
+  const int nc = sys.nc, tid = threadIdx.x;
+  if (nc > kBatchSmatMaxChannels) {  // the channel table would not fit
+    if (tid == 0) status[sidx] = 4;
+    return;
+  }
+  if (sys.vnl) {
+    if (tid == 0) status[sidx] = 5;
+    return;
+  }
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int c = tid; c < nc; c += 256) {
+    const double ec = it.E - sys.eps[c];
+    fg[4 * c] = fg[4 * c + 1] = fg[4 * c + 2] = fg[4 * c + 3] = 0.0;
+    sqrho[c] = 0.0;
+    if (!(ec > 0.0)) {
+      if (!(ec < 0.0)) {  // at the threshold (or NaN)
+        atomicMax(&s_bad, 1);
+        continue;
+      }
+      const double kappa = sqrt(-ec / sys.hbar2_2mu);
+      const double eta = sys.z1z2e2 / (2.0 * sys.hbar2_2mu * kappa);
+      int bad = 0;
+      fg[4 * c] = closed_logderiv(sys.l[c], eta, kappa * sys.a, &bad);
+      if (bad) atomicMax(&s_bad, 2);
+      continue;
+    }
+    const double k = sqrt(ec / sys.hbar2_2mu);
+    const double eta = sys.z1z2e2 / (2.0 * sys.hbar2_2mu * k);
+    const double rho = k * sys.a;
+    const CoulombOut o = coulomb_fg(sys.l[c], eta, rho);
+    fg[4 * c + 0] = o.F;
+    fg[4 * c + 1] = o.Fp;
+    fg[4 * c + 2] = o.G;
+    fg[4 * c + 3] = o.Gp;
+    sqrho[c] = sqrt(rho);
+    if (o.status) atomicMax(&s_bad, 2);
+  }
+  __syncthreads();
+  if (tid == 0) {  // open and closed channel lists, in channel order
+    int no = 0, ncl = 0;
+    for (int c = 0; c < nc; ++c) {
+      if (it.E - sys.eps[c] > 0.0)
+        oidx[no++] = c;
+      else
+        cidx[ncl++] = c;
+    }
+    s_no = no;
+    s_ncl = ncl;
+    if (no == 0) s_bad = max(s_bad, 1);
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) status[sidx] = s_bad;
+    return;
+  }
+  const int no = s_no, ncl = s_ncl;
+  const cplx<double> *Rs = R + it.r_off;
+  cplx<double> *Ss = S + it.r_off;
+  cplx<double> *z = Z + 2 * it.r_off;  // 2 nc^2 complex values of workspace
+  // the open channels' R: R itself, or R_eff in S's block (ld no)
+  const cplx<double> *Ro = Rs;
+  long ldr = nc;
+  if (ncl > 0) {
+    // [I - R_cc L | R_co] (ncl x (ncl + no)), then Y after it (ncl x no)
+    const int wa = ncl + no;
+    for (int e = tid; e < ncl * wa; e += 256) {
+      const int i = e / wa, j = e - i * wa;
+      cplx<double> m;
+      if (j < ncl) {
+        const double Lj = fg[4 * cidx[j]];
+        const cplx<double> r = Rs[(long)cidx[i] * nc + cidx[j]];
+        m = cplx<double>{-r.re * Lj, -r.im * Lj};
+        if (i == j) m.re += 1.0;
+      } else {
+        m = Rs[(long)cidx[i] * nc + oidx[j - ncl]];
+      }
+      z[e] = m;
+    }
+    __syncthreads();
+    if (block_eliminate(z, ncl, wa, sv, sr)) {
+      if (tid == 0) status[sidx] = 3;
+      return;
+    }
+    cplx<double> *Y = z + (long)ncl * wa;
+    block_back_substitute(z, ncl, wa, no, Y, no, nullptr, nullptr);
+    __syncthreads();
+    for (int e = tid; e < no * no; e += 256) {
+      const int i = e / no, j = e - i * no;
+      cplx<double> acc = Rs[(long)oidx[i] * nc + oidx[j]];
+      for (int k = 0; k < ncl; ++k) {
+        const double Lk = fg[4 * cidx[k]];
+        const cplx<double> r = Rs[(long)oidx[i] * nc + cidx[k]];
+        const cplx<double> y = Y[(long)k * no + j];
+        acc.re += Lk * (r.re * y.re - r.im * y.im);
+        acc.im += Lk * (r.re * y.im + r.im * y.re);
+      }
+      Ss[e] = acc;
+    }
+    __syncthreads();
+    Ro = Ss;
+    ldr = no;
+  }
+  // Z over the open channels (zmat_kernel's formula)
+  const int w2 = 2 * no;
+  for (int e = tid; e < no * no; e += 256) {
+    const int i = e / no, j = e - i * no;
+    const int c = ncl ? oidx[i] : i, cp = ncl ? oidx[j] : j;
+    const double sc = sqrho[c] * sqrho[cp];
+    const cplx<double> rr = Ro[(long)i * ldr + j];
+    const cplx<double> rt{sc * rr.re, sc * rr.im};
+    const double F = fg[4 * cp], Fp = fg[4 * cp + 1], G = fg[4 * cp + 2], Gp = fg[4 * cp + 3];
+    cplx<double> zo = cmul(rt, cplx<double>{Gp, Fp});
+    cplx<double> zi = cmul(rt, cplx<double>{Gp, -Fp});
+    zo = cplx<double>{-zo.re, -zo.im};
+    zi = cplx<double>{-zi.re, -zi.im};
+    if (i == j) {
+      zo.re += G;
+      zo.im += F;
+      zi.re += G;
+      zi.im -= F;
+    }
+    z[(long)i * w2 + j] = zo;
+    z[(long)i * w2 + no + j] = zi;
+  }
+  __syncthreads();  // R_eff (in S) is consumed
+  if (ncl > 0)
+    for (int e = tid; e < nc * nc; e += 256) Ss[e] = cplx<double>{0.0, 0.0};
+  __syncthreads();
+  if (block_eliminate(z, no, w2, sv, sr)) {
     if (tid == 0) status[sidx] = 3;
     return;
   }
-  // back substitution: S = U^-1 (right half), one right-hand column per thread
-  cplx<double> *Ss = S + it.r_off;
-  for (int cp = tid; cp < nc; cp += 256) {
-    for (int i = nc - 1; i >= 0; --i) {
-      cplx<double> acc = z[(long)i * w2 + nc + cp];
-      for (int j = i + 1; j < nc; ++j) acc = cfms(acc, z[(long)i * w2 + j], Ss[(long)j * nc + cp]);
-      Ss[(long)i * nc + cp] = cdiv(acc, z[(long)i * w2 + i]);
-    }
-  }
+  // back substitution: S_oo = U^-1 (right half), scattered to the open rows and columns
+  block_back_substitute(z, no, w2, no, Ss, nc, ncl ? oidx : nullptr, ncl ? oidx : nullptr);
   if (tid == 0) status[sidx] = 0;
 }
 

@@ -178,8 +178,9 @@ class Server:
                 out[bk.index[k]] = (r.R.cpu().numpy().copy(), r.S.cpu().numpy().copy(), int(it[k]), True)
                 continue
             if sst[k] != 0:
-                raise H.HprmatError(H.HP_ERR_UNSUPPORTED if sst[k] in (1, 4) else H.HP_ERR_SINGULAR,
-                                    f"hp_batch_smatrix (request {req.rid})")
+                code = H.HP_ERR_UNSUPPORTED if sst[k] in (1, 4, 5) else (
+                    H.HP_ERR_NOCONV if sst[k] == 2 else H.HP_ERR_SINGULAR)
+                raise H.HprmatError(code, f"hp_batch_smatrix (request {req.rid})")
             c = int(bk.nc[k])
             o = int(bk.r_off[k])
             out[bk.index[k]] = (R_all[o:o + c * c].reshape(c, c).copy(), S_all[o:o + c * c].reshape(c, c).copy(),

@@ -157,3 +157,37 @@ def test_full_size_with_closed_channels(mods):
     R = res.R.cpu().numpy()
     U, op, _ = ormat.smatrix_closed(R, E, sp.eps, np.asarray(sp.l), sp.hbar2_2mu, sp.z1z2, sp.a)
     _check_S(res.S.cpu().numpy(), {"open": op, "S": U}, 1e-12)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_matching_with_closed_channels(mods, prec):
+    """hp_batch_smatrix with closed channels: systems of the batch family
+    (N <= 800) at 8 MeV with every second, third or no threshold raised above
+    E, one with every channel closed (status 1); S over the open channels
+    against the oracle, zero in the closed rows and columns."""
+    H, P = mods
+    from paper_2512_11590_amd import batch as B
+    from workload import batch_systems
+    E = 8.0
+    sps = [sp for sp in batch_systems(200, seed=1159301) if sp.nc * sp.nr <= 800][:5]
+    for k, sp in enumerate(sps):
+        e = np.asarray(sp.eps, dtype=np.float64)
+        step = (0, 2, 3, 2, 1)[k]
+        if step:
+            sp.eps = np.where(np.arange(sp.nc) % step == step - 1, E + 1.5 + e, e)
+    assert np.all(sps[4].eps > E) and np.all(sps[0].eps < E - 0.5)
+    bk = B.Bucket(sps, [E] * len(sps), list(range(len(sps))), prec)
+    bk.factor(8, 0, 8)
+    bk.solve(30)
+    bk.rmatrix()
+    bk.smatrix()
+    st, _ = bk.status()
+    sst = bk.sstat.cpu().numpy()
+    say("batched closed, prec", prec, "open", [int(np.sum(sp.eps < E)) for sp in bk.systems])
+    for k, sp in enumerate(bk.systems):
+        if np.all(sp.eps > E):
+            assert sst[k] == 1
+            continue
+        assert st[k] == 1 and sst[k] == 0
+        o = opipe.solve_energy(sp, E)
+        _check_S(bk.S_of(k), o, 1e-10)
