@@ -55,11 +55,20 @@ def request_bytes(nc: int, nr: int, prec: int) -> int:
     return need
 
 
+def is_nonlocal(params) -> bool:
+    """Whether the system carries a non-local kernel (evaluated on its mesh)."""
+    fn = getattr(params, "nonlocal_potential", None)
+    return fn is not None and fn(H.hp_mesh(int(params.nr), float(params.a))[0]) is not None
+
+
 def served_bytes(params, prec: int, batched_max_n: int) -> int:
     """Device bytes a request holds while admitted: one system's buffers, or,
     on the batched path, one per energy (a bound: the bucket holds each
-    energy's matrix, solution and potential values)."""
+    energy's matrix, solution and potential values).  Non-local systems take
+    the single-system path and hold their n x n kernel values too."""
     nc, nr = int(params.nc), int(params.nr)
+    if is_nonlocal(params):
+        return request_bytes(nc, nr, prec) + (nc * nr) ** 2 * 16
     ne = len(params.energies) if nc * nr <= batched_max_n else 1
     return ne * request_bytes(nc, nr, prec)
 
@@ -146,7 +155,7 @@ class Server:
 
     # -- one slot --------------------------------------------------------------
     def _run_request(self, req: Served, params) -> None:
-        if req.n <= self.batched_max_n:
+        if req.n <= self.batched_max_n and not is_nonlocal(params):  # the batched kernels are local-only
             return self._run_request_batched(req, params)
         d = P.DeviceSystem(params, device=str(self.device))
         s = P.Solver(d, self.prec)

@@ -100,3 +100,22 @@ def test_admission_by_memory(mods):
         assert a1 >= d0 - 1e-3  # one request on the device at a time
     big = S.Server(slots=2, prec=H.HP_C64, hbm_budget=need // 8).run(reqs[:1])
     assert big[0].error is not None and not big[0].S
+
+
+def test_nonlocal_request_takes_the_single_system_path(mods):
+    """A small non-local request (below the batched-path size) is served by
+    the single-system solver, which takes the kernel: its S equals the
+    oracle's, beside local requests in the same stream."""
+    H, S = mods
+    from workload import with_perey_buck
+    nl = with_perey_buck(make_system("small"))
+    nl.energies = nl.energies[:2]
+    reqs = small_stream(count=3, seed=1159108)
+    reqs.insert(1, (reqs[1][0], nl))
+    say("non-local request in the mix")
+    res = S.Server(slots=2, prec=H.HP_C64).run(reqs)
+    assert all(r.error is None for r in res), [r.error for r in res]
+    md = osys.MeshData(nl.nr, nl.a)
+    for e, E in enumerate(nl.energies):
+        o = opipe.solve_energy(nl, float(E), md)
+        assert relerr(res[1].S[e], o["S"]) < 1e-10
