@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-closed", action="store_true", help="skip the closed-channel matching block")
     ap.add_argument("--no-nonlocal", action="store_true", help="skip the non-local potential block")
     ap.add_argument("--no-woodbury", action="store_true", help="skip the Woodbury-kinetic (Type 3) block")
+    ap.add_argument("--block-steps", type=int, default=3,
+                    help="timed energies of the non-local and Woodbury-kinetic blocks")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-systems", type=int, default=512)
     ap.add_argument("--served-requests", type=int, default=24)
@@ -415,9 +417,9 @@ def main():
         return
     if args.only:
         if args.only == "nonlocal":
-            blk = nonlocal_block(make_system(args.config), H, P, torch)
+            blk = nonlocal_block(make_system(args.config), H, P, torch, steps=args.block_steps)
         elif args.only == "woodbury":
-            blk = woodbury_block(make_system(args.config), H, P, torch)
+            blk = woodbury_block(make_system(args.config), H, P, torch, steps=args.block_steps)
         else:
             blk = batched(args, H, torch) if args.only == "batched" else served_stream(args, H, torch)
         print(json.dumps({"only": args.only, args.only: blk}), flush=True)
@@ -527,9 +529,9 @@ def main():
     if not args.no_closed:
         out["closed_channels"] = closed_channels(sp, H, P, torch)
     if not args.no_nonlocal:
-        out["nonlocal"] = nonlocal_block(sp, H, P, torch)
+        out["nonlocal"] = nonlocal_block(sp, H, P, torch, steps=args.block_steps)
     if not args.no_woodbury:
-        out["woodbury_kinetic"] = woodbury_block(sp, H, P, torch)
+        out["woodbury_kinetic"] = woodbury_block(sp, H, P, torch, steps=args.block_steps)
     if not args.no_batched:
         out["batched"] = batched(args, H, torch)
     if not args.no_served:
