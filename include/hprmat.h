@@ -74,8 +74,7 @@ typedef struct hp_system {
    * vnl[(c*nr+i)*n + c'*nr+j] = W_cc'(r_i, r_j) (MeV/fm), the kernel at the
    * mesh-point pairs.  The library adds the Lagrange-mesh matrix element
    * sqrt(w_i w_j) W_cc'(r_i, r_j) (Gauss quadrature) to element
-   * ((c,i),(c',j)) of C(E).  The batched entry points report it per system
-   * as unsupported. */
+   * ((c,i),(c',j)) of C(E) (batched entry points too). */
   const double *w;   /* device [nr]: mesh weights w_i on (0, a); required when vnl != NULL */
   const double *vnl;
 } hp_system;
@@ -311,10 +310,8 @@ typedef struct hp_batch_item {
 size_t hp_batch_workspace_bytes(int count, long sum_nc, long sum_xn, int nmax, int prec);
 
 /* C(E) of every system into A (precision prec), as hp_build_matrix does for one
- * (Eq. block_structure).  One workgroup per system.  Local systems only:
- * the non-local term of an item with sys.vnl != NULL is not assembled, and
- * such an item is reported per system (hp_batch_status 4,
- * hp_batch_smatrix 5) instead of solved. */
+ * (Eq. block_structure, with the non-local term of an item whose sys.vnl is
+ * set).  64 workgroups per system. */
 int hp_batch_build(int count, const hp_batch_item *items, int prec, void *A, void *stream);
 
 /* LU with partial pivoting of every system (Sec. 3.1), in place, as
@@ -361,7 +358,8 @@ int hp_batch_solve_init(int count, const hp_batch_item *items, const int *shape_
                         long sum_xn, void *work, size_t work_bytes, void *stream);
 
 /* One FP64 refinement step of FP32 factors for every system still refining
- * (Sec. 3.2): r = B - C X from the block structure, d from the factors
+ * (Sec. 3.2): r = B - C X from the block structure (plus, for a non-local
+ * system, its kernel product, one output per thread), d from the factors
  * (column-scaled; solves as chosen by shape_host), X += d, and the stop rule
  * of hp_solve per system (relative correction <= tol, tol <= 0: 2^-29; a
  * correction larger than half the previous one: converged if it is itself
@@ -378,9 +376,9 @@ int hp_batch_refine_step(int count, const hp_batch_item *items, const int *shape
 int hp_batch_active(const void *work, unsigned *active, void *stream);
 
 /* Per-system outcome (host arrays of count): status 1 converged (or no
- * refinement), 2 not converged, 3 zero pivot, 4 non-local system (not
- * supported by the batched path: its X is not a solution), 0 still
- * refining; iters =
+ * refinement), 2 not converged, 3 zero pivot, 4 a non-local system with
+ * more than 1024 mesh points in a refined batch (not supported: its X is
+ * not a solution), 0 still refining; iters =
  * corrections applied (may be NULL).  Synchronizes the stream. */
 int hp_batch_status(int count, const void *work, int *status, int *iters, void *stream);
 
@@ -396,8 +394,8 @@ int hp_batch_status(int count, const void *work, int *status, int *iters, void *
  * int[count], per system 0 ok, 1 no open channel or E exactly at a
  * threshold, 2 a Coulomb continued fraction (or a closed channel's
  * integration) did not converge, 3 an exactly zero pivot, 4 more than 512
- * channels, 5 a non-local system (sys.vnl != NULL); S of a system with status
- * 1, 2, 4 or 5 is not written, with status 3 it holds no result.
+ * channels; S of a system with status 1, 2 or 4 is not written, with status
+ * 3 it holds no result.
  * sum_nc2 = sum of nc^2 over the systems (host), nc_max = the largest nc
  * (host, at most 512, else HP_ERR_UNSUPPORTED).  work: device, at least
  * 32 * sum_nc2 bytes.  Asynchronous, no host synchronisation (may be

@@ -79,12 +79,14 @@ class Bucket:
         self.c_off = np.concatenate([[0], np.cumsum(nc)[:-1]])
         self.sum_nc, self.sum_xn = int(nc.sum()), int((n * nc).sum())
         # per-system mesh, channel and potential data, concatenated
-        r_h, q_h, tl_h, l_h, eps_h, v_h = [], [], [], [], [], []
+        r_h, q_h, tl_h, l_h, eps_h, v_h, w_h, nl_h = [], [], [], [], [], [], [], []
         for s in self.systems:
             r, w, q, tl = H.hp_mesh(int(s.nr), float(s.a))
             fn = getattr(s, "nonlocal_potential", None)
-            if fn is not None and fn(r) is not None:  # the batched kernels handle local systems only
-                raise ValueError("non-local systems are solved one at a time (pipeline.Solver), not batched")
+            W = fn(r) if fn is not None else None
+            nl_h.append(None if W is None else
+                        np.ascontiguousarray(np.asarray(W, dtype=np.complex128).reshape(-1)))
+            w_h.append(w)
             r_h.append(r)
             q_h.append(q)
             tl_h.append(np.ascontiguousarray(tl).ravel())
@@ -97,6 +99,12 @@ class Bucket:
         self.l = torch.from_numpy(np.concatenate(l_h)).to(dev)
         self.eps = torch.from_numpy(np.concatenate(eps_h)).to(dev)
         self.v = torch.from_numpy(np.concatenate(v_h)).to(dev)
+        self.w = torch.from_numpy(np.concatenate(w_h)).to(dev)
+        # non-local kernel values of the systems that have them (n x n each)
+        nl_len = np.array([0 if W is None else W.size for W in nl_h], dtype=np.int64)
+        off_nl = np.concatenate([[0], np.cumsum(nl_len)[:-1]])
+        self.vnl = (torch.from_numpy(np.concatenate([W for W in nl_h if W is not None])).to(dev)
+                    if nl_len.sum() else None)
         off_r = np.concatenate([[0], np.cumsum(nr)[:-1]])
         off_tl = np.concatenate([[0], np.cumsum(nr * nr)[:-1]])
         off_c = self.c_off
@@ -107,7 +115,9 @@ class Bucket:
             sy = H.HpSystem(int(nc[k]), int(nr[k]), float(s.a), float(s.hbar2_2mu), float(s.z1z2) * E2,
                             self.r.data_ptr() + 8 * int(off_r[k]), self.q.data_ptr() + 8 * int(off_r[k]),
                             self.tl.data_ptr() + 8 * int(off_tl[k]), self.l.data_ptr() + 4 * int(off_c[k]),
-                            self.eps.data_ptr() + 8 * int(off_c[k]), self.v.data_ptr() + 16 * int(off_v[k]))
+                            self.eps.data_ptr() + 8 * int(off_c[k]), self.v.data_ptr() + 16 * int(off_v[k]),
+                            self.w.data_ptr() + 8 * int(off_r[k]),
+                            (self.vnl.data_ptr() + 16 * int(off_nl[k])) if nl_len[k] else None)
             self.sys.append(sy)
             items[k] = H.HpBatchItem(sy, self.energies[k], int(self.a_off[k]), int(self.x_off[k]),
                                      int(self.p_off[k]), int(self.r_off[k]), int(self.c_off[k]))
@@ -351,10 +361,12 @@ class Batch:
 
     def results(self, fallback: bool = True):
         """[(R, S)] in the original order of the systems (host arrays).  A
-        system whose FP32 refinement did not converge (status 2) or whose FP32
-        factor met an exactly zero pivot (status 3) is solved again in FP64
-        through the single-system path when `fallback` is set (its index is
-        then listed in self.fallbacks), else HprmatError is raised."""
+        system whose FP32 refinement did not converge (status 2), whose FP32
+        factor met an exactly zero pivot (status 3) or that the batched
+        refinement does not take (status 4: a non-local system on more than
+        1024 mesh points) is solved again in FP64 through the single-system
+        path when `fallback` is set (its index is then listed in
+        self.fallbacks), else HprmatError is raised."""
         from . import pipeline as P
         out = [None] * self.count
         st, _ = self.status()
@@ -365,17 +377,17 @@ class Batch:
             S_all = b.S.cpu().numpy()
             for k in range(b.count):
                 g = b.index[k]
-                if st[g] in (2, 3):
+                if st[g] in (2, 3, 4):
                     if not fallback:
-                        raise H.HprmatError(H.HP_ERR_NOCONV if st[g] == 2 else H.HP_ERR_SINGULAR,
-                                            f"batched system {g}")
+                        code = {2: H.HP_ERR_NOCONV, 3: H.HP_ERR_SINGULAR, 4: H.HP_ERR_UNSUPPORTED}[int(st[g])]
+                        raise H.HprmatError(code, f"batched system {g}")
                     res = P.Solver(P.DeviceSystem(b.systems[k], device=str(b.device)), H.HP_C128).run(
                         b.energies[k])
                     out[g] = (res.R.cpu().numpy(), res.S.cpu().numpy())
                     self.fallbacks.append(g)
                     continue
                 if sst[k] != 0:
-                    code = H.HP_ERR_UNSUPPORTED if sst[k] in (1, 4, 5) else (
+                    code = H.HP_ERR_UNSUPPORTED if sst[k] in (1, 4) else (
                         H.HP_ERR_NOCONV if sst[k] == 2 else H.HP_ERR_SINGULAR)
                     raise H.HprmatError(code, f"hp_batch_smatrix, system {g}")
                 c = int(b.nc[k])

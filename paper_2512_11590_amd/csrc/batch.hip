@@ -452,7 +452,8 @@ __global__ void batch_zero_kernel(unsigned *p, int n) {
 }
 
 // ---------------------------------------------------------------- assembly --
-// Assembly of every system's C(E) (as hp_build_matrix, Eq. block_structure):
+// Assembly of every system's C(E) (as hp_build_matrix, Eq. block_structure,
+// with a non-local system's sqrt(w_i w_j) W_cc'(r_i, r_j) on every element):
 // rows spread over kBuildGroups workgroups per system so that a bucket's
 // matrices are written by thousands of workgroups at once.
 constexpr int kBuildGroups = 64;
@@ -466,6 +467,7 @@ __global__ __launch_bounds__(256) void batch_build_kernel(int count, const hp_ba
   const hp_batch_item it = items[s];
   const int nc = it.sys.nc, nr = it.sys.nr, n = nc * nr;
   const double h = it.sys.hbar2_2mu, E = it.E;
+  const cplx<double> *W = reinterpret_cast<const cplx<double> *>(it.sys.vnl);  // null: local
   cplx<T> *a = A + it.a_off;
   for (int row = blockIdx.x; row < n; row += gridDim.x) {
     const int c = row / nr, i = row - c * nr;
@@ -474,6 +476,7 @@ __global__ __launch_bounds__(256) void batch_build_kernel(int count, const hp_ba
     const double diag = h * (double)lc * (double)(lc + 1) / (ri * ri) + it.sys.eps[c] - E;
     const double *tl_row = it.sys.tl + (size_t)i * nr;
     const double *v_row = it.sys.v + 2 * ((size_t)i * nc + c) * nc;
+    const double si = W ? sqrt(it.sys.w[i]) : 0.0;
     for (int col = threadIdx.x; col < n; col += 256) {
       const int cp = col / nr, j = col - cp * nr;
       double re = 0.0, im = 0.0;
@@ -484,6 +487,12 @@ __global__ __launch_bounds__(256) void batch_build_kernel(int count, const hp_ba
       if (j == i) {
         re += v_row[2 * cp];
         im += v_row[2 * cp + 1];
+      }
+      if (W) {
+        const double f = si * sqrt(it.sys.w[j]);
+        const cplx<double> x = W[(long)row * n + col];
+        re += f * x.re;
+        im += f * x.im;
       }
       a[(long)row * n + col] = cplx<T>{(T)re, (T)im};
     }
@@ -932,7 +941,7 @@ __device__ void wg_lu_solve(int n, int nc, const cplx<T> *__restrict__ lu, cplx<
 
 // Per-system refinement state.
 struct BatchState {
-  int status;  // 0 running, 1 converged, 2 not converged, 3 zero pivot, 4 non-local system
+  int status;  // 0 running, 1 converged, 2 not converged, 3 zero pivot, 4 unsupported
   int iters;
   double corr_prev;
   double corr;
@@ -1037,6 +1046,52 @@ __global__ __launch_bounds__(256) void batch_res_kinetic_kernel(int count, const
         rr[((long)c * nr + i) * nc + cc] = cplx<double>{sr[u] + dg * xi.re, si[u] + dg * xi.im};
       }
     }
+  }
+}
+
+// Non-local systems: rr[(c,i)][cc] += sqrt(w_i) sum over (c',j) of
+// W[(c,i),(c',j)] sqrt(w_j) x[(c',j)][cc], between the kinetic pass and the
+// coupling pass (which forms b - the sum).  One output per thread, threads
+// of a wavefront on consecutive right-hand columns (coalesced x reads, W
+// broadcast); sqrt(w) of the mesh in LDS.
+constexpr int kNlMaxPoints = 1024;
+__global__ __launch_bounds__(256) void batch_res_nonlocal_kernel(int count, const hp_batch_item *__restrict__ items,
+                                                                 const cplx<double> *__restrict__ X,
+                                                                 cplx<double> *__restrict__ Rr,
+                                                                 const BatchState *state) {
+  __shared__ double sw[kNlMaxPoints];
+  const int s = blockIdx.y;
+  if (s >= count || state[s].status != 0) return;
+  const hp_batch_item it = items[s];
+  if (!it.sys.vnl || it.sys.nr > kNlMaxPoints) return;  // the latter: status 4, never refining
+  const int nc = it.sys.nc, nr = it.sys.nr;
+  const long n = (long)nc * nr;
+  const cplx<double> *W = reinterpret_cast<const cplx<double> *>(it.sys.vnl);
+  const cplx<double> *x = X + it.x_off;
+  cplx<double> *rr = Rr + it.x_off;
+  for (int j = threadIdx.x; j < nr; j += 256) sw[j] = sqrt(it.sys.w[j]);
+  __syncthreads();
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n * nc; e += (long)kResChunks * 256) {
+    const long row = e / nc;
+    const int cc = (int)(e - row * nc);
+    const cplx<double> *wr = W + row * n;
+    double ar = 0.0, ai = 0.0;
+    for (int cp = 0; cp < nc; ++cp) {
+      const cplx<double> *wb = wr + (long)cp * nr;
+      const cplx<double> *xb = x + (long)cp * nr * nc + cc;
+      for (int j = 0; j < nr; ++j) {
+        const cplx<double> wv = wb[j];
+        const cplx<double> xv = xb[(long)j * nc];
+        const double f = sw[j];
+        ar += f * (wv.re * xv.re - wv.im * xv.im);
+        ai += f * (wv.re * xv.im + wv.im * xv.re);
+      }
+    }
+    const double si = sw[(int)(row % nr)];
+    cplx<double> p = rr[e];
+    p.re += si * ar;
+    p.im += si * ai;
+    rr[e] = p;
   }
 }
 
@@ -1166,8 +1221,9 @@ __global__ void batch_state_init_kernel(int count, const hp_batch_item *__restri
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= count) return;
   BatchState st;
-  // the batched kernels assemble and refine local systems only
-  st.status = items[s].sys.vnl ? 4 : (info && info[s] != 0) ? 3 : (refine ? 0 : 1);
+  // a non-local system's refinement residual holds sqrt(w) of its mesh in LDS
+  const bool too_fine = refine && items[s].sys.vnl && items[s].sys.nr > kNlMaxPoints;
+  st.status = too_fine ? 4 : (info && info[s] != 0) ? 3 : (refine ? 0 : 1);
   st.iters = 0;
   st.corr_prev = 0.0;
   st.corr = 0.0;
@@ -1627,6 +1683,9 @@ extern "C" int hp_batch_refine_step(int count, const hp_batch_item *items, const
     TraceScope ts(TR_RESIDUAL, st, 0.0, 0.0);
     hipLaunchKernelGGL(batch_res_kinetic_kernel, dim3(kResChunks, count), dim3(256), 0, st, count, items,
                        (const cplx<double> *)X, w.res, w.cscale, w.state);
+    HP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(batch_res_nonlocal_kernel, dim3(kResChunks, count), dim3(256), 0, st, count, items,
+                       (const cplx<double> *)X, w.res, w.state);
     HP_CHECK_LAUNCH();
     hipLaunchKernelGGL(batch_res_coupling_kernel, dim3(kResChunks, count), dim3(256), 0, st, count, items,
                        (const cplx<double> *)X, w.res, w.cscale, w.state);

@@ -443,8 +443,7 @@ __device__ static void block_back_substitute(const cplx<double> *z, int n, int w
 // substitution into S (at r_off), whose closed rows and columns are zero.
 // status[s]: 0 ok, 1 no open channel or E at a threshold, 2 a continued
 // fraction or a closed channel's integration failed, 3 an exactly zero pivot,
-// 4 more than 512 channels, 5 a non-local system (its R did not come from the
-// batched solves).
+// 4 more than 512 channels.
 constexpr int kBatchSmatMaxChannels = 512;
 
 __global__ __launch_bounds__(256) void batch_smatrix_kernel(int count, const hp_batch_item *__restrict__ items,
@@ -464,10 +463,6 @@ __global__ __launch_bounds__(256) void batch_smatrix_kernel(int count, const hp_
   const int nc = sys.nc, tid = threadIdx.x;
   if (nc > kBatchSmatMaxChannels) {  // the channel table would not fit
     if (tid == 0) status[sidx] = 4;
-    return;
-  }
-  if (sys.vnl) {
-    if (tid == 0) status[sidx] = 5;
     return;
   }
   if (tid == 0) s_bad = 0;

@@ -155,7 +155,9 @@ class Server:
 
     # -- one slot --------------------------------------------------------------
     def _run_request(self, req: Served, params) -> None:
-        if req.n <= self.batched_max_n and not is_nonlocal(params):  # the batched kernels are local-only
+        # a non-local request keeps one copy of its kernel values for all its
+        # energies on the single-system path (a bucket holds one per energy)
+        if req.n <= self.batched_max_n and not is_nonlocal(params):
             return self._run_request_batched(req, params)
         d = P.DeviceSystem(params, device=str(self.device))
         s = P.Solver(d, self.prec)
@@ -182,12 +184,12 @@ class Server:
         S_all = bk.S.cpu().numpy()
         out = [None] * ne
         for k in range(ne):
-            if st[k] in (2, 3):  # FP32 refinement did not converge / zero pivot: FP64 single-system solve
+            if st[k] in (2, 3, 4):  # not converged / zero pivot / not taken: FP64 single-system solve
                 r = P.Solver(P.DeviceSystem(params, device=str(self.device)), H.HP_C128).run(bk.energies[k])
                 out[bk.index[k]] = (r.R.cpu().numpy().copy(), r.S.cpu().numpy().copy(), int(it[k]), True)
                 continue
             if sst[k] != 0:
-                code = H.HP_ERR_UNSUPPORTED if sst[k] in (1, 4, 5) else (
+                code = H.HP_ERR_UNSUPPORTED if sst[k] in (1, 4) else (
                     H.HP_ERR_NOCONV if sst[k] == 2 else H.HP_ERR_SINGULAR)
                 raise H.HprmatError(code, f"hp_batch_smatrix (request {req.rid})")
             c = int(bk.nc[k])

@@ -6,8 +6,6 @@ variant, against the oracle; a separable kernel against its closed-form K
 matrix, up to N = 25600 (256 s-wave channels, 100 points each)."""
 from __future__ import annotations
 
-import ctypes
-
 import numpy as np
 import pytest
 
@@ -154,34 +152,33 @@ def test_separable_kernel_closed_form_on_device(mods, prec):
         assert np.max(np.abs(S - Sa)) < 5e-11
 
 
-def test_batched_path_reports_nonlocal_items(mods):
-    """An item whose sys.vnl is set is reported per system by the batched
-    entry points (solve status 4, S status 5) while the others are solved."""
+@pytest.mark.parametrize("form", ["persistent", "stepped"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_nonlocal_systems_against_oracle(mods, prec, form):
+    """A bucket mixing local systems and systems with non-local kernels
+    (Gaussian non-locality, Perey-Buck form): the batched assembly takes the
+    kernel, the batched FP32 refinement its product; R and S of every system
+    against the oracle."""
     H, P = mods
     from paper_2512_11590_amd import batch as B
-    systems = [make_system("small", nc=4, nr=30, seed=s) for s in (5, 6)]
-    energies = [float(s.energies[2]) for s in systems]
-    bk = B.Bucket(systems, energies, [0, 1], H.HP_C128)
-    # point the second item's vnl at a device buffer (never read by these kernels)
-    dummy = torch.zeros(16, dtype=torch.float64, device="cuda")
-    size = ctypes.sizeof(H.HpBatchItem)
-    off = H.HpBatchItem.sys.offset + H.HpSystem.vnl.offset
-    raw = bk.items.cpu().numpy().copy()
-    k = [i for i in range(2) if bk.index[i] == 1][0]
-    raw[k * size + off:k * size + off + 8] = np.frombuffer(np.uint64(dummy.data_ptr()).tobytes(), dtype=np.uint8)
-    bk.items.copy_(torch.from_numpy(raw))
-    assert size * 2 == raw.size
-    say("batched non-local item")
-    bk.factor(8, 8)
-    bk.solve(0)
-    bk.rmatrix()
-    bk.smatrix()
-    st, _ = bk.status()
-    sstat = bk.sstat.cpu().numpy()
-    assert st[k] == 4 and sstat[k] == 5
-    assert st[1 - k] == 1 and sstat[1 - k] == 0
-    o = opipe.solve_energy(bk.systems[1 - k], bk.energies[1 - k])
-    assert relerr(bk.S_of(1 - k), o["S"]) < 1e-10
+    sps = [make_system("small", nc=nc, nr=nr, seed=sd) for nc, nr, sd in ((4, 30, 5), (3, 41, 6), (6, 25, 7),
+                                                                         (5, 36, 8))]
+    with_nonlocal(sps[0], gaussian_nonlocal(4, 31))
+    with_perey_buck(sps[2])
+    with_nonlocal(sps[3], gaussian_nonlocal(5, 33))
+    energies = [float(s.energies[2 + k]) for k, s in enumerate(sps)]
+    bt = B.Batch(sps, energies, prec)
+    for b in bt.buckets:
+        bt.tuning[b.key] = B.BucketTuning(8, 2 * bt.cus if form == "persistent" else 0, 0.0, 8)
+    say("batched non-local, prec", prec, form)
+    bt.run()
+    st, it = bt.status()
+    assert np.all(st == 1), (st, it)
+    for k, (R, S) in enumerate(bt.results(fallback=False)):
+        o = opipe.solve_energy(sps[k], energies[k])
+        er, es = relerr(R, o["R"]), relerr(S, o["S"])
+        print(f"   system {k} R err {er:.2e}  S err {es:.2e}  corrections {it[k]}", flush=True)
+        assert er < 1e-10 and es < 1e-10
 
 
 def test_full_size_separable_kernel(mods):

@@ -135,17 +135,6 @@ def test_nonlocal_arguments_checked_without_device(H):
                       None) == H.HP_ERR_ARG
 
 
-def test_batch_layer_rejects_nonlocal_systems(H):
-    """Non-local systems go through the single-system solver; the batched
-    layer refuses them before touching a device."""
-    from paper_2512_11590_amd import batch
-    from tests.helpers import CustomSystem, separable_nonlocal
-    sp = CustomSystem(nc=1, nr=10, a=10.0, l=np.array([0]), eps=np.array([0.0]),
-                      pot=lambda r: np.zeros((len(r), 1, 1), dtype=complex), nlpot=separable_nonlocal(1.0, 1.0))
-    with pytest.raises(ValueError, match="non-local"):
-        batch.Bucket([sp], [1.0], [0], H.HP_C128, device="cpu")
-
-
 @pytest.mark.parametrize("nr,a", [(7, 5.0), (60, 20.0)])
 def test_kinetic_inverse_is_the_rounded_exact_inverse(H, nr, a):
     """hp_kinetic_inverse returns the inverse of hp_mesh's rounded tl to
