@@ -371,6 +371,13 @@ int hp_batch_refine_step(int count, const hp_batch_item *items, const int *shape
                          const int *perm, double *X, int max_refine, double tol, long sum_nc, long sum_xn,
                          void *work, size_t work_bytes, void *stream);
 
+/* Whether hp_batch_factor_stepped takes FP32 panels of 8 columns on at most
+ * 4096 rows with the panel held in registers (one 1024-thread workgroup per
+ * system; default 1) or through memory (0).  The arithmetic, and so the
+ * factors, are the same.  Returns the previous setting.  For tests and
+ * tuning; not to be changed while a factorization is in flight. */
+int hp_set_batch_reg_panel(int on);
+
 /* Number of systems still refining after the last step (host *active);
  * synchronizes the stream. */
 int hp_batch_active(const void *work, unsigned *active, void *stream);

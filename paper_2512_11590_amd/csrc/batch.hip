@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <atomic>
 #include <type_traits>
 #include <vector>
 
@@ -721,6 +722,146 @@ __global__ __launch_bounds__(256) void batch_panel_kernel(const hp_batch_item *_
   __syncthreads();
   panel_steps<T>(A + it.a_off, n, j0, w, false, piv, &s_zero, urow, sv, sr, D);
   if (threadIdx.x == 0) {
+    info[s] = s_zero;
+    if (j0 + w == n) compose_perm(piv, perm + it.p_off, n);
+  }
+}
+
+// The same column steps with the panel held in registers: one workgroup of
+// 1024 threads per system, thread t owning panel rows j0 + t + 1024 k
+// (k < RPT, so n - j0 <= 1024 RPT) with their W columns.  Per column: the
+// pivot search over the registers, a workgroup argmax, the interchange of the
+// two rows through LDS, the pivot row broadcast in LDS, and the update of the
+// rows below in registers; the panel is read and written once instead of
+// once per column.  Same arithmetic as panel_steps (interchanges inside the
+// panel only).
+constexpr int kRegPanelThreads = 1024;
+std::atomic<int> g_reg_panel{1};  // hp_set_batch_reg_panel
+template <typename T, int W, int RPT>
+__global__ __launch_bounds__(kRegPanelThreads) void batch_panel_reg_kernel(
+    const hp_batch_item *__restrict__ items, cplx<T> *__restrict__ A, int *__restrict__ ipiv,
+    int *__restrict__ perm, int *__restrict__ info, int j0) {
+  constexpr int NW = kRegPanelThreads / 64;
+  __shared__ cplx<T> prow[W], jrow[W];
+  __shared__ T sv[NW];
+  __shared__ int sr[NW];
+  __shared__ int s_zero;
+  const int s = blockIdx.x;
+  const hp_batch_item it = items[s];
+  const int n = item_n(it);
+  if (j0 >= n) return;
+  const int w = min(W, n - j0);
+  cplx<T> *a = A + it.a_off;
+  int *piv = ipiv + it.p_off;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_zero = info[s];
+  cplx<T> P[RPT][W];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int r = j0 + tid + k * kRegPanelThreads;
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+      P[k][c] = (r < n && c < w) ? a[(long)r * n + j0 + c] : cplx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+#pragma unroll
+  for (int jj = 0; jj < W; ++jj) {
+    if (jj >= w) break;  // uniform
+    const int j = j0 + jj;
+    T best = T(-1);
+    int brow = INT_MAX;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int r = j0 + tid + k * kRegPanelThreads;
+      if (r >= j && r < n) {
+        const T v = cabs1(P[k][jj]);
+        if (v > best || (v == best && r < brow)) {
+          best = v;
+          brow = r;
+        }
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const T ov = __shfl_xor(best, off);
+      const int orow = __shfl_xor(brow, off);
+      if (ov > best || (ov == best && orow < brow)) {
+        best = ov;
+        brow = orow;
+      }
+    }
+    if ((tid & 63) == 0) {
+      sv[tid >> 6] = best;
+      sr[tid >> 6] = brow;
+    }
+    __syncthreads();
+    best = sv[0];
+    brow = sr[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q)
+      if (sv[q] > best || (sv[q] == best && sr[q] < brow)) {
+        best = sv[q];
+        brow = sr[q];
+      }
+    const int p = (brow >= j && brow < n) ? brow : j;
+    const bool nz = best > T(0);
+    if (tid == 0) {
+      piv[j] = p;
+      if (!nz && s_zero == 0) s_zero = j + 1;
+    }
+    // rows j and p: the pivot row to prow (the new row j), row j to jrow
+    const int oj = j - j0, op = p - j0;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int r = tid + k * kRegPanelThreads;
+      if (r == op) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) prow[c] = P[k][c];
+      }
+      if (r == oj && op != oj) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) jrow[c] = P[k][c];
+      }
+    }
+    __syncthreads();
+    if (op != oj) {
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int r = tid + k * kRegPanelThreads;
+        if (r == oj) {
+#pragma unroll
+          for (int c = 0; c < W; ++c) P[k][c] = prow[c];
+        }
+        if (r == op) {
+#pragma unroll
+          for (int c = 0; c < W; ++c) P[k][c] = jrow[c];
+        }
+      }
+    }
+    if (nz) {
+      const cplx<T> inv = crcp(prow[jj]);
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int r = j0 + tid + k * kRegPanelThreads;
+        if (r > j && r < n) {
+          const cplx<T> l = cmul(P[k][jj], inv);
+          P[k][jj] = l;
+#pragma unroll
+          for (int c = jj + 1; c < W; ++c) P[k][c] = cfms(P[k][c], l, prow[c]);
+        }
+      }
+    }
+    __syncthreads();  // prow and jrow are rewritten by the next column
+  }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int r = j0 + tid + k * kRegPanelThreads;
+    if (r < n) {
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+        if (c < w) a[(long)r * n + j0 + c] = P[k][c];
+    }
+  }
+  if (tid == 0) {
     info[s] = s_zero;
     if (j0 + w == n) compose_perm(piv, perm + it.p_off, n);
   }
@@ -1569,7 +1710,19 @@ extern "C" int hp_batch_factor_stepped(int count, const hp_batch_item *items, co
     for (int j0 = J; j0 < std::min(J + block, nmax); j0 += panel) {
       int active = 0;
       const long tiles = units(0, j0, &active);
-      if (prec == HP_C64)
+      // FP32 panels of 8 columns on at most 4096 rows: held in registers
+      const int prows = n_host[0] - j0;
+      if (prec == HP_C64 && panel == 8 && prows <= 4 * kRegPanelThreads && g_reg_panel.load() != 0) {
+        if (prows <= kRegPanelThreads)
+          hipLaunchKernelGGL((batch_panel_reg_kernel<float, 8, 1>), dim3(active), dim3(kRegPanelThreads), 0, st, items,
+                             (cplx<float> *)A, ipiv, perm, info, j0);
+        else if (prows <= 2 * kRegPanelThreads)
+          hipLaunchKernelGGL((batch_panel_reg_kernel<float, 8, 2>), dim3(active), dim3(kRegPanelThreads), 0, st, items,
+                             (cplx<float> *)A, ipiv, perm, info, j0);
+        else
+          hipLaunchKernelGGL((batch_panel_reg_kernel<float, 8, 4>), dim3(active), dim3(kRegPanelThreads), 0, st, items,
+                             (cplx<float> *)A, ipiv, perm, info, j0);
+      } else if (prec == HP_C64)
         hipLaunchKernelGGL(batch_panel_kernel<float>, dim3(active), dim3(256), 0, st, items, (cplx<float> *)A, ipiv,
                            perm, info, j0, panel, block);
       else
@@ -1715,6 +1868,8 @@ extern "C" int hp_batch_refine_step(int count, const hp_batch_item *items, const
   HP_CHECK_LAUNCH();
   return HP_OK;
 }
+
+extern "C" int hp_set_batch_reg_panel(int on) { return g_reg_panel.exchange(on ? 1 : 0); }
 
 extern "C" int hp_batch_active(const void *work, unsigned *active, void *stream) {
   if (!work || !active) return HP_ERR_ARG;

@@ -63,7 +63,7 @@ EXPORTS = ["hp_mesh", "hp_workspace_bytes", "hp_build_matrix", "hp_factor", "hp_
            "hp_gemm_sub", "hp_gemm_h3_sub", "hp_set_concurrency", "hp_set_solve_graphs", "hp_batch_workspace_bytes", "hp_batch_build",
            "hp_batch_factor", "hp_batch_factor_stepped", "hp_batch_solve_init", "hp_batch_refine_step", "hp_batch_active",
            "hp_batch_status", "hp_batch_rmatrix", "hp_batch_smatrix", "hp_kinetic_inverse",
-           "hp_schur_workspace_bytes", "hp_build_schur", "hp_solve_schur"]
+           "hp_schur_workspace_bytes", "hp_build_schur", "hp_solve_schur", "hp_set_batch_reg_panel"]
 
 _lib = None
 
@@ -380,6 +380,15 @@ def hp_batch_smatrix(count, items, R, S, status, sum_nc2, nc_max, work, stream=N
     _check(lib().hp_batch_smatrix(count, _ptr(items), _ptr(R), _ptr(S), _ptr(status), int(sum_nc2), int(nc_max),
                                   _ptr(work), work.numel() * work.element_size(), _stream(stream)),
            "hp_batch_smatrix")
+
+
+def hp_set_batch_reg_panel(on: bool) -> int:
+    """FP32 batched panels held in registers (default) or through memory;
+    returns the previous setting."""
+    L = lib()
+    L.hp_set_batch_reg_panel.argtypes = [c_int]
+    L.hp_set_batch_reg_panel.restype = c_int
+    return int(L.hp_set_batch_reg_panel(int(bool(on))))
 
 
 def hp_set_concurrency(factorizations: int) -> int:

@@ -156,3 +156,44 @@ def test_batched_fallback_to_fp64(mods, small):
     for (R, S), o in zip(out, refs):
         assert relerr(R, o["R"]) < 1e-10
         assert relerr(S, o["S"]) < 1e-10
+
+
+def test_register_panel_matches_memory_panel(mods):
+    """The FP32 stepped factorization with its 8-column panels held in
+    registers (one 1024-thread workgroup per system; 1, 2 and 4 rows per
+    thread) against the panels worked through memory: the same pivots, the
+    factors equal up to FP32 rounding (the two kernels may contract the
+    same products into fused multiply-adds differently), and R after
+    refinement within 1e-10 of each other and of the oracle."""
+    H, B, P = mods
+    pool = batch_systems(200, seed=1159203)
+    pick = []
+    for lo, hi in ((300, 1000), (1100, 2000), (3000, 4000)):
+        pick.append(next(sp for sp in pool if lo <= sp.nc * sp.nr <= hi))
+    say("register panel N", [sp.nc * sp.nr for sp in pick])
+    out = {}
+    for on in (True, False):
+        prev = H.hp_set_batch_reg_panel(on)
+        try:
+            bk = B.Bucket(pick, [float(sp.energies[0]) for sp in pick], list(range(3)), H.HP_C64)
+            bk.factor(8, 0, 64)
+            torch.cuda.synchronize()
+            A = bk.A.cpu().numpy()
+            facs = [A[int(bk.a_off[k]):int(bk.a_off[k]) + int(bk.n[k]) ** 2] for k in range(3)]
+            piv = bk.ipiv.cpu().numpy()
+            info = bk.info.cpu().numpy()
+            bk.solve(30)
+            bk.rmatrix()
+            out[on] = (facs, piv, info, [bk.R_of(k) for k in range(3)], list(bk.index))
+        finally:
+            H.hp_set_batch_reg_panel(prev)
+    reg, mem = out[True], out[False]
+    assert np.array_equal(reg[1], mem[1]) and not reg[2].any() and not mem[2].any()
+    for k in range(3):
+        e = relerr(reg[0][k], mem[0][k])
+        print(f"   system {k}: factors {e:.1e}  R {relerr(reg[3][k], mem[3][k]):.1e}", flush=True)
+        assert e < 1e-4
+        assert relerr(reg[3][k], mem[3][k]) < 1e-10
+    k = reg[4].index(0)
+    o = opipe.solve_energy(pick[0], float(pick[0].energies[0]))
+    assert relerr(reg[3][k], o["R"]) < 1e-10
