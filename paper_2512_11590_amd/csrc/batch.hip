@@ -1463,12 +1463,17 @@ __global__ void batch_solve_tiles_kernel(int count, const hp_batch_item *__restr
 // Diagonal block [b0, b0 + bs) of every system (state: skip systems not
 // refining): the block of LU staged in LDS, one right-hand column per thread
 // (diag_block_solve).
-template <typename T>
+// With STAGED the block's rows of Y (bs x nc) are first staged in LDS, so the
+// substitution's reads of the rows solved before a group stay on chip (the
+// same arithmetic as the unstaged form, which serves nc too large for LDS).
+template <typename T, bool STAGED>
 __global__ __launch_bounds__(256) void batch_sdiag_kernel(const hp_batch_item *__restrict__ items,
                                                           const cplx<T> *__restrict__ LU, cplx<T> *__restrict__ Y,
                                                           int b0, int upper, const BatchState *state) {
   // every lane reads the same element of D (a broadcast), so no padding
   __shared__ cplx<T> D[kSB * kSB];
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<T> *Ys = reinterpret_cast<cplx<T> *>(smem_raw);  // [bs][nc] (STAGED)
   const int s = blockIdx.x;
   if (state && state[s].status != 0) return;
   const hp_batch_item it = items[s];
@@ -1480,9 +1485,17 @@ __global__ __launch_bounds__(256) void batch_sdiag_kernel(const hp_batch_item *_
     const int r = e / kSB, k = e - r * kSB;
     D[e] = (r < bs && k < bs) ? lu[(long)(b0 + r) * n + b0 + k] : cplx<T>{T(0), T(0)};
   }
-  __syncthreads();
-  cplx<T> *y = Y + it.x_off;
-  for (int c = threadIdx.x; c < nc; c += 256) diag_block_solve<T, kSB>(D, y, nc, b0, bs, c, upper != 0);
+  cplx<T> *yb = Y + it.x_off + (long)b0 * nc;  // the block's rows
+  if constexpr (STAGED) {
+    for (int e = threadIdx.x; e < bs * nc; e += blockDim.x) Ys[e] = yb[e];
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += 256) diag_block_solve<T, kSB>(D, Ys, nc, 0, bs, c, upper != 0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < bs * nc; e += blockDim.x) yb[e] = Ys[e];
+  } else {
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += 256) diag_block_solve<T, kSB>(D, yb, nc, 0, bs, c, upper != 0);
+  }
 }
 
 // Update tiles of a solve step: forward Y[b0+bs:n] -= L[b0+bs:n, b0:b0+bs] Y[b0:b0+bs],
@@ -1580,6 +1593,12 @@ int stepped_solve(int count, const hp_batch_item *items, const int *shape_host, 
   const size_t shm = tile_lds_bytes<T>();
   int rc;
   if ((rc = ensure_dynamic_lds((const void *)batch_strail_kernel<T>, shm))) return rc;
+  // diagonal blocks with Y's block rows in LDS when every system's fit
+  int ncmax = 1;
+  for (int s = 0; s < count; ++s) ncmax = std::max(ncmax, shape_host[2 * s + 1]);
+  const size_t yshm = (size_t)kSB * ncmax * sizeof(cplx<T>);
+  const bool staged = yshm + sizeof(cplx<T>) * kSB * kSB <= 150 * 1024;
+  if (staged && (rc = ensure_dynamic_lds((const void *)batch_sdiag_kernel<T, true>, yshm))) return rc;
   hipLaunchKernelGGL(batch_rhs_kernel<T>, dim3(count), dim3(256), 0, st, count, items, perm, Y,
                      (const cplx<double> *)w.res, (const double *)w.cscale, (const BatchState *)w.state, mode);
   HP_CHECK_LAUNCH();
@@ -1596,7 +1615,12 @@ int stepped_solve(int count, const hp_batch_item *items, const int *shape_host, 
         const long rows = upper ? b0 : n - b0 - std::min(kSB, n - b0);
         tiles += ((rows + 63) / 64) * ((nc + 63) / 64);
       }
-      hipLaunchKernelGGL(batch_sdiag_kernel<T>, dim3(active), dim3(256), 0, st, items, LU, Y, b0, upper, state);
+      if (staged)
+        hipLaunchKernelGGL((batch_sdiag_kernel<T, true>), dim3(active), dim3(256), yshm, st, items, LU, Y, b0, upper,
+                           state);
+      else
+        hipLaunchKernelGGL((batch_sdiag_kernel<T, false>), dim3(active), dim3(256), 0, st, items, LU, Y, b0, upper,
+                           state);
       HP_CHECK_LAUNCH();
       if (tiles == 0) continue;
       hipLaunchKernelGGL(batch_strail_kernel<T>, dim3((unsigned)tiles), dim3(256), shm, st, active, items, LU, Y,
