@@ -110,6 +110,8 @@ def lib() -> ctypes.CDLL:
     L.hp_solve_schur.argtypes = [P(HpSystem), c_double, c_int, c_void_p, c_void_p, c_long, c_void_p, c_void_p,
                                  c_void_p, c_int, c_double, c_void_p, c_size_t, P(HpSolveInfo), c_void_p]
     L.hp_solve_schur.restype = c_int
+    L.hp_set_batch_reg_panel.argtypes = [c_int]
+    L.hp_set_batch_reg_panel.restype = c_int
     L.hp_lu_solve.argtypes = [c_int, c_int, c_int, c_void_p, c_long, c_void_p, c_void_p, c_long,
                               c_void_p, c_size_t, c_void_p]
     L.hp_lu_solve.restype = c_int
@@ -385,10 +387,7 @@ def hp_batch_smatrix(count, items, R, S, status, sum_nc2, nc_max, work, stream=N
 def hp_set_batch_reg_panel(on: bool) -> int:
     """FP32 batched panels held in registers (default) or through memory;
     returns the previous setting."""
-    L = lib()
-    L.hp_set_batch_reg_panel.argtypes = [c_int]
-    L.hp_set_batch_reg_panel.restype = c_int
-    return int(L.hp_set_batch_reg_panel(int(bool(on))))
+    return int(lib().hp_set_batch_reg_panel(int(bool(on))))
 
 
 def hp_set_concurrency(factorizations: int) -> int:

@@ -172,12 +172,13 @@ class EnergyScan:
     run beside the next slot's assembly and factorization.  Results are
     returned in energy order (R and S copied to the host)."""
 
-    def __init__(self, dsys: DeviceSystem, prec: int = H.HP_C64, slots: int = 2, fallback: bool = True):
+    def __init__(self, dsys: DeviceSystem, prec: int = H.HP_C64, slots: int = 2, fallback: bool = True,
+                 schur: bool = False):
         if slots < 1:
             raise ValueError("slots >= 1")
         self.d = dsys
         self.prec = prec
-        self.slots = [Solver(dsys, prec, fallback=fallback) for _ in range(slots)]
+        self.slots = [Solver(dsys, prec, fallback=fallback, schur=schur) for _ in range(slots)]
         self.streams = [torch.cuda.Stream(device=dsys.device) for _ in range(slots)]
 
     def run(self, energies, max_refine: int = 30, tol: float = 0.0) -> list[EnergyResult]:
