@@ -253,8 +253,11 @@ int hp_rmatrix(const hp_system *sys, const double *X, double *R, void *stream);
  * R, S: device nc x nc complex128; S receives U on the open-open entries and
  * zeros in the closed channels' rows and columns.  nopen (host, may be NULL)
  * receives the number of open channels.  HP_ERR_UNSUPPORTED if no channel is
- * open or E equals a threshold.  Uses work (hp_workspace_bytes(nc, nc,
- * HP_C128)).  Synchronizes the stream. */
+ * open or E equals a threshold; HP_ERR_NOCONV if an open channel's Coulomb
+ * functions cannot be formed (a continued fraction did not converge, or the
+ * channel lies so far below its Coulomb barrier that F and G leave double
+ * range).  Uses work (hp_workspace_bytes(nc, nc, HP_C128)).  Synchronizes
+ * the stream. */
 int hp_smatrix(const hp_system *sys, double E, const double *R, double *S, int *nopen,
                void *work, size_t work_bytes, void *stream);
 
@@ -279,7 +282,9 @@ int hp_smatrix_noalloc(const hp_system *sys, double E, const double *R, double *
 
 /* Coulomb functions F_l, F_l', G_l, G_l' (d/drho) at (eta, rho), computed on
  * the HOST with the same routine the device uses (for tests).  out: host [4].
- * Errors: HP_ERR_ARG if l < 0, rho <= 0 or eta < 0. */
+ * Errors: HP_ERR_ARG if l < 0, rho <= 0 or eta < 0; HP_ERR_NOCONV if a
+ * continued fraction did not converge or the functions leave double range
+ * (far below the Coulomb barrier: F underflows, G overflows). */
 int hp_coulomb(int l, double eta, double rho, double *out);
 
 /* Same routine on the device for nch channels: device arrays l[nch],
@@ -400,9 +405,9 @@ int hp_batch_status(int count, const void *work, int *status, int *iters, void *
  * substitution.  S is zero in closed rows and columns.  status: device
  * int[count], per system 0 ok, 1 no open channel or E exactly at a
  * threshold, 2 a Coulomb continued fraction (or a closed channel's
- * integration) did not converge, 3 an exactly zero pivot, 4 more than 512
- * channels; S of a system with status 1, 2 or 4 is not written, with status
- * 3 it holds no result.
+ * integration) did not converge or the Coulomb functions left double range,
+ * 3 an exactly zero pivot, 4 more than 512 channels; S of a system with
+ * status 1, 2 or 4 is not written, with status 3 it holds no result.
  * sum_nc2 = sum of nc^2 over the systems (host), nc_max = the largest nc
  * (host, at most 512, else HP_ERR_UNSUPPORTED).  work: device, at least
  * 32 * sum_nc2 bytes.  Asynchronous, no host synchronisation (may be

@@ -35,8 +35,16 @@ namespace hp {
 
 struct CoulombOut {
   double F, Fp, G, Gp;
-  int status;  // 0 ok, 1 continued fraction did not converge
+  int status;  // 0 ok, 1 a continued fraction did not converge or a value left double range
 };
+
+// Far below the Coulomb barrier (large eta, rho well inside the turning
+// point) F underflows and G overflows double range: reported, never returned
+// as a value.
+__host__ __device__ static void check_range(CoulombOut &o) {
+  auto finite = [](double v) { return v - v == 0.0; };  // false for inf and NaN
+  if (!(finite(o.F) && finite(o.Fp) && finite(o.G) && finite(o.Gp)) || o.F == 0.0) o.status = 1;
+}
 
 __host__ __device__ static double cf1_ratio(int L, double eta, double rho, double *sign) {
   const int ltop = L + (int)rho + 60;
@@ -130,6 +138,7 @@ __host__ __device__ static CoulombOut coulomb_fg(int L, double eta, double rho) 
   const double rtp = eta + sqrt(eta * eta + LL);
   if (rho >= rtp) {
     steed(L, eta, rho, o);
+    check_range(o);
     return o;
   }
   double x = rtp + 2.0;
@@ -147,6 +156,7 @@ __host__ __device__ static CoulombOut coulomb_fg(int L, double eta, double rho) 
   o.Fp = f * F;
   o.G = G;
   o.Gp = Gp;
+  check_range(o);
   return o;
 }
 

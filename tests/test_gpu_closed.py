@@ -191,3 +191,19 @@ def test_batched_matching_with_closed_channels(mods, prec):
         assert st[k] == 1 and sst[k] == 0
         o = opipe.solve_energy(sp, E)
         _check_S(bk.S_of(k), o, 1e-10)
+
+
+def test_open_channel_far_below_its_coulomb_barrier_is_reported(mods):
+    """An open channel 100 eV above its threshold under a strong Coulomb
+    field (eta ~ 4000): its Coulomb functions leave double range, which
+    hp_smatrix reports (HP_ERR_NOCONV) instead of returning NaN."""
+    H, P = mods
+    sp = make_system("small")
+    sp.z1z2 = 80
+    E = 12.0
+    sp.eps = np.array([0.0, E - 1e-4, 1.0, 2.0])
+    s = P.Solver(P.DeviceSystem(sp), H.HP_C128)
+    say("deep sub-barrier open channel")
+    with pytest.raises(H.HprmatError) as ei:
+        s.run(E)
+    assert ei.value.code == H.HP_ERR_NOCONV

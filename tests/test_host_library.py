@@ -165,3 +165,15 @@ def test_woodbury_arguments_checked_without_device(H):
     assert H.hp_schur_workspace_bytes(6, 2, H.HP_C64) > H.hp_workspace_bytes(6, 2, H.HP_C64)
     assert L.hp_solve_schur(ctypes.byref(s), 1.0, H.HP_C64, 1, 1, 6, 1, None, 1, 0, 0.0, 1, 16, None,
                             None) == H.HP_ERR_WORKSPACE
+
+
+def test_coulomb_out_of_range_is_reported(H):
+    """Far below the Coulomb barrier F underflows and G overflows double
+    range: the routine reports it instead of returning inf or NaN."""
+    with pytest.raises(H.HprmatError) as ei:
+        H.hp_coulomb(2, 322.0, 0.33)
+    assert ei.value.code == H.HP_ERR_NOCONV
+    with pytest.raises(H.HprmatError):
+        H.hp_coulomb(0, 300.0, 10.0)
+    f = H.hp_coulomb(0, 100.0, 3.0)  # deep, but inside double range
+    assert np.all(np.isfinite(f)) and f[0] > 0
