@@ -22,7 +22,10 @@ def solve_energy(params, E: float, md: system.MeshData | None = None,
         if np.all(E > np.asarray(params.eps, dtype=np.float64)):
             k, eta = rmatrix.wave_numbers(E, params.eps, params.hbar2_2mu, params.z1z2)
             fg = rmatrix.coulomb_table(params.l, eta, k * params.a)
-            U = rmatrix.smatrix(R, k, params.a, fg)
+            if rmatrix.in_double_range(fg):
+                U = rmatrix.smatrix(R, k, params.a, fg)
+            else:  # a channel far below its Coulomb barrier
+                U = rmatrix.smatrix_mp(R, k, params.a, np.asarray(params.l), eta)
             out.update(k=k, eta=eta, fg=fg, S=U, sigma=rmatrix.cross_sections(U, k),
                        open=np.arange(params.nc))
         else:

@@ -32,6 +32,11 @@ closed ones gives the open channels' effective R-matrix
 from which U (open channels only) follows as above (reading R12).
 Whittaker values come from mpmath; the derivative by mpmath's numerical
 differentiation at the working precision.
+
+Open channels far below their Coulomb barrier (large eta, rho well inside
+the turning point): F underflows and G overflows double range, so the same
+matching formula is evaluated with mpmath values and an mpmath solve
+(:func:`smatrix_mp`).
 """
 from __future__ import annotations
 
@@ -63,8 +68,9 @@ def wave_numbers(E: float, eps: np.ndarray, hbar2_2mu: float, z1z2: int) -> tupl
     return k, eta
 
 
-def coulomb(l: int, eta: float, rho: float, dps: int = 30) -> tuple[float, float, float, float]:
-    """(F, F', G, G') at (l, eta, rho), derivatives with respect to rho."""
+def coulomb_mp(l: int, eta: float, rho: float, dps: int = 30):
+    """(F, F', G, G') at (l, eta, rho) as mpmath numbers (no range limit),
+    derivatives with respect to rho."""
     with mpmath.workdps(dps):
         L = mpmath.mpf(l)
         et = mpmath.mpf(eta)
@@ -77,7 +83,12 @@ def coulomb(l: int, eta: float, rho: float, dps: int = 30) -> tuple[float, float
         r = mpmath.sqrt((L + 1) ** 2 + et ** 2)
         Fp = (s * F0 - r * F1) / (L + 1)
         Gp = (s * G0 - r * G1) / (L + 1)
-        return float(F0), float(Fp), float(G0), float(Gp)
+        return F0, Fp, G0, Gp
+
+
+def coulomb(l: int, eta: float, rho: float, dps: int = 30) -> tuple[float, float, float, float]:
+    """(F, F', G, G') at (l, eta, rho), derivatives with respect to rho."""
+    return tuple(float(x) for x in coulomb_mp(l, eta, rho, dps))
 
 
 def coulomb_table(l: np.ndarray, eta: np.ndarray, rho: np.ndarray) -> np.ndarray:
@@ -99,6 +110,47 @@ def smatrix(R: np.ndarray, k: np.ndarray, a: float, fg: np.ndarray) -> np.ndarra
     ZO = np.diag(O) - Rt * Op[None, :]
     ZI = np.diag(I) - Rt * Ip[None, :]
     return np.linalg.solve(ZO, ZI)
+
+
+def in_double_range(fg: np.ndarray) -> bool:
+    """Whether every channel's Coulomb values are finite doubles with F != 0
+    (far below a Coulomb barrier F underflows and G overflows)."""
+    return bool(np.all(np.isfinite(fg)) and np.all(fg[:, 0] != 0.0))
+
+
+def smatrix_mp(R: np.ndarray, k: np.ndarray, a: float, l: np.ndarray, eta: np.ndarray,
+               dps: int = 30) -> np.ndarray:
+    """The collision matrix of :func:`smatrix`, U = (O - Rt O')^-1 (I - Rt I'),
+    with the Coulomb values and the solve in mpmath arithmetic (for open
+    channels whose F and G leave double range); U rounded to complex128."""
+    nc = len(l)
+    with mpmath.workdps(dps):
+        fg = [coulomb_mp(int(l[c]), float(eta[c]), float(k[c] * a), dps) for c in range(nc)]
+        sq = [mpmath.sqrt(mpmath.mpf(float(k[c] * a))) for c in range(nc)]
+        ZO = mpmath.matrix(nc, nc)
+        ZI = mpmath.matrix(nc, nc)
+        for c in range(nc):
+            for cp in range(nc):
+                F, Fp, G, Gp = fg[cp]
+                rt = sq[c] * mpmath.mpc(complex(R[c, cp])) * sq[cp]
+                ZO[c, cp] = -rt * mpmath.mpc(Gp, Fp)
+                ZI[c, cp] = -rt * mpmath.mpc(Gp, -Fp)
+            F, Fp, G, Gp = fg[c]
+            ZO[c, c] += mpmath.mpc(G, F)
+            ZI[c, c] += mpmath.mpc(G, -F)
+        # columns scaled by d_c = 1/|G_c| (the solver's singularity test is
+        # relative to the matrix norm, which one G_c ~ 1e300 would dominate):
+        # U = D (ZO D)^-1 (ZI D) D^-1, an identity
+        d = [1 / abs(fg[c][2]) for c in range(nc)]
+        for c in range(nc):
+            for cp in range(nc):
+                ZO[c, cp] *= d[cp]
+                ZI[c, cp] *= d[cp]
+        U = np.zeros((nc, nc), dtype=np.complex128)
+        for j in range(nc):  # one right-hand column at a time
+            col = mpmath.lu_solve(ZO, ZI.column(j))
+            U[:, j] = [complex(d[i] * col[i] / d[j]) for i in range(nc)]
+        return U
 
 
 def closed_logderiv(l: int, eta: float, x: float, dps: int = 30) -> float:

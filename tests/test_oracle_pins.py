@@ -545,3 +545,77 @@ def test_woodbury_refuses_nonlocal_systems():
                       nlpot=separable_nonlocal(1.0, 1.0))
     with pytest.raises(ValueError, match="local"):
         woodbury.schur_system(sp, 1.0)
+
+
+# -------------------------------------------- far below a Coulomb barrier --
+# An open channel a few keV above its threshold under a Coulomb field of
+# Z1Z2 = 40 (eta ~ 300): F ~ 1e-300 and G ~ 1e+300 leave double range, and
+# the oracle evaluates the matching in mpmath (smatrix_mp).
+
+def _deep_system(coupled: bool):
+    nc, nr, a, h = 3, 40, 15.0, 2.0
+    Wt = np.array([[-30.0, 4.0, 3.0], [4.0, -22.0, 2.5], [3.0, 2.5, -27.0]])
+    if not coupled:
+        Wt[2, :2] = Wt[:2, 2] = 0.0
+
+    def pot(r):
+        f = 1.0 / (1.0 + np.exp((r - 5.0) / 0.6))
+        v = (Wt[None, :, :] * f[:, None, None]).astype(complex)
+        v[:, range(nc), range(nc)] += -4j * f[:, None]
+        return v
+    E = 12.0
+    return CustomSystem(nc=nc, nr=nr, a=a, l=np.array([0, 1, 2]), eps=np.array([0.0, 1.5, E - 0.005]),
+                        hbar2_2mu=h, pot=pot, z1z2=40), E
+
+
+def test_mp_matching_equals_double_matching_in_range():
+    sp = make_system("small")
+    E = float(sp.energies[3])
+    o = pipeline.solve_energy(sp, E)
+    k, eta = rmatrix.wave_numbers(E, sp.eps, sp.hbar2_2mu, sp.z1z2)
+    U = rmatrix.smatrix_mp(o["R"], k, sp.a, sp.l, eta)
+    assert relerr(U, o["S"]) < 1e-13
+
+
+def test_deep_channel_values_leave_double_range_and_keep_the_wronskian():
+    sp, E = _deep_system(True)
+    k, eta = rmatrix.wave_numbers(E, sp.eps, sp.hbar2_2mu, sp.z1z2)
+    assert eta[2] > 250
+    F, Fp, G, Gp = rmatrix.coulomb_mp(2, eta[2], k[2] * sp.a)
+    assert float(mpmath.log10(G)) > 300 and float(mpmath.log10(F)) < -300
+    assert abs(float(Fp * G - F * Gp) - 1.0) < 1e-20
+    fg = rmatrix.coulomb_table(sp.l, eta, k * sp.a)
+    assert not rmatrix.in_double_range(fg)
+
+
+def test_uncoupled_deep_channel_is_identity_and_leaves_the_rest():
+    """The deep channel coupled to nothing: its U row and column are those
+    of the identity (its nuclear phase is suppressed far beyond double
+    precision), and the other channels' U is that of the system without it."""
+    sp, E = _deep_system(False)
+    U = pipeline.solve_energy(sp, E)["S"]
+    sub = CustomSystem(nc=2, nr=sp.nr, a=sp.a, l=sp.l[:2], eps=sp.eps[:2], hbar2_2mu=sp.hbar2_2mu,
+                       pot=lambda r: sp.pot(r)[:, :2, :2].copy(), z1z2=sp.z1z2)
+    ref = pipeline.solve_energy(sub, E)["S"]
+    assert abs(U[2, 2] - 1.0) < 1e-12 and np.max(np.abs(U[2, :2])) < 1e-12 and np.max(np.abs(U[:2, 2])) < 1e-12
+    assert relerr(U[:2, :2], ref) < 1e-12
+
+
+def test_coupled_deep_channel_acts_through_its_log_derivative():
+    """A coupled deep channel carries no flux in double precision: over the
+    other channels U equals the matching with the effective R-matrix that
+    eliminates it with L = rho G'/G (its regular part F is negligible), the
+    closed-channel elimination of reading R12 with the irregular Coulomb
+    function in place of the Whittaker function."""
+    sp, E = _deep_system(True)
+    o = pipeline.solve_energy(sp, E)
+    U = o["S"]
+    k, eta = rmatrix.wave_numbers(E, sp.eps, sp.hbar2_2mu, sp.z1z2)
+    F, Fp, G, Gp = rmatrix.coulomb_mp(2, eta[2], k[2] * sp.a)
+    Ld = float(k[2] * sp.a * Gp / G)
+    R = o["R"]
+    Reff = R[:2, :2] + R[:2, 2:] * Ld @ np.linalg.inv(np.eye(1) - R[2:, 2:] * Ld) @ R[2:, :2]
+    fg = rmatrix.coulomb_table(sp.l[:2], eta[:2], k[:2] * sp.a)
+    ref = rmatrix.smatrix(Reff, k[:2], sp.a, fg)
+    assert relerr(U[:2, :2], ref) < 1e-10
+    assert np.max(np.abs(U[2, :2])) < 1e-12 and abs(U[2, 2] - 1.0) < 1e-12
