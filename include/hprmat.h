@@ -252,12 +252,15 @@ int hp_rmatrix(const hp_system *sys, const double *X, double *R, void *stream);
  * follows over the open channels as above.
  * R, S: device nc x nc complex128; S receives U on the open-open entries and
  * zeros in the closed channels' rows and columns.  nopen (host, may be NULL)
- * receives the number of open channels.  HP_ERR_UNSUPPORTED if no channel is
- * open or E equals a threshold; HP_ERR_NOCONV if an open channel's Coulomb
- * functions cannot be formed (a continued fraction did not converge, or the
- * channel lies so far below its Coulomb barrier that F and G leave double
- * range).  Uses work (hp_workspace_bytes(nc, nc, HP_C128)).  Synchronizes
- * the stream. */
+ * receives the number of open channels.  An open channel so far below its
+ * Coulomb barrier that F and G leave double range is carried with scaled
+ * values F~ = F e^theta, G~ = G e^-theta, and U is formed as
+ *   U = I - 2i E^-1 (diag O~ - Rt diag O~')^-1 (diag F~ - Rt diag F~') E^-1,
+ * E = diag(e^theta), O~ = G~ + i F~ e^-2theta (the same U; every factor
+ * e^-theta <= 1).  HP_ERR_UNSUPPORTED if no channel is open or E equals a
+ * threshold; HP_ERR_NOCONV if a continued fraction did not converge, or if
+ * such a channel occurs together with closed channels.  Uses work
+ * (hp_workspace_bytes(nc, nc, HP_C128)).  Synchronizes the stream. */
 int hp_smatrix(const hp_system *sys, double E, const double *R, double *S, int *nopen,
                void *work, size_t work_bytes, void *stream);
 

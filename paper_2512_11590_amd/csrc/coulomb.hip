@@ -42,8 +42,9 @@ struct CoulombOut {
 // point) F underflows and G overflows double range: reported, never returned
 // as a value.
 __host__ __device__ static void check_range(CoulombOut &o) {
-  auto finite = [](double v) { return v - v == 0.0; };  // false for inf and NaN
-  if (!(finite(o.F) && finite(o.Fp) && finite(o.G) && finite(o.Gp)) || o.F == 0.0) o.status = 1;
+  const bool finite = __builtin_isfinite(o.F) && __builtin_isfinite(o.Fp) && __builtin_isfinite(o.G) &&
+                      __builtin_isfinite(o.Gp);
+  if (!finite || o.F == 0.0) o.status = 1;
 }
 
 __host__ __device__ static double cf1_ratio(int L, double eta, double rho, double *sign) {
@@ -132,8 +133,15 @@ __host__ __device__ static void taylor_step(double LL, double eta, double x0, do
   up = sp;
 }
 
-__host__ __device__ static CoulombOut coulomb_fg(int L, double eta, double rho) {
+// With scale: far inside the turning point G grows beyond double range on
+// the way in; whenever |G| passes 1e150 the pair (G, G') is divided by |G|
+// and the logarithm added to *scale, so the values returned are
+// G~ = G e^-scale, G~' likewise and F~ = F e^scale = 1/(f G~ - G~') (the
+// Wronskian with the scaled G).  Channels that never pass 1e150 come out
+// exactly as unscaled, with *scale = 0.
+__host__ __device__ static CoulombOut coulomb_fg_scaled(int L, double eta, double rho, double *scale) {
   CoulombOut o;
+  *scale = 0.0;
   const double LL = (double)L * (L + 1);
   const double rtp = eta + sqrt(eta * eta + LL);
   if (rho >= rtp) {
@@ -143,11 +151,17 @@ __host__ __device__ static CoulombOut coulomb_fg(int L, double eta, double rho) 
   }
   double x = rtp + 2.0;
   steed(L, eta, x, o);
-  double G = o.G, Gp = o.Gp;
+  double G = o.G, Gp = o.Gp, th = 0.0;
   while (x > rho) {
     double h = -fmin(1.0, fmin(0.25 * x, x - rho));
     taylor_step(LL, eta, x, h, G, Gp);
     x += h;
+    const double m = fabs(G);
+    if (m > 1e150) {
+      G /= m;
+      Gp /= m;
+      th += log(m);
+    }
   }
   double sg;
   const double f = cf1_ratio(L, eta, rho, &sg);
@@ -157,6 +171,15 @@ __host__ __device__ static CoulombOut coulomb_fg(int L, double eta, double rho) 
   o.G = G;
   o.Gp = Gp;
   check_range(o);
+  *scale = th;
+  return o;
+}
+
+// Unscaled values; status 1 where they leave double range.
+__host__ __device__ static CoulombOut coulomb_fg(int L, double eta, double rho) {
+  double th;
+  CoulombOut o = coulomb_fg_scaled(L, eta, rho, &th);
+  if (th > 0.0) o.status = 1;
   return o;
 }
 
@@ -200,13 +223,15 @@ __global__ void coulomb_kernel(int nch, const int *__restrict__ l, const double 
 // Per channel: k, eta, rho, then (F, F', G, G'); status per channel in st[c]
 // (0 ok, 2 continued fraction did not converge, 3 closed channel with its
 // log-derivative L_c = a u'(a)/u(a) in fg[4c], 4 at a threshold or out of
-// range).
+// range, 6 open but far below its Coulomb barrier: fg holds the values
+// scaled by e^-+theta[c] as coulomb_fg_scaled returns them).
 __global__ void channel_kernel(int nc, double E, double h, double z1z2e2, double a, const int *__restrict__ l,
                                const double *__restrict__ eps, double *__restrict__ fg, double *__restrict__ sqrho,
-                               int *__restrict__ stat) {
+                               double *__restrict__ theta, int *__restrict__ stat) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   const double ec = E - eps[c];
+  theta[c] = 0.0;
   if (!(ec > 0.0)) {
     fg[4 * c] = fg[4 * c + 1] = fg[4 * c + 2] = fg[4 * c + 3] = 0.0;
     sqrho[c] = 0.0;
@@ -224,13 +249,63 @@ __global__ void channel_kernel(int nc, double E, double h, double z1z2e2, double
   const double k = sqrt(ec / h);
   const double eta = z1z2e2 / (2.0 * h * k);
   const double rho = k * a;
-  CoulombOut o = coulomb_fg(l[c], eta, rho);
+  double th;
+  CoulombOut o = coulomb_fg_scaled(l[c], eta, rho, &th);
   fg[4 * c + 0] = o.F;
   fg[4 * c + 1] = o.Fp;
   fg[4 * c + 2] = o.G;
   fg[4 * c + 3] = o.Gp;
   sqrho[c] = sqrt(rho);
-  stat[c] = o.status ? 2 : 0;
+  theta[c] = th;
+  stat[c] = o.status ? 2 : (th > 0.0 ? 6 : 0);
+}
+
+// The matching with scaled channel values (some open channel far below its
+// Coulomb barrier): with O = e^theta O~, O~ = G~ + i F~ e^-2theta (likewise
+// O', I, I'), ZO = (diag O~ - Rt diag O~') E and ZI = ZO - 2i Q E with
+// Q = diag F~ - Rt diag F~' and E = diag(e^theta), so
+//   U = ZO^-1 ZI = I - 2i E^-1 (diag O~ - Rt diag O~')^-1 Q E^-1,
+// every factor e^-theta <= 1.  This kernel writes ZO~ and Q E^-1 over the
+// no open channels (oidx: their channel numbers, null for all; R at stride
+// ldr indexed by open position).
+__global__ void zmat_scaled_kernel(int no, const cplx<double> *__restrict__ R, long ldr, const double *__restrict__ fg,
+                                   const double *__restrict__ sqrho, const double *__restrict__ theta,
+                                   const int *__restrict__ oidx, cplx<double> *__restrict__ ZO,
+                                   cplx<double> *__restrict__ ZQ) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)no * no) return;
+  const int i = (int)(e / no), j = (int)(e - (long)i * no);
+  const int c = oidx ? oidx[i] : i, cp = oidx ? oidx[j] : j;
+  const double s = sqrho[c] * sqrho[cp];
+  const cplx<double> r = R[(long)i * ldr + j];
+  const cplx<double> rt{s * r.re, s * r.im};
+  const double sc = exp(-2.0 * theta[cp]);
+  const double Fp = fg[4 * cp + 1], Gp = fg[4 * cp + 3];
+  cplx<double> zo = cmul(rt, cplx<double>{Gp, Fp * sc});
+  zo = cplx<double>{-zo.re, -zo.im};
+  cplx<double> q{-rt.re * Fp, -rt.im * Fp};
+  if (i == j) {  // c == cp
+    zo.re += fg[4 * c + 2];
+    zo.im += fg[4 * c] * sc;
+    q.re += fg[4 * c];
+  }
+  const double ej = exp(-theta[cp]);
+  ZO[e] = zo;
+  ZQ[e] = cplx<double>{q.re * ej, q.im * ej};
+}
+
+// U = I - 2i E^-1 Y in place (Y = ZO~^-1 Q E^-1, no x no).
+__global__ void u_scaled_kernel(int no, const double *__restrict__ theta, const int *__restrict__ oidx,
+                                cplx<double> *__restrict__ Y) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)no * no) return;
+  const int i = (int)(e / no), j = (int)(e - (long)i * no);
+  const double ei = exp(-theta[oidx ? oidx[i] : i]);
+  const cplx<double> y = Y[e];
+  // -2i ei y = (2 ei y.im, -2 ei y.re)
+  cplx<double> u{2.0 * ei * y.im, -2.0 * ei * y.re};
+  if (i == j) u.re += 1.0;
+  Y[e] = u;
 }
 
 // ZO = diag(O) - Rt diag(O'), ZI = diag(I) - Rt diag(I'), both nc x nc row-major.
@@ -613,13 +688,14 @@ static int smatrix_impl(const hp_system *sys, double E, const double *R, double 
   cplx<double> *tmp = (cplx<double> *)(w + ws.rhs_off);
   double *fg = (double *)(w + ws.red_off);
   double *sqrho = fg + 4 * (size_t)nc;
-  int *stat = (int *)(sqrho + nc);
+  double *theta = sqrho + nc;
+  int *stat = (int *)(theta + nc);
   int *ipiv = stat + nc;
   int *perm = ipiv + nc;
   int *finfo = (int *)(w + ws.flag_off);
   TraceScope ts(TR_SMATRIX, st, 8.0 / 3.0 * (double)nc * nc * nc, 0.0);
   hipLaunchKernelGGL(channel_kernel, dim3((nc + 63) / 64), dim3(64), 0, st, nc, E, sys->hbar2_2mu, sys->z1z2e2,
-                     sys->a, sys->l, sys->eps, fg, sqrho, stat);
+                     sys->a, sys->l, sys->eps, fg, sqrho, theta, stat);
   HP_CHECK_LAUNCH();
   const long cnt = (long)nc * nc;
   hipLaunchKernelGGL(zmat_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, nc,
@@ -632,21 +708,42 @@ static int smatrix_impl(const hp_system *sys, double E, const double *R, double 
   HP_CHECK_HIP(hipMemcpyAsync(&hinfo, finfo, sizeof(int), hipMemcpyDeviceToHost, st));
   HP_CHECK_HIP(hipMemcpyAsync(hstat, stat, sizeof(int) * nc, hipMemcpyDeviceToHost, st));
   HP_CHECK_HIP(hipStreamSynchronize(st));
-  int open = 0, closed = 0, bad = 0, edge = 0;
+  int open = 0, closed = 0, bad = 0, edge = 0, scaled = 0;
   for (int c = 0; c < nc; ++c) {
-    if (hstat[c] == 0)
+    if (hstat[c] == 0 || hstat[c] == 6) {
       ++open;
-    else if (hstat[c] == 3)
+      if (hstat[c] == 6) scaled = 1;
+    } else if (hstat[c] == 3) {
       ++closed;
-    else if (hstat[c] == 2)
+    } else if (hstat[c] == 2) {
       bad = 1;
-    else
+    } else {
       edge = 1;
+    }
   }
   if (nopen) *nopen = open;
   if (bad) return HP_ERR_NOCONV;
   if (edge || open == 0) return HP_ERR_UNSUPPORTED;  // at a threshold, or no open channel
-  if (closed == 0) {
+  if (scaled && closed) return HP_ERR_NOCONV;  // not handled together
+  if (closed == 0 && !scaled) {
+    if (hinfo == -1) return HP_ERR_SYNC;
+    if (hinfo > 0) return HP_ERR_SINGULAR;
+    return HP_OK;
+  }
+  if (scaled) {
+    // some open channel far below its Coulomb barrier: the pass above is
+    // discarded; U = I - 2i E^-1 ZO~^-1 Q E^-1 (zmat_scaled_kernel)
+    hipLaunchKernelGGL(zmat_scaled_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, nc,
+                       (const cplx<double> *)R, (long)nc, fg, sqrho, theta, (const int *)nullptr, ZO,
+                       (cplx<double> *)S);
+    HP_CHECK_LAUNCH();
+    if ((rc = lu_factor<double>(nc, ZO, nc, ipiv, perm, finfo, w, ws, st))) return rc;
+    if ((rc = lu_solve<double>(nc, nc, ZO, nc, perm, (cplx<double> *)S, nc, tmp, nullptr, st))) return rc;
+    hipLaunchKernelGGL(u_scaled_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, nc, theta,
+                       (const int *)nullptr, (cplx<double> *)S);
+    HP_CHECK_LAUNCH();
+    HP_CHECK_HIP(hipMemcpyAsync(&hinfo, finfo, sizeof(int), hipMemcpyDeviceToHost, st));
+    HP_CHECK_HIP(hipStreamSynchronize(st));
     if (hinfo == -1) return HP_ERR_SYNC;
     if (hinfo > 0) return HP_ERR_SINGULAR;
     return HP_OK;

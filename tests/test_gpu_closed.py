@@ -193,17 +193,64 @@ def test_batched_matching_with_closed_channels(mods, prec):
         _check_S(bk.S_of(k), o, 1e-10)
 
 
-def test_open_channel_far_below_its_coulomb_barrier_is_reported(mods):
-    """An open channel 100 eV above its threshold under a strong Coulomb
-    field (eta ~ 4000): its Coulomb functions leave double range, which
-    hp_smatrix reports (HP_ERR_NOCONV) instead of returning NaN."""
-    H, P = mods
-    sp = make_system("small")
-    sp.z1z2 = 80
+def _deep_system(coupled: bool, closed: bool = False):
+    """Three channels at 12 MeV, Z1Z2 = 40, the third 5 keV above its
+    threshold (eta ~ 290: F ~ 1e-310, G ~ 1e+307), optionally a fourth,
+    closed one."""
+    nc = 4 if closed else 3
+    Wt = np.full((nc, nc), 2.5)
+    Wt[np.diag_indices(nc)] = [-30.0, -22.0, -27.0, -25.0][:nc]
+    if not coupled:
+        Wt[2, :] = Wt[:, 2] = 0.0
+        Wt[2, 2] = -27.0
+
+    def pot(r):
+        f = 1.0 / (1.0 + np.exp((r - 5.0) / 0.6))
+        v = (Wt[None, :, :] * f[:, None, None]).astype(complex)
+        v[:, range(nc), range(nc)] += -4j * f[:, None]
+        return v
     E = 12.0
-    sp.eps = np.array([0.0, E - 1e-4, 1.0, 2.0])
+    eps = [0.0, 1.5, E - 0.005, 14.0][:nc]
+    return CustomSystem(nc=nc, nr=40, a=15.0, l=np.array([0, 1, 2, 1][:nc]), eps=np.array(eps), hbar2_2mu=2.0,
+                        pot=pot, z1z2=40), E
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("coupled", [True, False])
+def test_open_channel_far_below_its_coulomb_barrier(mods, prec, coupled):
+    """An open channel whose F and G leave double range: the device carries
+    them scaled by e^-+theta and matches with U = I - 2i E^-1 ZO~^-1 Q E^-1;
+    S against the oracle's mpmath matching."""
+    H, P = mods
+    sp, E = _deep_system(coupled)
+    o = opipe.solve_energy(sp, E)
+    say("deep sub-barrier channel, coupled", coupled, "prec", prec)
+    res = P.Solver(P.DeviceSystem(sp), prec).run(E)
+    S = res.S.cpu().numpy()
+    assert res.nopen == 3 and np.all(np.isfinite(S))
+    assert relerr(S, o["S"]) < 1e-10
+    assert abs(S[2, 2] - 1.0) < 1e-12
+
+
+def test_deep_channel_with_closed_channels_is_reported(mods):
+    """A channel far below its Coulomb barrier together with a closed
+    channel is not handled: HP_ERR_NOCONV, no values."""
+    H, P = mods
+    sp, E = _deep_system(True, closed=True)
     s = P.Solver(P.DeviceSystem(sp), H.HP_C128)
-    say("deep sub-barrier open channel")
     with pytest.raises(H.HprmatError) as ei:
         s.run(E)
     assert ei.value.code == H.HP_ERR_NOCONV
+
+
+def test_batched_matching_reports_a_deep_channel(mods):
+    """The batched matching takes in-range Coulomb values only: status 2."""
+    H, P = mods
+    from paper_2512_11590_amd import batch as B
+    sp, E = _deep_system(True)
+    bk = B.Bucket([sp], [E], [0], H.HP_C128)
+    bk.factor(8, 0, 8)
+    bk.solve(0)
+    bk.rmatrix()
+    bk.smatrix()
+    assert int(bk.sstat.cpu().numpy()[0]) == 2
