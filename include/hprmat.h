@@ -257,9 +257,9 @@ int hp_rmatrix(const hp_system *sys, const double *X, double *R, void *stream);
  * values F~ = F e^theta, G~ = G e^-theta, and U is formed as
  *   U = I - 2i E^-1 (diag O~ - Rt diag O~')^-1 (diag F~ - Rt diag F~') E^-1,
  * E = diag(e^theta), O~ = G~ + i F~ e^-2theta (the same U; every factor
- * e^-theta <= 1).  HP_ERR_UNSUPPORTED if no channel is open or E equals a
- * threshold; HP_ERR_NOCONV if a continued fraction did not converge, or if
- * such a channel occurs together with closed channels.  Uses work
+ * e^-theta <= 1; with closed channels, over the open ones from R_eff).
+ * HP_ERR_UNSUPPORTED if no channel is open or E equals a threshold;
+ * HP_ERR_NOCONV if a continued fraction did not converge.  Uses work
  * (hp_workspace_bytes(nc, nc, HP_C128)).  Synchronizes the stream. */
 int hp_smatrix(const hp_system *sys, double E, const double *R, double *S, int *nopen,
                void *work, size_t work_bytes, void *stream);
@@ -408,8 +408,8 @@ int hp_batch_status(int count, const void *work, int *status, int *iters, void *
  * substitution.  S is zero in closed rows and columns.  status: device
  * int[count], per system 0 ok, 1 no open channel or E exactly at a
  * threshold, 2 a Coulomb continued fraction (or a closed channel's
- * integration) did not converge or the Coulomb functions left double range,
- * 3 an exactly zero pivot, 4 more than 512 channels; S of a system with
+ * integration) did not converge (channels far below their Coulomb barrier
+ * are matched in the scaled form of hp_smatrix), 3 an exactly zero pivot, 4 more than 512 channels; S of a system with
  * status 1, 2 or 4 is not written, with status 3 it holds no result.
  * sum_nc2 = sum of nc^2 over the systems (host), nc_max = the largest nc
  * (host, at most 512, else HP_ERR_UNSUPPORTED).  work: device, at least

@@ -192,7 +192,10 @@ def smatrix_closed(R: np.ndarray, E: float, eps: np.ndarray, l: np.ndarray, hbar
         Y = np.linalg.solve(np.eye(len(c)) - R[np.ix_(c, c)] @ Lm, R[np.ix_(c, o)])
         Reff = Reff + R[np.ix_(o, c)] @ Lm @ Y
     fg = coulomb_table(np.asarray(l)[o], eta[o], kk[o] * a)
-    return smatrix(Reff, kk[o], a, fg), o, Reff
+    if in_double_range(fg):
+        return smatrix(Reff, kk[o], a, fg), o, Reff
+    # an open channel far below its Coulomb barrier
+    return smatrix_mp(Reff, kk[o], a, np.asarray(l)[o], eta[o]), o, Reff
 
 
 def cross_sections(U: np.ndarray, k: np.ndarray) -> np.ndarray:

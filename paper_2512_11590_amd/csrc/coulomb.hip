@@ -537,10 +537,11 @@ __global__ __launch_bounds__(256) void batch_smatrix_kernel(int count, const hp_
                                                             int *__restrict__ status) {
   __shared__ double fg[4 * kBatchSmatMaxChannels];
   __shared__ double sqrho[kBatchSmatMaxChannels];
+  __shared__ double thl[kBatchSmatMaxChannels];  // scales of channels far below their barrier
   __shared__ int oidx[kBatchSmatMaxChannels], cidx[kBatchSmatMaxChannels];
   __shared__ double sv[4];
   __shared__ int sr[4];
-  __shared__ int s_bad, s_no, s_ncl;
+  __shared__ int s_bad, s_no, s_ncl, s_scaled;
   const int sidx = blockIdx.x;
   if (sidx >= count) return;
   const hp_batch_item it = items[sidx];
@@ -550,12 +551,13 @@ __global__ __launch_bounds__(256) void batch_smatrix_kernel(int count, const hp_
     if (tid == 0) status[sidx] = 4;
     return;
   }
-  if (tid == 0) s_bad = 0;
+  if (tid == 0) s_bad = s_scaled = 0;
   __syncthreads();
   for (int c = tid; c < nc; c += 256) {
     const double ec = it.E - sys.eps[c];
     fg[4 * c] = fg[4 * c + 1] = fg[4 * c + 2] = fg[4 * c + 3] = 0.0;
     sqrho[c] = 0.0;
+    thl[c] = 0.0;
     if (!(ec > 0.0)) {
       if (!(ec < 0.0)) {  // at the threshold (or NaN)
         atomicMax(&s_bad, 1);
@@ -571,12 +573,15 @@ __global__ __launch_bounds__(256) void batch_smatrix_kernel(int count, const hp_
     const double k = sqrt(ec / sys.hbar2_2mu);
     const double eta = sys.z1z2e2 / (2.0 * sys.hbar2_2mu * k);
     const double rho = k * sys.a;
-    const CoulombOut o = coulomb_fg(sys.l[c], eta, rho);
+    double th;
+    const CoulombOut o = coulomb_fg_scaled(sys.l[c], eta, rho, &th);
     fg[4 * c + 0] = o.F;
     fg[4 * c + 1] = o.Fp;
     fg[4 * c + 2] = o.G;
     fg[4 * c + 3] = o.Gp;
     sqrho[c] = sqrt(rho);
+    thl[c] = th;
+    if (th > 0.0) atomicMax(&s_scaled, 1);
     if (o.status) atomicMax(&s_bad, 2);
   }
   __syncthreads();
@@ -653,6 +658,21 @@ __global__ __launch_bounds__(256) void batch_smatrix_kernel(int count, const hp_
     const cplx<double> rr = Ro[(long)i * ldr + j];
     const cplx<double> rt{sc * rr.re, sc * rr.im};
     const double F = fg[4 * cp], Fp = fg[4 * cp + 1], G = fg[4 * cp + 2], Gp = fg[4 * cp + 3];
+    if (s_scaled) {  // zmat_scaled_kernel's form: [ZO~ | Q E^-1]
+      const double sc = exp(-2.0 * thl[cp]);
+      cplx<double> zo = cmul(rt, cplx<double>{Gp, Fp * sc});
+      zo = cplx<double>{-zo.re, -zo.im};
+      cplx<double> q{-rt.re * Fp, -rt.im * Fp};
+      if (i == j) {
+        zo.re += G;
+        zo.im += F * sc;
+        q.re += F;
+      }
+      const double ej = exp(-thl[cp]);
+      z[(long)i * w2 + j] = zo;
+      z[(long)i * w2 + no + j] = cplx<double>{q.re * ej, q.im * ej};
+      continue;
+    }
     cplx<double> zo = cmul(rt, cplx<double>{Gp, Fp});
     cplx<double> zi = cmul(rt, cplx<double>{Gp, -Fp});
     zo = cplx<double>{-zo.re, -zo.im};
@@ -676,6 +696,18 @@ __global__ __launch_bounds__(256) void batch_smatrix_kernel(int count, const hp_
   }
   // back substitution: S_oo = U^-1 (right half), scattered to the open rows and columns
   block_back_substitute(z, no, w2, no, Ss, nc, ncl ? oidx : nullptr, ncl ? oidx : nullptr);
+  if (s_scaled) {  // U = I - 2i E^-1 Y over the open channels
+    __syncthreads();
+    for (int e = tid; e < no * no; e += 256) {
+      const int i = e / no, j = e - i * no;
+      const int ci = ncl ? oidx[i] : i, cj = ncl ? oidx[j] : j;
+      const double ei = exp(-thl[ci]);
+      const cplx<double> y = Ss[(long)ci * nc + cj];
+      cplx<double> u{2.0 * ei * y.im, -2.0 * ei * y.re};
+      if (i == j) u.re += 1.0;
+      Ss[(long)ci * nc + cj] = u;
+    }
+  }
   if (tid == 0) status[sidx] = 0;
 }
 
@@ -724,13 +756,12 @@ static int smatrix_impl(const hp_system *sys, double E, const double *R, double 
   if (nopen) *nopen = open;
   if (bad) return HP_ERR_NOCONV;
   if (edge || open == 0) return HP_ERR_UNSUPPORTED;  // at a threshold, or no open channel
-  if (scaled && closed) return HP_ERR_NOCONV;  // not handled together
   if (closed == 0 && !scaled) {
     if (hinfo == -1) return HP_ERR_SYNC;
     if (hinfo > 0) return HP_ERR_SINGULAR;
     return HP_OK;
   }
-  if (scaled) {
+  if (closed == 0) {
     // some open channel far below its Coulomb barrier: the pass above is
     // discarded; U = I - 2i E^-1 ZO~^-1 Q E^-1 (zmat_scaled_kernel)
     hipLaunchKernelGGL(zmat_scaled_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, nc,
@@ -752,7 +783,7 @@ static int smatrix_impl(const hp_system *sys, double E, const double *R, double 
   // R_eff and match over the open channels
   const int no = open, ncl = closed;
   for (int c = 0, io = 0, ic = 0; c < nc; ++c) {
-    if (hstat[c] == 0)
+    if (hstat[c] == 0 || hstat[c] == 6)
       hidx[io++] = c;
     else
       hidx[no + ic++] = c;
@@ -773,11 +804,21 @@ static int smatrix_impl(const hp_system *sys, double E, const double *R, double 
   hipLaunchKernelGGL(reff_kernel, dim3((unsigned)((cnt_o + 255) / 256)), dim3(256), 0, st, nc, ncl, no,
                      (const cplx<double> *)R, fg, cidx, oidx, Y, Reff);
   HP_CHECK_LAUNCH();
-  hipLaunchKernelGGL(zmat_open_kernel, dim3((unsigned)((cnt_o + 255) / 256)), dim3(256), 0, st, no, Reff, fg,
-                     sqrho, oidx, ZO, (cplx<double> *)S);
+  if (scaled)  // an open channel far below its Coulomb barrier: the scaled form over the open channels
+    hipLaunchKernelGGL(zmat_scaled_kernel, dim3((unsigned)((cnt_o + 255) / 256)), dim3(256), 0, st, no,
+                       (const cplx<double> *)Reff, (long)no, fg, sqrho, theta, (const int *)oidx, ZO,
+                       (cplx<double> *)S);
+  else
+    hipLaunchKernelGGL(zmat_open_kernel, dim3((unsigned)((cnt_o + 255) / 256)), dim3(256), 0, st, no, Reff, fg,
+                       sqrho, oidx, ZO, (cplx<double> *)S);
   HP_CHECK_LAUNCH();
   if ((rc = lu_factor<double>(no, ZO, no, ipiv, perm, finfo, w, ws, st))) return rc;
   if ((rc = lu_solve<double>(no, no, ZO, no, perm, (cplx<double> *)S, no, tmp, nullptr, st))) return rc;
+  if (scaled) {
+    hipLaunchKernelGGL(u_scaled_kernel, dim3((unsigned)((cnt_o + 255) / 256)), dim3(256), 0, st, no, theta,
+                       (const int *)oidx, (cplx<double> *)S);
+    HP_CHECK_LAUNCH();
+  }
   // U (no x no, packed at the start of S) to its place in S, zeros elsewhere
   HP_CHECK_HIP(hipMemcpyAsync(Reff, S, sizeof(cplx<double>) * (size_t)cnt_o, hipMemcpyDeviceToDevice, st));
   {

@@ -232,25 +232,32 @@ def test_open_channel_far_below_its_coulomb_barrier(mods, prec, coupled):
     assert abs(S[2, 2] - 1.0) < 1e-12
 
 
-def test_deep_channel_with_closed_channels_is_reported(mods):
+def test_deep_channel_with_closed_channels(mods):
     """A channel far below its Coulomb barrier together with a closed
-    channel is not handled: HP_ERR_NOCONV, no values."""
+    channel: the closed one eliminated through R_eff, the scaled matching
+    over the open ones; S against the oracle."""
     H, P = mods
     sp, E = _deep_system(True, closed=True)
-    s = P.Solver(P.DeviceSystem(sp), H.HP_C128)
-    with pytest.raises(H.HprmatError) as ei:
-        s.run(E)
-    assert ei.value.code == H.HP_ERR_NOCONV
+    o = opipe.solve_energy(sp, E)
+    say("deep and closed channels")
+    res = P.Solver(P.DeviceSystem(sp), H.HP_C128).run(E)
+    assert res.nopen == 3
+    _check_S(res.S.cpu().numpy(), o, 1e-10)
 
 
-def test_batched_matching_reports_a_deep_channel(mods):
-    """The batched matching takes in-range Coulomb values only: status 2."""
+@pytest.mark.parametrize("closed", [False, True])
+def test_batched_matching_with_a_deep_channel(mods, closed):
+    """The batched matching takes the same scaled form, with and without a
+    closed channel; S against the oracle."""
     H, P = mods
     from paper_2512_11590_amd import batch as B
-    sp, E = _deep_system(True)
+    sp, E = _deep_system(True, closed=closed)
+    o = opipe.solve_energy(sp, E)
     bk = B.Bucket([sp], [E], [0], H.HP_C128)
     bk.factor(8, 0, 8)
     bk.solve(0)
     bk.rmatrix()
     bk.smatrix()
-    assert int(bk.sstat.cpu().numpy()[0]) == 2
+    say("batched deep channel, closed", closed)
+    assert int(bk.sstat.cpu().numpy()[0]) == 0
+    _check_S(bk.S_of(0), o, 1e-10)
