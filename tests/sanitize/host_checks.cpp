@@ -81,6 +81,33 @@ static void coulomb_checks() {
   check(hp_coulomb(0, 0.0, 1.0, nullptr) == HP_ERR_ARG, "hp_coulomb null out");
 }
 
+// The kinetic inverse (binary128 elimination) against the matrix it inverts,
+// and the Woodbury-kinetic and deep-Coulomb host paths.
+static void woodbury_and_range_checks() {
+  const int nrs[] = {1, 7, 40};
+  for (int nr : nrs) {
+    double *tl = exact<double>((size_t)nr * nr), *ki = exact<double>((size_t)nr * nr);
+    check(hp_mesh(nr, 10.0, nullptr, nullptr, nullptr, tl) == HP_OK, "mesh for the inverse", nr);
+    check(hp_kinetic_inverse(nr, 10.0, ki) == HP_OK, "hp_kinetic_inverse status", nr);
+    double worst = 0.0;
+    for (int i = 0; i < nr; ++i)
+      for (int j = 0; j < nr; ++j) {
+        long double s = 0.0L;
+        for (int k = 0; k < nr; ++k) s += (long double)tl[(size_t)i * nr + k] * ki[(size_t)k * nr + j];
+        worst = std::fmax(worst, std::fabs((double)(s - (i == j ? 1.0L : 0.0L))));
+      }
+    check(worst < 1e-6, "tl * kinv = I", worst, nr);
+    std::free(tl);
+    std::free(ki);
+  }
+  check(hp_kinetic_inverse(0, 1.0, nullptr) == HP_ERR_ARG, "kinetic_inverse nr = 0");
+  check(hp_schur_workspace_bytes(6, 4, HP_C64) == 0, "schur workspace n % nrhs");
+  check(hp_schur_workspace_bytes(600, 6, HP_C64) > hp_workspace_bytes(600, 6, HP_C64), "schur workspace extra");
+  double out[4];
+  check(hp_coulomb(2, 322.0, 0.33, out) == HP_ERR_NOCONV, "coulomb far below the barrier reported");
+  check(hp_coulomb(0, 100.0, 3.0, out) == HP_OK, "coulomb deep but in range");
+}
+
 static void workspace_checks() {
   const int ns[] = {1, 2, 127, 128, 129, 1000, 4000, 25600, 60000};
   const int nrhs[] = {0, 1, 64, 256};
@@ -164,6 +191,7 @@ static void argument_checks() {
 int main() {
   mesh_checks();
   coulomb_checks();
+  woodbury_and_range_checks();
   workspace_checks();
   argument_checks();
   if (g_fail) {

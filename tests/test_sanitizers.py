@@ -24,7 +24,7 @@ INCLUDE = os.path.join(ROOT, "include")
 HERE = os.path.join(ROOT, "tests", "sanitize")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_SOURCES = ["assemble.hip", "lu.hip", "gemm.hip", "gemm_h3.hip", "solve.hip", "wsolve.hip", "coulomb.hip",
-               "abi.hip", "trace.hip", "batch.hip"]
+               "abi.hip", "trace.hip", "batch.hip", "woodbury.hip"]
 # sanitizers on the host pass only
 HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
             "-Xarch_host", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
