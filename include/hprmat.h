@@ -101,7 +101,9 @@ int hp_mesh(int nr, double a, double *r, double *w, double *q, double *tl);
  * block K = (hbar^2/2mu) tl of the Woodbury-kinetic form, Sec. 3.3, step 1,
  * without the factor hbar^2/2mu): kinv[i*nr + j] = (tl^-1)_ij for the rounded
  * tl that hp_mesh returns, by Gauss-Jordan elimination with partial pivoting
- * in binary128, rounded once.  Energy-independent: once per mesh.  kinv:
+ * in binary128, rounded once.  Energy-independent: once per mesh.  Runs on
+ * the calling host thread: about 2 nr^3 binary128 operations in software
+ * arithmetic (0.08 s at nr = 100, 4 s at nr = 400 on one core).  kinv:
  * HOST nr*nr doubles.  Errors: HP_ERR_ARG (nr < 1, a <= 0, kinv NULL),
  * HP_ERR_SINGULAR. */
 int hp_kinetic_inverse(int nr, double a, double *kinv);
