@@ -246,6 +246,27 @@ def test_deep_channel_with_closed_channels(mods):
 
 
 @pytest.mark.parametrize("closed", [False, True])
+def test_noalloc_form_with_a_deep_channel(mods, closed):
+    """hp_smatrix_noalloc on the scaled matching (and with a closed channel
+    eliminated first): the same S as hp_smatrix, bit for bit, and the
+    oracle's S."""
+    H, P = mods
+    sp, E = _deep_system(True, closed=closed)
+    o = opipe.solve_energy(sp, E)
+    d = P.DeviceSystem(sp)
+    R = torch.from_numpy(o["R"]).to("cuda")
+    S1 = torch.empty_like(R)
+    S2 = torch.full_like(R, complex(np.nan, np.nan))
+    work = torch.empty(H.hp_workspace_bytes(sp.nc, sp.nc, H.HP_C128), dtype=torch.uint8, device="cuda")
+    say("noalloc deep channel, closed", closed)
+    n1 = H.hp_smatrix(d.sys, E, R, S1, work)
+    n2 = H.hp_smatrix_noalloc(d.sys, E, R, S2)
+    assert n1 == n2 == 3
+    assert torch.equal(S1, S2)
+    _check_S(S2.cpu().numpy(), o, 1e-10)
+
+
+@pytest.mark.parametrize("closed", [False, True])
 def test_batched_matching_with_a_deep_channel(mods, closed):
     """The batched matching takes the same scaled form, with and without a
     closed channel; S against the oracle."""
