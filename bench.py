@@ -396,7 +396,7 @@ def main():
         print(json.dumps(counter_summary(args.counter_summary, args.kernel, args.window)), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2512_11590_amd import hprmat as H

@@ -41,7 +41,7 @@ extern "C" {
 #define HP_ERR_SINGULAR (-3)    /* the factorization met an exactly zero pivot */
 #define HP_ERR_NOCONV (-4)      /* iterative refinement did not reach the tolerance */
 #define HP_ERR_WORKSPACE (-5)   /* workspace smaller than hp_workspace_bytes() */
-#define HP_ERR_UNSUPPORTED (-6) /* outside what this build implements (e.g. closed channels) */
+#define HP_ERR_UNSUPPORTED (-6) /* outside what the library implements (e.g. no open channel, sizes beyond a kernel's limits) */
 #define HP_ERR_SYNC (-7)        /* a bounded inter-workgroup wait expired (no hang: reported) */
 
 /* Working precision of the matrix and its LU factors. */
