@@ -92,3 +92,29 @@ def test_arrivals_are_respected():
     res = run(reqs, slots=2, budget=100, rec=rec)
     assert res[1].admitted >= 0.15 - 1e-3
     assert res[1].latency < 0.1
+
+
+# -- device-memory accounting of a request (host arithmetic only) -----------
+
+def test_served_bytes_by_path():
+    """A request's admitted bytes: one set of buffers per energy on the
+    batched path (up to batched_max_n unknowns), one set on the
+    single-system path; FP32 requests also hold the FP64 fallback's
+    matrix; non-local requests take the single-system path at any size and
+    hold their n x n kernel values too."""
+    from paper_2512_11590_amd import hprmat as H
+    from workload import make_system, with_perey_buck
+    sp = make_system("small", nc=4, nr=40)
+    n, ne = sp.nc * sp.nr, len(sp.energies)
+    one = serve.request_bytes(sp.nc, sp.nr, H.HP_C64)
+    assert not serve.is_nonlocal(sp)
+    assert serve.served_bytes(sp, H.HP_C64, batched_max_n=n) == ne * one
+    assert serve.served_bytes(sp, H.HP_C64, batched_max_n=n - 1) == one
+    # FP32 factors: the FP32 matrix and the FP64 fallback's matrix at least
+    assert one >= n * n * (8 + 16)
+    assert serve.request_bytes(sp.nc, sp.nr, H.HP_C128) >= n * n * 16
+    assert serve.request_bytes(sp.nc, sp.nr, H.HP_C128) < one
+    nl = with_perey_buck(make_system("small", nc=4, nr=40))
+    assert serve.is_nonlocal(nl)
+    for bmax in (n, n - 1):
+        assert serve.served_bytes(nl, H.HP_C64, batched_max_n=bmax) == one + n * n * 16
