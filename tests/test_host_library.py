@@ -177,3 +177,41 @@ def test_coulomb_out_of_range_is_reported(H):
         H.hp_coulomb(0, 300.0, 10.0)
     f = H.hp_coulomb(0, 100.0, 3.0)  # deep, but inside double range
     assert np.all(np.isfinite(f)) and f[0] > 0
+
+
+def test_missing_library_fails_loudly():
+    """Without the built library every call through the binding raises; the
+    package has no other path (no CPU fallback)."""
+    import subprocess
+    import sys
+    code = ("import paper_2512_11590_amd.hprmat as H\n"
+            "H.LIB_PATH = '/nonexistent/libhprmat.so'\n"
+            "try:\n"
+            "    H.hp_mesh(8, 10.0)\n"
+            "except ImportError as e:\n"
+            "    print('raised:', e)\n"
+            "    raise SystemExit(0)\n"
+            "raise SystemExit(1)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "is missing" in r.stdout
+
+
+def test_product_package_does_not_import_the_oracle():
+    """No module of the product package imports the oracle (test
+    infrastructure only)."""
+    import ast
+    pkg = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2512_11590_amd")
+    for name in sorted(os.listdir(pkg)):
+        if not name.endswith(".py"):
+            continue
+        tree = ast.parse(open(os.path.join(pkg, name)).read())
+        for node in ast.walk(tree):
+            if isinstance(node, ast.Import):
+                mods = [a.name for a in node.names]
+            elif isinstance(node, ast.ImportFrom):
+                mods = [node.module or ""]
+            else:
+                continue
+            assert not any(m == "oracle" or m.startswith("oracle.") for m in mods), (name, mods)
